@@ -1,0 +1,778 @@
+// oracle.cpp -- plain CPU FP64 reference for generalized-stabilizer (GS) shot
+// sampling of noisy Clifford+T circuits (arXiv 2512.23037).
+//
+// TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+// CPU-baseline leg of the benchmark to check the GPU sampler.  It shares no
+// code with the product library.  Everything here is written for clarity, not
+// speed: a per-shot literal tableau, a std::map coefficient vector, and one
+// Philox evaluation per random word.
+//
+// Conventions fixed where the paper is silent (each one is a reading of the
+// paper, listed with its reason in the design notes of the repository):
+//   * signs are tracked on all 2n rows (needed for Theorem 1 part 1: v is
+//     unchanged by a Clifford only if the destabilizer signs move with it);
+//   * T keeps the exact global phase e^{+-i pi/8} of Eqs. 1-2;
+//   * a measurement with beta != 0 pivots on the lowest anticommuting
+//     stabilizer (Aaronson-Gottesman) and the new stabilizer state is
+//     sqrt(2) * Pi_m |psi_S>;
+//   * outcome +1 (record bit 0) iff u < p0 with u = (w + 1/2) 2^-32;
+//   * entries with |v|^2 < tau^2 * sum|v|^2 are dropped after every T and
+//     measurement;
+//   * noise: DEP1 picks X/Y/Z with p/3 each, DEP2 one of the 15 non-identity
+//     two-qubit Paulis with p/15 each, XERR an X, FLIP a classical record flip.
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+typedef std::complex<double> cplx;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10, written from Salmon et al., "Parallel random numbers: as easy
+// as 1, 2, 3", SC'11: ten rounds of two 32x32->64 multiplies with the round
+// key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Word number `slot` of per-shot stream `stream` (0 = noise, 1 = measurement):
+// counter = (slot / 4, shot low, shot high, stream), key = seed, word slot % 4.
+uint32_t philox_word(uint64_t seed, uint64_t shot, uint32_t stream, uint64_t slot) {
+    uint32_t ctr[4] = {(uint32_t)(slot >> 2), (uint32_t)shot, (uint32_t)(shot >> 32), stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    philox4x32_10(ctr, key, out);
+    return out[slot & 3];
+}
+
+// ---------------------------------------------------------------------------
+// Circuit representation after parsing and noise insertion.
+// ---------------------------------------------------------------------------
+enum Kind {
+    K_H, K_S, K_SDG, K_X, K_Y, K_Z, K_CX, K_CZ, K_T, K_TDG,
+    K_M, K_MPP, K_R,
+    K_DEP1, K_DEP2, K_XERR, K_FLIP,
+    K_DETECTOR, K_OBSERVABLE
+};
+
+struct Op {
+    Kind kind;
+    int a = -1, b = -1;       // qubits
+    uint64_t px = 0, pz = 0;  // MPP Pauli string (sign +)
+    std::vector<int> recs;    // DETECTOR / OBSERVABLE record indices
+    int expect = 0;           // DETECTOR / OBSERVABLE constant
+    uint64_t thr = 0;         // noise threshold floor(p * 2^32)
+    int src = -1;             // index of the source op it came from
+    int slot = -1;            // noise slot (noise ops) or measurement slot
+    int rec = -1;             // record written (M, MPP) or flipped (FLIP)
+    int obs = -1;             // observable index
+};
+
+}  // namespace
+
+struct oracle_circuit {
+    int n = 0;
+    int n_src = 0, n_rec = 0, n_noise = 0, n_meas = 0, n_obs = 0;
+    std::vector<Op> ops;
+};
+
+namespace {
+
+struct ParseError {
+    int line;
+    std::string msg;
+};
+
+uint64_t threshold_of(double p) {
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+int to_int(const std::string &s, int line) {
+    if (s.empty()) throw ParseError{line, "empty integer"};
+    for (char ch : s)
+        if (ch < '0' || ch > '9') throw ParseError{line, "bad integer '" + s + "'"};
+    if (s.size() > 9) throw ParseError{line, "integer too large '" + s + "'"};
+    return std::stoi(s);
+}
+
+double to_prob(const std::string &s, int line) {
+    char *end = nullptr;
+    double p = std::strtod(s.c_str(), &end);
+    if (end == s.c_str() || *end != '\0') throw ParseError{line, "bad probability '" + s + "'"};
+    if (!(p >= 0.0 && p <= 1.0)) throw ParseError{line, "probability out of [0,1]"};
+    return p;
+}
+
+// Parse the circuit text and lower it: every noise location with p > 0 gets a
+// noise slot, every M / MPP / R a measurement slot, every M / MPP a record.
+void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
+    std::istringstream in(text);
+    std::string raw;
+    int line = 0;
+    bool have_qubits = false;
+    std::vector<char> active;  // qubits touched since the last TICK
+
+    auto qubit = [&](const std::string &s) {
+        int q = to_int(s, line);
+        if (q >= c.n) throw ParseError{line, "qubit out of range"};
+        return q;
+    };
+    auto add_noise = [&](Kind k, double p, int a, int b, int src) {
+        if (p <= 0.0) return;
+        Op o;
+        o.kind = k; o.a = a; o.b = b; o.thr = threshold_of(p); o.src = src;
+        o.slot = c.n_noise++;
+        c.ops.push_back(o);
+    };
+    auto add_flip = [&](double p, int rec, int src) {
+        if (p <= 0.0) return;
+        Op o;
+        o.kind = K_FLIP; o.rec = rec; o.thr = threshold_of(p); o.src = src;
+        o.slot = c.n_noise++;
+        c.ops.push_back(o);
+    };
+
+    while (std::getline(in, raw)) {
+        ++line;
+        std::string s = raw.substr(0, raw.find('#'));
+        std::istringstream ts(s);
+        std::vector<std::string> tok;
+        std::string t;
+        while (ts >> t) tok.push_back(t);
+        if (tok.empty()) continue;
+        const std::string &name = tok[0];
+        if (!have_qubits) {
+            if (name != "QUBITS" || tok.size() != 2) throw ParseError{line, "first line must be QUBITS n"};
+            c.n = to_int(tok[1], line);
+            if (c.n < 1 || c.n > 64) throw ParseError{line, "QUBITS must be in 1..64"};
+            active.assign(c.n, 0);
+            have_qubits = true;
+            continue;
+        }
+        int src = c.n_src++;
+        static const char *one_q[] = {"H", "S", "SDG", "X", "Y", "Z", "T", "TDG"};
+        static const Kind one_k[] = {K_H, K_S, K_SDG, K_X, K_Y, K_Z, K_T, K_TDG};
+        bool done = false;
+        for (int i = 0; i < 8 && !done; ++i) {
+            if (name == one_q[i]) {
+                if (tok.size() != 2) throw ParseError{line, name + " takes one qubit"};
+                Op o;
+                o.kind = one_k[i]; o.a = qubit(tok[1]); o.src = src;
+                c.ops.push_back(o);
+                active[o.a] = 1;
+                add_noise(K_DEP1, nm.p1, o.a, -1, src);
+                done = true;
+            }
+        }
+        if (done) continue;
+        if (name == "CX" || name == "CZ") {
+            if (tok.size() != 3) throw ParseError{line, name + " takes two qubits"};
+            Op o;
+            o.kind = name == "CX" ? K_CX : K_CZ;
+            o.a = qubit(tok[1]); o.b = qubit(tok[2]); o.src = src;
+            if (o.a == o.b) throw ParseError{line, "two-qubit gate on one qubit"};
+            c.ops.push_back(o);
+            active[o.a] = active[o.b] = 1;
+            add_noise(K_DEP2, nm.p2, o.a, o.b, src);
+        } else if (name == "M") {
+            if (tok.size() != 2) throw ParseError{line, "M takes one qubit"};
+            int q = qubit(tok[1]);
+            add_noise(K_XERR, nm.p_meas, q, -1, src);
+            Op o;
+            o.kind = K_M; o.a = q; o.src = src; o.slot = c.n_meas++; o.rec = c.n_rec++;
+            c.ops.push_back(o);
+            active[q] = 1;
+        } else if (name == "R") {
+            if (tok.size() != 2) throw ParseError{line, "R takes one qubit"};
+            int q = qubit(tok[1]);
+            Op o;
+            o.kind = K_R; o.a = q; o.src = src; o.slot = c.n_meas++;
+            c.ops.push_back(o);
+            active[q] = 1;
+            add_noise(K_XERR, nm.p_reset, q, -1, src);
+        } else if (name == "MPP") {
+            if (tok.size() != 2) throw ParseError{line, "MPP takes one Pauli product"};
+            Op o;
+            o.kind = K_MPP; o.src = src;
+            std::string prod = tok[1];
+            size_t pos = 0;
+            while (pos <= prod.size()) {
+                size_t star = prod.find('*', pos);
+                std::string f = prod.substr(pos, star == std::string::npos ? std::string::npos : star - pos);
+                if (f.size() < 2) throw ParseError{line, "bad Pauli factor '" + f + "'"};
+                int q = qubit(f.substr(1));
+                uint64_t bit = 1ULL << q;
+                if ((o.px | o.pz) & bit) throw ParseError{line, "repeated qubit in MPP"};
+                if (f[0] == 'X') o.px |= bit;
+                else if (f[0] == 'Z') o.pz |= bit;
+                else if (f[0] == 'Y') { o.px |= bit; o.pz |= bit; }
+                else throw ParseError{line, "bad Pauli letter"};
+                active[q] = 1;
+                if (star == std::string::npos) break;
+                pos = star + 1;
+            }
+            o.slot = c.n_meas++;
+            o.rec = c.n_rec++;
+            c.ops.push_back(o);
+            add_flip(nm.p_mpp, o.rec, src);
+        } else if (name == "DEP1" || name == "XERR") {
+            if (tok.size() < 3) throw ParseError{line, name + " takes p and qubits"};
+            double p = to_prob(tok[1], line);
+            for (size_t i = 2; i < tok.size(); ++i)
+                add_noise(name == "DEP1" ? K_DEP1 : K_XERR, p, qubit(tok[i]), -1, src);
+        } else if (name == "DEP2") {
+            if (tok.size() < 4 || (tok.size() - 2) % 2 != 0) throw ParseError{line, "DEP2 takes p and qubit pairs"};
+            double p = to_prob(tok[1], line);
+            for (size_t i = 2; i < tok.size(); i += 2) {
+                int a = qubit(tok[i]), b = qubit(tok[i + 1]);
+                if (a == b) throw ParseError{line, "DEP2 on one qubit"};
+                add_noise(K_DEP2, p, a, b, src);
+            }
+        } else if (name == "TICK") {
+            if (tok.size() != 1) throw ParseError{line, "TICK takes no arguments"};
+            for (int q = 0; q < c.n; ++q)
+                if (!active[q]) add_noise(K_DEP1, nm.p_idle, q, -1, src);
+            active.assign(c.n, 0);
+        } else if (name == "DETECTOR" || name == "OBSERVABLE") {
+            if (tok.size() < 2) throw ParseError{line, name + " takes an expected bit"};
+            Op o;
+            o.kind = name == "DETECTOR" ? K_DETECTOR : K_OBSERVABLE;
+            o.src = src;
+            o.expect = to_int(tok[1], line);
+            if (o.expect > 1) throw ParseError{line, "expected bit must be 0 or 1"};
+            for (size_t i = 2; i < tok.size(); ++i) {
+                int r = to_int(tok[i], line);
+                if (r >= c.n_rec) throw ParseError{line, "record index not yet measured"};
+                o.recs.push_back(r);
+            }
+            if (o.kind == K_OBSERVABLE) {
+                if (c.n_obs >= 32) throw ParseError{line, "at most 32 observables"};
+                o.obs = c.n_obs++;
+            }
+            c.ops.push_back(o);
+        } else {
+            throw ParseError{line, "unknown op '" + name + "'"};
+        }
+    }
+    if (!have_qubits) throw ParseError{line, "missing QUBITS line"};
+}
+
+// ---------------------------------------------------------------------------
+// Pauli rows.  A row (x, z, e) means i^e * (x) sigma(x_j, z_j) with
+// sigma(0,0)=I, sigma(1,0)=X, sigma(0,1)=Z, sigma(1,1)=Y.  Tableau rows carry
+// e = 2 r (a sign).
+// ---------------------------------------------------------------------------
+struct Pauli {
+    uint64_t x = 0, z = 0;
+    int e = 0;  // exponent of i, mod 4
+};
+
+int popc(uint64_t w) { return __builtin_popcountll(w); }
+
+int mod4(int k) { return ((k % 4) + 4) % 4; }
+
+// 1 iff A and B anticommute (symplectic product).
+int anticommute(uint64_t ax, uint64_t az, uint64_t bx, uint64_t bz) {
+    return popc((ax & bz) ^ (az & bx)) & 1;
+}
+
+// C = A * B.  With sigma(x,z) = i^{xz} X^x Z^z per qubit, moving each Z^{zA}
+// past X^{xB} costs (-1)^{zA.xB}, hence
+//   e_C = e_A + e_B + |xA&zA| + |xB&zB| + 2|zA&xB| - |xC&zC|  (mod 4).
+Pauli mul(const Pauli &A, const Pauli &B) {
+    Pauli C;
+    C.x = A.x ^ B.x;
+    C.z = A.z ^ B.z;
+    C.e = mod4(A.e + B.e + popc(A.x & A.z) + popc(B.x & B.z) + 2 * popc(A.z & B.x) - popc(C.x & C.z));
+    return C;
+}
+
+const double kPi = 3.14159265358979323846;
+
+struct ShotState {
+    int n;
+    std::vector<uint64_t> x, z;  // rows 0..n-1: destabilizers, n..2n-1: stabilizers
+    std::vector<int> r;          // sign bits
+    std::map<uint64_t, cplx> v;  // alpha -> v_alpha
+};
+
+Pauli row(const ShotState &st, int i) {
+    Pauli p;
+    p.x = st.x[i]; p.z = st.z[i]; p.e = 2 * st.r[i];
+    return p;
+}
+
+void set_row(ShotState &st, int i, const Pauli &p) {
+    if (p.e % 2 != 0) { std::fprintf(stderr, "oracle: non-Hermitian tableau row\n"); std::abort(); }
+    st.x[i] = p.x; st.z[i] = p.z; st.r[i] = p.e / 2;
+}
+
+int bit(uint64_t w, int q) { return (int)((w >> q) & 1ULL); }
+
+void set_bit(uint64_t &w, int q, int b) {
+    w = (w & ~(1ULL << q)) | ((uint64_t)b << q);
+}
+
+// Clifford conjugation rules of the Aaronson-Gottesman tableau, signs included.
+void apply_clifford(ShotState &st, Kind k, int a, int b) {
+    for (int i = 0; i < 2 * st.n; ++i) {
+        int xa = bit(st.x[i], a), za = bit(st.z[i], a);
+        switch (k) {
+            case K_H:
+                st.r[i] ^= xa & za;
+                set_bit(st.x[i], a, za);
+                set_bit(st.z[i], a, xa);
+                break;
+            case K_S:
+                st.r[i] ^= xa & za;
+                set_bit(st.z[i], a, za ^ xa);
+                break;
+            case K_SDG:
+                st.r[i] ^= xa & (za ^ 1);
+                set_bit(st.z[i], a, za ^ xa);
+                break;
+            case K_X: st.r[i] ^= za; break;
+            case K_Z: st.r[i] ^= xa; break;
+            case K_Y: st.r[i] ^= xa ^ za; break;
+            case K_CX: {
+                int xb = bit(st.x[i], b), zb = bit(st.z[i], b);
+                st.r[i] ^= xa & zb & (xb ^ za ^ 1);
+                set_bit(st.x[i], b, xb ^ xa);
+                set_bit(st.z[i], a, za ^ zb);
+                break;
+            }
+            case K_CZ: {
+                int xb = bit(st.x[i], b), zb = bit(st.z[i], b);
+                st.r[i] ^= xa & xb & (za ^ zb);
+                set_bit(st.z[i], a, za ^ xb);
+                set_bit(st.z[i], b, zb ^ xa);
+                break;
+            }
+            default: std::abort();
+        }
+    }
+}
+
+// Single-qubit Pauli code 0=I 1=X 2=Y 3=Z applied as a conjugation.
+void apply_pauli_code(ShotState &st, int code, int q) {
+    if (code == 1) apply_clifford(st, K_X, q, -1);
+    if (code == 2) apply_clifford(st, K_Y, q, -1);
+    if (code == 3) apply_clifford(st, K_Z, q, -1);
+}
+
+// Q = c * d_beta * s_gamma with beta_i = [Q anticommutes with s_i] and
+// gamma_i = [Q anticommutes with d_i] (the index shift of Eq. 4).  The product
+// is taken left to right in index order; c = i^{e_Q - e_R}.
+struct Decomp {
+    uint64_t beta = 0, gamma = 0;
+    int c_exp = 0;
+};
+
+Decomp decompose(const ShotState &st, const Pauli &Q) {
+    Decomp d;
+    int n = st.n;
+    for (int i = 0; i < n; ++i) {
+        if (anticommute(Q.x, Q.z, st.x[n + i], st.z[n + i])) d.beta |= 1ULL << i;
+        if (anticommute(Q.x, Q.z, st.x[i], st.z[i])) d.gamma |= 1ULL << i;
+    }
+    Pauli R;
+    for (int i = 0; i < n; ++i)
+        if (bit(d.beta, i)) R = mul(R, row(st, i));
+    for (int i = 0; i < n; ++i)
+        if (bit(d.gamma, i)) R = mul(R, row(st, n + i));
+    if (R.x != Q.x || R.z != Q.z) { std::fprintf(stderr, "oracle: decomposition failed\n"); std::abort(); }
+    d.c_exp = mod4(Q.e - R.e);
+    return d;
+}
+
+cplx ipow(int k) {
+    static const cplx tab[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
+    return tab[mod4(k)];
+}
+
+double sgn_parity(uint64_t w) { return (popc(w) & 1) ? -1.0 : 1.0; }
+
+double norm2(const std::map<uint64_t, cplx> &v) {
+    double s = 0.0;
+    for (const auto &kv : v) s += std::norm(kv.second);
+    return s;
+}
+
+// Drop entries with |v_alpha|^2 < tau^2 * sum |v|^2.
+void prune(std::map<uint64_t, cplx> &v, double tau) {
+    double limit = tau * tau * norm2(v);
+    for (auto it = v.begin(); it != v.end();) {
+        if (std::norm(it->second) < limit) it = v.erase(it);
+        else ++it;
+    }
+}
+
+// T^s on qubit q (s = +1 for T, -1 for T-dagger):
+// T^s = e^{i s theta} (cos theta I - i s sin theta Z_q), theta = pi/8 (Eqs. 1-2),
+// with Z_q |b_alpha> = c (-1)^{gamma.alpha} |b_{alpha^beta}> (Eq. 4).
+void apply_t(ShotState &st, int q, int s, double tau) {
+    Pauli Z;
+    Z.z = 1ULL << q;
+    Decomp d = decompose(st, Z);
+    const double th = kPi / 8.0;
+    const cplx glob = std::exp(cplx(0.0, s * th));
+    const double cs = std::cos(th), sn = std::sin(th);
+    const cplx c = ipow(d.c_exp);
+    const cplx mi_s(0.0, -(double)s);  // -i s
+    std::map<uint64_t, cplx> out;
+    if (d.beta == 0) {
+        for (const auto &kv : st.v) {
+            cplx lam = c * sgn_parity(d.gamma & kv.first);
+            out[kv.first] = glob * (cs + mi_s * sn * lam) * kv.second;
+        }
+    } else {
+        std::set<uint64_t> keys;
+        for (const auto &kv : st.v) {
+            keys.insert(kv.first);
+            keys.insert(kv.first ^ d.beta);
+        }
+        for (uint64_t a : keys) {
+            auto it0 = st.v.find(a);
+            auto it1 = st.v.find(a ^ d.beta);
+            cplx v0 = it0 == st.v.end() ? cplx(0) : it0->second;
+            cplx v1 = it1 == st.v.end() ? cplx(0) : it1->second;
+            out[a] = glob * (cs * v0 + mi_s * sn * c * sgn_parity(d.gamma & (a ^ d.beta)) * v1);
+        }
+    }
+    st.v.swap(out);
+    prune(st.v, tau);
+}
+
+// Measurement of the Hermitian Pauli P with uniform u.  Returns the record
+// bit, or -1 for a numerically empty branch.  p0 receives P(outcome +1).
+int measure(ShotState &st, const Pauli &P, double u, double tau, double *p0_out) {
+    Decomp d = decompose(st, P);
+    const cplx c = ipow(d.c_exp);
+    const int n = st.n;
+    if (d.beta == 0) {
+        // P = c * s_gamma acts diagonally: P |b_alpha> = lambda_alpha |b_alpha>.
+        double Np = 0.0, Nm = 0.0;
+        for (const auto &kv : st.v) {
+            double lam = (c * sgn_parity(d.gamma & kv.first)).real();
+            if (lam > 0) Np += std::norm(kv.second);
+            else Nm += std::norm(kv.second);
+        }
+        double p0 = Np / (Np + Nm);
+        if (p0_out) *p0_out = p0;
+        int m = u < p0 ? +1 : -1;
+        double Nsel = m > 0 ? Np : Nm;
+        if (!(Nsel > 1e-300)) return -1;
+        std::map<uint64_t, cplx> out;
+        for (const auto &kv : st.v) {
+            double lam = (c * sgn_parity(d.gamma & kv.first)).real();
+            if ((lam > 0) == (m > 0)) out[kv.first] = kv.second / std::sqrt(Nsel);
+        }
+        st.v.swap(out);
+        prune(st.v, tau);
+        return m > 0 ? 0 : 1;
+    }
+    // beta != 0: pivot on the lowest stabilizer that anticommutes with P.
+    int p = __builtin_ctzll(d.beta);
+    std::set<uint64_t> reps;
+    for (const auto &kv : st.v) {
+        uint64_t a = kv.first;
+        reps.insert(bit(a, p) ? (a ^ d.beta) : a);
+    }
+    std::map<uint64_t, cplx> wplus, wminus;
+    double Np = 0.0, Nm = 0.0;
+    for (uint64_t a : reps) {
+        auto it0 = st.v.find(a);
+        auto it1 = st.v.find(a ^ d.beta);
+        cplx v0 = it0 == st.v.end() ? cplx(0) : it0->second;
+        cplx v1 = it1 == st.v.end() ? cplx(0) : it1->second;
+        cplx f = std::conj(c) * sgn_parity(d.gamma & a);
+        wplus[a] = v0 + f * v1;
+        wminus[a] = v0 - f * v1;
+        Np += 0.5 * std::norm(wplus[a]);
+        Nm += 0.5 * std::norm(wminus[a]);
+    }
+    double p0 = Np / (Np + Nm);
+    if (p0_out) *p0_out = p0;
+    int m = u < p0 ? +1 : -1;
+    double Nsel = m > 0 ? Np : Nm;
+    if (!(Nsel > 1e-300)) return -1;
+    std::map<uint64_t, cplx> out;
+    for (uint64_t a : reps) out[a] = (m > 0 ? wplus[a] : wminus[a]) / std::sqrt(2.0 * Nsel);
+    // Tableau: rows anticommuting with P (other than s_p, d_p) absorb s_p;
+    // d_p takes the old s_p; s_p becomes m P.
+    Pauli sp = row(st, n + p);
+    for (int i = 0; i < 2 * n; ++i) {
+        if (i == p || i == n + p) continue;
+        if (anticommute(P.x, P.z, st.x[i], st.z[i])) set_row(st, i, mul(row(st, i), sp));
+    }
+    set_row(st, p, sp);
+    Pauli mp = P;
+    mp.e = mod4(P.e + (m > 0 ? 0 : 2));
+    set_row(st, n + p, mp);
+    st.v.swap(out);
+    prune(st.v, tau);
+    return m > 0 ? 0 : 1;
+}
+
+struct ShotResult {
+    std::vector<uint32_t> record;
+    oracle_shot_info info;
+};
+
+double uniform_of(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint32_t *words, double tau,
+              uint32_t cap, ShotState &st, ShotResult &res, double *p0_trace) {
+    const int n = c.n;
+    st.n = n;
+    st.x.assign(2 * n, 0);
+    st.z.assign(2 * n, 0);
+    st.r.assign(2 * n, 0);
+    for (int i = 0; i < n; ++i) {
+        st.x[i] = 1ULL << i;      // d_i = +X_i
+        st.z[n + i] = 1ULL << i;  // s_i = +Z_i
+    }
+    st.v.clear();
+    st.v[0] = cplx(1.0, 0.0);
+    res.record.assign((c.n_rec + 31) / 32, 0u);
+    std::memset(&res.info, 0, sizeof(res.info));
+    res.info.abort_op = 0xffffffffu;
+    res.info.max_support = 1;
+
+    auto noise_word = [&](int slot) {
+        return words ? words[slot] : philox_word(seed, shot, 0, (uint64_t)slot);
+    };
+    auto meas_word = [&](int slot) {
+        return words ? words[c.n_noise + slot] : philox_word(seed, shot, 1, (uint64_t)slot);
+    };
+    auto rec_bit = [&](int k) { return (int)((res.record[k >> 5] >> (k & 31)) & 1u); };
+    auto note_support = [&]() {
+        res.info.max_support = std::max<uint32_t>(res.info.max_support, (uint32_t)st.v.size());
+    };
+
+    for (const Op &o : c.ops) {
+        switch (o.kind) {
+            case K_H: case K_S: case K_SDG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ:
+                apply_clifford(st, o.kind, o.a, o.b);
+                break;
+            case K_T: case K_TDG: {
+                Pauli Z;
+                Z.z = 1ULL << o.a;
+                bool branching = decompose(st, Z).beta != 0;
+                if (!branching) res.info.t_phase_entries += st.v.size();
+                apply_t(st, o.a, o.kind == K_T ? +1 : -1, tau);
+                if (branching) res.info.t_entries += st.v.size();
+                res.info.events++;
+                note_support();
+                if (st.v.size() > cap) {
+                    res.info.status = ORACLE_OVERFLOW;
+                    res.info.abort_op = o.src;
+                    res.info.norm2 = norm2(st.v);
+                    return;
+                }
+                break;
+            }
+            case K_M: case K_MPP: case K_R: {
+                Pauli P;
+                if (o.kind == K_MPP) { P.x = o.px; P.z = o.pz; }
+                else P.z = 1ULL << o.a;
+                res.info.m_entries += st.v.size();
+                res.info.events++;
+                double p0 = 0.0;
+                int b = measure(st, P, uniform_of(meas_word(o.slot)), tau, &p0);
+                if (p0_trace) p0_trace[o.slot] = p0;
+                if (b < 0) {
+                    res.info.status = ORACLE_NUMERIC;
+                    res.info.abort_op = o.src;
+                    res.info.norm2 = norm2(st.v);
+                    return;
+                }
+                if (o.kind == K_R) {
+                    if (b) apply_clifford(st, K_X, o.a, -1);
+                } else if (b) {
+                    res.record[o.rec >> 5] |= 1u << (o.rec & 31);
+                }
+                note_support();
+                break;
+            }
+            case K_DEP1: case K_DEP2: case K_XERR: case K_FLIP: {
+                res.info.noise_slots++;
+                uint32_t w = noise_word(o.slot);
+                if ((uint64_t)w >= o.thr) break;
+                if (o.kind == K_DEP1) {
+                    int idx = (int)((3ULL * w) / o.thr);  // 0,1,2 -> X,Y,Z
+                    apply_pauli_code(st, idx + 1, o.a);
+                } else if (o.kind == K_DEP2) {
+                    int code = (int)((15ULL * w) / o.thr) + 1;  // 1..15
+                    apply_pauli_code(st, code >> 2, o.a);
+                    apply_pauli_code(st, code & 3, o.b);
+                } else if (o.kind == K_XERR) {
+                    apply_pauli_code(st, 1, o.a);
+                } else {
+                    res.record[o.rec >> 5] ^= 1u << (o.rec & 31);
+                }
+                break;
+            }
+            case K_DETECTOR: case K_OBSERVABLE: {
+                int par = o.expect;
+                for (int k : o.recs) par ^= rec_bit(k);
+                if (o.kind == K_DETECTOR) {
+                    if (par) {
+                        res.info.status = ORACLE_DISCARDED;
+                        res.info.abort_op = o.src;
+                        res.info.norm2 = norm2(st.v);
+                        return;
+                    }
+                } else if (par) {
+                    res.info.obs |= 1u << o.obs;
+                }
+                break;
+            }
+        }
+    }
+    res.info.status = ORACLE_PASSED;
+    res.info.norm2 = norm2(st.v);
+}
+
+}  // namespace
+
+extern "C" {
+
+oracle_circuit *oracle_compile(const char *text, const oracle_noise *noise, char *err, int errlen) {
+    oracle_noise nm = {0, 0, 0, 0, 0, 0};
+    if (noise) nm = *noise;
+    const double ps[6] = {nm.p1, nm.p2, nm.p_idle, nm.p_meas, nm.p_reset, nm.p_mpp};
+    for (double p : ps) {
+        if (!(p >= 0.0 && p <= 1.0)) {
+            if (err && errlen > 0) std::snprintf(err, errlen, "noise probability out of [0,1]");
+            return nullptr;
+        }
+    }
+    oracle_circuit *c = new oracle_circuit();
+    try {
+        compile(text ? text : "", nm, *c);
+    } catch (const ParseError &e) {
+        if (err && errlen > 0) std::snprintf(err, errlen, "line %d: %s", e.line, e.msg.c_str());
+        delete c;
+        return nullptr;
+    }
+    return c;
+}
+
+void oracle_free(oracle_circuit *c) { delete c; }
+
+void oracle_counts(const oracle_circuit *c, uint64_t counts[7]) {
+    counts[0] = c->n;
+    counts[1] = c->n_src;
+    counts[2] = c->n_rec;
+    counts[3] = c->n_noise;
+    counts[4] = c->n_meas;
+    counts[5] = c->n_obs;
+    counts[6] = c->ops.size();
+}
+
+int oracle_shot(const oracle_circuit *c, uint64_t seed, uint64_t shot, const uint32_t *words, double tau,
+                uint32_t cap, uint32_t *record, oracle_shot_info *info, uint64_t *tab_x, uint64_t *tab_z,
+                uint8_t *tab_r, uint64_t *alpha, double *re, double *im, uint32_t coeff_cap, uint32_t *n_coeff,
+                double *p0_trace) {
+    if (!c || !(tau >= 0.0)) return -1;
+    ShotState st;
+    ShotResult res;
+    run_shot(*c, seed, shot, words, tau, cap, st, res, p0_trace);
+    if (record)
+        for (size_t i = 0; i < res.record.size(); ++i) record[i] = res.record[i];
+    if (info) *info = res.info;
+    for (int i = 0; i < 2 * c->n; ++i) {
+        if (tab_x) tab_x[i] = st.x[i];
+        if (tab_z) tab_z[i] = st.z[i];
+        if (tab_r) tab_r[i] = (uint8_t)st.r[i];
+    }
+    if (n_coeff) *n_coeff = (uint32_t)st.v.size();
+    uint32_t k = 0;
+    for (const auto &kv : st.v) {
+        if (k >= coeff_cap) break;
+        if (alpha) alpha[k] = kv.first;
+        if (re) re[k] = kv.second.real();
+        if (im) im[k] = kv.second.imag();
+        ++k;
+    }
+    return 0;
+}
+
+int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_t n, const uint32_t *words,
+                 double tau, uint32_t cap, int threads, uint32_t *outcomes, uint32_t *status, uint32_t *abort_op,
+                 uint32_t *obs, uint32_t *max_support, uint64_t *work) {
+    if (!c || !(tau >= 0.0)) return -1;
+    if (threads < 1) threads = 1;
+    const uint64_t stride = (uint64_t)c->n_noise + c->n_meas;
+    const int nw = (c->n_rec + 31) / 32;
+    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(5, 0));
+    auto worker = [&](int t) {
+        uint64_t lo = n * t / threads, hi = n * (t + 1) / threads;
+        ShotState st;
+        ShotResult res;
+        for (uint64_t i = lo; i < hi; ++i) {
+            run_shot(*c, seed, shot0 + i, words ? words + i * stride : nullptr, tau, cap, st, res, nullptr);
+            for (int w = 0; w < nw; ++w)
+                if (outcomes) outcomes[(uint64_t)w * n + i] = res.record[w];
+            if (status) status[i] = res.info.status;
+            if (abort_op) abort_op[i] = res.info.abort_op;
+            if (obs) obs[i] = res.info.obs;
+            if (max_support) max_support[i] = res.info.max_support;
+            part[t][0] += res.info.t_entries;
+            part[t][1] += res.info.t_phase_entries;
+            part[t][2] += res.info.m_entries;
+            part[t][3] += res.info.noise_slots;
+            part[t][4] += res.info.events;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(worker, t);
+    worker(0);
+    for (auto &th : pool) th.join();
+    if (work)
+        for (int k = 0; k < 5; ++k) {
+            work[k] = 0;
+            for (int t = 0; t < threads; ++t) work[k] += part[t][k];
+        }
+    return 0;
+}
+
+void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox4x32_10(ctr, key, out); }
+
+void oracle_pauli_mul(const uint64_t a[3], const uint64_t b[3], uint64_t out[3]) {
+    Pauli A, B;
+    A.x = a[0]; A.z = a[1]; A.e = mod4((int)(a[2] & 3));
+    B.x = b[0]; B.z = b[1]; B.e = mod4((int)(b[2] & 3));
+    Pauli C = mul(A, B);
+    out[0] = C.x; out[1] = C.z; out[2] = (uint64_t)C.e;
+}
+
+}  // extern "C"

@@ -1,0 +1,48 @@
+"""Small seeded random circuits for the pins and parity tests (test code)."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: float = 0.08,
+                   p_mpp: float = 0.04, p_reset: float = 0.03, p_pauli: float = 0.08,
+                   clifford_only: bool = False, allow_mpp: bool = True, gates=("H", "S", "SDG", "CX", "CZ")):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if clifford_only:
+        p_t = 0.0
+    if not allow_mpp:
+        p_mpp = 0.0
+    lines = ["QUBITS %d" % n]
+    n_meas_slots = 0
+    for _ in range(length):
+        u = rng.random()
+        if u < p_t:
+            lines.append("%s %d" % ("T" if rng.integers(2) == 0 else "TDG", rng.integers(n)))
+        elif u < p_t + p_meas:
+            lines.append("M %d" % rng.integers(n))
+            n_meas_slots += 1
+        elif u < p_t + p_meas + p_mpp:
+            k = int(rng.integers(1, n + 1))
+            qs = rng.choice(n, size=k, replace=False)
+            lines.append("MPP " + "*".join("%s%d" % ("XYZ"[rng.integers(3)], q) for q in qs))
+            n_meas_slots += 1
+        elif u < p_t + p_meas + p_mpp + p_reset:
+            lines.append("R %d" % rng.integers(n))
+            n_meas_slots += 1
+        elif u < p_t + p_meas + p_mpp + p_reset + p_pauli:
+            lines.append("%s %d" % ("XYZ"[rng.integers(3)], rng.integers(n)))
+        else:
+            g = gates[int(rng.integers(len(gates)))]
+            if g in ("CX", "CZ"):
+                if n < 2:
+                    continue
+                a, b = rng.choice(n, size=2, replace=False)
+                lines.append("%s %d %d" % (g, a, b))
+            else:
+                lines.append("%s %d" % (g, rng.integers(n)))
+    return "\n".join(lines) + "\n", n_meas_slots
+
+
+def random_words(seed: int, count: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, 1 << 32, size=count, dtype=np.uint64).astype(np.uint32)

@@ -1,0 +1,180 @@
+"""Dense statevector checker for the oracle (test code, numpy, <= ~12 qubits).
+
+It runs a circuit on a plain 2^n statevector with the textbook gate matrices
+(H, S = diag(1, i), T = diag(1, e^{i pi/4}), CNOT, CZ, Paulis) and, beside it,
+a "shadow" copy of the stabilizer state |psi_S> whose global phase follows the
+same reading the oracle uses: Cliffords and Paulis act on it as matrices, T
+leaves it alone, and a measurement that is random on |psi_S> replaces it by
+sqrt(2) Pi_m |psi_S>.  With the shadow, a generalized-stabilizer state
+(tableau, v) can be expanded as sum_alpha v_alpha d_alpha |psi_S>
+(Definition 1) and compared with the statevector with no global-phase freedom.
+
+Measurement outcomes are decided here from the same explicit uniforms the
+oracle receives (outcome +1 iff u < P(+1)), so the records are an independent
+check too.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SQ2 = np.sqrt(0.5)
+MATS = {
+    "H": np.array([[1, 1], [1, -1]], dtype=complex) * SQ2,
+    "S": np.diag([1, 1j]).astype(complex),
+    "SDG": np.diag([1, -1j]).astype(complex),
+    "X": np.array([[0, 1], [1, 0]], dtype=complex),
+    "Y": np.array([[0, -1j], [1j, 0]], dtype=complex),
+    "Z": np.diag([1, -1]).astype(complex),
+    "T": np.diag([1, np.exp(1j * np.pi / 4)]),
+    "TDG": np.diag([1, np.exp(-1j * np.pi / 4)]),
+}
+
+
+def popcount(a):
+    return np.bitwise_count(np.asarray(a, dtype=np.uint64)).astype(np.int64)
+
+
+def apply_1q(psi, U, q, n):
+    t = psi.reshape([2] * n)
+    ax = n - 1 - q
+    t = np.moveaxis(np.tensordot(U, t, axes=([1], [ax])), 0, ax)
+    return t.reshape(-1)
+
+
+def apply_cx(psi, a, b, n):
+    idx = np.arange(1 << n, dtype=np.uint64)
+    src = idx ^ (((idx >> np.uint64(a)) & np.uint64(1)) << np.uint64(b))
+    return psi[src]
+
+
+def apply_cz(psi, a, b, n):
+    idx = np.arange(1 << n, dtype=np.uint64)
+    ph = ((idx >> np.uint64(a)) & (idx >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return psi * (1 - 2 * ph)
+
+
+def pauli_apply(psi, x, z, e, n):
+    """Apply i^e (x) sigma(x_j, z_j) with sigma(1,1) = Y = i X Z."""
+    idx = np.arange(1 << n, dtype=np.uint64)
+    j = idx ^ np.uint64(x)
+    sign = 1 - 2 * (popcount(j & np.uint64(z)) & 1)
+    phase = 1j ** ((e + bin(x & z).count("1")) % 4)
+    return phase * sign * psi[j]
+
+
+def expval(psi, x, z, e, n):
+    return np.vdot(psi, pauli_apply(psi, x, z, e, n))
+
+
+def parse(text):
+    ops = []
+    n = None
+    for raw in text.splitlines():
+        tok = raw.split("#")[0].split()
+        if not tok:
+            continue
+        if tok[0] == "QUBITS":
+            n = int(tok[1])
+            continue
+        ops.append(tok)
+    return n, ops
+
+
+def mpp_pauli(spec):
+    x = z = 0
+    for f in spec.split("*"):
+        q = int(f[1:])
+        if f[0] in "XY":
+            x |= 1 << q
+        if f[0] in "ZY":
+            z |= 1 << q
+    return x, z
+
+
+def run(text, meas_words):
+    """Run a noiseless circuit (explicit Paulis allowed) on a statevector.
+
+    Returns (phi, shadow, record, p0_list) where p0_list[k] = P(+1) at
+    measurement slot k.  DETECTOR/OBSERVABLE lines are ignored."""
+    n, ops = parse(text)
+    phi = np.zeros(1 << n, dtype=complex)
+    phi[0] = 1
+    shadow = phi.copy()
+    record = []
+    p0s = []
+    slot = 0
+    for tok in ops:
+        g = tok[0]
+        if g in ("H", "S", "SDG", "X", "Y", "Z"):
+            q = int(tok[1])
+            phi = apply_1q(phi, MATS[g], q, n)
+            shadow = apply_1q(shadow, MATS[g], q, n)
+        elif g in ("T", "TDG"):
+            phi = apply_1q(phi, MATS[g], int(tok[1]), n)
+        elif g == "CX":
+            phi = apply_cx(phi, int(tok[1]), int(tok[2]), n)
+            shadow = apply_cx(shadow, int(tok[1]), int(tok[2]), n)
+        elif g == "CZ":
+            phi = apply_cz(phi, int(tok[1]), int(tok[2]), n)
+            shadow = apply_cz(shadow, int(tok[1]), int(tok[2]), n)
+        elif g in ("M", "R", "MPP"):
+            if g == "MPP":
+                x, z = mpp_pauli(tok[1])
+            else:
+                x, z = 0, 1 << int(tok[1])
+            Pphi = pauli_apply(phi, x, z, 0, n)
+            p0 = float(np.real(0.5 * (1 + np.vdot(phi, Pphi))))
+            u = (float(meas_words[slot]) + 0.5) / 2.0 ** 32
+            m = 1 if u < p0 else -1
+            p0s.append(p0)
+            slot += 1
+            prob = p0 if m == 1 else 1 - p0
+            phi = 0.5 * (phi + m * Pphi) / np.sqrt(prob)
+            Psh = pauli_apply(shadow, x, z, 0, n)
+            ev = np.vdot(shadow, Psh)
+            if abs(abs(ev) - 1) < 1e-9:
+                pass                          # deterministic on |psi_S>: unchanged
+            elif abs(ev) < 1e-9:
+                shadow = np.sqrt(2) * 0.5 * (shadow + m * Psh)
+            else:
+                raise AssertionError("shadow is not a stabilizer state")
+            bit = 0 if m == 1 else 1
+            if g == "R":
+                if bit:
+                    phi = apply_1q(phi, MATS["X"], int(tok[1]), n)
+                    shadow = apply_1q(shadow, MATS["X"], int(tok[1]), n)
+            else:
+                record.append(bit)
+        elif g in ("DETECTOR", "OBSERVABLE", "TICK"):
+            pass
+        else:
+            raise ValueError("dense checker does not model " + g)
+    return phi, shadow, record, p0s
+
+
+def reconstruct(tab_x, tab_z, tab_r, coeffs, shadow, n):
+    """sum_alpha v_alpha d_alpha |psi_S> from an oracle tableau and map."""
+    out = np.zeros(1 << n, dtype=complex)
+    for alpha, v in coeffs.items():
+        vec = shadow.copy()
+        for k in range(n):
+            if (alpha >> k) & 1:
+                vec = pauli_apply(vec, int(tab_x[k]), int(tab_z[k]), 2 * int(tab_r[k]), n)
+        out += v * vec
+    return out
+
+
+def check_tableau(tab_x, tab_z, tab_r, shadow, n, tol=1e-10):
+    """Stabilizer rows (with signs) fix the shadow; the symplectic relations
+    d_i s_j = (-1)^{delta_ij} s_j d_i hold; stabilizers and destabilizers commute
+    among themselves."""
+    def anti(i, j):
+        return bin((int(tab_x[i]) & int(tab_z[j])) ^ (int(tab_z[i]) & int(tab_x[j]))).count("1") & 1
+    for i in range(n):
+        s = n + i
+        v = pauli_apply(shadow, int(tab_x[s]), int(tab_z[s]), 2 * int(tab_r[s]), n)
+        assert np.max(np.abs(v - shadow)) < tol, "stabilizer %d does not fix |psi_S>" % i
+        for j in range(n):
+            assert anti(i, n + j) == (1 if i == j else 0)
+            assert anti(i, j) == 0
+            assert anti(n + i, n + j) == 0

@@ -1,0 +1,500 @@
+"""Pins of the CPU oracle against things other than itself (no GPU).
+
+* Pauli products against 2x2 / Kronecker matrix products;
+* every tableau rule against dense conjugation U P U^dagger;
+* random Clifford+T+measurement circuits against a dense statevector with a
+  phase-tracked stabilizer shadow, exact to 1e-12 with no global-phase freedom
+  (Definition 1, Eqs. 1-4, Theorem 1);
+* Clifford-only circuits against an independent Aaronson-Gottesman tableau;
+* identities T^2 = S, T^8 = I, T T^dagger = I, S^4 = H^2 = I, unit norm;
+* closed forms for T|+>, T|1>, P(X=+1) after T;
+* the support bounds of Theorem 1, the 2^min(t,n) bound, Proposition 1's coset
+  bound and Theorem 2's |v| <= 16 / 1024;
+* Philox4x32-10 known-answer vectors;
+* the noise model and outcome sampling against exact enumeration (chi^2).
+"""
+from __future__ import annotations
+
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import ref_chp, ref_dense
+from tests.gen_small import random_circuit, random_words
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# ---------------------------------------------------------------------------
+# Philox
+# ---------------------------------------------------------------------------
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = oracle.philox(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+# ---------------------------------------------------------------------------
+# Pauli products (the word-level phase formula)
+# ---------------------------------------------------------------------------
+def _pauli_matrix(x, z, e, n):
+    m = np.array([[1.0 + 0j]])
+    for q in reversed(range(n)):
+        xb, zb = (x >> q) & 1, (z >> q) & 1
+        if xb and zb:
+            f = ref_dense.MATS["Y"]
+        elif xb:
+            f = ref_dense.MATS["X"]
+        elif zb:
+            f = ref_dense.MATS["Z"]
+        else:
+            f = np.eye(2)
+        m = np.kron(m, f)
+    return (1j ** e) * m
+
+
+def test_pauli_product_single_qubit_exhaustive():
+    for ax, az, ae, bx, bz, be in itertools.product((0, 1), (0, 1), range(4), (0, 1), (0, 1), range(4)):
+        cx, cz, ce = oracle.pauli_mul((ax, az, ae), (bx, bz, be))
+        want = _pauli_matrix(ax, az, ae, 1) @ _pauli_matrix(bx, bz, be, 1)
+        assert np.allclose(_pauli_matrix(cx, cz, ce, 1), want, atol=1e-15)
+
+
+def test_pauli_product_multi_qubit_matrices():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        n = 4
+        a = [int(rng.integers(16)), int(rng.integers(16)), int(rng.integers(4))]
+        b = [int(rng.integers(16)), int(rng.integers(16)), int(rng.integers(4))]
+        c = oracle.pauli_mul(a, b)
+        assert np.allclose(_pauli_matrix(*c, n), _pauli_matrix(*a, n) @ _pauli_matrix(*b, n), atol=1e-14)
+
+
+def test_pauli_product_64_qubit_words_compose_per_qubit():
+    # A 64-qubit product is the tensor product of per-qubit products, whose
+    # phases multiply: check against the exhaustive single-qubit table.
+    rng = np.random.default_rng(6)
+    table = {}
+    for ax, az, bx, bz in itertools.product((0, 1), repeat=4):
+        table[(ax, az, bx, bz)] = oracle.pauli_mul((ax, az, 0), (bx, bz, 0))
+    for _ in range(200):
+        ax, az, bx, bz = (int(rng.integers(0, 1 << 63)) * 2 + int(rng.integers(2)) for _ in range(4))
+        ae, be = int(rng.integers(4)), int(rng.integers(4))
+        cx, cz, ce = oracle.pauli_mul((ax, az, ae), (bx, bz, be))
+        e = ae + be
+        for q in range(64):
+            t = table[((ax >> q) & 1, (az >> q) & 1, (bx >> q) & 1, (bz >> q) & 1)]
+            assert t[0] == ((cx >> q) & 1) and t[1] == ((cz >> q) & 1)
+            e += t[2]
+        assert e % 4 == ce
+
+
+# ---------------------------------------------------------------------------
+# Tableau rules against dense conjugation
+# ---------------------------------------------------------------------------
+def _unitary(text, n):
+    cols = []
+    for k in range(1 << n):
+        psi = np.zeros(1 << n, dtype=complex)
+        psi[k] = 1
+        _, ops = ref_dense.parse(text)
+        for tok in ops:
+            g = tok[0]
+            if g in ref_dense.MATS:
+                psi = ref_dense.apply_1q(psi, ref_dense.MATS[g], int(tok[1]), n)
+            elif g == "CX":
+                psi = ref_dense.apply_cx(psi, int(tok[1]), int(tok[2]), n)
+            elif g == "CZ":
+                psi = ref_dense.apply_cz(psi, int(tok[1]), int(tok[2]), n)
+        cols.append(psi)
+    return np.array(cols).T
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_every_gate_rule_matches_dense_conjugation(seed):
+    # Random Clifford words on 2-3 qubits reach rows containing every Pauli and
+    # sign; every final row must equal U P U^dagger exactly, sign included.
+    n = 2 + seed % 2
+    text, _ = random_circuit(seed, n, 12, clifford_only=True, p_meas=0, p_mpp=0, p_reset=0, p_pauli=0.3,
+                             gates=("H", "S", "SDG", "CX", "CZ"))
+    r = oracle.Circuit(text).shot(0, 0)
+    U = _unitary(text, n)
+    for i in range(n):
+        for P0, row in ((_pauli_matrix(1 << i, 0, 0, n), i), (_pauli_matrix(0, 1 << i, 0, n), n + i)):
+            want = U @ P0 @ U.conj().T
+            got = _pauli_matrix(int(r.tab_x[row]), int(r.tab_z[row]), 2 * int(r.tab_r[row]), n)
+            assert np.allclose(got, want, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Dense statevector with phase-tracked shadow
+# ---------------------------------------------------------------------------
+def _check_dense(text, seed, tol=1e-12):
+    c = oracle.Circuit(text)
+    words = random_words(seed, c.words_per_shot)
+    r = c.shot(0, 0, words=words, coeff_cap=1 << 14)
+    assert r.status == oracle.PASSED
+    phi, shadow, record, p0s = ref_dense.run(text, words[c.n_noise_slots:])
+    n = c.n_qubits
+    assert r.record == record
+    assert np.allclose(r.p0, p0s, atol=tol, rtol=0)
+    ref_dense.check_tableau(r.tab_x, r.tab_z, r.tab_r, shadow, n)
+    got = ref_dense.reconstruct(r.tab_x, r.tab_z, r.tab_r, r.coeffs, shadow, n)
+    assert np.max(np.abs(got - phi)) < tol, np.max(np.abs(got - phi))
+    assert abs(sum(abs(v) ** 2 for v in r.coeffs.values()) - 1) < tol
+    return r
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_clifford_t_measure_matches_dense(seed):
+    n = 1 + seed % 5
+    text, _ = random_circuit(1000 + seed, n, 40 + 3 * (seed % 7))
+    _check_dense(text, seed)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_every_prefix_matches_dense(seed):
+    # Step-by-step identity (the paper's Sec. V-B cross-check): every prefix of
+    # a circuit gives the same state as the dense run of that prefix.
+    text, _ = random_circuit(5000 + seed, 3 + seed % 2, 30)
+    lines = text.strip().splitlines()
+    for k in range(2, len(lines) + 1):
+        _check_dense("\n".join(lines[:k]) + "\n", seed)
+
+
+def test_dense_on_larger_register():
+    text, _ = random_circuit(77, 10, 120, p_t=0.1)
+    _check_dense(text, 77, tol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# Clifford-only circuits against an independent CHP tableau
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(40))
+def test_clifford_only_matches_chp_bit_exact(seed):
+    n = 2 + seed % 7
+    text, _ = random_circuit(2000 + seed, n, 80, clifford_only=True, allow_mpp=False,
+                             gates=("H", "S", "SDG", "CX", "CZ"))
+    c = oracle.Circuit(text)
+    words = random_words(seed, c.words_per_shot)
+    r = c.shot(0, 0, words=words)
+    sim, record = ref_chp.run(text, words[c.n_noise_slots:])
+    assert r.record == record
+    assert [int(v) for v in r.tab_x] == sim.x[: 2 * n]
+    assert [int(v) for v in r.tab_z] == sim.z[: 2 * n]
+    assert [int(v) for v in r.tab_r] == sim.r[: 2 * n]
+    # a Clifford-only state keeps a single coefficient of modulus 1
+    assert len(r.coeffs) == 1 and abs(abs(list(r.coeffs.values())[0]) - 1) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Identities and closed forms
+# ---------------------------------------------------------------------------
+def _state(text, words=None):
+    c = oracle.Circuit(text)
+    r = c.shot(0, 0, words=words)
+    phi, shadow, _, _ = ref_dense.run(text, [] if words is None else words[c.n_noise_slots:])
+    return r, ref_dense.reconstruct(r.tab_x, r.tab_z, r.tab_r, r.coeffs, shadow, c.n_qubits)
+
+
+def test_t_squared_is_s_exactly():
+    for prep in ("H 0", "H 0\nS 0", "H 0\nH 1\nCX 0 1", "X 0\nH 1"):
+        _, a = _state("QUBITS 2\n%s\nT 0\nT 0\n" % prep)
+        _, b = _state("QUBITS 2\n%s\nS 0\n" % prep)
+        assert np.max(np.abs(a - b)) < 1e-14  # includes the global phase
+
+
+def test_t8_and_t_tdg_are_identity_on_coefficients():
+    for prep in ("H 0", "H 0\nS 0\nH 1\nCX 0 1"):
+        base = oracle.Circuit("QUBITS 2\n%s\n" % prep).shot(0, 0)
+        for body in ("T 0\n" * 8, "T 0\nTDG 0\n", "TDG 0\nT 0\n", "T 0\nT 0\nTDG 0\nTDG 0\n"):
+            r = oracle.Circuit("QUBITS 2\n%s\n%s" % (prep, body)).shot(0, 0)
+            assert set(r.coeffs) == set(base.coeffs)
+            for a in base.coeffs:
+                assert abs(r.coeffs[a] - base.coeffs[a]) < 1e-12
+            assert (r.tab_x == base.tab_x).all() and (r.tab_z == base.tab_z).all() and (r.tab_r == base.tab_r).all()
+
+
+def test_s4_h2_identity_on_tableau():
+    base = oracle.Circuit("QUBITS 2\nH 0\nCX 0 1\n").shot(0, 0)
+    for body in ("S 1\n" * 4, "H 1\nH 1\n", "SDG 0\nS 0\n", "CZ 0 1\nCZ 0 1\n"):
+        r = oracle.Circuit("QUBITS 2\nH 0\nCX 0 1\n" + body).shot(0, 0)
+        assert (r.tab_x == base.tab_x).all() and (r.tab_z == base.tab_z).all() and (r.tab_r == base.tab_r).all()
+
+
+def test_t_plus_closed_form():
+    r = oracle.Circuit("QUBITS 1\nH 0\nT 0\n").shot(0, 0)
+    w = np.exp(1j * np.pi / 4)
+    assert abs(r.coeffs[0] - (1 + w) / 2) < 1e-15
+    assert abs(r.coeffs[1] - (1 - w) / 2) < 1e-15
+
+
+def test_x_measurement_after_t_plus_probability():
+    r = oracle.Circuit("QUBITS 1\nH 0\nT 0\nH 0\nM 0\n").shot(0, 0)
+    assert abs(r.p0[0] - 0.8535533905932737) < 1e-15          # cos^2(pi/8)
+    assert abs(np.cos(np.pi / 8) ** 2 - 0.8535533905932737) < 1e-16
+
+
+def test_t_on_one_does_not_branch():
+    # Observation 3: Z_q in the stabilizer group -> no branching, phase only.
+    r = oracle.Circuit("QUBITS 1\nX 0\nT 0\n").shot(0, 0)
+    assert list(r.coeffs) == [0]
+    assert abs(r.coeffs[0] - np.exp(1j * np.pi / 4)) < 1e-15
+    assert r.work["t_phase_entries"] == 1 and r.work["t_entries"] == 0
+
+
+def test_unit_norm_after_every_measurement():
+    for seed in range(10):
+        text, _ = random_circuit(300 + seed, 4, 60)
+        lines = text.strip().splitlines()
+        c = oracle.Circuit(text)
+        words = random_words(seed, c.words_per_shot)
+        for k in range(2, len(lines) + 1):
+            if lines[k - 1].split()[0] in ("M", "MPP", "R"):
+                ck = oracle.Circuit("\n".join(lines[:k]) + "\n")
+                r = ck.shot(0, 0, words=words[: ck.words_per_shot])
+                assert abs(r.norm2 - 1) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Support bounds
+# ---------------------------------------------------------------------------
+def test_theorem1_support_changes():
+    # Clifford: |v'| = |v|; T: |v'| <= 2|v|; measurement: |v'| <= |v|.
+    for seed in range(15):
+        text, _ = random_circuit(400 + seed, 5, 70, p_t=0.3)
+        lines = text.strip().splitlines()
+        c = oracle.Circuit(text)
+        words = random_words(seed, c.words_per_shot)
+        prev = 1
+        for k in range(2, len(lines) + 1):
+            ck = oracle.Circuit("\n".join(lines[:k]) + "\n")
+            size = len(ck.shot(0, 0, words=words[: ck.words_per_shot]).coeffs)
+            g = lines[k - 1].split()[0]
+            if g in ("T", "TDG"):
+                assert size <= 2 * prev
+            elif g in ("M", "MPP", "R"):
+                assert size <= prev
+            else:
+                assert size == prev
+            prev = size
+
+
+def test_support_at_most_two_to_min_t_n():
+    for seed in range(20):
+        text, _ = random_circuit(600 + seed, 4, 80, p_t=0.3, p_meas=0, p_mpp=0, p_reset=0)
+        t = text.count("\nT ") + text.count("\nTDG ")
+        r = oracle.Circuit(text).shot(0, 0)
+        assert r.max_support <= 2 ** min(t, 4)
+
+
+def _gf2_rank(rows):
+    basis = {}
+    for r in rows:
+        while r:
+            h = r.bit_length() - 1
+            if h in basis:
+                r ^= basis[h]
+            else:
+                basis[h] = r
+                break
+    return len(basis)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_proposition1_coset_bound(seed):
+    # Random stabilizer state on 5 qubits, then a layer of T/T^dagger on Q:
+    # |v| <= 2^{|Q| - r_Q}, with r_Q the rank of the Z-strings on Q that
+    # stabilize the state up to sign (found by brute force on the statevector).
+    n = 5
+    text, _ = random_circuit(700 + seed, n, 40, clifford_only=True, p_meas=0, p_mpp=0, p_reset=0)
+    rng = np.random.default_rng(seed)
+    Q = sorted(rng.choice(n, size=int(rng.integers(2, n + 1)), replace=False).tolist())
+    phi, _, _, _ = ref_dense.run(text, [])
+    stab = [g for g in range(1, 1 << n) if all(((g >> q) & 1) == 0 or q in Q for q in range(n))
+            and abs(abs(ref_dense.expval(phi, 0, g, 0, n)) - 1) < 1e-9]
+    r_q = _gf2_rank(stab)
+    layer = "".join("%s %d\n" % ("T" if rng.integers(2) == 0 else "TDG", q) for q in Q)
+    r = oracle.Circuit(text + layer).shot(0, 0)
+    assert len(r.coeffs) <= 2 ** (len(Q) - r_q)
+
+
+def test_theorem2_bounds_on_cultivation_shaped_circuits():
+    # Thm 2: |v| <= 2^{|Q| - r_Z} = 16 (7 data, r_Z = 3) and 1024 (19 data,
+    # r_Z = 9), reached by the noiseless run.
+    for name, bound in (("cultivation_15q", 16), ("cultivation_42q", 1024)):
+        w = workloads.config(name, seed=1)
+        r = oracle.Circuit(w.text).batch(3, 0, 4)
+        assert (r["status"] == oracle.PASSED).all() and (r["obs"] == 0).all()
+        assert r["max_support"].max() == bound
+        noisy = oracle.Circuit(w.text, w.noise).batch(3, 0, 64)
+        assert noisy["max_support"].max() <= bound
+
+
+# ---------------------------------------------------------------------------
+# Noise model and sampling against exact enumeration
+# ---------------------------------------------------------------------------
+def _exact_distribution(text, noise_sites, n):
+    """Enumerate every Pauli pattern of the listed noise sites with its
+    probability and return the exact distribution of the record."""
+    dist = {}
+    options = []
+    for kind, p, qs in noise_sites:
+        if kind == "DEP1":
+            options.append([(1 - p, [])] + [(p / 3, [(P, qs[0])]) for P in "XYZ"])
+        elif kind == "DEP2":
+            opts = [(1 - p, [])]
+            for code in range(1, 16):
+                pa, pb = "IXYZ"[code >> 2], "IXYZ"[code & 3]
+                opts.append((p / 15, [(P, q) for P, q in ((pa, qs[0]), (pb, qs[1])) if P != "I"]))
+            options.append(opts)
+        elif kind == "XERR":
+            options.append([(1 - p, []), (p, [("X", qs[0])])])
+    for combo in itertools.product(*options):
+        prob = float(np.prod([c[0] for c in combo]))
+        # substitute the chosen Paulis into the marked lines
+        out = []
+        k = 0
+        for line in text.splitlines():
+            if line.startswith("NOISE"):
+                out += ["%s %d" % (P, q) for P, q in combo[k][1]]
+                k += 1
+            else:
+                out.append(line)
+        sub = "\n".join(out) + "\n"
+        # exact outcome probabilities by branching over measurements
+        _branch(sub, n, prob, dist)
+    return dist
+
+
+def _branch(text, n, prob, dist):
+    _, ops = ref_dense.parse(text)
+    states = [(np.eye(1 << n, dtype=complex)[0], prob, ())]
+    for tok in ops:
+        g = tok[0]
+        new = []
+        for psi, pr, rec in states:
+            if g in ref_dense.MATS:
+                new.append((ref_dense.apply_1q(psi, ref_dense.MATS[g], int(tok[1]), n), pr, rec))
+            elif g == "CX":
+                new.append((ref_dense.apply_cx(psi, int(tok[1]), int(tok[2]), n), pr, rec))
+            elif g == "M":
+                P = ref_dense.pauli_apply(psi, 0, 1 << int(tok[1]), 0, n)
+                for m in (1, -1):
+                    proj = 0.5 * (psi + m * P)
+                    w = float(np.real(np.vdot(proj, proj)))
+                    if w > 1e-15:
+                        new.append((proj / np.sqrt(w), pr * w, rec + ((1 - m) // 2,)))
+        states = new
+    for _, pr, rec in states:
+        dist[rec] = dist.get(rec, 0.0) + pr
+
+
+def test_noise_and_sampling_chi_square():
+    p = 0.2
+    body = [("H 0", None), ("NOISE", ("DEP1", p, [0])), ("T 0", None), ("CX 0 1", None),
+            ("NOISE", ("DEP2", p, [0, 1])), ("H 1", None), ("NOISE", ("XERR", p, [1])), ("M 0", None), ("M 1", None)]
+    sites = [s for l, s in body if s]
+    enum_text = "QUBITS 2\n" + "\n".join(l for l, _ in body) + "\n"
+    exact = _exact_distribution(enum_text, sites, 2)
+    sim_text = "QUBITS 2\nH 0\nDEP1 %g 0\nT 0\nCX 0 1\nDEP2 %g 0 1\nH 1\nXERR %g 1\nM 0\nM 1\n" % (p, p, p)
+    c = oracle.Circuit(sim_text)
+    N = 200000
+    r = c.batch(11, 0, N)
+    recs = r["outcomes"][0]
+    counts = {}
+    for v in recs:
+        key = (int(v) & 1, (int(v) >> 1) & 1)
+        counts[key] = counts.get(key, 0) + 1
+    chi2 = 0.0
+    for key, pr in exact.items():
+        e = pr * N
+        chi2 += (counts.get(key, 0) - e) ** 2 / e
+    assert set(counts) <= set(exact)
+    # 3 degrees of freedom: P(chi2 > 16.27) = 0.001
+    assert chi2 < 16.27, (chi2, exact, counts)
+
+
+def test_model_noise_matches_explicit_noise_ops():
+    # Model insertion (p1 after 1q gates, p2 after 2q gates, XERR before M,
+    # after R, idle DEP1 per TICK, MPP flip) equals the same noise written out.
+    text = "QUBITS 3\nH 0\nCX 0 1\nTICK\nT 1\nM 2\nR 1\nTICK\nMPP X0*Z1\n"
+    explicit = ("QUBITS 3\nH 0\nDEP1 0.1 0\nCX 0 1\nDEP2 0.2 0 1\nTICK\nDEP1 0.3 2\nT 1\nDEP1 0.1 1\n"
+                "XERR 0.4 2\nM 2\nR 1\nXERR 0.5 1\nTICK\nDEP1 0.3 0\nMPP X0*Z1\n")
+    model = {"p1": 0.1, "p2": 0.2, "p_idle": 0.3, "p_meas": 0.4, "p_reset": 0.5, "p_mpp": 0.0}
+    a = oracle.Circuit(text, model).batch(5, 0, 2000)
+    b = oracle.Circuit(explicit).batch(5, 0, 2000)
+    assert (a["outcomes"] == b["outcomes"]).all()
+
+
+def test_forced_noise_words():
+    # w = 0 < thr always hits; DEP1 index floor(3 w / thr) = 0 -> X.
+    c = oracle.Circuit("QUBITS 1\nDEP1 0.5 0\nM 0\n")
+    r = c.shot(0, 0, words=np.array([0, 7], dtype=np.uint32))
+    assert r.record == [1]
+    thr = int(np.floor(0.5 * 2 ** 32))
+    r = c.shot(0, 0, words=np.array([thr, 7], dtype=np.uint32))   # no hit
+    assert r.record == [0]
+    r = c.shot(0, 0, words=np.array([thr - 1, 7], dtype=np.uint32))  # index 2 -> Z
+    assert r.record == [0]
+
+
+# ---------------------------------------------------------------------------
+# Host logic: parse errors, postselection, overflow, shard determinism
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("text,frag", [
+    ("H 0\n", "line 1"), ("QUBITS 2\nH 2\n", "line 2"), ("QUBITS 2\nCX 1 1\n", "line 2"),
+    ("QUBITS 2\nFOO 1\n", "unknown"), ("QUBITS 2\nDETECTOR 0 0\n", "record"),
+    ("QUBITS 2\nDEP1 1.5 0\n", "probability"), ("QUBITS 2\nMPP X0*X0\n", "repeated"),
+    ("QUBITS 65\n", "QUBITS"),
+])
+def test_parse_errors(text, frag):
+    with pytest.raises(ValueError, match=frag):
+        oracle.Circuit(text)
+
+
+def test_postselection_abort_and_overflow_flags():
+    c = oracle.Circuit("QUBITS 1\nX 0\nM 0\nDETECTOR 0 0\nH 0\nT 0\n")
+    r = c.shot(0, 0)
+    assert r.status == oracle.DISCARDED and r.abort_op == 2
+    c = oracle.Circuit("QUBITS 2\nH 0\nH 1\nT 0\nT 1\n")
+    r = c.shot(0, 0, cap=3)
+    assert r.status == oracle.OVERFLOW and r.abort_op == 3 and r.max_support == 4
+
+
+def test_shard_determinism():
+    w = workloads.config("cultivation_15q", seed=2)
+    c = oracle.Circuit(w.text, w.noise)
+    a = c.batch(9, 100, 400)
+    b1 = c.batch(9, 100, 200)
+    b2 = c.batch(9, 300, 200)
+    assert (a["outcomes"] == np.concatenate([b1["outcomes"], b2["outcomes"]], axis=1)).all()
+    assert (a["status"] == np.concatenate([b1["status"], b2["status"]])).all()
+
+
+def test_forced_dep2_code_mapping():
+    # code = floor(15 w / thr) + 1 -> Pauli (code >> 2) on the first qubit and
+    # (code & 3) on the second, with 0=I 1=X 2=Y 3=Z.  A Z-basis readout of |00>
+    # shows the X part, an X-basis readout of |++> shows the Z part.
+    thr = int(np.floor(0.5 * 2 ** 32))
+    zc = oracle.Circuit("QUBITS 2\nDEP2 0.5 0 1\nM 0\nM 1\n")
+    xc = oracle.Circuit("QUBITS 2\nH 0\nH 1\nDEP2 0.5 0 1\nH 0\nH 1\nM 0\nM 1\n")
+    for code in range(1, 16):
+        w = -((-(code - 1) * thr) // 15)           # ceil((code-1) thr / 15)
+        assert (15 * w) // thr + 1 == code
+        pa, pb = code >> 2, code & 3
+        words = np.array([w, 3, 3], dtype=np.uint32)
+        assert zc.shot(0, 0, words=words).record == [int(pa in (1, 2)), int(pb in (1, 2))]
+        assert xc.shot(0, 0, words=words).record == [int(pa in (2, 3)), int(pb in (2, 3))]
