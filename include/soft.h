@@ -1,0 +1,192 @@
+/*
+ * soft.h -- C ABI of the MI355X generalized-stabilizer shot sampler.
+ *
+ * The library samples noisy Clifford+T circuits with mid-circuit
+ * measurements and postselection in the generalized stabilizer (GS)
+ * formalism of arXiv 2512.23037: every shot is an independent pure state
+ * (v, B(S, D)) -- a stabilizer/destabilizer tableau plus a sparse coefficient
+ * vector over destabilizer strings alpha (Sec. II-C, Definition 1, Eq. 3).
+ * Cliffords update the tableau, T/T-dagger split coefficients (Eqs. 1-2 with
+ * the Pauli-on-basis identity Eq. 4, Theorem 1 part 3), Pauli measurements
+ * collapse and renormalise (Theorem 1 part 2), and Pauli noise is drawn per
+ * shot (Sec. II-C, pure-state simulation model; uniform depolarizing noise of
+ * Sec. III).  All shots of a run execute on one GPU in one persistent,
+ * work-stealing kernel.
+ *
+ * General conventions
+ *  - Every call returns 0 on success or a negative SOFT_E* code; the message
+ *    of the last failure is available from soft_last_error().  No C++
+ *    exception or abort crosses this boundary.
+ *  - "_dev" pointers are device pointers (hipMalloc / torch CUDA tensors on
+ *    ROCm); the caller owns them and the library never frees them.  Other
+ *    pointers are host pointers, owned by the caller, read or written only
+ *    during the call.
+ *  - A context is not thread-safe; use one per thread.
+ *  - Qubit counts are limited to n <= 64.
+ */
+#ifndef SOFT_H
+#define SOFT_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SOFT_OK = 0,
+    SOFT_EINVAL = -1,       /* bad argument                                  */
+    SOFT_EPARSE = -2,       /* circuit text rejected ("line N: ..." message) */
+    SOFT_ECAPACITY = -3,    /* a size limit was exceeded                     */
+    SOFT_EDEVICE = -4,      /* HIP runtime error (message has the HIP text)  */
+    SOFT_ESTATE = -5,       /* call order (e.g. run before load_circuit)     */
+    SOFT_EUNSUPPORTED = -6  /* request outside what the library implements   */
+};
+
+/* Per-shot status (soft_run's status_dev). */
+enum { SOFT_PASSED = 0, SOFT_DISCARDED = 1, SOFT_OVERFLOW = 2, SOFT_NUMERIC = 3 };
+
+typedef struct soft_ctx soft_ctx;
+
+/* Uniform depolarizing noise model (Sec. III): every probability in [0, 1].
+ * p1: DEP1 after each single-qubit gate (H S SDG X Y Z T TDG); p2: DEP2 after
+ * each CX/CZ; p_idle: DEP1 on every qubit untouched since the previous TICK,
+ * inserted at the TICK; p_meas: X flip before each M; p_reset: X flip after
+ * each R; p_mpp: classical flip of each MPP result.  DEP1 applies X, Y or Z
+ * with p/3 each; DEP2 one of the 15 non-identity two-qubit Paulis, p/15 each. */
+typedef struct {
+    double p1, p2, p_idle, p_meas, p_reset, p_mpp;
+} soft_noise;
+
+/* Aggregates of the last soft_run. */
+typedef struct {
+    uint64_t shots, passed, discarded, overflow, numeric;
+    uint64_t logical_errors;     /* passed shots with a nonzero observable   */
+    uint64_t entries_t;          /* coefficient entries written by T/T-dagger */
+    uint64_t entries_m;          /* coefficient entries read by measurements */
+    uint64_t noise_slots;        /* noise words drawn                          */
+    uint64_t events;             /* T/T-dagger and measurements executed      */
+    uint64_t support_hist[16];   /* shots by floor(log2(max |v|)), last bin 15+ */
+    double max_norm_dev;         /* max over shots of |sum |v|^2 - 1| at the end */
+} soft_counters;
+
+/* Create a context on HIP device `hip_device` (made current for the call).
+ * *out receives the handle (NULL on failure). */
+int soft_create(soft_ctx **out, int hip_device);
+
+/* Free everything the context owns.  NULL is allowed. */
+void soft_destroy(soft_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next
+ * call on ctx.  With ctx == NULL, the message of the last failed
+ * soft_create on this thread. */
+const char *soft_last_error(const soft_ctx *ctx);
+
+/* Load circuit text (len bytes, need not be NUL-terminated; copied).  One op
+ * per line, '#' starts a comment, first line "QUBITS n":
+ *   H q | S q | SDG q | X q | Y q | Z q | T q | TDG q | CX c t | CZ a b |
+ *   M q | R q | MPP P0*P1*...  (factors X3, Y0, Z7; distinct qubits) |
+ *   DEP1 p q... | DEP2 p a b [a b...] | XERR p q... | TICK |
+ *   DETECTOR e r... | OBSERVABLE e r...
+ * M and MPP append to the measurement record; R measures Z and flips back
+ * to |0> (not recorded).  DETECTOR ends the shot as DISCARDED when
+ * e ^ XOR(record bits r...) != 0; OBSERVABLE stores that parity as an
+ * observable bit.  Op indices (used by abort_op) count op lines from 0.
+ * EPARSE on malformed text; ECAPACITY when the circuit's coefficient span
+ * exceeds the largest tile the library supports. */
+int soft_load_circuit(soft_ctx *ctx, const char *text, size_t len);
+
+/* Set the noise model inserted around the circuit's ops (default: none). */
+int soft_load_noise(soft_ctx *ctx, const soft_noise *model);
+
+/* Key of the per-shot Philox4x32-10 streams (Salmon et al., SC'11).  Noise
+ * slot s of shot t uses word s%4 of the block at counter
+ * (s/4, t low 32 bits, t high 32 bits, 0); measurement slot s uses stream 1.
+ * A noise slot hits iff word < floor(p * 2^32); a measurement's outcome is
+ * +1 (record bit 0) iff (word + 1/2) 2^-32 < P(+1). */
+int soft_set_rng(soft_ctx *ctx, uint64_t seed);
+
+/* Replace Philox by explicit per-shot words (test mode): words_dev holds
+ * n_shots rows of noise_slots + meas_slots words, row i used by the shot at
+ * position i of the next soft_run.  The counts must match the loaded circuit
+ * and noise model.  words_dev == NULL returns to Philox. */
+int soft_set_uniforms(soft_ctx *ctx, const uint32_t *words_dev, uint64_t n_shots,
+                      uint32_t noise_slots, uint32_t meas_slots);
+
+/* Coefficient precision: 64 (FP64, default) or 32 (FP32 complex storage and
+ * products; outcome probabilities, renormalisation and norms stay FP64). */
+int soft_set_precision(soft_ctx *ctx, int coeff_bits);
+
+/* Pruning threshold tau: after every T and measurement, coefficients with
+ * |v|^2 < tau^2 sum|v|^2 are dropped.  Default 1e-12 (FP64), 1e-6 (FP32);
+ * tau < 0 restores the default. */
+int soft_set_prune(soft_ctx *ctx, double tau);
+
+/* support_cap: a shot whose support exceeds it after a T ends as OVERFLOW
+ * (0 = no cap).  waves_per_block, blocks_per_cu, grab: launch shape (0 = the
+ * autotuned or default value). */
+int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
+                  uint32_t blocks_per_cu, uint32_t grab);
+
+/* Time a grid of launch shapes on `sample_shots` shots (outputs discarded)
+ * and keep the fastest for this circuit, noise model and precision.  Runs on
+ * hip_stream and synchronizes it. */
+int soft_autotune(soft_ctx *ctx, uint64_t sample_shots, void *hip_stream);
+
+/* Keep the final state of shots [shot_lo, shot_lo + count) of later runs for
+ * soft_read_coeffs / soft_read_tableau (count <= 4096; 0 disables). */
+int soft_set_keep(soft_ctx *ctx, uint64_t shot_lo, uint32_t count);
+
+/* Sample shots shot0 .. shot0 + n_shots - 1 (global indices: a shot's result
+ * depends only on seed, shot index, circuit and noise, not on batching).
+ * Asynchronous on hip_stream (a hipStream_t; NULL = default stream).
+ *   outcomes_dev: uint32 [ceil(records/32)][n_shots], bit r%32 of word r/32
+ *                 of shot i = record r (0 after an abort), or NULL;
+ *   status_dev:   uint32 [n_shots] SOFT_PASSED/DISCARDED/OVERFLOW/NUMERIC;
+ *   abort_op_dev: uint32 [n_shots] op index that ended the shot
+ *                 (0xffffffff if it passed), or NULL;
+ *   obs_dev:      uint32 [n_shots], bit j = observable j, or NULL. */
+int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes_dev,
+             uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev,
+             void *hip_stream);
+
+/* Aggregates of the last run; synchronizes that run's stream. */
+int soft_read_counters(soft_ctx *ctx, soft_counters *out);
+
+/* Final coefficients of a kept shot of the last run, sorted by alpha (bit k =
+ * destabilizer d_k), entries below the pruning threshold left out.  Up to
+ * cap entries are written; *count receives the full number.  Synchronizes. */
+int soft_read_coeffs(soft_ctx *ctx, uint64_t shot, uint64_t *alpha, double *re, double *im,
+                     uint32_t cap, uint32_t *count);
+
+/* Final tableau of a kept shot: 2n rows (destabilizers d_0..d_{n-1}, then
+ * stabilizers s_0..s_{n-1}); row i is (-1)^r[i] prod_q sigma(x_q, z_q) with
+ * x = bit q of x[i], z = bit q of z[i], sigma(1,1) = Y.  Synchronizes. */
+int soft_read_tableau(soft_ctx *ctx, uint64_t shot, uint64_t *x, uint64_t *z, uint8_t *r);
+
+/* Trace mode (the step-by-step cross-check): record the state of shot
+ * `shot` after each of its first `steps` events (T/T-dagger, measurements,
+ * detectors, observables, end) in the next runs; steps = 0 disables it
+ * (steps <= 65536). */
+int soft_set_trace(soft_ctx *ctx, uint64_t shot, uint32_t steps);
+
+/* State of the traced shot after event `step` of the last run.  info[0..5] =
+ * written (0/1), op index of the event, status at that point, span dimension
+ * k, carried FP64 norm (bits of a double), 1 if the shot ended there.
+ * x, z, r: 2n tableau rows as in soft_read_tableau; alpha/re/im/count as in
+ * soft_read_coeffs.  Any output pointer may be NULL.  Synchronizes. */
+int soft_read_trace(soft_ctx *ctx, uint32_t step, uint64_t info[6], uint64_t *x, uint64_t *z, uint8_t *r,
+                    uint64_t *alpha, double *re, double *im, uint32_t cap, uint32_t *count);
+
+/* Facts about the loaded circuit: info[0..7] = qubits, records, noise slots,
+ * measurement slots, observables, events, largest span dimension k_max,
+ * record words. */
+int soft_circuit_info(soft_ctx *ctx, uint64_t info[8]);
+
+/* Launch shape used by the next run: out[0..3] = waves_per_block,
+ * blocks_per_cu, grab, LDS bytes per wave. */
+int soft_launch_shape(soft_ctx *ctx, uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,588 @@
+// compile.cpp -- parse circuit text, insert model noise, and compile the
+// shot-independent frame into events for the sampler kernel.
+//
+// Method (arXiv 2512.23037): the generalized stabilizer state of
+// Definition 1, updated by the rules of Theorem 1 -- Cliffords conjugate the
+// tableau, T/T-dagger expand into I and Z_q (Eqs. 1-2) acting on the basis
+// through the index shift of Eq. 4, and Pauli measurements project with
+// (I +- P)/2 after the Aaronson-Gottesman pivot.  This file does the part of
+// that work that is the same for every shot (see program.h).
+#include "compile.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace soft {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Pauli strings with a phase: i^ph * prod_q sigma(x_q, z_q), sigma(1,1) = Y.
+// Products go qubit by qubit through the single-qubit table
+// sigma_a sigma_b = i^{kTab[a][b]} sigma_{a^b}, codes I=0, X=1, Z=2, Y=3.
+// ---------------------------------------------------------------------------
+struct PauliStr {
+    uint64_t x = 0, z = 0;
+    int ph = 0;
+};
+
+const int kTab[4][4] = {
+    // I  X  Z  Y   (right factor)
+    {0, 0, 0, 0},   // I
+    {0, 0, 3, 1},   // X: XZ = -iY, XY = iZ
+    {0, 1, 0, 3},   // Z: ZX = iY,  ZY = -iX
+    {0, 3, 1, 0},   // Y: YX = -iZ, YZ = iX
+};
+
+PauliStr times(const PauliStr &a, const PauliStr &b) {
+    PauliStr c;
+    c.x = a.x ^ b.x;
+    c.z = a.z ^ b.z;
+    int ph = a.ph + b.ph;
+    uint64_t both = (a.x | a.z) & (b.x | b.z);
+    while (both) {
+        int q = __builtin_ctzll(both);
+        both &= both - 1;
+        int ca = (int)((a.x >> q) & 1) | (int)(((a.z >> q) & 1) << 1);
+        int cb = (int)((b.x >> q) & 1) | (int)(((b.z >> q) & 1) << 1);
+        ph += kTab[ca][cb];
+    }
+    c.ph = ph & 3;
+    return c;
+}
+
+inline int par64(uint64_t w) { return __builtin_parityll(w); }
+inline uint64_t bitq(int q) { return 1ULL << q; }
+
+// Two-word row mask: bit i of d = destabilizer row i, of s = stabilizer row i.
+struct RowMask {
+    uint64_t d = 0, s = 0;
+    RowMask operator^(const RowMask &o) const { return {d ^ o.d, s ^ o.s}; }
+    RowMask operator&(const RowMask &o) const { return {d & o.d, s & o.s}; }
+    RowMask &operator^=(const RowMask &o) { d ^= o.d; s ^= o.s; return *this; }
+};
+
+// The shot-independent tableau, by column, plus the span and the event list.
+class FrameCompiler {
+  public:
+    FrameCompiler(int n, Program &prog) : n_(n), P_(prog), cx_(n), cz_(n) {
+        for (int q = 0; q < n; ++q) {
+            cx_[q].d = bitq(q);  // d_q = X_q
+            cz_[q].s = bitq(q);  // s_q = Z_q
+        }
+    }
+
+    // ---- Cliffords: x/z columns move, sign flips accumulate in acc_ ----
+    void h(int a) { acc_ ^= cx_[a] & cz_[a]; std::swap(cx_[a], cz_[a]); }
+    void s(int a) { acc_ ^= cx_[a] & cz_[a]; cz_[a] ^= cx_[a]; }
+    void sdg(int a) {
+        RowMask notz = {~cz_[a].d, ~cz_[a].s};
+        acc_ ^= cx_[a] & notz;
+        cz_[a] ^= cx_[a];
+    }
+    void px(int a) { acc_ ^= cz_[a]; }
+    void pz(int a) { acc_ ^= cx_[a]; }
+    void py(int a) { acc_ ^= cx_[a] ^ cz_[a]; }
+    void cnot(int a, int b) {
+        RowMask t = cx_[b] ^ cz_[a];
+        RowMask nt = {~t.d, ~t.s};
+        acc_ ^= cx_[a] & cz_[b] & nt;
+        cx_[b] ^= cx_[a];
+        cz_[a] ^= cz_[b];
+    }
+    void cz(int a, int b) {
+        acc_ ^= cx_[a] & cx_[b] & (cz_[a] ^ cz_[b]);
+        cz_[a] ^= cx_[b];
+        cz_[b] ^= cx_[a];
+    }
+
+    // ---- noise locations ----
+    void noise(uint32_t kind, double p, int a, int b, uint32_t rec) {
+        if (!(p > 0.0)) return;
+        NoiseLoc L;
+        std::memset(&L, 0, sizeof(L));
+        L.thr = (uint64_t)std::floor(p * 4294967296.0);
+        L.kind = L.thr == 0 ? NZ_NONE : kind;
+        L.rec = rec;
+        if (a >= 0) {
+            L.masks[0] = cz_[a].d; L.masks[1] = cz_[a].s;   // anticommute with X_a
+            L.masks[2] = cx_[a].d; L.masks[3] = cx_[a].s;   // anticommute with Z_a
+        }
+        if (b >= 0) {
+            L.masks[4] = cz_[b].d; L.masks[5] = cz_[b].s;
+            L.masks[6] = cx_[b].d; L.masks[7] = cx_[b].s;
+        }
+        P_.noise.push_back(L);
+        P_.noise_tm1.push_back(L.thr == 0 ? 0u : (uint32_t)(L.thr - 1));
+    }
+
+    // ---- events ----
+    void t_gate(int q, bool dagger, uint32_t src) {
+        PauliStr Z;
+        Z.z = bitq(q);
+        Event E = begin(src);
+        uint64_t beta, gamma;
+        int cexp;
+        decompose(Z, beta, gamma, cexp);
+        E.beta = beta;
+        E.gamma = gamma;
+        E.cexp = (uint32_t)cexp;
+        E.g = gmask(gamma);
+        if (dagger) E.flags |= EVF_TDG;
+        const double s = dagger ? -1.0 : 1.0;
+        const double th = M_PI / 8.0;
+        const double cs = std::cos(th), sn = std::sin(th);
+        if (beta == 0) {
+            if (cexp & 1) throw CompileError{0, "internal: imaginary phase on a diagonal T"};
+            E.kind = EV_T_PHASE;
+            // lambda = -1 entries: e^{i s theta}(cos theta + i s sin theta) = e^{i s pi/4}
+            E.Are = std::sqrt(0.5);
+            E.Aim = s * std::sqrt(0.5);
+        } else {
+            // A = e^{i s theta} cos theta; B = e^{i s theta} (-i s sin theta) i^cexp
+            const double er = std::cos(th), ei = s * std::sin(th);
+            E.Are = er * cs;
+            E.Aim = ei * cs;
+            double br = 0.0, bi = -s * sn;           // -i s sin theta
+            double tr = er * br - ei * bi, ti = er * bi + ei * br;
+            for (int r = 0; r < cexp; ++r) {         // times i^cexp
+                double nr = -ti, ni = tr;
+                tr = nr; ti = ni;
+            }
+            E.Bre = tr;
+            E.Bim = ti;
+            uint32_t mu;
+            if (coords(beta, mu)) {
+                E.kind = EV_T_BFLY;
+                E.mu = mu;
+                E.tstar = 31 - __builtin_clz(mu);
+            } else {
+                E.kind = EV_T_DOUBLE;
+                basis_.push_back(beta);
+                if (basis_.size() > kMaxSpanDim)
+                    throw CompileError{0, "coefficient span dimension exceeds " + std::to_string(kMaxSpanDim)};
+                if (basis_.size() > P_.kmax) P_.kmax = (uint32_t)basis_.size();
+            }
+        }
+        E.Afr = (float)E.Are; E.Afi = (float)E.Aim; E.Bfr = (float)E.Bre; E.Bfi = (float)E.Bim;
+        finish(E);
+    }
+
+    // Measurement of P (Hermitian, sign +); reset adds a conditional X_q.
+    void measure(const PauliStr &P, uint32_t mslot, int rec, int reset_q, uint32_t src) {
+        Event E = begin(src);
+        uint64_t beta, gamma;
+        int cexp;
+        decompose(P, beta, gamma, cexp);
+        E.beta = beta;
+        E.gamma = gamma;
+        E.cexp = (uint32_t)cexp;
+        E.g = gmask(gamma);
+        E.gbeta = (uint32_t)par64(gamma & beta);
+        E.mslot = mslot;
+        if (rec >= 0) {
+            E.flags |= EVF_RECORD;
+            E.rec = (uint32_t)rec;
+        }
+        const uint32_t k = (uint32_t)basis_.size();
+        if (beta == 0) {
+            if (cexp & 1) throw CompileError{0, "internal: imaginary phase on a diagonal measurement"};
+            if (E.g == 0) {
+                E.kind = EV_M_DET;
+            } else {
+                E.kind = EV_M_CUT;
+                uint32_t ts = 31 - __builtin_clz(E.g);
+                E.tstar = ts;
+                E.avec = basis_[ts];
+                std::vector<uint64_t> nb;
+                for (uint32_t t = 0; t < k; ++t)
+                    if (t != ts) nb.push_back(basis_[t] ^ (((E.g >> t) & 1) ? basis_[ts] : 0));
+                basis_.swap(nb);
+            }
+        } else {
+            const int p = __builtin_ctzll(beta);
+            E.pbit = (uint32_t)p;
+            E.avec = beta;
+            uint32_t pm = 0;
+            for (uint32_t t = 0; t < k; ++t) pm |= (uint32_t)((basis_[t] >> p) & 1) << t;
+            E.pm = pm;
+            uint32_t mu;
+            std::vector<uint64_t> nb;
+            auto L = [&](uint64_t v) { return ((v >> p) & 1) ? (v ^ beta) : v; };
+            if (coords(beta, mu)) {
+                E.kind = EV_M_MERGE;
+                E.mu = mu;
+                uint32_t ts = 31 - __builtin_clz(mu);
+                E.tstar = ts;
+                for (uint32_t t = 0; t < k; ++t)
+                    if (t != ts) nb.push_back(L(basis_[t]));
+            } else {
+                E.kind = EV_M_SPLIT;
+                for (uint32_t t = 0; t < k; ++t) nb.push_back(L(basis_[t]));
+            }
+            basis_.swap(nb);
+            // Tableau: rows anticommuting with P (other than d_p, s_p) absorb
+            // s_p, d_p takes s_p, s_p becomes +-P.
+            PauliStr sp = row_s(p);
+            RowMask A = {gamma & ~bitq(p), beta & ~bitq(p)};
+            E.AD = A.d;
+            E.AS = A.s;
+            for (uint64_t w = A.d; w; w &= w - 1) {
+                int i = __builtin_ctzll(w);
+                PauliStr prod = times(row_d(i), sp);
+                if (prod.ph & 1) throw CompileError{0, "internal: non-Hermitian row"};
+                if (prod.ph == 2) E.PhD |= bitq(i);
+            }
+            for (uint64_t w = A.s; w; w &= w - 1) {
+                int i = __builtin_ctzll(w);
+                PauliStr prod = times(row_s(i), sp);
+                if (prod.ph & 1) throw CompileError{0, "internal: non-Hermitian row"};
+                if (prod.ph == 2) E.PhS |= bitq(i);
+            }
+            for (uint64_t w = sp.x; w; w &= w - 1) {
+                int q = __builtin_ctzll(w);
+                cx_[q] ^= A;
+            }
+            for (uint64_t w = sp.z; w; w &= w - 1) {
+                int q = __builtin_ctzll(w);
+                cz_[q] ^= A;
+            }
+            set_row(false, p, sp.x, sp.z);
+            set_row(true, p, P.x, P.z);
+        }
+        if (reset_q >= 0) {
+            E.flags |= EVF_RESET;
+            E.xD = cz_[reset_q].d;
+            E.xS = cz_[reset_q].s;
+        }
+        finish(E);
+    }
+
+    void parity_check(bool detector, int expect, const std::vector<int> &recs, uint32_t obs, uint32_t src) {
+        Event E = begin(src);
+        E.kind = detector ? EV_DETECTOR : EV_OBSERVABLE;
+        E.expect = (uint32_t)expect;
+        E.rec = obs;
+        // fold the record list into (word, mask) pairs; repeats cancel
+        std::vector<uint32_t> words, masks;
+        for (int r : recs) {
+            uint32_t w = (uint32_t)r >> 5, m = 1u << (r & 31);
+            size_t i = 0;
+            while (i < words.size() && words[i] != w) ++i;
+            if (i == words.size()) { words.push_back(w); masks.push_back(0); }
+            masks[i] ^= m;
+        }
+        E.det_off = (uint32_t)(P_.det_pairs.size() / 2);
+        for (size_t i = 0; i < words.size(); ++i)
+            if (masks[i]) { P_.det_pairs.push_back(words[i]); P_.det_pairs.push_back(masks[i]); }
+        E.det_cnt = (uint32_t)(P_.det_pairs.size() / 2) - E.det_off;
+        finish(E);
+    }
+
+    void end(uint32_t src) {
+        Event E = begin(src);
+        E.kind = EV_END;
+        finish(E);
+    }
+
+  private:
+    int n_;
+    Program &P_;
+    std::vector<RowMask> cx_, cz_;
+    RowMask acc_;
+    std::vector<uint64_t> basis_;
+
+    PauliStr row_d(int i) const {
+        PauliStr r;
+        for (int q = 0; q < n_; ++q) {
+            r.x |= ((cx_[q].d >> i) & 1) << q;
+            r.z |= ((cz_[q].d >> i) & 1) << q;
+        }
+        return r;
+    }
+    PauliStr row_s(int i) const {
+        PauliStr r;
+        for (int q = 0; q < n_; ++q) {
+            r.x |= ((cx_[q].s >> i) & 1) << q;
+            r.z |= ((cz_[q].s >> i) & 1) << q;
+        }
+        return r;
+    }
+    void set_row(bool stab, int i, uint64_t x, uint64_t z) {
+        for (int q = 0; q < n_; ++q) {
+            uint64_t &cxw = stab ? cx_[q].s : cx_[q].d;
+            uint64_t &czw = stab ? cz_[q].s : cz_[q].d;
+            cxw = (cxw & ~bitq(i)) | (((x >> q) & 1) << i);
+            czw = (czw & ~bitq(i)) | (((z >> q) & 1) << i);
+        }
+    }
+
+    // P = c * d_beta * s_gamma (Eq. 4): beta over the stabilizers, gamma over
+    // the destabilizers, c = i^cexp when every row sign is +.
+    void decompose(const PauliStr &P, uint64_t &beta, uint64_t &gamma, int &cexp) const {
+        RowMask anti;
+        for (uint64_t w = P.x; w; w &= w - 1) anti ^= cz_[__builtin_ctzll(w)];
+        for (uint64_t w = P.z; w; w &= w - 1) anti ^= cx_[__builtin_ctzll(w)];
+        beta = anti.s;
+        gamma = anti.d;
+        PauliStr R;
+        for (uint64_t w = beta; w; w &= w - 1) R = times(R, row_d(__builtin_ctzll(w)));
+        for (uint64_t w = gamma; w; w &= w - 1) R = times(R, row_s(__builtin_ctzll(w)));
+        if (R.x != P.x || R.z != P.z) throw CompileError{0, "internal: decomposition mismatch"};
+        cexp = (P.ph - R.ph + 8) & 3;
+    }
+
+    uint32_t gmask(uint64_t gamma) const {
+        uint32_t g = 0;
+        for (size_t t = 0; t < basis_.size(); ++t) g |= (uint32_t)par64(gamma & basis_[t]) << t;
+        return g;
+    }
+
+    // Coordinates of v in the span basis, if it lies in the span.
+    bool coords(uint64_t v, uint32_t &mu) const {
+        // echelon form with coordinate bookkeeping
+        std::vector<uint64_t> vec;
+        std::vector<uint32_t> crd;
+        for (size_t t = 0; t < basis_.size(); ++t) {
+            uint64_t b = basis_[t];
+            uint32_t c = 1u << t;
+            for (size_t i = 0; i < vec.size(); ++i) {
+                uint64_t top = 1ULL << (63 - __builtin_clzll(vec[i]));
+                if (b & top) { b ^= vec[i]; c ^= crd[i]; }
+            }
+            if (!b) throw CompileError{0, "internal: dependent span basis"};
+            // keep vec[] reduced: clear b's top bit from the others
+            uint64_t top = 1ULL << (63 - __builtin_clzll(b));
+            for (size_t i = 0; i < vec.size(); ++i)
+                if (vec[i] & top) { vec[i] ^= b; crd[i] ^= c; }
+            vec.push_back(b);
+            crd.push_back(c);
+        }
+        uint32_t m = 0;
+        for (size_t i = 0; i < vec.size(); ++i) {
+            uint64_t top = 1ULL << (63 - __builtin_clzll(vec[i]));
+            if (v & top) { v ^= vec[i]; m ^= crd[i]; }
+        }
+        mu = m;
+        return v == 0;
+    }
+
+    Frame snapshot() const {
+        Frame f;
+        f.xd.resize(n_); f.xs.resize(n_); f.zd.resize(n_); f.zs.resize(n_);
+        for (int q = 0; q < n_; ++q) {
+            f.xd[q] = cx_[q].d; f.xs[q] = cx_[q].s; f.zd[q] = cz_[q].d; f.zs[q] = cz_[q].s;
+        }
+        f.basis = basis_;
+        return f;
+    }
+
+    Event begin(uint32_t src) {
+        Event E;
+        std::memset(&E, 0, sizeof(E));
+        E.src = src;
+        E.noise_end = (uint32_t)P_.noise.size();
+        E.k = (uint32_t)basis_.size();
+        E.cliffD = acc_.d;
+        E.cliffS = acc_.s;
+        acc_ = RowMask();
+        P_.before.push_back(snapshot());
+        return E;
+    }
+    void finish(const Event &E) {
+        P_.events.push_back(E);
+        P_.after.push_back(snapshot());
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Text front end: one op per line, '#' comments, "QUBITS n" first.
+// ---------------------------------------------------------------------------
+struct Cursor {
+    const std::string &t;
+    size_t pos = 0;
+    int line = 0;
+};
+
+bool next_line(Cursor &c, std::vector<std::string> &tok) {
+    tok.clear();
+    while (c.pos < c.t.size()) {
+        size_t eol = c.t.find('\n', c.pos);
+        if (eol == std::string::npos) eol = c.t.size();
+        ++c.line;
+        size_t end = c.t.find('#', c.pos);
+        if (end == std::string::npos || end > eol) end = eol;
+        size_t i = c.pos;
+        while (i < end) {
+            while (i < end && (c.t[i] == ' ' || c.t[i] == '\t' || c.t[i] == '\r')) ++i;
+            size_t j = i;
+            while (j < end && !(c.t[j] == ' ' || c.t[j] == '\t' || c.t[j] == '\r')) ++j;
+            if (j > i) tok.emplace_back(c.t, i, j - i);
+            i = j;
+        }
+        c.pos = eol + 1;
+        if (!tok.empty()) return true;
+    }
+    return false;
+}
+
+int parse_uint(const std::string &s, int line) {
+    if (s.empty() || s.size() > 9) throw CompileError{line, "bad integer '" + s + "'"};
+    int v = 0;
+    for (char ch : s) {
+        if (ch < '0' || ch > '9') throw CompileError{line, "bad integer '" + s + "'"};
+        v = v * 10 + (ch - '0');
+    }
+    return v;
+}
+
+double parse_prob(const std::string &s, int line) {
+    char *endp = nullptr;
+    double p = std::strtod(s.c_str(), &endp);
+    if (endp == s.c_str() || *endp != '\0') throw CompileError{line, "bad probability '" + s + "'"};
+    if (!(p >= 0.0 && p <= 1.0)) throw CompileError{line, "probability out of [0,1]"};
+    return p;
+}
+
+uint64_t fnv1a(const void *data, size_t len, uint64_t h) {
+    const unsigned char *p = (const unsigned char *)data;
+    for (size_t i = 0; i < len; ++i) { h ^= p[i]; h *= 1099511628211ULL; }
+    return h;
+}
+
+}  // namespace
+
+void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out) {
+    out = Program();
+    const double probs[6] = {nm.p1, nm.p2, nm.p_idle, nm.p_meas, nm.p_reset, nm.p_mpp};
+    for (double p : probs)
+        if (!(p >= 0.0 && p <= 1.0)) throw CompileError{0, "noise probability out of [0,1]"};
+
+    Cursor cur{text};
+    std::vector<std::string> tok;
+    if (!next_line(cur, tok) || tok[0] != "QUBITS" || tok.size() != 2)
+        throw CompileError{cur.line, "first line must be QUBITS n"};
+    const int n = parse_uint(tok[1], cur.line);
+    if (n < 1 || n > 64) throw CompileError{cur.line, "QUBITS must be in 1..64"};
+    out.n = n;
+    FrameCompiler fc(n, out);
+    std::vector<char> busy(n, 0);
+    uint32_t src = 0;
+
+    while (next_line(cur, tok)) {
+        const int ln = cur.line;
+        const std::string &op = tok[0];
+        auto qubit = [&](const std::string &s) {
+            int q = parse_uint(s, ln);
+            if (q >= n) throw CompileError{ln, "qubit out of range"};
+            return q;
+        };
+        auto want = [&](size_t k) {
+            if (tok.size() != k) throw CompileError{ln, op + ": wrong number of arguments"};
+        };
+        if (op == "H" || op == "S" || op == "SDG" || op == "X" || op == "Y" || op == "Z" || op == "T" ||
+            op == "TDG") {
+            want(2);
+            int q = qubit(tok[1]);
+            busy[q] = 1;
+            if (op == "H") fc.h(q);
+            else if (op == "S") fc.s(q);
+            else if (op == "SDG") fc.sdg(q);
+            else if (op == "X") fc.px(q);
+            else if (op == "Y") fc.py(q);
+            else if (op == "Z") fc.pz(q);
+            else fc.t_gate(q, op == "TDG", src);
+            fc.noise(NZ_DEP1, nm.p1, q, -1, 0);
+        } else if (op == "CX" || op == "CZ") {
+            want(3);
+            int a = qubit(tok[1]), b = qubit(tok[2]);
+            if (a == b) throw CompileError{ln, "two-qubit gate on one qubit"};
+            busy[a] = busy[b] = 1;
+            if (op == "CX") fc.cnot(a, b);
+            else fc.cz(a, b);
+            fc.noise(NZ_DEP2, nm.p2, a, b, 0);
+        } else if (op == "M" || op == "R") {
+            want(2);
+            int q = qubit(tok[1]);
+            busy[q] = 1;
+            PauliStr Z;
+            Z.z = bitq(q);
+            if (op == "M") {
+                fc.noise(NZ_XERR, nm.p_meas, q, -1, 0);
+                fc.measure(Z, out.n_meas++, (int)out.n_rec++, -1, src);
+            } else {
+                fc.measure(Z, out.n_meas++, -1, q, src);
+                fc.noise(NZ_XERR, nm.p_reset, q, -1, 0);
+            }
+        } else if (op == "MPP") {
+            want(2);
+            PauliStr P;
+            const std::string &spec = tok[1];
+            size_t i = 0;
+            while (true) {
+                size_t j = spec.find('*', i);
+                std::string f = spec.substr(i, j == std::string::npos ? std::string::npos : j - i);
+                if (f.size() < 2) throw CompileError{ln, "bad Pauli factor '" + f + "'"};
+                int q = qubit(f.substr(1));
+                if (((P.x | P.z) >> q) & 1) throw CompileError{ln, "repeated qubit in MPP"};
+                switch (f[0]) {
+                    case 'X': P.x |= bitq(q); break;
+                    case 'Z': P.z |= bitq(q); break;
+                    case 'Y': P.x |= bitq(q); P.z |= bitq(q); break;
+                    default: throw CompileError{ln, "bad Pauli letter"};
+                }
+                busy[q] = 1;
+                if (j == std::string::npos) break;
+                i = j + 1;
+            }
+            uint32_t rec = out.n_rec++;
+            fc.measure(P, out.n_meas++, (int)rec, -1, src);
+            fc.noise(NZ_FLIP, nm.p_mpp, -1, -1, rec);
+        } else if (op == "DEP1" || op == "XERR") {
+            if (tok.size() < 3) throw CompileError{ln, op + ": wrong number of arguments"};
+            double p = parse_prob(tok[1], ln);
+            for (size_t i = 2; i < tok.size(); ++i) fc.noise(op == "DEP1" ? NZ_DEP1 : NZ_XERR, p, qubit(tok[i]), -1, 0);
+        } else if (op == "DEP2") {
+            if (tok.size() < 4 || tok.size() % 2 != 0) throw CompileError{ln, "DEP2: wrong number of arguments"};
+            double p = parse_prob(tok[1], ln);
+            for (size_t i = 2; i < tok.size(); i += 2) {
+                int a = qubit(tok[i]), b = qubit(tok[i + 1]);
+                if (a == b) throw CompileError{ln, "DEP2 on one qubit"};
+                fc.noise(NZ_DEP2, p, a, b, 0);
+            }
+        } else if (op == "TICK") {
+            want(1);
+            for (int q = 0; q < n; ++q)
+                if (!busy[q]) fc.noise(NZ_DEP1, nm.p_idle, q, -1, 0);
+            std::fill(busy.begin(), busy.end(), 0);
+        } else if (op == "DETECTOR" || op == "OBSERVABLE") {
+            if (tok.size() < 2) throw CompileError{ln, op + ": wrong number of arguments"};
+            int e = parse_uint(tok[1], ln);
+            if (e > 1) throw CompileError{ln, "expected bit must be 0 or 1"};
+            std::vector<int> recs;
+            for (size_t i = 2; i < tok.size(); ++i) {
+                int r = parse_uint(tok[i], ln);
+                if ((uint32_t)r >= out.n_rec) throw CompileError{ln, "record index not yet measured"};
+                recs.push_back(r);
+            }
+            uint32_t obs = 0;
+            if (op == "OBSERVABLE") {
+                if (out.n_obs >= 32) throw CompileError{ln, "at most 32 observables"};
+                obs = out.n_obs++;
+            }
+            fc.parity_check(op == "DETECTOR", e, recs, obs, src);
+        } else {
+            throw CompileError{ln, "unknown op '" + op + "'"};
+        }
+        ++src;
+    }
+    fc.end(src);
+    out.n_src = src;
+    out.n_noise = (uint32_t)out.noise.size();
+    // pad the threshold table to whole 256-slot chunks
+    while (out.noise_tm1.size() % 256) out.noise_tm1.push_back(0);
+    if (out.noise_tm1.empty()) out.noise_tm1.assign(256, 0);
+    uint64_t h = fnv1a(text.data(), text.size(), 1469598103934665603ULL);
+    out.hash = fnv1a(probs, sizeof(probs), h);
+}
+
+}  // namespace soft

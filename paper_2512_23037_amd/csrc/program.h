@@ -1,0 +1,113 @@
+// program.h -- the compiled form of a circuit that the sampler kernel walks.
+//
+// The circuit compiler (compile.cpp) turns circuit text into a list of events
+// (T/T-dagger, measurements, detectors, observables) and a table of noise
+// locations.  Two facts make this form possible:
+//
+//  * Only the signs of the 2n tableau rows depend on the shot.  Every Clifford
+//    rule and the Aaronson-Gottesman measurement update compute the x/z bits
+//    from x/z bits alone, noise Paulis only flip signs, and T does not touch
+//    the tableau (Theorem 1).  The x/z "frame" is therefore computed once per
+//    circuit, and each Clifford between two events folds into one XOR mask on
+//    the per-shot sign bits.
+//  * The coefficient support of every shot lies in an affine subspace
+//    a ^ span(b_0..b_{k-1}) of {0,1}^n whose linear part is also the same for
+//    every shot: T adds the index shift beta of Eq. 4 when it is new, and a
+//    measurement either cuts the span by the hyperplane gamma.alpha = const or
+//    maps it through sigma -> sigma ^ sigma_p beta.  Only the offset a depends
+//    on the shot.  The coefficients are then a dense array of 2^k entries
+//    indexed by coordinates j, with alpha(j) = a ^ sum_t j_t b_t, and the
+//    alpha <-> alpha ^ beta pairing of Eq. 4 becomes j <-> j ^ mu.
+//
+// Sign vectors are two 64-bit words: bit i of the D word is the sign of
+// destabilizer d_i, bit i of the S word the sign of stabilizer s_i (n <= 64).
+#pragma once
+#include <stdint.h>
+
+namespace soft {
+
+enum EvKind : uint32_t {
+    EV_T_PHASE = 0,  // beta = 0: entries with lambda = -1 pick up e^{i s pi/4}
+    EV_T_DOUBLE,     // beta outside the span: k -> k+1, new coordinate on top
+    EV_T_BFLY,       // beta = sum_t mu_t b_t: butterfly on pairs (j, j ^ mu)
+    EV_M_DET,        // beta = 0 and gamma orthogonal to the span: outcome fixed
+    EV_M_CUT,        // beta = 0, gamma.b_t not all 0: keep one parity class
+    EV_M_SPLIT,      // beta != 0 outside the span: outcome 50/50
+    EV_M_MERGE,      // beta != 0 inside the span: pairs merge, k -> k-1
+    EV_DETECTOR,     // parity check of record bits, abort on failure
+    EV_OBSERVABLE,   // parity of record bits, stored as an observable bit
+    EV_END
+};
+
+enum EvFlags : uint32_t {
+    EVF_TDG = 1u,      // T-dagger (s = -1)
+    EVF_RECORD = 2u,   // store the outcome in the measurement record
+    EVF_RESET = 4u,    // reset: apply X_q (masks xD/xS) when the outcome is 1
+};
+
+// One event, 256 bytes, read by every wave with uniform (scalar) loads.
+struct alignas(16) Event {
+    uint32_t kind;
+    uint32_t src;        // index of the circuit op this event came from
+    uint32_t noise_end;  // noise slots [.., noise_end) precede this event
+    uint32_t k;          // span dimension before the event
+    uint32_t flags;
+    uint32_t mslot;      // measurement slot (M, MPP, R)
+    uint32_t rec;        // record index (recorded measurements) / observable index
+    uint32_t g;          // bit t = parity(gamma & b_t)
+    uint32_t mu;         // coordinates of beta in the span (BFLY, MERGE)
+    uint32_t pm;         // bit t = bit p of b_t (SPLIT, MERGE)
+    uint32_t tstar;      // coordinate removed (CUT, MERGE) / top bit of mu (BFLY)
+    uint32_t cexp;       // c = i^cexp * (-1)^(parity(rD&beta) ^ parity(rS&gamma))
+    uint32_t pbit;       // pivot p (SPLIT, MERGE)
+    uint32_t gbeta;      // parity(gamma & beta)
+    uint32_t det_off;    // DETECTOR/OBSERVABLE: first (word, mask) pair
+    uint32_t det_cnt;    //   and number of pairs
+    uint32_t expect;     //   expected parity
+    uint32_t psign;      // sign bit of the measured Pauli (0 for parsed ops)
+    uint32_t pad0[2];
+    uint64_t cliffD, cliffS;  // sign flips of the Cliffords since the last event
+    uint64_t beta, gamma;     // index shift / anticommuting destabilizers
+    uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
+    uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
+    uint64_t PhD, PhS;        // extra sign bits of those products
+    uint64_t xD, xS;          // reset: rows anticommuting with X_q afterwards
+    double Are, Aim;          // T: e^{i s pi/8} cos(pi/8)
+    double Bre, Bim;          // T: e^{i s pi/8} (-i s sin(pi/8)) i^cexp
+    float Afr, Afi, Bfr, Bfi; // the same in single precision
+    uint32_t pad1[10];
+};
+static_assert(sizeof(Event) == 256, "event layout");
+
+enum NoiseKind : uint32_t { NZ_NONE = 0, NZ_DEP1, NZ_DEP2, NZ_XERR, NZ_FLIP };
+
+// One noise location (one random word).  masks[0..3] = rows anticommuting
+// with X_a (D, S) and with Z_a (D, S); masks[4..7] the same for qubit b.
+struct alignas(16) NoiseLoc {
+    uint32_t kind;
+    uint32_t rec;     // FLIP: record bit to flip
+    uint64_t thr;     // floor(p * 2^32), 0..2^32
+    uint64_t masks[8];
+};
+static_assert(sizeof(NoiseLoc) == 80, "noise layout");
+
+// Per-shot status codes (low byte of the status word).
+enum Status : uint32_t { ST_PASSED = 0, ST_DISCARDED = 1, ST_OVERFLOW = 2, ST_NUMERIC = 3 };
+
+// Device counters, all 64-bit.
+enum Counter {
+    C_SHOTS = 0, C_PASSED, C_DISCARDED, C_OVERFLOW, C_NUMERIC, C_LOGICAL,
+    C_ENTRIES_T, C_ENTRIES_M, C_NOISE, C_EVENTS, C_NORMDEV_BITS,
+    C_HIST0,                 // 16 buckets of floor(log2(max |v|))
+    C_COUNT = C_HIST0 + 16
+};
+
+// Per kept shot (and per traced step): meta words, and separately the dense
+// coefficient tile as double pairs.  KM_VALID holds kStateValid once written.
+enum KeepMeta {
+    KM_STATUS = 0, KM_ABORT, KM_TERM_EV, KM_AFTER, KM_RD, KM_RS, KM_A, KM_K, KM_NRM2, KM_VALID, KM_COUNT
+};
+
+constexpr unsigned long long kStateValid = 0x5f7a7e5f7a7e0001ull;
+
+}  // namespace soft

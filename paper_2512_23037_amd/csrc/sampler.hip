@@ -1,0 +1,584 @@
+// sampler.hip -- persistent, work-stealing shot sampler for gfx950 (CDNA4).
+//
+// One wavefront (64 lanes) runs one shot at a time and then steals the next
+// shot index from a global counter, so early postselection aborts and uneven
+// coefficient supports balance themselves.  Per shot a wave holds:
+//   * the 2n tableau signs as two 64-bit words (rD, rS) and the offset a of
+//     the coefficient support -- wave-uniform scalars;
+//   * the coefficients as a dense LDS tile of 2^k complex numbers (k = span
+//     dimension, the same for every shot at a given event), FP32 or FP64;
+//   * the measurement record in LDS.
+// The circuit is the event list built by compile.cpp; each event is read with
+// uniform loads.  Every pass over the tile puts consecutive coordinates on
+// consecutive lanes, so LDS accesses are contiguous and conflict-free.
+//
+// The arithmetic per event follows arXiv 2512.23037: T/T-dagger by Eqs. 1-2
+// with the index shift of Eq. 4 (Theorem 1 part 3); measurements with the
+// projectors (I +- P)/2 (Theorem 1 part 2), outcome probabilities and
+// renormalisation accumulated in FP64; Pauli noise per shot as sign flips.
+#include <hip/hip_runtime.h>
+
+#include "program.h"
+#include "sampler.h"
+
+namespace soft {
+namespace {
+
+template <typename R> struct Cx;
+template <> struct Cx<float> { typedef float2 T; };
+template <> struct Cx<double> { typedef double2 T; };
+
+__device__ __forceinline__ uint32_t par64(uint64_t w) { return (uint32_t)__popcll(w) & 1u; }
+__device__ __forceinline__ uint32_t par32(uint32_t w) { return (uint32_t)__popc(w) & 1u; }
+
+// insert a zero bit at position h of p
+__device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t h) {
+    const uint32_t lo = p & ((1u << h) - 1u);
+    return ((p ^ lo) << 1) | lo;
+}
+
+// readfirstlane yields a signed int: widen through uint32_t, never directly.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+__device__ __forceinline__ double unid(double x) { return __longlong_as_double((long long)uni64((uint64_t)__double_as_longlong(x))); }
+
+// Butterfly sum over the 64 lanes; every lane ends with the same bits because
+// each step adds the same two partial sums in either order.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return unid(x);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                         uint32_t k1, uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    o0 = c0; o1 = c1; o2 = c2; o3 = c3;
+}
+
+template <typename C> __device__ __forceinline__ C mk(double re, double im) {
+    C c;
+    c.x = re;
+    c.y = im;
+    return c;
+}
+
+template <typename R> __device__ __forceinline__ double nrm(typename Cx<R>::T a) {
+    return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+
+// i^q * a for q in 0..3
+template <typename C> __device__ __forceinline__ C rot(C a, uint32_t q) {
+    C r;
+    switch (q & 3u) {
+        case 0: r = a; break;
+        case 1: r.x = -a.y; r.y = a.x; break;
+        case 2: r.x = -a.x; r.y = -a.y; break;
+        default: r.x = a.y; r.y = -a.x; break;
+    }
+    return r;
+}
+
+// a * b + (s ? -1 : 1) * c * d, complex
+template <typename R, typename C>
+__device__ __forceinline__ C cmad2(C a, R br, R bi, C c, R dr, R di, bool neg) {
+    R tr = c.x * dr - c.y * di;
+    R ti = c.x * di + c.y * dr;
+    if (neg) { tr = -tr; ti = -ti; }
+    C o;
+    o.x = fma(a.x, br, fma(-a.y, bi, tr));
+    o.y = fma(a.x, bi, fma(a.y, br, ti));
+    return o;
+}
+
+template <typename C, typename R> __device__ __forceinline__ C scale(C a, R s) {
+    a.x *= s;
+    a.y *= s;
+    return a;
+}
+
+// Write one shot's state (status, signs, offset, span dimension, carried norm
+// and the coefficient tile widened to double) for the readout calls.
+template <typename C>
+__device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const C *v, uint32_t lane,
+                                           uint32_t tile_entries, uint32_t status, uint32_t abort_src, uint32_t term,
+                                           uint32_t after, uint64_t rD, uint64_t rS, uint64_t a, uint32_t k,
+                                           double nrm2) {
+    if (lane == 0) {
+        m[KM_STATUS] = status;
+        m[KM_ABORT] = abort_src;
+        m[KM_TERM_EV] = term;
+        m[KM_AFTER] = after;
+        m[KM_RD] = rD;
+        m[KM_RS] = rS;
+        m[KM_A] = a;
+        m[KM_K] = k;
+        m[KM_NRM2] = (unsigned long long)__double_as_longlong(nrm2);
+        m[KM_VALID] = kStateValid;
+    }
+    const uint32_t cnt = 1u << k;
+    for (uint32_t j = lane; j < tile_entries; j += 64u) {
+        C x;
+        if (j < cnt) x = v[j];
+        else { x.x = 0; x.y = 0; }
+        dst[2u * j] = (double)x.x;
+        dst[2u * j + 1u] = (double)x.y;
+    }
+}
+
+struct WaveTotals {
+    uint64_t entries_t = 0, entries_m = 0, noise = 0, events = 0;
+    double maxdev = 0.0;
+};
+
+template <typename R, bool EXPL>
+__global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
+                                                const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
+                                                const uint32_t *__restrict__ words, RunParams P) {
+    typedef typename Cx<R>::T C;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    C *v = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
+    uint32_t *rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes + P.tile_bytes);
+    const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
+    const double tau2 = P.tau2;
+
+    WaveTotals tot;
+    uint64_t myc = 0;  // counter number `lane` of this wave
+
+    uint64_t grab_base = 0, grab_left = 0;
+    while (true) {
+        if (grab_left == 0) {
+            unsigned long long got = 0;
+            if (lane == 0) got = atomicAdd(P.next, (unsigned long long)P.grab);
+            grab_base = uni64(__shfl((unsigned long long)got, 0, 64));
+            grab_left = P.grab;
+        }
+        const uint64_t i = grab_base;
+        ++grab_base;
+        --grab_left;
+        if (i >= P.n_shots) break;
+        const uint64_t shot = P.shot0 + i;
+        const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
+        const uint32_t *wrow = EXPL ? words + i * P.word_stride : nullptr;
+
+        // ---- shot start: d_i = +X_i, s_i = +Z_i, v = {0: 1} ----
+        for (uint32_t w = lane; w < P.rec_words; w += 64) rec[w] = 0u;
+        if (lane == 0) v[0] = mk<C>(1.0, 0.0);
+        uint64_t rD = 0, rS = 0, a = 0;
+        uint32_t k = 0;
+        double nrm2 = 1.0;
+        uint32_t status = ST_PASSED, abort_src = 0xFFFFFFFFu, obs = 0, maxsup = 1;
+        uint32_t term = 0, after = 0;
+        // noise: 256 slots per chunk, 4 consecutive slots (one Philox block) per lane
+        uint32_t nz_next = 0, nz_cb = 0, nz_have = 0;
+        uint32_t hits = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+
+        const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
+        for (uint32_t e = 0;; ++e) {
+            const Event &E = ev[e];
+            if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
+                dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
+                           P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
+                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2);
+            // ---- noise slots before this event ----
+            const uint32_t nend = E.noise_end;
+            while (true) {
+                if (nz_have) {
+                    const uint32_t lb = nz_cb + 4u * lane;
+                    const uint32_t allow = nend > lb ? (nend - lb >= 4u ? 0xFu : ((1u << (nend - lb)) - 1u)) : 0u;
+                    const uint32_t todo = hits & allow;
+                    hits &= ~allow;
+                    uint64_t lanes = __ballot(todo != 0u);
+                    while (lanes) {
+                        const uint32_t L = (uint32_t)__builtin_ctzll(lanes);
+                        lanes &= lanes - 1;
+                        uint32_t t = __builtin_amdgcn_readlane(todo, L);
+                        const uint32_t ws[4] = {(uint32_t)__builtin_amdgcn_readlane(w0, L),
+                                                (uint32_t)__builtin_amdgcn_readlane(w1, L),
+                                                (uint32_t)__builtin_amdgcn_readlane(w2, L),
+                                                (uint32_t)__builtin_amdgcn_readlane(w3, L)};
+                        while (t) {
+                            const uint32_t b = (uint32_t)__builtin_ctz(t);
+                            t &= t - 1u;
+                            const NoiseLoc &NL = nz[nz_cb + 4u * L + b];
+                            const uint32_t kind = NL.kind;
+                            const uint64_t wv = ws[b];
+                            if (kind == NZ_DEP1 || kind == NZ_DEP2 || kind == NZ_XERR) {
+                                uint32_t ca, cb = 0;
+                                if (kind == NZ_DEP1) {
+                                    ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
+                                } else if (kind == NZ_DEP2) {
+                                    const uint32_t code = (uint32_t)((15ull * wv) / NL.thr) + 1u;
+                                    ca = code >> 2;
+                                    cb = code & 3u;
+                                } else {
+                                    ca = 1u;
+                                }
+                                // Pauli codes: 1 = X, 2 = Y, 3 = Z
+                                if (ca == 1u || ca == 2u) { rD ^= NL.masks[0]; rS ^= NL.masks[1]; }
+                                if (ca == 3u || ca == 2u) { rD ^= NL.masks[2]; rS ^= NL.masks[3]; }
+                                if (cb == 1u || cb == 2u) { rD ^= NL.masks[4]; rS ^= NL.masks[5]; }
+                                if (cb == 3u || cb == 2u) { rD ^= NL.masks[6]; rS ^= NL.masks[7]; }
+                            } else if (kind == NZ_FLIP) {
+                                const uint32_t r = NL.rec;
+                                if (lane == 0) rec[r >> 5] ^= 1u << (r & 31u);
+                            }
+                        }
+                    }
+                    if (nend <= nz_cb + 256u) break;
+                    nz_have = 0;
+                }
+                if (nz_next >= nend) break;
+                nz_cb = nz_next;
+                nz_next += 256u;
+                nz_have = 1;
+                const uint32_t s0 = nz_cb + 4u * lane;
+                if (EXPL) {
+                    w0 = s0 + 0u < P.n_noise ? wrow[s0 + 0u] : 0u;
+                    w1 = s0 + 1u < P.n_noise ? wrow[s0 + 1u] : 0u;
+                    w2 = s0 + 2u < P.n_noise ? wrow[s0 + 2u] : 0u;
+                    w3 = s0 + 3u < P.n_noise ? wrow[s0 + 3u] : 0u;
+                } else {
+                    philox10(s0 >> 2, s_lo, s_hi, 0u, key0, key1, w0, w1, w2, w3);
+                }
+                const uint4 th = *reinterpret_cast<const uint4 *>(tm1 + s0);
+                hits = (s0 + 0u < P.n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < P.n_noise && w1 <= th.y ? 2u : 0u) |
+                       (s0 + 2u < P.n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < P.n_noise && w3 <= th.w ? 8u : 0u);
+                tot.noise += min(256u, P.n_noise - nz_cb);
+            }
+            // ---- Cliffords since the previous event: one XOR ----
+            rD ^= E.cliffD;
+            rS ^= E.cliffS;
+            const uint32_t kind = E.kind;
+            if (kind == EV_END) {
+                term = e;
+                break;
+            }
+            const uint32_t sc = par64(rD & E.beta) ^ par64(rS & E.gamma);  // sign part of c
+            const uint32_t ga = par64(E.gamma & a);                          // gamma . a
+            const uint32_t g = E.g;
+            if (kind == EV_T_PHASE) {
+                // lambda_j = (-1)^(sig ^ parity(g & j)); lambda = -1 picks up e^{i s pi/4}
+                const uint32_t sig = (E.cexp == 2u ? 1u : 0u) ^ sc ^ ga;
+                const R fr = (R)E.Are, fi = (R)E.Aim;
+                const uint32_t cnt = 1u << k;
+                if (g != 0u || sig) {
+                    for (uint32_t j = lane; j < cnt; j += 64u) {
+                        if (sig ^ par32(g & j)) {
+                            C x = v[j];
+                            C y;
+                            y.x = x.x * fr - x.y * fi;
+                            y.y = x.x * fi + x.y * fr;
+                            v[j] = y;
+                        }
+                    }
+                }
+                tot.events++;
+            } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
+                const R ar = sizeof(R) == 4 ? (R)E.Afr : (R)E.Are, ai = sizeof(R) == 4 ? (R)E.Afi : (R)E.Aim;
+                const R br = sizeof(R) == 4 ? (R)E.Bfr : (R)E.Bre, bi = sizeof(R) == 4 ? (R)E.Bfi : (R)E.Bim;
+                const C z = mk<C>(0.0, 0.0);
+                const uint32_t sig = sc ^ ga;
+                const double thr2 = tau2 * nrm2;
+                double nn = 0.0;
+                uint32_t cnt = 0;
+                if (kind == EV_T_DOUBLE) {
+                    const uint32_t half = 1u << k;
+                    for (uint32_t j = lane; j < half; j += 64u) {
+                        const C v0 = v[j];
+                        const bool neg = (sig ^ par32(g & j)) != 0u;
+                        C o0 = cmad2<R, C>(v0, ar, ai, z, (R)0, (R)0, false);
+                        C o1 = cmad2<R, C>(z, (R)0, (R)0, v0, br, bi, neg);
+                        const double n0 = nrm<R>(o0), n1 = nrm<R>(o1);
+                        const bool k0 = n0 >= thr2, k1 = n1 >= thr2;
+                        if (!k0) o0 = z;
+                        if (!k1) o1 = z;
+                        nn += (k0 ? n0 : 0.0) + (k1 ? n1 : 0.0);
+                        cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
+                        v[j] = o0;
+                        v[j + half] = o1;
+                    }
+                    tot.entries_t += 2u * half;
+                    ++k;
+                } else {
+                    const uint32_t npairs = 1u << (k - 1u);
+                    const uint32_t mu = E.mu, h = E.tstar;
+                    const uint32_t gmu = par32(g & mu);
+                    for (uint32_t p = lane; p < npairs; p += 64u) {
+                        const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
+                        const C v0 = v[j0], v1 = v[j1];
+                        const uint32_t s1 = sig ^ par32(g & j0);
+                        const uint32_t s0 = s1 ^ gmu;
+                        C o0 = cmad2<R, C>(v0, ar, ai, v1, br, bi, s0 != 0u);
+                        C o1 = cmad2<R, C>(v1, ar, ai, v0, br, bi, s1 != 0u);
+                        const double n0 = nrm<R>(o0), n1 = nrm<R>(o1);
+                        const bool k0 = n0 >= thr2, k1 = n1 >= thr2;
+                        if (!k0) o0 = z;
+                        if (!k1) o1 = z;
+                        nn += (k0 ? n0 : 0.0) + (k1 ? n1 : 0.0);
+                        cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
+                        v[j0] = o0;
+                        v[j1] = o1;
+                    }
+                    tot.entries_t += 2u * npairs;
+                }
+                nrm2 = wave_sum(nn);
+                cnt = uni(cnt);
+                maxsup = max(maxsup, cnt);
+                tot.events++;
+                if (cnt > P.support_cap) {
+                    status = ST_OVERFLOW;
+                    abort_src = E.src;
+                    term = e;
+                    after = 1;
+                    break;
+                }
+            } else if (kind <= EV_M_MERGE) {
+                // ---- measurement ----
+                uint32_t mw;
+                if (EXPL) {
+                    mw = wrow[P.n_noise + E.mslot];
+                } else {
+                    uint32_t o0, o1, o2, o3;
+                    philox10(E.mslot >> 2, s_lo, s_hi, 1u, key0, key1, o0, o1, o2, o3);
+                    const uint32_t q = E.mslot & 3u;
+                    mw = q == 0u ? o0 : q == 1u ? o1 : q == 2u ? o2 : o3;
+                }
+                mw = uni(mw);
+                const double u = ((double)mw + 0.5) * (1.0 / 4294967296.0);
+                uint32_t bit = 0;
+                tot.events++;
+                if (kind == EV_M_DET) {
+                    bit = (E.cexp == 2u ? 1u : 0u) ^ sc ^ ga;
+                } else if (kind == EV_M_CUT) {
+                    const uint32_t sig = (E.cexp == 2u ? 1u : 0u) ^ sc ^ ga;
+                    const uint32_t cnt = 1u << k;
+                    double n0 = 0.0, n1 = 0.0;
+                    for (uint32_t j = lane; j < cnt; j += 64u) {
+                        const double q = nrm<R>(v[j]);
+                        if (par32(g & j)) n1 += q;
+                        else n0 += q;
+                    }
+                    n0 = wave_sum(n0);
+                    n1 = wave_sum(n1);
+                    const double Np = sig ? n1 : n0, Nm = sig ? n0 : n1;
+                    const double p0 = Np / (Np + Nm);
+                    bit = u < p0 ? 0u : 1u;
+                    const uint32_t bsel = sig ^ bit;
+                    const double Ns = bsel ? n1 : n0;
+                    tot.entries_m += cnt;
+                    if (!(Ns > 1e-300)) {
+                        status = ST_NUMERIC;
+                        abort_src = E.src;
+                        term = e;
+                        break;
+                    }
+                    const R s = (R)(1.0 / sqrt(Ns));
+                    const uint32_t ts = E.tstar, half = cnt >> 1;
+                    const C z = mk<C>(0.0, 0.0);
+                    double nn = 0.0;
+                    for (uint32_t jp = lane; jp < half; jp += 64u) {
+                        uint32_t j = ins0(jp, ts);
+                        if (par32(g & j) != bsel) j |= 1u << ts;
+                        C x = scale(v[j], s);
+                        const double q = nrm<R>(x);
+                        const bool keep = q >= tau2;
+                        if (!keep) x = z;
+                        nn += keep ? q : 0.0;
+                        v[jp] = x;
+                    }
+                    nrm2 = wave_sum(nn);
+                    --k;
+                    if (bsel) a ^= E.avec;
+                } else if (kind == EV_M_SPLIT) {
+                    bit = u < 0.5 ? 0u : 1u;
+                    const uint32_t ap = (uint32_t)(a >> E.pbit) & 1u;
+                    const uint32_t fs = bit ^ sc ^ ga ^ E.gbeta;
+                    const uint32_t q0 = (4u - E.cexp) & 3u;
+                    const uint32_t cnt = 1u << k, pm = E.pm;
+                    const R s = (R)(1.0 / sqrt(nrm2));
+                    const C z = mk<C>(0.0, 0.0);
+                    double nn = 0.0;
+                    for (uint32_t j = lane; j < cnt; j += 64u) {
+                        C x = v[j];
+                        if (ap ^ par32(pm & j)) x = rot(x, q0 + 2u * (fs ^ par32(g & j)));
+                        x = scale(x, s);
+                        const double q = nrm<R>(x);
+                        const bool keep = q >= tau2;
+                        if (!keep) x = z;
+                        nn += keep ? q : 0.0;
+                        v[j] = x;
+                    }
+                    nrm2 = wave_sum(nn);
+                    tot.entries_m += cnt;
+                } else {  // EV_M_MERGE
+                    const uint32_t ap = (uint32_t)(a >> E.pbit) & 1u;
+                    const uint32_t q0 = (4u - E.cexp) & 3u;
+                    const uint32_t npairs = 1u << (k - 1u), mu = E.mu, h = E.tstar, pm = E.pm;
+                    const uint32_t fs0 = sc ^ ga;
+                    double np = 0.0, nm = 0.0;
+                    for (uint32_t p = lane; p < npairs; p += 64u) {
+                        const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
+                        const uint32_t a0 = ap ^ par32(pm & j0);
+                        const uint32_t x = a0 ? j1 : j0, y = a0 ? j0 : j1;
+                        const C vx = v[x];
+                        const C fy = rot(v[y], q0 + 2u * (fs0 ^ par32(g & x)));
+                        const double px = (double)vx.x + (double)fy.x, py = (double)vx.y + (double)fy.y;
+                        const double mx = (double)vx.x - (double)fy.x, my = (double)vx.y - (double)fy.y;
+                        np += px * px + py * py;
+                        nm += mx * mx + my * my;
+                    }
+                    np = 0.5 * wave_sum(np);
+                    nm = 0.5 * wave_sum(nm);
+                    const double p0 = np / (np + nm);
+                    bit = u < p0 ? 0u : 1u;
+                    const double Ns = bit ? nm : np;
+                    tot.entries_m += 2u * npairs;
+                    if (!(Ns > 1e-300)) {
+                        status = ST_NUMERIC;
+                        abort_src = E.src;
+                        term = e;
+                        break;
+                    }
+                    const R s = (R)(1.0 / sqrt(2.0 * Ns));
+                    const C z = mk<C>(0.0, 0.0);
+                    double nn = 0.0;
+                    for (uint32_t p = lane; p < npairs; p += 64u) {
+                        const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
+                        const uint32_t a0 = ap ^ par32(pm & j0);
+                        const uint32_t x = a0 ? j1 : j0, y = a0 ? j0 : j1;
+                        const C vx = v[x];
+                        const C fy = rot(v[y], q0 + 2u * (fs0 ^ par32(g & x)));
+                        C o;
+                        if (bit) { o.x = vx.x - fy.x; o.y = vx.y - fy.y; }
+                        else { o.x = vx.x + fy.x; o.y = vx.y + fy.y; }
+                        o = scale(o, s);
+                        const double q = nrm<R>(o);
+                        const bool keep = q >= tau2;
+                        if (!keep) o = z;
+                        nn += keep ? q : 0.0;
+                        v[p] = o;
+                    }
+                    nrm2 = wave_sum(nn);
+                    --k;
+                }
+                if (kind == EV_M_SPLIT || kind == EV_M_MERGE) {
+                    // rows anticommuting with P absorb s_p; d_p <- s_p; s_p <- (-1)^bit P
+                    const uint32_t p = E.pbit;
+                    const uint64_t bsp = (rS >> p) & 1ull;
+                    rD ^= (bsp ? E.AD : 0ull) ^ E.PhD;
+                    rS ^= (bsp ? E.AS : 0ull) ^ E.PhS;
+                    rD = (rD & ~(1ull << p)) | (bsp << p);
+                    rS = (rS & ~(1ull << p)) | ((uint64_t)(bit ^ E.psign) << p);
+                    if ((a >> p) & 1ull) a ^= E.beta;
+                }
+                if ((E.flags & EVF_RECORD) && bit && lane == 0) rec[E.rec >> 5] |= 1u << (E.rec & 31u);
+                if ((E.flags & EVF_RESET) && bit) {
+                    rD ^= E.xD;
+                    rS ^= E.xS;
+                }
+            } else {
+                // ---- DETECTOR / OBSERVABLE ----
+                uint32_t pbits = E.expect;
+                for (uint32_t t = 0; t < E.det_cnt; ++t) {
+                    const uint32_t w = det[2u * (E.det_off + t)], m = det[2u * (E.det_off + t) + 1u];
+                    pbits ^= par32(rec[w] & m);
+                }
+                pbits = uni(pbits);
+                if (kind == EV_DETECTOR) {
+                    if (pbits) {
+                        status = ST_DISCARDED;
+                        abort_src = E.src;
+                        term = e;
+                        break;
+                    }
+                } else {
+                    obs |= pbits << E.rec;
+                }
+            }
+        }
+
+        // ---- shot end: norm check, outputs, kept states, counters ----
+        const uint32_t cnt = 1u << k;
+        double nn = 0.0;
+        for (uint32_t j = lane; j < cnt; j += 64u) nn += nrm<R>(v[j]);
+        nn = wave_sum(nn);
+        tot.maxdev = fmax(tot.maxdev, fabs(nn - 1.0));
+        if (P.outcomes)
+            for (uint32_t w = lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
+        if (lane == 0) {
+            P.status[i] = status;
+            if (P.abort_op) P.abort_op[i] = abort_src;
+            if (P.obs) P.obs[i] = obs;
+        }
+        if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
+            const uint64_t kk = shot - P.keep_lo;
+            dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
+                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2);
+        }
+        if (tracing && term < P.trace_n)
+            dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
+                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2);
+        const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
+        myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
+               (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
+    }
+    myc += lane == C_ENTRIES_T ? tot.entries_t : 0ull;
+    myc += lane == C_ENTRIES_M ? tot.entries_m : 0ull;
+    myc += lane == C_NOISE ? tot.noise : 0ull;
+    myc += lane == C_EVENTS ? tot.events : 0ull;
+    if (lane < (uint32_t)C_COUNT && lane != (uint32_t)C_NORMDEV_BITS && myc) atomicAdd(P.counters + lane, (unsigned long long)myc);
+    if (lane == (uint32_t)C_NORMDEV_BITS) atomicMax(P.counters + lane, (unsigned long long)__double_as_longlong(tot.maxdev));
+}
+
+__global__ void k_reset(unsigned long long *counters, unsigned long long *next) {
+    const uint32_t t = threadIdx.x;
+    if (t < (uint32_t)C_COUNT) counters[t] = 0ull;
+    if (t == 0) *next = 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_reset(unsigned long long *counters, unsigned long long *next, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, counters, next);
+    return hipGetLastError();
+}
+
+hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
+    const bool expl = p.words != nullptr;
+    if (fp64) {
+        if (expl) hipLaunchKernelGGL((k_sample<double, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
+        else hipLaunchKernelGGL((k_sample<double, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
+    } else {
+        if (expl) hipLaunchKernelGGL((k_sample<float, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
+        else hipLaunchKernelGGL((k_sample<float, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
+    }
+    return hipGetLastError();
+}
+
+hipError_t sampler_set_lds_limit(int bytes) {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_sample<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_sample<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)k_sample<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_sample<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace soft

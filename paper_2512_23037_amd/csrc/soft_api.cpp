@@ -1,0 +1,728 @@
+// soft_api.cpp -- the C ABI declared in include/soft.h.
+//
+// Host side of the sampler: owns the compiled circuit and its device copy,
+// chooses the launch shape (fixed, default or autotuned), captures the
+// reset + sampler launch pair into a hipGraph, and decodes kept final states
+// for the readout calls.  No simulation arithmetic runs here; every shot is
+// computed by the kernels in sampler.hip.
+#include "soft.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "compile.h"
+#include "sampler.h"
+
+using namespace soft;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Shape {
+    uint32_t wpb = 0, bpc = 0, grab = 0;
+};
+
+template <typename T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;  // elements allocated
+};
+
+}  // namespace
+
+struct soft_ctx {
+    int device = 0;
+    int num_cus = 0;
+    int max_lds_block = 65536;
+    std::string err;
+
+    bool have_text = false;
+    std::string text;
+    NoiseModel noise;
+    bool dirty = true;  // program must be recompiled
+    Program prog;
+
+    uint64_t seed = 0;
+    const uint32_t *words_dev = nullptr;
+    uint64_t words_n = 0;
+    uint32_t words_noise = 0, words_meas = 0;
+    int bits = 64;
+    double tau = -1.0;
+    uint32_t support_cap = 0;
+    Shape user;                               // explicit launch shape parts
+    std::map<std::tuple<uint64_t, int, double, uint32_t>, Shape> tuned;
+
+    DevBuf<Event> d_ev;
+    DevBuf<NoiseLoc> d_nz;
+    DevBuf<uint32_t> d_tm1, d_det;
+    unsigned long long *d_counters = nullptr;  // C_COUNT + 1 (work cursor)
+
+    uint64_t keep_lo = 0;
+    uint32_t keep_n = 0;
+    DevBuf<unsigned long long> d_keep_meta;
+    DevBuf<double> d_keep_v;
+    uint32_t keep_tile = 0;  // tile entries of the last run's keep buffer
+
+    uint64_t trace_shot = 0;
+    uint32_t trace_n = 0;
+    DevBuf<unsigned long long> d_trace_meta;
+    DevBuf<double> d_trace_v;
+    uint32_t trace_tile = 0;
+
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;
+
+    bool ran = false;
+    hipStream_t last_stream = nullptr;
+    uint64_t last_shot0 = 0, last_n = 0;
+};
+
+namespace {
+
+int fail(soft_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail((ctx), SOFT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T> int ensure(soft_ctx *c, DevBuf<T> &b, size_t n) {
+    if (n == 0) n = 1;
+    if (b.n >= n) return SOFT_OK;
+    if (b.p) HIPCHK(c, hipFree(b.p));
+    b.p = nullptr;
+    b.n = 0;
+    HIPCHK(c, hipMalloc((void **)&b.p, n * sizeof(T)));
+    b.n = n;
+    return SOFT_OK;
+}
+
+template <typename T> void release(DevBuf<T> &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+double tau_of(const soft_ctx *c) { return c->tau >= 0.0 ? c->tau : (c->bits == 32 ? 1e-6 : 1e-12); }
+
+uint32_t tile_entries(const soft_ctx *c) { return 1u << c->prog.kmax; }
+uint32_t rec_words(const soft_ctx *c) { return (c->prog.n_rec + 31u) / 32u; }
+uint32_t tile_bytes(const soft_ctx *c) { return tile_entries(c) * (c->bits == 64 ? 16u : 8u); }
+uint32_t wave_bytes(const soft_ctx *c) { return ((tile_bytes(c) + 15u) & ~15u) + ((rec_words(c) * 4u + 15u) & ~15u); }
+
+void drop_graph(soft_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gkey.clear();
+}
+
+// Compile the text (if changed) and upload the program.
+int prepare(soft_ctx *c) {
+    if (!c->have_text) return fail(c, SOFT_ESTATE, "no circuit loaded");
+    if (!c->dirty) return SOFT_OK;
+    Program p;
+    try {
+        compile_circuit(c->text, c->noise, p);
+    } catch (const CompileError &e) {
+        return fail(c, e.line > 0 ? SOFT_EPARSE : SOFT_ECAPACITY,
+                    e.line > 0 ? "line " + std::to_string(e.line) + ": " + e.msg : e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(c, SOFT_ECAPACITY, "out of host memory while compiling");
+    }
+    c->prog = std::move(p);
+    int rc;
+    if ((rc = ensure(c, c->d_ev, c->prog.events.size())) ||
+        (rc = ensure(c, c->d_nz, std::max<size_t>(c->prog.noise.size(), 1))) ||
+        (rc = ensure(c, c->d_tm1, c->prog.noise_tm1.size())) ||
+        (rc = ensure(c, c->d_det, std::max<size_t>(c->prog.det_pairs.size(), 2))))
+        return rc;
+    HIPCHK(c, hipMemcpy(c->d_ev.p, c->prog.events.data(), c->prog.events.size() * sizeof(Event), hipMemcpyHostToDevice));
+    if (!c->prog.noise.empty())
+        HIPCHK(c, hipMemcpy(c->d_nz.p, c->prog.noise.data(), c->prog.noise.size() * sizeof(NoiseLoc), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_tm1.p, c->prog.noise_tm1.data(), c->prog.noise_tm1.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!c->prog.det_pairs.empty())
+        HIPCHK(c, hipMemcpy(c->d_det.p, c->prog.det_pairs.data(), c->prog.det_pairs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    c->dirty = false;
+    drop_graph(c);
+    return SOFT_OK;
+}
+
+// Largest LDS a CU offers to resident blocks (gfx950: 160 KiB).
+constexpr uint32_t kLdsPerCu = 160u * 1024u;
+constexpr uint32_t kMaxWavesPerCu = 32u;
+
+Shape default_shape(const soft_ctx *c) {
+    Shape s;
+    const uint32_t wb = wave_bytes(c);
+    s.wpb = 4;
+    while (s.wpb > 1 && s.wpb * wb > (uint32_t)c->max_lds_block) s.wpb /= 2;
+    uint32_t per_cu = std::max<uint32_t>(1u, kLdsPerCu / (s.wpb * wb));
+    s.bpc = std::min<uint32_t>(per_cu, kMaxWavesPerCu / s.wpb);
+    s.grab = 1;
+    return s;
+}
+
+Shape current_shape(const soft_ctx *c) {
+    Shape s = default_shape(c);
+    auto it = c->tuned.find(std::make_tuple(c->prog.hash, c->bits, tau_of(c), c->support_cap));
+    if (it != c->tuned.end()) s = it->second;
+    if (c->user.wpb) s.wpb = c->user.wpb;
+    if (c->user.bpc) s.bpc = c->user.bpc;
+    if (c->user.grab) s.grab = c->user.grab;
+    return s;
+}
+
+int check_shape(soft_ctx *c, const Shape &s) {
+    const uint64_t lds = (uint64_t)s.wpb * wave_bytes(c);
+    if (s.wpb < 1 || s.wpb > 4) return fail(c, SOFT_EINVAL, "waves_per_block must be 1..4");
+    if (lds > (uint64_t)c->max_lds_block)
+        return fail(c, SOFT_ECAPACITY, "coefficient tile needs " + std::to_string(lds) + " bytes of LDS per block; the device allows " +
+                                           std::to_string(c->max_lds_block) + " (span dimension " + std::to_string(c->prog.kmax) + ")");
+    if (s.bpc < 1 || s.grab < 1) return fail(c, SOFT_EINVAL, "blocks_per_cu and grab must be >= 1");
+    return SOFT_OK;
+}
+
+// Launch reset + sampler on `stream` through a cached hipGraph.
+int launch(soft_ctx *c, const RunParams &rp, const Shape &s, uint64_t n_shots, hipStream_t stream) {
+    const uint32_t wb = wave_bytes(c);
+    const size_t lds = (size_t)s.wpb * wb;
+    uint64_t blocks_needed = (n_shots + s.wpb - 1) / s.wpb;
+    uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cus * s.bpc, std::max<uint64_t>(blocks_needed, 1));
+    const dim3 g((uint32_t)grid), b(64u * s.wpb);
+    std::vector<unsigned char> key(sizeof(RunParams) + 3 * sizeof(uint64_t) + sizeof(int));
+    unsigned char *kp = key.data();
+    std::memcpy(kp, &rp, sizeof(RunParams));
+    const uint64_t extra[3] = {grid, (uint64_t)b.x, (uint64_t)lds};
+    std::memcpy(kp + sizeof(RunParams), extra, sizeof(extra));
+    std::memcpy(kp + sizeof(RunParams) + sizeof(extra), &c->bits, sizeof(int));
+    if (!c->gexec || key != c->gkey) {
+        drop_graph(c);
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = launch_reset(rp.counters, rp.next, c->capture_stream);
+        hipError_t e2 = e1 == hipSuccess ? launch_sampler(rp, c->bits == 64, g, b, lds, c->capture_stream) : e1;
+        hipError_t e3 = hipStreamEndCapture(c->capture_stream, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+            return fail(c, SOFT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        hipError_t e4 = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e4 != hipSuccess) {
+            c->gexec = nullptr;
+            return fail(c, SOFT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e4));
+        }
+        c->gkey = key;
+    }
+    HIPCHK(c, hipGraphLaunch(c->gexec, stream));
+    return SOFT_OK;
+}
+
+int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, uint32_t *status, uint32_t *abort_op,
+                uint32_t *obs, RunParams &rp) {
+    std::memset(&rp, 0, sizeof(rp));
+    rp.ev = c->d_ev.p;
+    rp.nz = c->d_nz.p;
+    rp.tm1 = c->d_tm1.p;
+    rp.det = c->d_det.p;
+    rp.words = c->words_dev;
+    rp.word_stride = (uint64_t)c->prog.n_noise + c->prog.n_meas;
+    rp.outcomes = outcomes;
+    rp.status = status;
+    rp.abort_op = abort_op;
+    rp.obs = obs;
+    rp.counters = c->d_counters;
+    rp.next = c->d_counters + C_COUNT;
+    rp.seed = c->seed;
+    rp.shot0 = shot0;
+    rp.n_shots = n_shots;
+    rp.n_noise = c->prog.n_noise;
+    rp.rec_words = rec_words(c);
+    rp.support_cap = c->support_cap ? c->support_cap : 0xFFFFFFFFu;
+    rp.tile_entries = tile_entries(c);
+    rp.tile_bytes = tile_bytes(c);
+    rp.wave_bytes = wave_bytes(c);
+    const double t = tau_of(c);
+    rp.tau2 = t * t;
+    rp.grab = 1;
+    if (c->keep_n) {
+        const uint32_t te = tile_entries(c);
+        int rc;
+        if ((rc = ensure(c, c->d_keep_meta, (size_t)c->keep_n * KM_COUNT)) ||
+            (rc = ensure(c, c->d_keep_v, (size_t)c->keep_n * te * 2)))
+            return rc;
+        rp.keep_meta = c->d_keep_meta.p;
+        rp.keep_v = c->d_keep_v.p;
+        rp.keep_lo = c->keep_lo;
+        rp.keep_n = c->keep_n;
+        c->keep_tile = te;
+    }
+    if (c->trace_n) {
+        const uint32_t te = tile_entries(c);
+        int rc;
+        if ((rc = ensure(c, c->d_trace_meta, (size_t)c->trace_n * KM_COUNT)) ||
+            (rc = ensure(c, c->d_trace_v, (size_t)c->trace_n * te * 2)))
+            return rc;
+        rp.trace_meta = c->d_trace_meta.p;
+        rp.trace_v = c->d_trace_v.p;
+        rp.trace_shot = c->trace_shot;
+        rp.trace_n = c->trace_n;
+        c->trace_tile = te;
+    }
+    return SOFT_OK;
+}
+
+int run_impl(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, uint32_t *status, uint32_t *abort_op,
+             uint32_t *obs, hipStream_t stream, const Shape &s) {
+    RunParams rp;
+    int rc = make_params(c, shot0, n_shots, outcomes, status, abort_op, obs, rp);
+    if (rc) return rc;
+    rp.grab = s.grab;
+    if (c->trace_n)  // outside the graph: mark every trace step unwritten
+        HIPCHK(c, hipMemsetAsync(c->d_trace_meta.p, 0, (size_t)c->trace_n * KM_COUNT * sizeof(unsigned long long), stream));
+    if ((rc = launch(c, rp, s, n_shots, stream))) return rc;
+    c->ran = true;
+    c->last_stream = stream;
+    c->last_shot0 = shot0;
+    c->last_n = n_shots;
+    return SOFT_OK;
+}
+
+const Frame *kept_frame(soft_ctx *c, uint64_t shot, std::vector<unsigned long long> &meta, std::vector<double> &tile, int &rc) {
+    rc = SOFT_OK;
+    if (!c->ran) { rc = fail(c, SOFT_ESTATE, "no run yet"); return nullptr; }
+    if (!c->keep_n || shot < c->keep_lo || shot - c->keep_lo >= c->keep_n || shot < c->last_shot0 ||
+        shot - c->last_shot0 >= c->last_n) {
+        rc = fail(c, SOFT_EINVAL, "shot was not kept by the last run (see soft_set_keep)");
+        return nullptr;
+    }
+    hipError_t e = hipStreamSynchronize(c->last_stream);
+    if (e != hipSuccess) { rc = fail(c, SOFT_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e)); return nullptr; }
+    const uint64_t kk = shot - c->keep_lo;
+    meta.resize(KM_COUNT);
+    tile.resize((size_t)c->keep_tile * 2);
+    e = hipMemcpy(meta.data(), c->d_keep_meta.p + kk * KM_COUNT, KM_COUNT * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(tile.data(), c->d_keep_v.p + kk * (uint64_t)c->keep_tile * 2, tile.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { rc = fail(c, SOFT_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e)); return nullptr; }
+    const uint64_t term = meta[KM_TERM_EV];
+    if (term >= c->prog.events.size()) { rc = fail(c, SOFT_EDEVICE, "corrupt kept state"); return nullptr; }
+    return meta[KM_AFTER] ? &c->prog.after[term] : &c->prog.before[term];
+}
+
+// Coefficients of a dumped state: alpha(j) = a ^ sum_t j_t b_t over the
+// frame's span basis; entries below the pruning threshold are left out.
+int decode_coeffs(soft_ctx *c, const Frame &f, const std::vector<unsigned long long> &meta,
+                  const std::vector<double> &tile, uint64_t *alpha, double *re, double *im, uint32_t cap,
+                  uint32_t *count) {
+    const uint32_t k = (uint32_t)meta[KM_K];
+    if (k != f.basis.size() || (1ull << k) * 2 > tile.size())
+        return fail(c, SOFT_EDEVICE, "dumped state does not match the compiled frame");
+    const uint64_t a = meta[KM_A];
+    const uint32_t cnt = 1u << k;
+    double n2 = 0.0;
+    for (uint32_t j = 0; j < cnt; ++j) n2 += tile[2 * j] * tile[2 * j] + tile[2 * j + 1] * tile[2 * j + 1];
+    const double t = tau_of(c);
+    std::vector<std::pair<uint64_t, uint32_t>> keep;
+    for (uint32_t j = 0; j < cnt; ++j) {
+        const double q = tile[2 * j] * tile[2 * j] + tile[2 * j + 1] * tile[2 * j + 1];
+        if (q == 0.0 || q < t * t * n2) continue;
+        uint64_t al = a;
+        for (uint32_t b = 0; b < k; ++b)
+            if ((j >> b) & 1u) al ^= f.basis[b];
+        keep.push_back({al, j});
+    }
+    std::sort(keep.begin(), keep.end());
+    *count = (uint32_t)keep.size();
+    for (uint32_t i = 0; i < keep.size() && i < cap; ++i) {
+        if (alpha) alpha[i] = keep[i].first;
+        if (re) re[i] = tile[2 * keep[i].second];
+        if (im) im[i] = tile[2 * keep[i].second + 1];
+    }
+    return SOFT_OK;
+}
+
+// Tableau rows of a dumped state: x/z from the frame, signs from the shot.
+void decode_tableau(const soft_ctx *c, const Frame &f, const std::vector<unsigned long long> &meta, uint64_t *x,
+                    uint64_t *z, uint8_t *r) {
+    const int n = c->prog.n;
+    for (int i = 0; i < n; ++i) {
+        uint64_t xd = 0, zd = 0, xs = 0, zs = 0;
+        for (int q = 0; q < n; ++q) {
+            xd |= ((f.xd[q] >> i) & 1ull) << q;
+            zd |= ((f.zd[q] >> i) & 1ull) << q;
+            xs |= ((f.xs[q] >> i) & 1ull) << q;
+            zs |= ((f.zs[q] >> i) & 1ull) << q;
+        }
+        if (x) { x[i] = xd; x[n + i] = xs; }
+        if (z) { z[i] = zd; z[n + i] = zs; }
+        if (r) {
+            r[i] = (uint8_t)((meta[KM_RD] >> i) & 1ull);
+            r[n + i] = (uint8_t)((meta[KM_RS] >> i) & 1ull);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int soft_create(soft_ctx **out, int hip_device) {
+    if (!out) return SOFT_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+        g_create_error = e != hipSuccess ? std::string("hipGetDeviceCount: ") + hipGetErrorString(e) : "no such HIP device";
+        return e != hipSuccess ? SOFT_EDEVICE : SOFT_EINVAL;
+    }
+    soft_ctx *c = new (std::nothrow) soft_ctx();
+    if (!c) { g_create_error = "out of host memory"; return SOFT_ECAPACITY; }
+    c->device = hip_device;
+    auto bad = [&](hipError_t err, const char *what) {
+        g_create_error = std::string(what) + ": " + hipGetErrorString(err);
+        soft_destroy(c);
+        return SOFT_EDEVICE;
+    };
+    if ((e = hipSetDevice(hip_device)) != hipSuccess) return bad(e, "hipSetDevice");
+    if ((e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, hip_device)) != hipSuccess)
+        return bad(e, "hipDeviceGetAttribute");
+    int lds = 0;
+    if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device)) != hipSuccess)
+        return bad(e, "hipDeviceGetAttribute");
+    c->max_lds_block = lds;
+    if (sampler_set_lds_limit(lds) != hipSuccess) {
+        (void)hipGetLastError();
+        c->max_lds_block = std::min(lds, 65536);
+    }
+    if ((e = hipMalloc((void **)&c->d_counters, (C_COUNT + 1) * sizeof(unsigned long long))) != hipSuccess)
+        return bad(e, "hipMalloc");
+    if ((e = hipMemset(c->d_counters, 0, (C_COUNT + 1) * sizeof(unsigned long long))) != hipSuccess) return bad(e, "hipMemset");
+    if ((e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess) return bad(e, "hipStreamCreate");
+    *out = c;
+    return SOFT_OK;
+}
+
+void soft_destroy(soft_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->ran && c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+    drop_graph(c);
+    release(c->d_ev);
+    release(c->d_nz);
+    release(c->d_tm1);
+    release(c->d_det);
+    release(c->d_keep_meta);
+    release(c->d_keep_v);
+    release(c->d_trace_meta);
+    release(c->d_trace_v);
+    if (c->d_counters) (void)hipFree(c->d_counters);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+const char *soft_last_error(const soft_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int soft_load_circuit(soft_ctx *c, const char *text, size_t len) {
+    if (!c || (!text && len)) return fail(c, SOFT_EINVAL, "null argument");
+    std::string t(text ? text : "", len);
+    // validate now so that errors surface at load time
+    Program p;
+    try {
+        compile_circuit(t, c->noise, p);
+    } catch (const CompileError &e) {
+        return fail(c, e.line > 0 ? SOFT_EPARSE : SOFT_ECAPACITY,
+                    e.line > 0 ? "line " + std::to_string(e.line) + ": " + e.msg : e.msg);
+    }
+    c->text = std::move(t);
+    c->have_text = true;
+    c->dirty = true;
+    (void)hipSetDevice(c->device);
+    return prepare(c);
+}
+
+int soft_load_noise(soft_ctx *c, const soft_noise *m) {
+    if (!c || !m) return fail(c, SOFT_EINVAL, "null argument");
+    const double ps[6] = {m->p1, m->p2, m->p_idle, m->p_meas, m->p_reset, m->p_mpp};
+    for (double p : ps)
+        if (!(p >= 0.0 && p <= 1.0)) return fail(c, SOFT_EINVAL, "noise probability out of [0,1]");
+    c->noise.p1 = m->p1;
+    c->noise.p2 = m->p2;
+    c->noise.p_idle = m->p_idle;
+    c->noise.p_meas = m->p_meas;
+    c->noise.p_reset = m->p_reset;
+    c->noise.p_mpp = m->p_mpp;
+    c->dirty = true;
+    if (!c->have_text) return SOFT_OK;
+    (void)hipSetDevice(c->device);
+    return prepare(c);
+}
+
+int soft_set_rng(soft_ctx *c, uint64_t seed) {
+    if (!c) return SOFT_EINVAL;
+    c->seed = seed;
+    return SOFT_OK;
+}
+
+int soft_set_uniforms(soft_ctx *c, const uint32_t *words_dev, uint64_t n_shots, uint32_t noise_slots, uint32_t meas_slots) {
+    if (!c) return SOFT_EINVAL;
+    if (!words_dev) {
+        c->words_dev = nullptr;
+        c->words_n = 0;
+        return SOFT_OK;
+    }
+    if (((uintptr_t)words_dev & 3u) != 0) return fail(c, SOFT_EINVAL, "words_dev must be 4-byte aligned");
+    c->words_dev = words_dev;
+    c->words_n = n_shots;
+    c->words_noise = noise_slots;
+    c->words_meas = meas_slots;
+    return SOFT_OK;
+}
+
+int soft_set_precision(soft_ctx *c, int bits) {
+    if (!c) return SOFT_EINVAL;
+    if (bits != 32 && bits != 64) return fail(c, SOFT_EINVAL, "coeff_bits must be 32 or 64");
+    c->bits = bits;
+    return SOFT_OK;
+}
+
+int soft_set_prune(soft_ctx *c, double tau) {
+    if (!c) return SOFT_EINVAL;
+    if (std::isnan(tau) || tau >= 1.0) return fail(c, SOFT_EINVAL, "tau must be < 1");
+    c->tau = tau < 0.0 ? -1.0 : tau;
+    return SOFT_OK;
+}
+
+int soft_set_caps(soft_ctx *c, uint32_t support_cap, uint32_t wpb, uint32_t bpc, uint32_t grab) {
+    if (!c) return SOFT_EINVAL;
+    if (wpb > 4) return fail(c, SOFT_EINVAL, "waves_per_block must be <= 4");
+    if (bpc > kMaxWavesPerCu) return fail(c, SOFT_EINVAL, "blocks_per_cu must be <= 32");
+    if (grab > 4096) return fail(c, SOFT_EINVAL, "grab must be <= 4096");
+    c->support_cap = support_cap;
+    c->user.wpb = wpb;
+    c->user.bpc = bpc;
+    c->user.grab = grab;
+    return SOFT_OK;
+}
+
+int soft_set_keep(soft_ctx *c, uint64_t shot_lo, uint32_t count) {
+    if (!c) return SOFT_EINVAL;
+    if (count > 4096) return fail(c, SOFT_ECAPACITY, "at most 4096 kept shots");
+    c->keep_lo = shot_lo;
+    c->keep_n = count;
+    return SOFT_OK;
+}
+
+int soft_run(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, uint32_t *status, uint32_t *abort_op,
+             uint32_t *obs, void *hip_stream) {
+    if (!c) return SOFT_EINVAL;
+    if (!status && n_shots) return fail(c, SOFT_EINVAL, "status_dev is required");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = prepare(c);
+    if (rc) return rc;
+    if (c->words_dev) {
+        if (c->words_noise != c->prog.n_noise || c->words_meas != c->prog.n_meas)
+            return fail(c, SOFT_EINVAL, "explicit words: expected " + std::to_string(c->prog.n_noise) + " noise and " +
+                                            std::to_string(c->prog.n_meas) + " measurement slots per shot");
+        if (n_shots > c->words_n) return fail(c, SOFT_EINVAL, "explicit words: fewer rows than shots");
+    }
+    if (n_shots == 0) return SOFT_OK;
+    Shape s = current_shape(c);
+    if ((rc = check_shape(c, s))) return rc;
+    return run_impl(c, shot0, n_shots, outcomes, status, abort_op, obs, (hipStream_t)hip_stream, s);
+}
+
+int soft_read_counters(soft_ctx *c, soft_counters *out) {
+    if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
+    if (!c->ran) return fail(c, SOFT_ESTATE, "no run yet");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->last_stream));
+    unsigned long long h[C_COUNT];
+    HIPCHK(c, hipMemcpy(h, c->d_counters, sizeof(h), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->shots = h[C_SHOTS];
+    out->passed = h[C_PASSED];
+    out->discarded = h[C_DISCARDED];
+    out->overflow = h[C_OVERFLOW];
+    out->numeric = h[C_NUMERIC];
+    out->logical_errors = h[C_LOGICAL];
+    out->entries_t = h[C_ENTRIES_T];
+    out->entries_m = h[C_ENTRIES_M];
+    out->noise_slots = h[C_NOISE];
+    out->events = h[C_EVENTS];
+    for (int b = 0; b < 16; ++b) out->support_hist[b] = h[C_HIST0 + b];
+    std::memcpy(&out->max_norm_dev, &h[C_NORMDEV_BITS], sizeof(double));
+    return SOFT_OK;
+}
+
+int soft_read_coeffs(soft_ctx *c, uint64_t shot, uint64_t *alpha, double *re, double *im, uint32_t cap, uint32_t *count) {
+    if (!c || !count) return fail(c, SOFT_EINVAL, "null argument");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<unsigned long long> meta;
+    std::vector<double> tile;
+    int rc;
+    const Frame *f = kept_frame(c, shot, meta, tile, rc);
+    if (!f) return rc;
+    return decode_coeffs(c, *f, meta, tile, alpha, re, im, cap, count);
+}
+
+int soft_read_tableau(soft_ctx *c, uint64_t shot, uint64_t *x, uint64_t *z, uint8_t *r) {
+    if (!c) return SOFT_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<unsigned long long> meta;
+    std::vector<double> tile;
+    int rc;
+    const Frame *f = kept_frame(c, shot, meta, tile, rc);
+    if (!f) return rc;
+    decode_tableau(c, *f, meta, x, z, r);
+    return SOFT_OK;
+}
+
+int soft_set_trace(soft_ctx *c, uint64_t shot, uint32_t steps) {
+    if (!c) return SOFT_EINVAL;
+    if (steps > 65536) return fail(c, SOFT_ECAPACITY, "at most 65536 traced steps");
+    c->trace_shot = shot;
+    c->trace_n = steps;
+    return SOFT_OK;
+}
+
+int soft_read_trace(soft_ctx *c, uint32_t step, uint64_t info[6], uint64_t *x, uint64_t *z, uint8_t *r,
+                    uint64_t *alpha, double *re, double *im, uint32_t cap, uint32_t *count) {
+    if (!c || !info) return fail(c, SOFT_EINVAL, "null argument");
+    if (!c->ran || !c->trace_n || !c->trace_tile) return fail(c, SOFT_ESTATE, "no traced run");
+    if (step >= c->trace_n) return fail(c, SOFT_EINVAL, "step beyond the traced range");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->last_stream));
+    std::vector<unsigned long long> meta(KM_COUNT);
+    std::vector<double> tile((size_t)c->trace_tile * 2);
+    HIPCHK(c, hipMemcpy(meta.data(), c->d_trace_meta.p + (uint64_t)step * KM_COUNT, KM_COUNT * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost));
+    for (int i = 0; i < 6; ++i) info[i] = 0;
+    if (count) *count = 0;
+    if (meta[KM_VALID] != kStateValid) return SOFT_OK;
+    HIPCHK(c, hipMemcpy(tile.data(), c->d_trace_v.p + (uint64_t)step * c->trace_tile * 2, tile.size() * sizeof(double),
+                        hipMemcpyDeviceToHost));
+    const uint64_t term = meta[KM_TERM_EV];
+    if (term >= c->prog.events.size()) return fail(c, SOFT_EDEVICE, "corrupt trace entry");
+    const Frame &f = meta[KM_AFTER] ? c->prog.after[term] : c->prog.before[term];
+    info[0] = 1;
+    info[1] = c->prog.events[term].src;
+    info[2] = meta[KM_STATUS];
+    info[3] = meta[KM_K];
+    info[4] = meta[KM_NRM2];
+    info[5] = (meta[KM_STATUS] != ST_PASSED || c->prog.events[term].kind == EV_END) ? 1 : 0;
+    decode_tableau(c, f, meta, x, z, r);
+    uint32_t cnt = 0;
+    int rc = decode_coeffs(c, f, meta, tile, alpha, re, im, cap, &cnt);
+    if (count) *count = cnt;
+    return rc;
+}
+
+int soft_circuit_info(soft_ctx *c, uint64_t info[8]) {
+    if (!c || !info) return fail(c, SOFT_EINVAL, "null argument");
+    (void)hipSetDevice(c->device);
+    int rc = prepare(c);
+    if (rc) return rc;
+    info[0] = (uint64_t)c->prog.n;
+    info[1] = c->prog.n_rec;
+    info[2] = c->prog.n_noise;
+    info[3] = c->prog.n_meas;
+    info[4] = c->prog.n_obs;
+    info[5] = c->prog.events.size();
+    info[6] = c->prog.kmax;
+    info[7] = rec_words(c);
+    return SOFT_OK;
+}
+
+int soft_launch_shape(soft_ctx *c, uint32_t out[4]) {
+    if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
+    (void)hipSetDevice(c->device);
+    int rc = prepare(c);
+    if (rc) return rc;
+    Shape s = current_shape(c);
+    out[0] = s.wpb;
+    out[1] = s.bpc;
+    out[2] = s.grab;
+    out[3] = wave_bytes(c);
+    return SOFT_OK;
+}
+
+int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
+    if (!c) return SOFT_EINVAL;
+    if (sample_shots == 0) return fail(c, SOFT_EINVAL, "sample_shots must be > 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = prepare(c);
+    if (rc) return rc;
+    if (c->words_dev) return fail(c, SOFT_ESTATE, "autotune runs on Philox draws; clear explicit uniforms first");
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint32_t *d_status = nullptr;
+    HIPCHK(c, hipMalloc((void **)&d_status, sample_shots * sizeof(uint32_t)));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    HIPCHK(c, hipEventCreate(&t0));
+    HIPCHK(c, hipEventCreate(&t1));
+    const uint32_t keep_n = c->keep_n;
+    c->keep_n = 0;
+    const uint32_t wb = wave_bytes(c);
+    Shape best;
+    float best_ms = 1e30f;
+    const uint32_t wpbs[3] = {1, 2, 4};
+    const uint32_t grabs[2] = {1, 4};
+    for (uint32_t wpb : wpbs) {
+        if (wpb * wb > (uint32_t)c->max_lds_block) continue;
+        const uint32_t occ = std::min<uint32_t>(std::max<uint32_t>(1u, kLdsPerCu / (wpb * wb)), kMaxWavesPerCu / wpb);
+        std::vector<uint32_t> bpcs;
+        for (uint32_t d : {4u, 2u, 1u}) {
+            uint32_t v = std::max<uint32_t>(1u, occ / d);
+            if (std::find(bpcs.begin(), bpcs.end(), v) == bpcs.end()) bpcs.push_back(v);
+        }
+        for (uint32_t bpc : bpcs) {
+            for (uint32_t grab : grabs) {
+                Shape s;
+                s.wpb = wpb;
+                s.bpc = bpc;
+                s.grab = grab;
+                float ms = 0.0f;
+                // one untimed run, then one timed run
+                rc = run_impl(c, 0, sample_shots, nullptr, d_status, nullptr, nullptr, st, s);
+                hipError_t e = rc ? hipSuccess : hipEventRecord(t0, st);
+                if (!rc && e == hipSuccess) rc = run_impl(c, 0, sample_shots, nullptr, d_status, nullptr, nullptr, st, s);
+                if (!rc && e == hipSuccess) e = hipEventRecord(t1, st);
+                if (!rc && e == hipSuccess) e = hipEventSynchronize(t1);
+                if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (!rc && e != hipSuccess) rc = fail(c, SOFT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+                if (rc) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = s;
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    c->keep_n = keep_n;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(d_status);
+    if (rc) return rc;
+    c->tuned[std::make_tuple(c->prog.hash, c->bits, tau_of(c), c->support_cap)] = best;
+    c->ran = false;  // counters of the last sample run are not a user run
+    return SOFT_OK;
+}
+
+}  // extern "C"

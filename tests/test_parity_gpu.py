@@ -1,0 +1,195 @@
+"""GPU parity: the HIP sampler (through the C ABI) against the CPU oracle on
+the same seeded inputs.  Tableaux, outcomes, statuses, abort ops and
+observables bit-exact; coefficients within 1e-10 (FP64) / 1e-5 (FP32) of the
+oracle's, relative to its 2-norm."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2512_23037_amd import soft
+from tests.gen_small import random_circuit, random_words
+from tests.gpu_helpers import compare_batch, compare_kept, make_ctx, run_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _words(circ, n, seed):
+    return random_words(seed, n * circ.words_per_shot).reshape(n, circ.words_per_shot)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_circuits_explicit_words(seed):
+    n = 1 + seed % 8
+    text, _ = random_circuit(31000 + seed, n, 90)
+    circ = oracle.Circuit(text)
+    N = 128
+    words = _words(circ, N, seed)
+    ctx = make_ctx(text, keep=(0, N))
+    gpu = run_gpu(ctx, 0, N, words)
+    ref = circ.batch(0, 0, N, words=words)
+    compare_batch(gpu, ref)
+    compare_kept(ctx, circ, 0, range(N), words=words)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_noisy_circuits_philox(seed):
+    n = 2 + seed % 6
+    text, _ = random_circuit(32000 + seed, n, 80)
+    rng = np.random.default_rng(seed)
+    lines = text.strip().split("\n")
+    out = [lines[0]]
+    for line in lines[1:]:
+        out.append(line)
+        if rng.random() < 0.2:
+            out.append("TICK")
+    text = "\n".join(out) + "\n"
+    noise = {k: 0.03 for k in ("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp")}
+    cap = [0, 1, 2, 4][seed % 4]
+    circ = oracle.Circuit(text, noise)
+    N = 512
+    ctx = make_ctx(text, noise, seed=99 + seed, cap=cap, keep=(1000, 64))
+    gpu = run_gpu(ctx, 1000, N)
+    ref = circ.batch(99 + seed, 1000, N, cap=cap if cap else 0xFFFFFFFF)
+    compare_batch(gpu, ref)
+    compare_kept(ctx, circ, 99 + seed, range(1000, 1064), cap=cap if cap else 0xFFFFFFFF)
+
+
+def test_clifford_t_8q_full():
+    w = workloads.config("clifford_t_8q", seed=1)
+    circ = oracle.Circuit(w.text, w.noise)
+    N = 10000
+    ctx = make_ctx(w.text, w.noise, seed=2024, keep=(0, 512))
+    gpu = run_gpu(ctx, 0, N)
+    ref = circ.batch(2024, 0, N)
+    compare_batch(gpu, ref)
+    compare_kept(ctx, circ, 2024, range(512))
+    c = ctx.counters()
+    assert c["shots"] == N
+    assert c["passed"] == int((ref["status"] == 0).sum())
+    assert c["discarded"] == int((ref["status"] == 1).sum())
+
+
+def test_cultivation_15q_full():
+    w = workloads.config("cultivation_15q", seed=1)
+    circ = oracle.Circuit(w.text, w.noise)
+    N = 1_000_000
+    ctx = make_ctx(w.text, w.noise, seed=7, keep=(0, 256))
+    gpu = run_gpu(ctx, 0, N)
+    ref = circ.batch(7, 0, N)
+    compare_batch(gpu, ref)
+    compare_kept(ctx, circ, 7, range(256))
+    c = ctx.counters()
+    assert c["passed"] == int((ref["status"] == 0).sum())
+    assert c["logical_errors"] == int(((ref["status"] == 0) & (ref["obs"] != 0)).sum())
+    hist = np.bincount(np.floor(np.log2(ref["max_support"])).astype(int), minlength=16)
+    assert list(hist[:16]) == c["support_hist"]
+
+
+@pytest.mark.parametrize("bits,tol", [(64, 1e-10), (32, 1e-5)])
+def test_cultivation_42q_subset(bits, tol):
+    w = workloads.config("cultivation_42q", seed=1)
+    circ = oracle.Circuit(w.text, w.noise)
+    N = 3000
+    ctx = make_ctx(w.text, w.noise, seed=11, bits=bits, keep=(0, 200))
+    gpu = run_gpu(ctx, 0, N)
+    ref = circ.batch(11, 0, N)
+    diff = (gpu["status"] != ref["status"]) | (gpu["outcomes"] != ref["outcomes"]).any(axis=0)
+    if bits == 64:
+        assert not diff.any()
+    else:
+        # FP32: an outcome may differ only where the draw lies within 1e-5 of
+        # the oracle's probability (guard band); such shots are reported.
+        for shot in np.nonzero(diff)[0][:20]:
+            r = circ.shot(11, int(shot))
+            us = []
+            for slot in range(circ.n_meas_slots):
+                blk = oracle.philox([slot >> 2, int(shot) & 0xFFFFFFFF, int(shot) >> 32, 1], [11, 0])
+                us.append((float(blk[slot & 3]) + 0.5) / 2 ** 32)
+            near = [abs(u - p) < 1e-5 for u, p in zip(us, r.p0) if not np.isnan(p)]
+            assert any(near), "FP32 outcome flip outside the guard band at shot %d" % shot
+        assert diff.sum() <= 3
+    compare_batch(gpu, ref, skip=diff)
+    kept = [s for s in range(200) if not diff[s]]
+    worst = compare_kept(ctx, circ, 11, kept, tol=tol, tau=1e-12 if bits == 64 else 1e-6)
+    print("bits=%d worst coefficient error %.3g" % (bits, worst))
+
+
+def test_full_size_sampled_shots():
+    # The benchmark's workload and launch shape at full size; sampled shots
+    # are checked one by one against the oracle, the rest by invariants.
+    w = workloads.config("cultivation_42q", seed=1)
+    circ = oracle.Circuit(w.text, w.noise)
+    N = 2_000_000
+    ctx = make_ctx(w.text, w.noise, seed=5, bits=32)
+    gpu = run_gpu(ctx, 0, N)
+    c = ctx.counters()
+    assert c["shots"] == N
+    assert c["passed"] + c["discarded"] + c["overflow"] + c["numeric"] == N
+    assert c["passed"] == int((gpu["status"] == 0).sum())
+    assert ((gpu["status"] == 0) == (gpu["abort_op"] == soft.NO_ABORT)).all()
+    assert c["max_norm_dev"] < 1e-4
+    rng = np.random.default_rng(0)
+    for shot in rng.choice(N, size=150, replace=False):
+        r = circ.shot(5, int(shot))
+        assert gpu["status"][shot] == r.status and gpu["abort_op"][shot] == r.abort_op
+        rec = [int((gpu["outcomes"][k >> 5, shot] >> (k & 31)) & 1) for k in range(circ.n_records)]
+        assert rec == r.record
+
+
+def test_shard_determinism_and_graph_replay():
+    w = workloads.config("cultivation_15q", seed=3)
+    ctx = make_ctx(w.text, w.noise, seed=21)
+    a = run_gpu(ctx, 0, 40000)
+    b1 = run_gpu(ctx, 0, 20000)
+    b2 = run_gpu(ctx, 20000, 20000)
+    for key in ("status", "abort_op", "obs"):
+        assert (a[key] == np.concatenate([b1[key], b2[key]])).all()
+    assert (a["outcomes"] == np.concatenate([b1["outcomes"], b2["outcomes"]], axis=1)).all()
+    t = torch()
+    # the same graph replayed, with the program's own eager work in between
+    outs = soft.sample(ctx, 0, 40000)
+    for rep in range(4):
+        _ = (t.randn(4096, device="cuda") * 2.0).sum().item()
+        for o in outs:
+            o.zero_()
+        ctx.run(0, 40000, *outs)
+        t.cuda.synchronize()
+        assert (outs[1].cpu().numpy().view(np.uint32) == a["status"]).all()
+        got = outs[0].cpu().numpy().view(np.uint32)[: a["outcomes"].shape[0]]
+        assert (got == a["outcomes"]).all()
+
+
+def test_parse_errors_and_degenerate_inputs():
+    ctx = soft.Context(0)
+    for bad in ("H 0\n", "QUBITS 2\nH 2\n", "QUBITS 2\nCX 1 1\n", "QUBITS 2\nFOO 1\n", "QUBITS 2\nDETECTOR 0 0\n",
+                "QUBITS 2\nDEP1 1.5 0\n", "QUBITS 2\nMPP X0*X0\n", "QUBITS 65\n"):
+        with pytest.raises(soft.SoftError) as ei:
+            ctx.load_circuit(bad)
+        assert ei.value.code == soft.SOFT_EPARSE
+        with pytest.raises(ValueError):
+            oracle.Circuit(bad)
+    # empty circuit, zero shots, Clifford-only, p = 1 and p below 2^-32
+    for text, noise in (("QUBITS 1\n", {}), ("QUBITS 3\nH 0\nCX 0 1\nM 1\nM 0\n", {}),
+                        ("QUBITS 2\nH 0\nT 0\nCX 0 1\nM 0\nM 1\n", {"p1": 1.0, "p2": 1.0}),
+                        ("QUBITS 2\nH 0\nT 0\nM 0\n", {"p1": 1e-10})):
+        circ = oracle.Circuit(text, noise)
+        ctx = make_ctx(text, noise, seed=3, keep=(0, 16))
+        ctx.run(0, 0, None, None)
+        gpu = run_gpu(ctx, 0, 300)
+        compare_batch(gpu, circ.batch(3, 0, 300))
+        compare_kept(ctx, circ, 3, range(16))
+
+
+def test_autotune_keeps_results():
+    w = workloads.config("cultivation_15q", seed=1)
+    ctx = make_ctx(w.text, w.noise, seed=4)
+    base = run_gpu(ctx, 0, 20000)
+    ctx.autotune(20000)
+    shape = ctx.launch_shape()
+    assert 1 <= shape["waves_per_block"] <= 4
+    tuned = run_gpu(ctx, 0, 20000)
+    for key in ("status", "abort_op", "obs", "outcomes"):
+        assert (base[key] == tuned[key]).all()
