@@ -1,0 +1,209 @@
+"""Throughput benchmark: shots/s of the GPU generalized-stabilizer sampler on
+the 42-qubit / 72-T cultivation-shaped circuit (19 data + 23 ancilla qubits,
+circuit-level depolarizing noise p = 1e-3), 10^7 shots per step.
+
+One step = one soft_run over 10^7 shots (the whole hot path: noise draws,
+sign-frame Cliffords, T/T-dagger, measurements, postselection, outputs) with
+every input resident on the GPU.  The headline runs FP32 coefficients (FP64
+probabilities and renormalisation); the FP64-coefficient run of the same
+workload is reported beside it, with the FP32-vs-FP64 differences.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "shots/sec on 1 MI355X (42q/72T noisy circuit), FP32 vs FP64 coeffs at err≤1e-5"
+WORKLOAD = "cultivation_42q"
+SEED_CIRCUIT = 1
+SEED_RNG = 20251223
+
+# Peak 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Algorithmic operations per unit of work ("Roofline"):
+OPS_T_BRANCH = 8 + 6    # per coefficient written by a branching T: complex 2-term combination + index/sign
+OPS_T_PHASE = 2 + 3     # per coefficient under a non-branching T: half pick up a phase
+OPS_M = 5 + 4           # per coefficient read by a measurement: |v|^2 in FP64, scale, index/sign
+OPS_NOISE = 25 + 2      # per noise word: a quarter Philox4x32-10 block, threshold compare
+
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sampler_cultivation_42q_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_23037_amd", "csrc", f)
+                  for f in ("sampler.hip", "program.h", "sampler.h")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_ctx(soft, w, bits):
+    ctx = soft.Context(0)
+    ctx.load_noise(**w.noise)
+    ctx.load_circuit(w.text)
+    ctx.set_rng(SEED_RNG)
+    ctx.set_precision(bits)
+    return ctx
+
+
+def time_steps(torch, ctx, shots, steps, warmup, bufs):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.run(0, shots, *bufs, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for s in range(steps):
+        ctx.run(s * shots, shots, *bufs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(w, shots_sample: int):
+    import oracle
+    oracle.build(force=False)
+    circ = oracle.Circuit(w.text, w.noise)
+    threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+    t0 = time.perf_counter()
+    r = circ.batch(SEED_RNG, 0, shots_sample, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": shots_sample / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
+            "sample": "shots 0..%d of the same workload (seed %d), %d host threads, %.1f s wall"
+                      % (shots_sample - 1, SEED_RNG, threads, dt)}, r["work"], shots_sample
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=10_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--autotune", type=int, default=0, help="sample shots for the autotuner (0 = library default shape)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy 3 times (HBM counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the sampler shards shot ranges across GPUs by design, "
+              "but this build launches no multi-GPU runs); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2512_23037_amd import soft
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}))
+        return
+
+    w = workloads.config(WORKLOAD, seed=SEED_CIRCUIT)
+    stats_tab = workloads.circuit_stats(w.text)
+    shots = args.shots
+    dev = torch.device("cuda", 0)
+
+    results = {}
+    for bits in ([32] if args.no_fp64 else [32, 64]):
+        ctx = make_ctx(soft, w, bits)
+        if args.autotune:
+            ctx.autotune(args.autotune)
+        nw = ctx.info()["record_words"]
+        bufs = (torch.zeros((nw, shots), dtype=torch.int32, device=dev),
+                torch.zeros(shots, dtype=torch.int32, device=dev),
+                torch.zeros(shots, dtype=torch.int32, device=dev),
+                torch.zeros(shots, dtype=torch.int32, device=dev))
+        # the last timed step keeps shots [(steps-1)*shots, +256) for the FP32-vs-FP64 comparison
+        ctx.set_keep((args.steps - 1) * shots, 256)
+        ms, wall = time_steps(torch, ctx, shots, args.steps, args.warmup, bufs)
+        c = ctx.counters()   # counters of the last timed step
+        results[bits] = {"ms": ms, "wall": wall, "counters": c, "shape": ctx.launch_shape(),
+                         "status": bufs[1][:200000].cpu().numpy(), "outcomes": bufs[0][:, :200000].cpu().numpy()}
+        base = (args.steps - 1) * shots
+        results[bits]["coeffs"] = [ctx.read_coeffs(base + s) for s in range(256)]
+        results[bits]["kept_status"] = bufs[1][:256].cpu().numpy()
+        del bufs
+        ctx.close()
+        torch.cuda.empty_cache()
+
+    r32 = results[32]
+    value = shots / (r32["ms"] / 1e3)
+    c = r32["counters"]
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r32["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cultivation-shaped 42q/72T circuit (19 data + 23 ancilla, brackets 19+7+5+5, "
+                               "seed %d), circuit-level depolarizing p=1e-3, %d shots per step" % (SEED_CIRCUIT, shots),
+                   "coefficients": "fp32 complex; fp64 probabilities, renormalisation, norm check",
+                   "circuit": stats_tab, "launch": r32["shape"]},
+        "stats": {"passed": c["passed"], "discarded": c["discarded"], "overflow": c["overflow"],
+                  "numeric": c["numeric"], "logical_errors": c["logical_errors"],
+                  "discard_rate": c["discarded"] / max(1, c["shots"]), "max_norm_dev": c["max_norm_dev"]},
+    }
+    if 64 in results:
+        r64 = results[64]
+        v64 = shots / (r64["ms"] / 1e3)
+        both = (r32["kept_status"] == r64["kept_status"])
+        errs = []
+        for a, b in zip(r32["coeffs"], r64["coeffs"]):
+            keys = set(a) | set(b)
+            nb = np.sqrt(sum(abs(x) ** 2 for x in b.values())) or 1.0
+            errs.append(max([abs(a.get(k, 0) - b.get(k, 0)) for k in keys] + [0.0]) / nb)
+        mism = int(((r32["status"] != r64["status"]) | (r32["outcomes"] != r64["outcomes"]).any(axis=0)).sum())
+        c64 = r64["counters"]
+        ler32 = c["logical_errors"] / max(1, c["passed"])
+        ler64 = c64["logical_errors"] / max(1, c64["passed"])
+        out["fp64"] = {"value": v64, "ms_per_step": r64["ms"], "launch": r64["shape"], "fp32_speedup": value / v64}
+        out["fp32_vs_fp64"] = {"max_coeff_err": float(max(errs)) if errs else None,
+                               "kept_shots_compared": int(both.sum()),
+                               "shots_with_different_outcomes": mism, "shots_compared": int(len(r32["status"])),
+                               "ler_fp32": ler32, "ler_fp64": ler64}
+
+    # ---- roofline: algorithmic VALU work per launch over the measured time ----
+    work = None
+    if not args.no_cpu_baseline:
+        base, work, nsample = cpu_baseline(w, args.cpu_sample)
+        out["cpu_baseline"] = base
+    if work is not None:
+        per_shot = {k: v / nsample for k, v in work.items()}
+        ops = (OPS_T_BRANCH * per_shot["t_entries"] + OPS_T_PHASE * per_shot["t_phase_entries"] +
+               OPS_M * per_shot["m_entries"] + OPS_NOISE * per_shot["noise_slots"]) * shots
+        achieved = ops / (r32["ms"] / 1e3) / 1e12
+        traffic = None
+        if os.path.exists(PROFILE_TRAFFIC):
+            t = json.load(open(PROFILE_TRAFFIC))
+            if t.get("kernel_hash") == kernel_hash() and t.get("shots") == shots:
+                traffic = t.get("bytes_per_launch")
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                           "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                           "ops_per_launch": ops, "work_per_shot": per_shot,
+                           "kernel_ms": r32["ms"], "kernel_hash": kernel_hash()}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

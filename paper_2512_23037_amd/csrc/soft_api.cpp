@@ -164,13 +164,15 @@ int prepare(soft_ctx *c) {
 constexpr uint32_t kLdsPerCu = 160u * 1024u;
 constexpr uint32_t kMaxWavesPerCu = 32u;
 
+// Untuned launch shape: as many resident waves per CU as the LDS tiles allow
+// (at most 32), two waves per block when that still leaves >= 16 waves.
 Shape default_shape(const soft_ctx *c) {
     Shape s;
     const uint32_t wb = wave_bytes(c);
-    s.wpb = 4;
+    const uint32_t waves_cu = std::max<uint32_t>(1u, std::min<uint32_t>(kMaxWavesPerCu, kLdsPerCu / wb));
+    s.wpb = (waves_cu >= 16u && 2u * wb <= (uint32_t)c->max_lds_block) ? 2u : 1u;
     while (s.wpb > 1 && s.wpb * wb > (uint32_t)c->max_lds_block) s.wpb /= 2;
-    uint32_t per_cu = std::max<uint32_t>(1u, kLdsPerCu / (s.wpb * wb));
-    s.bpc = std::min<uint32_t>(per_cu, kMaxWavesPerCu / s.wpb);
+    s.bpc = std::max<uint32_t>(1u, waves_cu / s.wpb);
     s.grab = 1;
     return s;
 }
