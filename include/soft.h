@@ -122,8 +122,9 @@ int soft_set_precision(soft_ctx *ctx, int coeff_bits);
 int soft_set_prune(soft_ctx *ctx, double tau);
 
 /* support_cap: a shot whose support exceeds it after a T ends as OVERFLOW
- * (0 = no cap).  waves_per_block, blocks_per_cu, grab: launch shape (0 = the
- * autotuned or default value). */
+ * (0 = no cap).  waves_per_block (1..4), blocks_per_cu (1..32), grab (1..64,
+ * consecutive shots a wave takes per steal; their outputs are written
+ * together): launch shape, 0 = the autotuned or default value. */
 int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
                   uint32_t blocks_per_cu, uint32_t grab);
 

@@ -138,18 +138,14 @@ class FrameCompiler {
             E.Are = std::sqrt(0.5);
             E.Aim = s * std::sqrt(0.5);
         } else {
-            // A = e^{i s theta} cos theta; B = e^{i s theta} (-i s sin theta) i^cexp
-            const double er = std::cos(th), ei = s * std::sin(th);
-            E.Are = er * cs;
-            E.Aim = ei * cs;
-            double br = 0.0, bi = -s * sn;           // -i s sin theta
-            double tr = er * br - ei * bi, ti = er * bi + ei * br;
-            for (int r = 0; r < cexp; ++r) {         // times i^cexp
-                double nr = -ti, ni = tr;
-                tr = nr; ti = ni;
-            }
-            E.Bre = tr;
-            E.Bim = ti;
+            // T^s = e^{i s theta}(cos theta - i s sin theta Z_q).  The global
+            // factor e^{i s theta} is counted per shot; the rest is
+            // cos theta v + sin theta i^qb c' v_partner with i^qb = (-i s) i^cexp.
+            E.Are = cs;
+            E.Aim = 0.0;
+            E.Bre = sn;
+            E.Bim = 0.0;
+            E.qb = (uint32_t)((cexp + (dagger ? 1 : 3)) & 3);
             uint32_t mu;
             if (coords(beta, mu)) {
                 E.kind = EV_T_BFLY;

@@ -19,6 +19,11 @@
 //    indexed by coordinates j, with alpha(j) = a ^ sum_t j_t b_t, and the
 //    alpha <-> alpha ^ beta pairing of Eq. 4 becomes j <-> j ^ mu.
 //
+// A branching T^s multiplies the whole state by e^{i s pi/8} (Eqs. 1-2); that
+// factor is kept as an exact per-shot count of eighth turns and applied only
+// when a state is read out, so the tile update is
+//   v'_j = cos(pi/8) v_j + sin(pi/8) i^qb (-1)^(...) v_{j^mu}.
+//
 // Sign vectors are two 64-bit words: bit i of the D word is the sign of
 // destabilizer d_i, bit i of the S word the sign of stabilizer s_i (n <= 64).
 #pragma once
@@ -65,15 +70,16 @@ struct alignas(16) Event {
     uint32_t det_cnt;    //   and number of pairs
     uint32_t expect;     //   expected parity
     uint32_t psign;      // sign bit of the measured Pauli (0 for parsed ops)
-    uint32_t pad0[2];
+    uint32_t qb;         // branching T: quarter turns of B' = sin(pi/8) i^qb
+    uint32_t pad0;
     uint64_t cliffD, cliffS;  // sign flips of the Cliffords since the last event
     uint64_t beta, gamma;     // index shift / anticommuting destabilizers
     uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products
     uint64_t xD, xS;          // reset: rows anticommuting with X_q afterwards
-    double Are, Aim;          // T: e^{i s pi/8} cos(pi/8)
-    double Bre, Bim;          // T: e^{i s pi/8} (-i s sin(pi/8)) i^cexp
+    double Are, Aim;          // T_PHASE: e^{i s pi/4}; branching T: cos(pi/8), 0
+    double Bre, Bim;          // branching T: sin(pi/8), 0 (the weight of the partner term)
     float Afr, Afi, Bfr, Bfi; // the same in single precision
     uint32_t pad1[10];
 };

@@ -13,6 +13,7 @@ struct RunParams {
     const uint32_t *tm1;      // per noise slot: threshold - 1 (padded to 256)
     const uint32_t *det;      // DETECTOR/OBSERVABLE (word, mask) pairs
     const uint32_t *words;    // explicit uniforms [n_shots][word_stride] or null
+    const double *phase_tab;  // cos(k pi/8) for k = 0..15, then sin(k pi/8)
     uint32_t *outcomes;       // [rec_words][n_shots] or null
     uint32_t *status;         // [n_shots]
     uint32_t *abort_op;       // [n_shots] or null

@@ -82,15 +82,16 @@ template <typename R> __device__ __forceinline__ double nrm(typename Cx<R>::T a)
     return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
 }
 
-// i^q * a for q in 0..3
+// i^q * a for q mod 4, without branches: odd q swaps the parts, then the
+// real part flips sign for q = 1, 2 and the imaginary part for q = 2, 3.
 template <typename C> __device__ __forceinline__ C rot(C a, uint32_t q) {
+    q &= 3u;
+    const bool sw = (q & 1u) != 0u;
     C r;
-    switch (q & 3u) {
-        case 0: r = a; break;
-        case 1: r.x = -a.y; r.y = a.x; break;
-        case 2: r.x = -a.x; r.y = -a.y; break;
-        default: r.x = a.y; r.y = -a.x; break;
-    }
+    r.x = sw ? a.y : a.x;
+    r.y = sw ? a.x : a.y;
+    if (((q + 1u) & 2u) != 0u) r.x = -r.x;
+    if ((q & 2u) != 0u) r.y = -r.y;
     return r;
 }
 
@@ -114,11 +115,14 @@ template <typename C, typename R> __device__ __forceinline__ C scale(C a, R s) {
 
 // Write one shot's state (status, signs, offset, span dimension, carried norm
 // and the coefficient tile widened to double) for the readout calls.
+// Write one shot's state for the readout calls: status, signs, offset, span
+// dimension, carried norm, and the coefficient tile widened to double with the
+// counted global phase e^{i pi phase8 / 8} applied.
 template <typename C>
 __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const C *v, uint32_t lane,
                                            uint32_t tile_entries, uint32_t status, uint32_t abort_src, uint32_t term,
                                            uint32_t after, uint64_t rD, uint64_t rS, uint64_t a, uint32_t k,
-                                           double nrm2) {
+                                           double nrm2, const double *phase_tab, uint32_t phase8) {
     if (lane == 0) {
         m[KM_STATUS] = status;
         m[KM_ABORT] = abort_src;
@@ -131,14 +135,118 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
         m[KM_NRM2] = (unsigned long long)__double_as_longlong(nrm2);
         m[KM_VALID] = kStateValid;
     }
+    const double pc = phase_tab[phase8], ps = phase_tab[16u + phase8];
     const uint32_t cnt = 1u << k;
     for (uint32_t j = lane; j < tile_entries; j += 64u) {
-        C x;
-        if (j < cnt) x = v[j];
-        else { x.x = 0; x.y = 0; }
-        dst[2u * j] = (double)x.x;
-        dst[2u * j + 1u] = (double)x.y;
+        double x = 0.0, y = 0.0;
+        if (j < cnt) {
+            const C e = v[j];
+            x = (double)e.x;
+            y = (double)e.y;
+        }
+        dst[2u * j] = x * pc - y * ps;
+        dst[2u * j + 1u] = x * ps + y * pc;
     }
+}
+
+// Record words per shot held in lanes until the group is written.
+constexpr uint32_t kRecRegs = 8;
+
+// Write the outputs of shots [base, base + len) held by lanes 0..len-1.
+__device__ __forceinline__ void flush_group(const RunParams &P, uint64_t base, uint32_t len, uint32_t lane,
+                                            uint32_t st, uint32_t ab, uint32_t ob, const uint32_t (&rec)[kRecRegs]) {
+    if (lane < len) {
+        const uint64_t i = base + lane;
+        P.status[i] = st;
+        if (P.abort_op) P.abort_op[i] = ab;
+        if (P.obs) P.obs[i] = ob;
+        if (P.outcomes) {
+#pragma unroll
+            for (uint32_t w = 0; w < kRecRegs; ++w)
+                if (w < P.rec_words) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
+        }
+    }
+}
+
+// i^Q * a for a compile-time Q: only register moves and sign modifiers.
+template <uint32_t Q, typename C> __device__ __forceinline__ C rotc(C a) {
+    C r;
+    if (Q == 0) { r = a; }
+    else if (Q == 1) { r.x = -a.y; r.y = a.x; }
+    else if (Q == 2) { r.x = -a.x; r.y = -a.y; }
+    else { r.x = a.y; r.y = -a.x; }
+    return r;
+}
+
+// out = cs * a + c * i^Q b, then drop it below the pruning level.
+template <uint32_t Q, typename R, typename C>
+__device__ __forceinline__ C t_out(C a, C b, R cs, R c, R thr, bool &keep) {
+    const C w = rotc<Q>(b);
+    C o;
+    o.x = fma(c, w.x, cs * a.x);
+    o.y = fma(c, w.y, cs * a.y);
+    keep = fma(o.x, o.x, o.y * o.y) >= thr;
+    if (!keep) { o.x = 0; o.y = 0; }
+    return o;
+}
+
+// Branching T on an existing coordinate: pairs (j0, j1 = j0 ^ mu), j0 with
+// bit h clear.  v'_j0 = cs v_j0 + sn i^Q (-1)^(sig ^ g.j1) v_j1 and the same
+// with j0, j1 exchanged.  j0 = ins0(lane, h) | ins0(64 it, h): the lane part
+// and its sign parity are fixed for the event, the rest is uniform.
+template <uint32_t Q, typename R, typename C>
+__device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
+                                           uint32_t sig, R cs, R sn, R thr) {
+    const uint32_t npairs = 1u << (k - 1u);
+    const uint32_t lc = ins0(lane, h);
+    const R base1 = ((sig ^ par32(g & lc)) != 0u) ? -sn : sn;   // weight of v_j0 in v'_j1
+    const R base0 = par32(g & mu) ? -base1 : base1;             // weight of v_j1 in v'_j0
+    uint32_t cnt = 0;
+    const uint32_t iters = (npairs + 63u) >> 6;
+    for (uint32_t it = 0; it < iters; ++it) {
+        const uint32_t J = ins0(it << 6, h);
+        const bool flip = par32(g & J) != 0u;
+        if (npairs >= 64u || lane < npairs) {
+            const uint32_t j0 = lc | J, j1 = j0 ^ mu;
+            const C v0 = v[j0], v1 = v[j1];
+            const R c1 = flip ? -base1 : base1, c0 = flip ? -base0 : base0;
+            bool k0, k1;
+            const C o0 = t_out<Q, R, C>(v0, v1, cs, c0, thr, k0);
+            const C o1 = t_out<Q, R, C>(v1, v0, cs, c1, thr, k1);
+            cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
+            v[j0] = o0;
+            v[j1] = o1;
+        }
+    }
+    return cnt;
+}
+
+// Branching T on a new coordinate (k -> k+1): v'_j = cs v_j and
+// v'_{j+2^k} = sn i^Q (-1)^(sig ^ g.j) v_j.
+template <uint32_t Q, typename R, typename C>
+__device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R cs, R sn,
+                                             R thr) {
+    const uint32_t half = 1u << k;
+    const R base = ((sig ^ par32(g & lane)) != 0u) ? -sn : sn;
+    const C z = {0, 0};
+    uint32_t cnt = 0;
+    const uint32_t iters = (half + 63u) >> 6;
+    for (uint32_t it = 0; it < iters; ++it) {
+        const uint32_t J = it << 6;
+        const bool flip = par32(g & J) != 0u;
+        if (half >= 64u || lane < half) {
+            const uint32_t j = J | lane;
+            const C v0 = v[j];
+            const R c1 = flip ? -base : base;
+            bool k0, k1;
+            const C o0 = t_out<0, R, C>(v0, z, cs, (R)0, thr, k0);
+            const C o1 = t_out<Q, R, C>(z, v0, (R)0, c1, thr, k1);
+            cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
+            v[j] = o0;
+            v[j + half] = o1;
+        }
+    }
+    return cnt;
 }
 
 struct WaveTotals {
@@ -162,18 +270,26 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
     WaveTotals tot;
     uint64_t myc = 0;  // counter number `lane` of this wave
 
-    uint64_t grab_base = 0, grab_left = 0;
+    // Work stealing by groups of `grab` (<= 64) consecutive shots.  Lane g keeps
+    // the output words of the group's g-th shot, so each output plane is
+    // written as one contiguous store per group.
+    uint64_t group_base = 0;
+    uint32_t group_len = 0, group_pos = 0;
+    uint32_t o_status = 0, o_abort = 0, o_obs = 0;
+    uint32_t o_rec[kRecRegs];
+#pragma unroll
+    for (uint32_t w = 0; w < kRecRegs; ++w) o_rec[w] = 0u;
     while (true) {
-        if (grab_left == 0) {
+        if (group_pos == group_len) {
+            if (group_len) flush_group(P, group_base, group_len, lane, o_status, o_abort, o_obs, o_rec);
             unsigned long long got = 0;
             if (lane == 0) got = atomicAdd(P.next, (unsigned long long)P.grab);
-            grab_base = uni64(__shfl((unsigned long long)got, 0, 64));
-            grab_left = P.grab;
+            group_base = uni64(__shfl((unsigned long long)got, 0, 64));
+            if (group_base >= P.n_shots) break;
+            group_len = (uint32_t)min((uint64_t)P.grab, P.n_shots - group_base);
+            group_pos = 0;
         }
-        const uint64_t i = grab_base;
-        ++grab_base;
-        --grab_left;
-        if (i >= P.n_shots) break;
+        const uint64_t i = group_base + group_pos;
         const uint64_t shot = P.shot0 + i;
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
         const uint32_t *wrow = EXPL ? words + i * P.word_stride : nullptr;
@@ -183,12 +299,15 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         if (lane == 0) v[0] = mk<C>(1.0, 0.0);
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
+        uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
         double nrm2 = 1.0;
         uint32_t status = ST_PASSED, abort_src = 0xFFFFFFFFu, obs = 0, maxsup = 1;
         uint32_t term = 0, after = 0;
         // noise: 256 slots per chunk, 4 consecutive slots (one Philox block) per lane
         uint32_t nz_next = 0, nz_cb = 0, nz_have = 0;
         uint32_t hits = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        // measurement words: slots [m_base, m_base + 256), one Philox block per lane
+        uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
         const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
         for (uint32_t e = 0;; ++e) {
@@ -196,7 +315,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
-                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2);
+                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8);
             // ---- noise slots before this event ----
             const uint32_t nend = E.noise_end;
             while (true) {
@@ -292,54 +411,33 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 }
                 tot.events++;
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
-                const R ar = sizeof(R) == 4 ? (R)E.Afr : (R)E.Are, ai = sizeof(R) == 4 ? (R)E.Afi : (R)E.Aim;
-                const R br = sizeof(R) == 4 ? (R)E.Bfr : (R)E.Bre, bi = sizeof(R) == 4 ? (R)E.Bfi : (R)E.Bim;
-                const C z = mk<C>(0.0, 0.0);
+                const R cs = sizeof(R) == 4 ? (R)E.Afr : (R)E.Are;
+                const R sn = sizeof(R) == 4 ? (R)E.Bfr : (R)E.Bre;
                 const uint32_t sig = sc ^ ga;
-                const double thr2 = tau2 * nrm2;
-                double nn = 0.0;
-                uint32_t cnt = 0;
+                // T is unitary: the carried norm stays, and it sets the pruning level
+                const R thr = (R)(tau2 * nrm2);
+                const uint32_t qb = E.qb;
+                uint32_t cnt;
                 if (kind == EV_T_DOUBLE) {
-                    const uint32_t half = 1u << k;
-                    for (uint32_t j = lane; j < half; j += 64u) {
-                        const C v0 = v[j];
-                        const bool neg = (sig ^ par32(g & j)) != 0u;
-                        C o0 = cmad2<R, C>(v0, ar, ai, z, (R)0, (R)0, false);
-                        C o1 = cmad2<R, C>(z, (R)0, (R)0, v0, br, bi, neg);
-                        const double n0 = nrm<R>(o0), n1 = nrm<R>(o1);
-                        const bool k0 = n0 >= thr2, k1 = n1 >= thr2;
-                        if (!k0) o0 = z;
-                        if (!k1) o1 = z;
-                        nn += (k0 ? n0 : 0.0) + (k1 ? n1 : 0.0);
-                        cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
-                        v[j] = o0;
-                        v[j + half] = o1;
+                    switch (qb) {
+                        case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
+                        case 1: cnt = t_double<1, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
+                        case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
+                        default: cnt = t_double<3, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
                     }
-                    tot.entries_t += 2u * half;
+                    tot.entries_t += 2u << k;
                     ++k;
                 } else {
-                    const uint32_t npairs = 1u << (k - 1u);
                     const uint32_t mu = E.mu, h = E.tstar;
-                    const uint32_t gmu = par32(g & mu);
-                    for (uint32_t p = lane; p < npairs; p += 64u) {
-                        const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
-                        const C v0 = v[j0], v1 = v[j1];
-                        const uint32_t s1 = sig ^ par32(g & j0);
-                        const uint32_t s0 = s1 ^ gmu;
-                        C o0 = cmad2<R, C>(v0, ar, ai, v1, br, bi, s0 != 0u);
-                        C o1 = cmad2<R, C>(v1, ar, ai, v0, br, bi, s1 != 0u);
-                        const double n0 = nrm<R>(o0), n1 = nrm<R>(o1);
-                        const bool k0 = n0 >= thr2, k1 = n1 >= thr2;
-                        if (!k0) o0 = z;
-                        if (!k1) o1 = z;
-                        nn += (k0 ? n0 : 0.0) + (k1 ? n1 : 0.0);
-                        cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
-                        v[j0] = o0;
-                        v[j1] = o1;
+                    switch (qb) {
+                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
+                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
+                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
+                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
                     }
-                    tot.entries_t += 2u * npairs;
+                    tot.entries_t += 1u << k;
                 }
-                nrm2 = wave_sum(nn);
+                phase8 = (phase8 + ((E.flags & EVF_TDG) ? 15u : 1u)) & 15u;
                 cnt = uni(cnt);
                 maxsup = max(maxsup, cnt);
                 tot.events++;
@@ -352,17 +450,27 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 }
             } else if (kind <= EV_M_MERGE) {
                 // ---- measurement ----
-                uint32_t mw;
-                if (EXPL) {
-                    mw = wrow[P.n_noise + E.mslot];
-                } else {
-                    uint32_t o0, o1, o2, o3;
-                    philox10(E.mslot >> 2, s_lo, s_hi, 1u, key0, key1, o0, o1, o2, o3);
-                    const uint32_t q = E.mslot & 3u;
-                    mw = q == 0u ? o0 : q == 1u ? o1 : q == 2u ? o2 : o3;
+                // The uniform is drawn only when the outcome is random.  Philox
+                // words of stream 1 come 256 at a time, one block per lane,
+                // and are picked out with one readlane.
+                double u = 0.0;
+                if (kind != EV_M_DET) {
+                    const uint32_t ms = E.mslot;
+                    uint32_t mw;
+                    if (EXPL) {
+                        mw = wrow[P.n_noise + ms];
+                    } else {
+                        if (ms < m_base || ms - m_base >= 256u) {
+                            m_base = ms & ~255u;
+                            philox10((m_base >> 2) + lane, s_lo, s_hi, 1u, key0, key1, mw0, mw1, mw2, mw3);
+                        }
+                        const uint32_t q = ms & 3u;
+                        const uint32_t pick = q == 0u ? mw0 : q == 1u ? mw1 : q == 2u ? mw2 : mw3;
+                        mw = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)((ms - m_base) >> 2));
+                    }
+                    mw = uni(mw);
+                    u = ((double)mw + 0.5) * (1.0 / 4294967296.0);
                 }
-                mw = uni(mw);
-                const double u = ((double)mw + 0.5) * (1.0 / 4294967296.0);
                 uint32_t bit = 0;
                 tot.events++;
                 if (kind == EV_M_DET) {
@@ -521,21 +629,25 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         for (uint32_t j = lane; j < cnt; j += 64u) nn += nrm<R>(v[j]);
         nn = wave_sum(nn);
         tot.maxdev = fmax(tot.maxdev, fabs(nn - 1.0));
-        if (P.outcomes)
-            for (uint32_t w = lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
-        if (lane == 0) {
-            P.status[i] = status;
-            if (P.abort_op) P.abort_op[i] = abort_src;
-            if (P.obs) P.obs[i] = obs;
+        if (lane == group_pos) {
+            o_status = status;
+            o_abort = abort_src;
+            o_obs = obs;
+#pragma unroll
+            for (uint32_t w = 0; w < kRecRegs; ++w)
+                if (w < P.rec_words) o_rec[w] = rec[w];
         }
+        if (P.outcomes)  // record words beyond the lane-held ones go out directly
+            for (uint32_t w = kRecRegs + lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
+        ++group_pos;
         if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
             const uint64_t kk = shot - P.keep_lo;
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
-                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2);
+                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8);
         }
         if (tracing && term < P.trace_n)
             dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
-                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2);
+                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8);
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);

@@ -64,6 +64,7 @@ struct soft_ctx {
     DevBuf<NoiseLoc> d_nz;
     DevBuf<uint32_t> d_tm1, d_det;
     unsigned long long *d_counters = nullptr;  // C_COUNT + 1 (work cursor)
+    double *d_phase = nullptr;                 // cos/sin of k pi/8, k = 0..15
 
     uint64_t keep_lo = 0;
     uint32_t keep_n = 0;
@@ -173,7 +174,7 @@ Shape default_shape(const soft_ctx *c) {
     s.wpb = (waves_cu >= 16u && 2u * wb <= (uint32_t)c->max_lds_block) ? 2u : 1u;
     while (s.wpb > 1 && s.wpb * wb > (uint32_t)c->max_lds_block) s.wpb /= 2;
     s.bpc = std::max<uint32_t>(1u, waves_cu / s.wpb);
-    s.grab = 1;
+    s.grab = 16;
     return s;
 }
 
@@ -193,7 +194,7 @@ int check_shape(soft_ctx *c, const Shape &s) {
     if (lds > (uint64_t)c->max_lds_block)
         return fail(c, SOFT_ECAPACITY, "coefficient tile needs " + std::to_string(lds) + " bytes of LDS per block; the device allows " +
                                            std::to_string(c->max_lds_block) + " (span dimension " + std::to_string(c->prog.kmax) + ")");
-    if (s.bpc < 1 || s.grab < 1) return fail(c, SOFT_EINVAL, "blocks_per_cu and grab must be >= 1");
+    if (s.bpc < 1 || s.grab < 1 || s.grab > 64) return fail(c, SOFT_EINVAL, "blocks_per_cu must be >= 1 and grab in 1..64");
     return SOFT_OK;
 }
 
@@ -242,6 +243,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.tm1 = c->d_tm1.p;
     rp.det = c->d_det.p;
     rp.words = c->words_dev;
+    rp.phase_tab = c->d_phase;
     rp.word_stride = (uint64_t)c->prog.n_noise + c->prog.n_meas;
     rp.outcomes = outcomes;
     rp.status = status;
@@ -415,6 +417,15 @@ int soft_create(soft_ctx **out, int hip_device) {
         return bad(e, "hipMalloc");
     if ((e = hipMemset(c->d_counters, 0, (C_COUNT + 1) * sizeof(unsigned long long))) != hipSuccess) return bad(e, "hipMemset");
     if ((e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess) return bad(e, "hipStreamCreate");
+    {
+        double tab[32];
+        for (int q = 0; q < 16; ++q) {
+            tab[q] = std::cos(M_PI * q / 8.0);
+            tab[16 + q] = std::sin(M_PI * q / 8.0);
+        }
+        if ((e = hipMalloc((void **)&c->d_phase, sizeof(tab))) != hipSuccess) return bad(e, "hipMalloc");
+        if ((e = hipMemcpy(c->d_phase, tab, sizeof(tab), hipMemcpyHostToDevice)) != hipSuccess) return bad(e, "hipMemcpy");
+    }
     *out = c;
     return SOFT_OK;
 }
@@ -433,6 +444,7 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_trace_meta);
     release(c->d_trace_v);
     if (c->d_counters) (void)hipFree(c->d_counters);
+    if (c->d_phase) (void)hipFree(c->d_phase);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
 }
@@ -513,7 +525,7 @@ int soft_set_caps(soft_ctx *c, uint32_t support_cap, uint32_t wpb, uint32_t bpc,
     if (!c) return SOFT_EINVAL;
     if (wpb > 4) return fail(c, SOFT_EINVAL, "waves_per_block must be <= 4");
     if (bpc > kMaxWavesPerCu) return fail(c, SOFT_EINVAL, "blocks_per_cu must be <= 32");
-    if (grab > 4096) return fail(c, SOFT_EINVAL, "grab must be <= 4096");
+    if (grab > 64) return fail(c, SOFT_EINVAL, "grab must be <= 64");
     c->support_cap = support_cap;
     c->user.wpb = wpb;
     c->user.bpc = bpc;
@@ -682,7 +694,7 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     Shape best;
     float best_ms = 1e30f;
     const uint32_t wpbs[3] = {1, 2, 4};
-    const uint32_t grabs[2] = {1, 4};
+    const uint32_t grabs[2] = {16, 64};
     for (uint32_t wpb : wpbs) {
         if (wpb * wb > (uint32_t)c->max_lds_block) continue;
         const uint32_t occ = std::min<uint32_t>(std::max<uint32_t>(1u, kLdsPerCu / (wpb * wb)), kMaxWavesPerCu / wpb);
