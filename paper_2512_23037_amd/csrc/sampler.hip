@@ -149,8 +149,22 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
     }
 }
 
+constexpr uint32_t kNoHit = 0xFFFFFFFFu;
+
+// Lowest slot with a pending noise hit in the chunk based at cb (lane l holds
+// slots cb + 4l .. cb + 4l + 3 as bits of `hits`), or kNoHit.
+__device__ __forceinline__ uint32_t first_hit(uint32_t hits, uint32_t cb) {
+    const uint64_t lanes = __ballot(hits != 0u);
+    if (lanes == 0ull) return kNoHit;
+    const uint32_t L = (uint32_t)__builtin_ctzll(lanes);
+    const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)hits, (int)L);
+    return cb + 4u * L + (uint32_t)__builtin_ctz(m);
+}
+
 // Record words per shot held in lanes until the group is written.
 constexpr uint32_t kRecRegs = 8;
+// Record words kept in scalar registers during a shot.
+constexpr uint32_t kRecSgpr = 4;
 
 // Write the outputs of shots [base, base + len) held by lanes 0..len-1.
 __device__ __forceinline__ void flush_group(const RunParams &P, uint64_t base, uint32_t len, uint32_t lane,
@@ -295,7 +309,19 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         const uint32_t *wrow = EXPL ? words + i * P.word_stride : nullptr;
 
         // ---- shot start: d_i = +X_i, s_i = +Z_i, v = {0: 1} ----
-        for (uint32_t w = lane; w < P.rec_words; w += 64) rec[w] = 0u;
+        for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64) rec[w] = 0u;
+        // record words 0..3 live in scalar registers, the rest in LDS
+        uint32_t rr0 = 0, rr1 = 0, rr2 = 0, rr3 = 0;
+        auto rec_read = [&](uint32_t w) -> uint32_t {
+            return w == 0u ? rr0 : w == 1u ? rr1 : w == 2u ? rr2 : w == 3u ? rr3 : rec[w];
+        };
+        auto rec_toggle = [&](uint32_t w, uint32_t m) {
+            if (w == 0u) rr0 ^= m;
+            else if (w == 1u) rr1 ^= m;
+            else if (w == 2u) rr2 ^= m;
+            else if (w == 3u) rr3 ^= m;
+            else if (lane == 0) rec[w] ^= m;
+        };
         if (lane == 0) v[0] = mk<C>(1.0, 0.0);
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
@@ -304,7 +330,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         uint32_t status = ST_PASSED, abort_src = 0xFFFFFFFFu, obs = 0, maxsup = 1;
         uint32_t term = 0, after = 0;
         // noise: 256 slots per chunk, 4 consecutive slots (one Philox block) per lane
-        uint32_t nz_next = 0, nz_cb = 0, nz_have = 0;
+        uint32_t nz_cb = 0, nz_drawn = 0, next_hit = kNoHit;
         uint32_t hits = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
         // measurement words: slots [m_base, m_base + 256), one Philox block per lane
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
@@ -317,57 +343,43 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
                            abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8);
             // ---- noise slots before this event ----
+            // Hits are rare: `next_hit` is the lowest pending hit of the drawn
+            // chunk, so an event with none before it costs two compares.
             const uint32_t nend = E.noise_end;
             while (true) {
-                if (nz_have) {
-                    const uint32_t lb = nz_cb + 4u * lane;
-                    const uint32_t allow = nend > lb ? (nend - lb >= 4u ? 0xFu : ((1u << (nend - lb)) - 1u)) : 0u;
-                    const uint32_t todo = hits & allow;
-                    hits &= ~allow;
-                    uint64_t lanes = __ballot(todo != 0u);
-                    while (lanes) {
-                        const uint32_t L = (uint32_t)__builtin_ctzll(lanes);
-                        lanes &= lanes - 1;
-                        uint32_t t = __builtin_amdgcn_readlane(todo, L);
-                        const uint32_t ws[4] = {(uint32_t)__builtin_amdgcn_readlane(w0, L),
-                                                (uint32_t)__builtin_amdgcn_readlane(w1, L),
-                                                (uint32_t)__builtin_amdgcn_readlane(w2, L),
-                                                (uint32_t)__builtin_amdgcn_readlane(w3, L)};
-                        while (t) {
-                            const uint32_t b = (uint32_t)__builtin_ctz(t);
-                            t &= t - 1u;
-                            const NoiseLoc &NL = nz[nz_cb + 4u * L + b];
-                            const uint32_t kind = NL.kind;
-                            const uint64_t wv = ws[b];
-                            if (kind == NZ_DEP1 || kind == NZ_DEP2 || kind == NZ_XERR) {
-                                uint32_t ca, cb = 0;
-                                if (kind == NZ_DEP1) {
-                                    ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
-                                } else if (kind == NZ_DEP2) {
-                                    const uint32_t code = (uint32_t)((15ull * wv) / NL.thr) + 1u;
-                                    ca = code >> 2;
-                                    cb = code & 3u;
-                                } else {
-                                    ca = 1u;
-                                }
-                                // Pauli codes: 1 = X, 2 = Y, 3 = Z
-                                if (ca == 1u || ca == 2u) { rD ^= NL.masks[0]; rS ^= NL.masks[1]; }
-                                if (ca == 3u || ca == 2u) { rD ^= NL.masks[2]; rS ^= NL.masks[3]; }
-                                if (cb == 1u || cb == 2u) { rD ^= NL.masks[4]; rS ^= NL.masks[5]; }
-                                if (cb == 3u || cb == 2u) { rD ^= NL.masks[6]; rS ^= NL.masks[7]; }
-                            } else if (kind == NZ_FLIP) {
-                                const uint32_t r = NL.rec;
-                                if (lane == 0) rec[r >> 5] ^= 1u << (r & 31u);
-                            }
+                while (next_hit < nend) {
+                    const uint32_t L = (next_hit - nz_cb) >> 2, b = next_hit & 3u;
+                    const uint32_t pick = b == 0u ? w0 : b == 1u ? w1 : b == 2u ? w2 : w3;
+                    const uint64_t wv = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)L);
+                    const NoiseLoc &NL = nz[next_hit];
+                    const uint32_t nkind = NL.kind;
+                    if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR) {
+                        uint32_t ca, cb = 0;
+                        if (nkind == NZ_DEP1) {
+                            ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
+                        } else if (nkind == NZ_DEP2) {
+                            const uint32_t code = (uint32_t)((15ull * wv) / NL.thr) + 1u;
+                            ca = code >> 2;
+                            cb = code & 3u;
+                        } else {
+                            ca = 1u;
                         }
+                        // Pauli codes: 1 = X, 2 = Y, 3 = Z
+                        if (ca == 1u || ca == 2u) { rD ^= NL.masks[0]; rS ^= NL.masks[1]; }
+                        if (ca == 3u || ca == 2u) { rD ^= NL.masks[2]; rS ^= NL.masks[3]; }
+                        if (cb == 1u || cb == 2u) { rD ^= NL.masks[4]; rS ^= NL.masks[5]; }
+                        if (cb == 3u || cb == 2u) { rD ^= NL.masks[6]; rS ^= NL.masks[7]; }
+                    } else if (nkind == NZ_FLIP) {
+                        const uint32_t r = NL.rec;
+                        rec_toggle(r >> 5, 1u << (r & 31u));
                     }
-                    if (nend <= nz_cb + 256u) break;
-                    nz_have = 0;
+                    if (lane == L) hits &= ~(1u << b);
+                    next_hit = first_hit(hits, nz_cb);
                 }
-                if (nz_next >= nend) break;
-                nz_cb = nz_next;
-                nz_next += 256u;
-                nz_have = 1;
+                if (nend <= nz_drawn || nz_drawn >= P.n_noise) break;
+                // draw the next 256 slots: one Philox block of 4 words per lane
+                nz_cb = nz_drawn;
+                nz_drawn += 256u;
                 const uint32_t s0 = nz_cb + 4u * lane;
                 if (EXPL) {
                     w0 = s0 + 0u < P.n_noise ? wrow[s0 + 0u] : 0u;
@@ -380,6 +392,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 const uint4 th = *reinterpret_cast<const uint4 *>(tm1 + s0);
                 hits = (s0 + 0u < P.n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < P.n_noise && w1 <= th.y ? 2u : 0u) |
                        (s0 + 2u < P.n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < P.n_noise && w3 <= th.w ? 8u : 0u);
+                next_hit = first_hit(hits, nz_cb);
                 tot.noise += min(256u, P.n_noise - nz_cb);
             }
             // ---- Cliffords since the previous event: one XOR ----
@@ -597,7 +610,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     rS = (rS & ~(1ull << p)) | ((uint64_t)(bit ^ E.psign) << p);
                     if ((a >> p) & 1ull) a ^= E.beta;
                 }
-                if ((E.flags & EVF_RECORD) && bit && lane == 0) rec[E.rec >> 5] |= 1u << (E.rec & 31u);
+                if ((E.flags & EVF_RECORD) && bit) rec_toggle(E.rec >> 5, 1u << (E.rec & 31u));
                 if ((E.flags & EVF_RESET) && bit) {
                     rD ^= E.xD;
                     rS ^= E.xS;
@@ -607,7 +620,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 uint32_t pbits = E.expect;
                 for (uint32_t t = 0; t < E.det_cnt; ++t) {
                     const uint32_t w = det[2u * (E.det_off + t)], m = det[2u * (E.det_off + t) + 1u];
-                    pbits ^= par32(rec[w] & m);
+                    pbits ^= par32(rec_read(w) & m);
                 }
                 pbits = uni(pbits);
                 if (kind == EV_DETECTOR) {
@@ -635,7 +648,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             o_obs = obs;
 #pragma unroll
             for (uint32_t w = 0; w < kRecRegs; ++w)
-                if (w < P.rec_words) o_rec[w] = rec[w];
+                if (w < P.rec_words) o_rec[w] = rec_read(w);
         }
         if (P.outcomes)  // record words beyond the lane-held ones go out directly
             for (uint32_t w = kRecRegs + lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];

@@ -193,3 +193,33 @@ def test_autotune_keeps_results():
     tuned = run_gpu(ctx, 0, 20000)
     for key in ("status", "abort_op", "obs", "outcomes"):
         assert (base[key] == tuned[key]).all()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_trace_matches_oracle_step_by_step(seed):
+    # The paper's step-by-step cross-check (Sec. V-B): after every event the
+    # GPU tableau and coefficient vector equal the oracle's for the same prefix.
+    n = 2 + seed % 5
+    text, _ = random_circuit(41000 + seed, n, 70)
+    lines = text.strip().split("\n")
+    circ = oracle.Circuit(text)
+    words = random_words(seed, circ.words_per_shot)
+    ctx = make_ctx(text)
+    ctx.set_trace(0, ctx.info()["events"])
+    run_gpu(ctx, 0, 1, words.reshape(1, -1))
+    steps = 0
+    for step in range(ctx.info()["events"]):
+        t = ctx.read_trace(step)
+        if t is None:
+            break
+        prefix = "\n".join(lines[: t["op"] + 2]) + "\n"
+        pc = oracle.Circuit(prefix)
+        r = pc.shot(0, 0, words=words[: pc.words_per_shot])
+        if t["final"] and r.status != oracle.PASSED:
+            assert t["status"] == r.status
+        assert (t["x"] == r.tab_x).all() and (t["z"] == r.tab_z).all() and (t["r"] == r.tab_r).all(), step
+        keys = set(t["coeffs"]) | set(r.coeffs)
+        err = max([abs(t["coeffs"].get(a, 0) - r.coeffs.get(a, 0)) for a in keys] + [0.0])
+        assert err < 1e-10, (step, lines[t["op"] + 1], err)
+        steps += 1
+    assert steps >= 5
