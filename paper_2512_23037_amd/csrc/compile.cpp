@@ -254,10 +254,6 @@ class FrameCompiler {
     }
 
     void parity_check(bool detector, int expect, const std::vector<int> &recs, uint32_t obs, uint32_t src) {
-        Event E = begin(src);
-        E.kind = detector ? EV_DETECTOR : EV_OBSERVABLE;
-        E.expect = (uint32_t)expect;
-        E.rec = obs;
         // fold the record list into (word, mask) pairs; repeats cancel
         std::vector<uint32_t> words, masks;
         for (int r : recs) {
@@ -267,10 +263,36 @@ class FrameCompiler {
             if (i == words.size()) { words.push_back(w); masks.push_back(0); }
             masks[i] ^= m;
         }
-        E.det_off = (uint32_t)(P_.det_pairs.size() / 2);
+        const uint32_t off = (uint32_t)(P_.det_pairs.size() / 2);
         for (size_t i = 0; i < words.size(); ++i)
             if (masks[i]) { P_.det_pairs.push_back(words[i]); P_.det_pairs.push_back(masks[i]); }
-        E.det_cnt = (uint32_t)(P_.det_pairs.size() / 2) - E.det_off;
+        const uint32_t cnt = (uint32_t)(P_.det_pairs.size() / 2) - off;
+        auto fill = [&](Event &E) {
+            E.expect = (uint32_t)expect;
+            E.det_off = off;
+            E.det_cnt = cnt;
+            if (cnt) {
+                E.dw0 = P_.det_pairs[2 * off];
+                E.dm0 = P_.det_pairs[2 * off + 1];
+            }
+        };
+        // A detector right after a measurement, with no noise and no Clifford
+        // in between, becomes a check inside that measurement's event.
+        if (detector && !P_.events.empty()) {
+            Event &last = P_.events.back();
+            const bool meas = last.kind >= EV_M_DET && last.kind <= EV_M_MERGE;
+            if (meas && !(last.flags & EVF_CHECK) && P_.noise.size() == noise_at_finish_ && acc_.d == 0 &&
+                acc_.s == 0) {
+                last.flags |= EVF_CHECK;
+                last.chk_src = src;
+                fill(last);
+                return;
+            }
+        }
+        Event E = begin(src);
+        E.kind = detector ? EV_DETECTOR : EV_OBSERVABLE;
+        E.rec = obs;
+        fill(E);
         finish(E);
     }
 
@@ -278,6 +300,11 @@ class FrameCompiler {
         Event E = begin(src);
         E.kind = EV_END;
         finish(E);
+        // one more END so that the kernel may always load event e + 1
+        Event pad = E;
+        P_.events.push_back(pad);
+        P_.before.push_back(P_.before.back());
+        P_.after.push_back(P_.after.back());
     }
 
   private:
@@ -286,6 +313,7 @@ class FrameCompiler {
     std::vector<RowMask> cx_, cz_;
     RowMask acc_;
     std::vector<uint64_t> basis_;
+    size_t noise_at_finish_ = 0;  // noise slots when the last event was finished
 
     PauliStr row_d(int i) const {
         PauliStr r;
@@ -387,6 +415,7 @@ class FrameCompiler {
     void finish(const Event &E) {
         P_.events.push_back(E);
         P_.after.push_back(snapshot());
+        noise_at_finish_ = P_.noise.size();
     }
 };
 

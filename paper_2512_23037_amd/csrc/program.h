@@ -48,32 +48,37 @@ enum EvFlags : uint32_t {
     EVF_TDG = 1u,      // T-dagger (s = -1)
     EVF_RECORD = 2u,   // store the outcome in the measurement record
     EVF_RESET = 4u,    // reset: apply X_q (masks xD/xS) when the outcome is 1
+    EVF_CHECK = 8u,    // a detector that directly follows this measurement
 };
 
-// One event, 256 bytes, read by every wave with uniform (scalar) loads.
+// One event: 64 dwords, which one wavefront loads with one dword per lane
+// and reads field by field with readlane.  The first 16 dwords are used by
+// every kind.
 struct alignas(16) Event {
     uint32_t kind;
-    uint32_t src;        // index of the circuit op this event came from
-    uint32_t noise_end;  // noise slots [.., noise_end) precede this event
-    uint32_t k;          // span dimension before the event
     uint32_t flags;
-    uint32_t mslot;      // measurement slot (M, MPP, R)
-    uint32_t rec;        // record index (recorded measurements) / observable index
-    uint32_t g;          // bit t = parity(gamma & b_t)
-    uint32_t mu;         // coordinates of beta in the span (BFLY, MERGE)
-    uint32_t pm;         // bit t = bit p of b_t (SPLIT, MERGE)
-    uint32_t tstar;      // coordinate removed (CUT, MERGE) / top bit of mu (BFLY)
-    uint32_t cexp;       // c = i^cexp * (-1)^(parity(rD&beta) ^ parity(rS&gamma))
-    uint32_t pbit;       // pivot p (SPLIT, MERGE)
-    uint32_t gbeta;      // parity(gamma & beta)
-    uint32_t det_off;    // DETECTOR/OBSERVABLE: first (word, mask) pair
-    uint32_t det_cnt;    //   and number of pairs
-    uint32_t expect;     //   expected parity
-    uint32_t psign;      // sign bit of the measured Pauli (0 for parsed ops)
-    uint32_t qb;         // branching T: quarter turns of B' = sin(pi/8) i^qb
-    uint32_t pad0;
+    uint32_t noise_end;  // noise slots [.., noise_end) precede this event
+    uint32_t src;        // index of the circuit op this event came from
     uint64_t cliffD, cliffS;  // sign flips of the Cliffords since the last event
     uint64_t beta, gamma;     // index shift / anticommuting destabilizers
+    uint32_t k;          // span dimension before the event
+    uint32_t g;          // bit t = parity(gamma & b_t)
+    uint32_t cexp;       // c = i^cexp * (-1)^(parity(rD&beta) ^ parity(rS&gamma))
+    uint32_t qb;         // branching T: quarter turns of the partner weight i^qb
+    uint32_t mu;         // coordinates of beta in the span (BFLY, MERGE)
+    uint32_t tstar;      // coordinate removed (CUT, MERGE) / top bit of mu (BFLY)
+    uint32_t pm;         // bit t = bit p of b_t (SPLIT, MERGE)
+    uint32_t pbit;       // pivot p (SPLIT, MERGE)
+    uint32_t mslot;      // measurement slot (M, MPP, R)
+    uint32_t rec;        // record index (recorded measurements) / observable index
+    uint32_t gbeta;      // parity(gamma & beta)
+    uint32_t psign;      // sign bit of the measured Pauli (0 for parsed ops)
+    uint32_t expect;     // DETECTOR/OBSERVABLE/check: expected parity
+    uint32_t det_off;    //   first (word, mask) pair in the pair table
+    uint32_t det_cnt;    //   number of pairs
+    uint32_t chk_src;    //   op index of a folded detector
+    uint32_t dw0, dm0;   //   the first pair, inline
+    uint32_t pad0[2];
     uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products
@@ -81,7 +86,7 @@ struct alignas(16) Event {
     double Are, Aim;          // T_PHASE: e^{i s pi/4}; branching T: cos(pi/8), 0
     double Bre, Bim;          // branching T: sin(pi/8), 0 (the weight of the partner term)
     float Afr, Afi, Bfr, Bfi; // the same in single precision
-    uint32_t pad1[10];
+    uint32_t pad1[6];
 };
 static_assert(sizeof(Event) == 256, "event layout");
 

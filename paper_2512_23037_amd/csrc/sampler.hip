@@ -268,12 +268,21 @@ struct WaveTotals {
     double maxdev = 0.0;
 };
 
+// Fields of the current event (held one dword per lane in `evc`).
+#define EV32(f) ((uint32_t)__builtin_amdgcn_readlane((int)evc, (int)(offsetof(Event, f) / 4u)))
+#define EV64(f)                                                                                  \
+    (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evc, (int)(offsetof(Event, f) / 4u + 1u)) << 32) | \
+     (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evc, (int)(offsetof(Event, f) / 4u)))
+#define EVF(f) __uint_as_float(EV32(f))
+#define EVD(f) __longlong_as_double((long long)EV64(f))
+
 template <typename R, bool EXPL>
 __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
                                                 const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
                                                 const uint32_t *__restrict__ words, RunParams P) {
     typedef typename Cx<R>::T C;
     extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t *ev32 = reinterpret_cast<const uint32_t *>(ev);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
     C *v = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
@@ -322,6 +331,21 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             else if (w == 3u) rr3 ^= m;
             else if (lane == 0) rec[w] ^= m;
         };
+        // expect ^ XOR of the listed record bits for the current event (the
+        // first (word, mask) pair is inline, the rest come from the pair table)
+        uint32_t evc;
+        auto parity_check = [&]() -> uint32_t {
+            uint32_t pbits = EV32(expect);
+            const uint32_t cnt_pairs = EV32(det_cnt);
+            if (cnt_pairs) {
+                pbits ^= par32(rec_read(EV32(dw0)) & EV32(dm0));
+                for (uint32_t t = 1; t < cnt_pairs; ++t) {
+                    const uint32_t w = det[2u * (EV32(det_off) + t)], m = det[2u * (EV32(det_off) + t) + 1u];
+                    pbits ^= par32(rec_read(w) & m);
+                }
+            }
+            return uni(pbits);
+        };
         if (lane == 0) v[0] = mk<C>(1.0, 0.0);
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
@@ -336,8 +360,11 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
         const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
+        // Event e sits in evc, one dword per lane; event e + 1 is loaded while
+        // event e runs (the list ends with two END events).
+        evc = ev32[lane];
         for (uint32_t e = 0;; ++e) {
-            const Event &E = ev[e];
+            const uint32_t evx = ev32[(uint64_t)(e + 1u) * 64u + lane];
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
@@ -345,7 +372,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
-            const uint32_t nend = E.noise_end;
+            const uint32_t nend = EV32(noise_end);
             while (true) {
                 while (next_hit < nend) {
                     const uint32_t L = (next_hit - nz_cb) >> 2, b = next_hit & 3u;
@@ -396,20 +423,20 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 tot.noise += min(256u, P.n_noise - nz_cb);
             }
             // ---- Cliffords since the previous event: one XOR ----
-            rD ^= E.cliffD;
-            rS ^= E.cliffS;
-            const uint32_t kind = E.kind;
+            rD ^= EV64(cliffD);
+            rS ^= EV64(cliffS);
+            const uint32_t kind = EV32(kind);
             if (kind == EV_END) {
                 term = e;
                 break;
             }
-            const uint32_t sc = par64(rD & E.beta) ^ par64(rS & E.gamma);  // sign part of c
-            const uint32_t ga = par64(E.gamma & a);                          // gamma . a
-            const uint32_t g = E.g;
+            const uint32_t sc = par64(rD & EV64(beta)) ^ par64(rS & EV64(gamma));  // sign part of c
+            const uint32_t ga = par64(EV64(gamma) & a);                          // gamma . a
+            const uint32_t g = EV32(g);
             if (kind == EV_T_PHASE) {
                 // lambda_j = (-1)^(sig ^ parity(g & j)); lambda = -1 picks up e^{i s pi/4}
-                const uint32_t sig = (E.cexp == 2u ? 1u : 0u) ^ sc ^ ga;
-                const R fr = (R)E.Are, fi = (R)E.Aim;
+                const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
+                const R fr = (R)EVD(Are), fi = (R)EVD(Aim);
                 const uint32_t cnt = 1u << k;
                 if (g != 0u || sig) {
                     for (uint32_t j = lane; j < cnt; j += 64u) {
@@ -424,12 +451,12 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 }
                 tot.events++;
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
-                const R cs = sizeof(R) == 4 ? (R)E.Afr : (R)E.Are;
-                const R sn = sizeof(R) == 4 ? (R)E.Bfr : (R)E.Bre;
+                const R cs = sizeof(R) == 4 ? (R)EVF(Afr) : (R)EVD(Are);
+                const R sn = sizeof(R) == 4 ? (R)EVF(Bfr) : (R)EVD(Bre);
                 const uint32_t sig = sc ^ ga;
                 // T is unitary: the carried norm stays, and it sets the pruning level
                 const R thr = (R)(tau2 * nrm2);
-                const uint32_t qb = E.qb;
+                const uint32_t qb = EV32(qb);
                 uint32_t cnt;
                 if (kind == EV_T_DOUBLE) {
                     switch (qb) {
@@ -441,7 +468,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     tot.entries_t += 2u << k;
                     ++k;
                 } else {
-                    const uint32_t mu = E.mu, h = E.tstar;
+                    const uint32_t mu = EV32(mu), h = EV32(tstar);
                     switch (qb) {
                         case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
                         case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
@@ -450,13 +477,13 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     }
                     tot.entries_t += 1u << k;
                 }
-                phase8 = (phase8 + ((E.flags & EVF_TDG) ? 15u : 1u)) & 15u;
+                phase8 = (phase8 + ((EV32(flags) & EVF_TDG) ? 15u : 1u)) & 15u;
                 cnt = uni(cnt);
                 maxsup = max(maxsup, cnt);
                 tot.events++;
                 if (cnt > P.support_cap) {
                     status = ST_OVERFLOW;
-                    abort_src = E.src;
+                    abort_src = EV32(src);
                     term = e;
                     after = 1;
                     break;
@@ -468,7 +495,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 // and are picked out with one readlane.
                 double u = 0.0;
                 if (kind != EV_M_DET) {
-                    const uint32_t ms = E.mslot;
+                    const uint32_t ms = EV32(mslot);
                     uint32_t mw;
                     if (EXPL) {
                         mw = wrow[P.n_noise + ms];
@@ -487,9 +514,9 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 uint32_t bit = 0;
                 tot.events++;
                 if (kind == EV_M_DET) {
-                    bit = (E.cexp == 2u ? 1u : 0u) ^ sc ^ ga;
+                    bit = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
                 } else if (kind == EV_M_CUT) {
-                    const uint32_t sig = (E.cexp == 2u ? 1u : 0u) ^ sc ^ ga;
+                    const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
                     const uint32_t cnt = 1u << k;
                     double n0 = 0.0, n1 = 0.0;
                     for (uint32_t j = lane; j < cnt; j += 64u) {
@@ -507,12 +534,12 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     tot.entries_m += cnt;
                     if (!(Ns > 1e-300)) {
                         status = ST_NUMERIC;
-                        abort_src = E.src;
+                        abort_src = EV32(src);
                         term = e;
                         break;
                     }
                     const R s = (R)(1.0 / sqrt(Ns));
-                    const uint32_t ts = E.tstar, half = cnt >> 1;
+                    const uint32_t ts = EV32(tstar), half = cnt >> 1;
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
                     for (uint32_t jp = lane; jp < half; jp += 64u) {
@@ -527,13 +554,13 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     }
                     nrm2 = wave_sum(nn);
                     --k;
-                    if (bsel) a ^= E.avec;
+                    if (bsel) a ^= EV64(avec);
                 } else if (kind == EV_M_SPLIT) {
                     bit = u < 0.5 ? 0u : 1u;
-                    const uint32_t ap = (uint32_t)(a >> E.pbit) & 1u;
-                    const uint32_t fs = bit ^ sc ^ ga ^ E.gbeta;
-                    const uint32_t q0 = (4u - E.cexp) & 3u;
-                    const uint32_t cnt = 1u << k, pm = E.pm;
+                    const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
+                    const uint32_t fs = bit ^ sc ^ ga ^ EV32(gbeta);
+                    const uint32_t q0 = (4u - EV32(cexp)) & 3u;
+                    const uint32_t cnt = 1u << k, pm = EV32(pm);
                     const R s = (R)(1.0 / sqrt(nrm2));
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
@@ -550,9 +577,9 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     nrm2 = wave_sum(nn);
                     tot.entries_m += cnt;
                 } else {  // EV_M_MERGE
-                    const uint32_t ap = (uint32_t)(a >> E.pbit) & 1u;
-                    const uint32_t q0 = (4u - E.cexp) & 3u;
-                    const uint32_t npairs = 1u << (k - 1u), mu = E.mu, h = E.tstar, pm = E.pm;
+                    const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
+                    const uint32_t q0 = (4u - EV32(cexp)) & 3u;
+                    const uint32_t npairs = 1u << (k - 1u), mu = EV32(mu), h = EV32(tstar), pm = EV32(pm);
                     const uint32_t fs0 = sc ^ ga;
                     double np = 0.0, nm = 0.0;
                     for (uint32_t p = lane; p < npairs; p += 64u) {
@@ -574,7 +601,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     tot.entries_m += 2u * npairs;
                     if (!(Ns > 1e-300)) {
                         status = ST_NUMERIC;
-                        abort_src = E.src;
+                        abort_src = EV32(src);
                         term = e;
                         break;
                     }
@@ -602,38 +629,43 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 }
                 if (kind == EV_M_SPLIT || kind == EV_M_MERGE) {
                     // rows anticommuting with P absorb s_p; d_p <- s_p; s_p <- (-1)^bit P
-                    const uint32_t p = E.pbit;
+                    const uint32_t p = EV32(pbit);
                     const uint64_t bsp = (rS >> p) & 1ull;
-                    rD ^= (bsp ? E.AD : 0ull) ^ E.PhD;
-                    rS ^= (bsp ? E.AS : 0ull) ^ E.PhS;
+                    rD ^= (bsp ? EV64(AD) : 0ull) ^ EV64(PhD);
+                    rS ^= (bsp ? EV64(AS) : 0ull) ^ EV64(PhS);
                     rD = (rD & ~(1ull << p)) | (bsp << p);
-                    rS = (rS & ~(1ull << p)) | ((uint64_t)(bit ^ E.psign) << p);
-                    if ((a >> p) & 1ull) a ^= E.beta;
+                    rS = (rS & ~(1ull << p)) | ((uint64_t)(bit ^ EV32(psign)) << p);
+                    if ((a >> p) & 1ull) a ^= EV64(beta);
                 }
-                if ((E.flags & EVF_RECORD) && bit) rec_toggle(E.rec >> 5, 1u << (E.rec & 31u));
-                if ((E.flags & EVF_RESET) && bit) {
-                    rD ^= E.xD;
-                    rS ^= E.xS;
+                if ((EV32(flags) & EVF_RECORD) && bit) rec_toggle(EV32(rec) >> 5, 1u << (EV32(rec) & 31u));
+                if ((EV32(flags) & EVF_RESET) && bit) {
+                    rD ^= EV64(xD);
+                    rS ^= EV64(xS);
+                }
+                if (EV32(flags) & EVF_CHECK) {  // a detector folded into this event
+                    if (parity_check()) {
+                        status = ST_DISCARDED;
+                        abort_src = EV32(chk_src);
+                        term = e;
+                        after = 1;
+                        break;
+                    }
                 }
             } else {
                 // ---- DETECTOR / OBSERVABLE ----
-                uint32_t pbits = E.expect;
-                for (uint32_t t = 0; t < E.det_cnt; ++t) {
-                    const uint32_t w = det[2u * (E.det_off + t)], m = det[2u * (E.det_off + t) + 1u];
-                    pbits ^= par32(rec_read(w) & m);
-                }
-                pbits = uni(pbits);
+                const uint32_t pbits = parity_check();
                 if (kind == EV_DETECTOR) {
                     if (pbits) {
                         status = ST_DISCARDED;
-                        abort_src = E.src;
+                        abort_src = EV32(src);
                         term = e;
                         break;
                     }
                 } else {
-                    obs |= pbits << E.rec;
+                    obs |= pbits << EV32(rec);
                 }
             }
+            evc = evx;
         }
 
         // ---- shot end: norm check, outputs, kept states, counters ----

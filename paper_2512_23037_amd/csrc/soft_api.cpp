@@ -634,7 +634,7 @@ int soft_read_trace(soft_ctx *c, uint32_t step, uint64_t info[6], uint64_t *x, u
     if (term >= c->prog.events.size()) return fail(c, SOFT_EDEVICE, "corrupt trace entry");
     const Frame &f = meta[KM_AFTER] ? c->prog.after[term] : c->prog.before[term];
     info[0] = 1;
-    info[1] = c->prog.events[term].src;
+    info[1] = (meta[KM_STATUS] != ST_PASSED && meta[KM_ABORT] != 0xFFFFFFFFull) ? meta[KM_ABORT] : c->prog.events[term].src;
     info[2] = meta[KM_STATUS];
     info[3] = meta[KM_K];
     info[4] = meta[KM_NRM2];
