@@ -420,6 +420,92 @@ class FrameCompiler {
 };
 
 // ---------------------------------------------------------------------------
+// Runs of outcome-fixed measurements evaluated side by side (see BatchMember).
+// ---------------------------------------------------------------------------
+bool batchable(const Event &E) { return E.kind == EV_M_DET && (!(E.flags & EVF_CHECK) || E.det_cnt <= 1); }
+
+void form_batches(Program &P) {
+    const size_t ne = P.events.size();
+    size_t e = 0;
+    while (e < ne) {
+        if (!batchable(P.events[e])) { ++e; continue; }
+        std::vector<BatchMember> run;
+        uint64_t cumD = 0, cumS = 0;
+        int rl0 = -1, rc = 0;
+        uint32_t r0 = 0;
+        for (size_t i = e; i < ne && run.size() < kBatchMax; ++i) {
+            const Event &E = P.events[i];
+            const uint32_t m = (uint32_t)run.size();
+            if (!batchable(E)) break;
+            if (m > 0) {
+                bool ok = true;
+                // no record flips between the previous member and this one
+                for (uint32_t s = P.events[i - 1].noise_end; s < E.noise_end && ok; ++s)
+                    if (P.noise[s].kind == NZ_FLIP) ok = false;
+                // earlier resets must commute with this measurement
+                for (const BatchMember &B : run)
+                    if ((B.info & BM_RESET) && (par64(B.xD & E.beta) ^ par64(B.xS & E.gamma))) ok = false;
+                // recorded members on consecutive lanes with consecutive records
+                if ((E.flags & EVF_RECORD) && rl0 >= 0 && !(rl0 + rc == (int)m && r0 + (uint32_t)rc == E.rec)) ok = false;
+                // a folded check may read its own bit and bits from before the run
+                if ((E.flags & EVF_CHECK) && E.det_cnt == 1 && rl0 >= 0) {
+                    for (uint32_t mk = E.dm0; mk; mk &= mk - 1) {
+                        const uint32_t r = E.dw0 * 32u + (uint32_t)__builtin_ctz(mk);
+                        const bool own = (E.flags & EVF_RECORD) && r == E.rec;
+                        if (!own && r >= r0) ok = false;
+                    }
+                }
+                if (!ok) break;
+                cumD ^= E.cliffD;
+                cumS ^= E.cliffS;
+            }
+            BatchMember B;
+            std::memset(&B, 0, sizeof(B));
+            B.beta = E.beta;
+            B.gamma = E.gamma;
+            B.cumD = cumD;
+            B.cumS = cumS;
+            B.noise_end = E.noise_end;
+            B.info = (E.cexp == 2 ? BM_CSIGN : 0u);
+            if (E.flags & EVF_RECORD) {
+                B.info |= BM_RECORD;
+                if (rl0 < 0) { rl0 = (int)m; r0 = E.rec; }
+                ++rc;
+            }
+            if (E.flags & EVF_RESET) {
+                B.info |= BM_RESET;
+                B.xD = E.xD;
+                B.xS = E.xS;
+            }
+            if (E.flags & EVF_CHECK) {
+                B.info |= BM_CHECK | (E.expect ? BM_EXPECT : 0u);
+                B.chk_src = E.chk_src;
+                if (E.det_cnt == 1) {
+                    B.dw0 = E.dw0;
+                    B.dm0 = E.dm0;
+                    if ((E.flags & EVF_RECORD) && E.dw0 == (E.rec >> 5) && ((E.dm0 >> (E.rec & 31u)) & 1u)) {
+                        B.info |= BM_OWN;
+                        B.dm0 &= ~(1u << (E.rec & 31u));
+                    }
+                }
+            }
+            run.push_back(B);
+        }
+        if (run.size() < 2) { ++e; continue; }
+        for (BatchMember &B : run) {
+            B.r0 = r0;
+            B.rlane = rl0 < 0 ? 0u : ((uint32_t)rl0 | ((uint32_t)rc << 8));
+        }
+        Event &F = P.events[e];
+        F.flags |= EVF_BATCH;
+        F.bcnt = (uint32_t)run.size();
+        F.boff = (uint32_t)P.batch.size();
+        P.batch.insert(P.batch.end(), run.begin(), run.end());
+        e += run.size();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Text front end: one op per line, '#' comments, "QUBITS n" first.
 // ---------------------------------------------------------------------------
 struct Cursor {
@@ -601,6 +687,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
         ++src;
     }
     fc.end(src);
+    form_batches(out);
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
     // pad the threshold table to whole 256-slot chunks

@@ -29,6 +29,7 @@ struct Program {
     std::vector<NoiseLoc> noise;
     std::vector<uint32_t> noise_tm1;  // per slot: thr-1 (hit iff word <= it), padded
     std::vector<uint32_t> det_pairs;  // (record word, mask) pairs
+    std::vector<BatchMember> batch;   // members of side-by-side measurement runs
     std::vector<Frame> before;        // frame when event e starts
     std::vector<Frame> after;         // frame when event e has finished
     uint64_t hash = 0;                // of the text and the noise model

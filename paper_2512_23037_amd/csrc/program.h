@@ -49,6 +49,7 @@ enum EvFlags : uint32_t {
     EVF_RECORD = 2u,   // store the outcome in the measurement record
     EVF_RESET = 4u,    // reset: apply X_q (masks xD/xS) when the outcome is 1
     EVF_CHECK = 8u,    // a detector that directly follows this measurement
+    EVF_BATCH = 16u,   // first of `bcnt` outcome-fixed measurements run side by side
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane
@@ -78,7 +79,8 @@ struct alignas(16) Event {
     uint32_t det_cnt;    //   number of pairs
     uint32_t chk_src;    //   op index of a folded detector
     uint32_t dw0, dm0;   //   the first pair, inline
-    uint32_t pad0[2];
+    uint32_t bcnt;       // EVF_BATCH: number of members (events e .. e + bcnt - 1)
+    uint32_t boff;       //   their first record in the member table
     uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products
@@ -89,6 +91,38 @@ struct alignas(16) Event {
     uint32_t pad1[6];
 };
 static_assert(sizeof(Event) == 256, "event layout");
+
+// A run of consecutive outcome-fixed measurements (EV_M_DET) whose results do
+// not depend on one another is evaluated with one member per lane.  The
+// compiler only forms such a run when
+//  * no reset inside it anticommutes with a later member's measured Pauli,
+//  * each folded detector reads only its own member's record bit and record
+//    bits written before the run (one (word, mask) pair at most),
+//  * the recorded members sit on consecutive lanes with consecutive record
+//    indices, and no record-flip noise falls between the members.
+// Member layout: 20 dwords.
+enum BatchInfo : uint32_t {
+    BM_CSIGN = 1u,    // c = -1 (cexp == 2)
+    BM_RECORD = 2u,
+    BM_RESET = 4u,
+    BM_CHECK = 8u,
+    BM_OWN = 16u,     // the check reads this member's own record bit
+    BM_EXPECT = 32u,  // expected parity of the check
+};
+struct alignas(16) BatchMember {
+    uint64_t beta, gamma;
+    uint64_t cumD, cumS;  // Clifford sign flips from the first member up to this one
+    uint64_t xD, xS;      // reset flip masks (0 without reset)
+    uint32_t noise_end;   // noise slots [.., noise_end) precede this member
+    uint32_t info;        // BatchInfo bits
+    uint32_t dw0, dm0;    // check: record word and mask (own bit removed)
+    uint32_t chk_src;     // op index of the folded detector
+    uint32_t r0;          // first record written by the run
+    uint32_t rlane;       // lane of the first recorded member | (recorded count << 8)
+    uint32_t pad;
+};
+static_assert(sizeof(BatchMember) == 80, "batch member layout");
+constexpr uint32_t kBatchMax = 64;
 
 enum NoiseKind : uint32_t { NZ_NONE = 0, NZ_DEP1, NZ_DEP2, NZ_XERR, NZ_FLIP };
 

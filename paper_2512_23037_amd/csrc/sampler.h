@@ -12,6 +12,7 @@ struct RunParams {
     const NoiseLoc *nz;
     const uint32_t *tm1;      // per noise slot: threshold - 1 (padded to 256)
     const uint32_t *det;      // DETECTOR/OBSERVABLE (word, mask) pairs
+    const BatchMember *bm;    // members of side-by-side measurement runs
     const uint32_t *words;    // explicit uniforms [n_shots][word_stride] or null
     const double *phase_tab;  // cos(k pi/8) for k = 0..15, then sin(k pi/8)
     uint32_t *outcomes;       // [rec_words][n_shots] or null

@@ -44,6 +44,12 @@ __device__ __forceinline__ uint64_t uni64(uint64_t x) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
     return ((uint64_t)hi << 32) | (uint64_t)lo;
 }
+// The 64-bit value held by lane l (l wave-uniform).
+__device__ __forceinline__ uint64_t lane64(uint64_t x, uint32_t l) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)l);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
 __device__ __forceinline__ double unid(double x) { return __longlong_as_double((long long)uni64((uint64_t)__double_as_longlong(x))); }
 
 // Butterfly sum over the 64 lanes; every lane ends with the same bits because
@@ -279,7 +285,8 @@ struct WaveTotals {
 template <typename R, bool EXPL>
 __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
                                                 const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
-                                                const uint32_t *__restrict__ words, RunParams P) {
+                                                const uint32_t *__restrict__ words,
+                                                const BatchMember *__restrict__ bm, RunParams P) {
     typedef typename Cx<R>::T C;
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t *ev32 = reinterpret_cast<const uint32_t *>(ev);
@@ -360,11 +367,65 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
         const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
+
+        // Draw the next 256 noise slots: one Philox block of 4 words per lane.
+        auto draw_chunk = [&]() {
+            nz_cb = nz_drawn;
+            nz_drawn += 256u;
+            const uint32_t s0 = nz_cb + 4u * lane;
+            if (EXPL) {
+                w0 = s0 + 0u < P.n_noise ? wrow[s0 + 0u] : 0u;
+                w1 = s0 + 1u < P.n_noise ? wrow[s0 + 1u] : 0u;
+                w2 = s0 + 2u < P.n_noise ? wrow[s0 + 2u] : 0u;
+                w3 = s0 + 3u < P.n_noise ? wrow[s0 + 3u] : 0u;
+            } else {
+                philox10(s0 >> 2, s_lo, s_hi, 0u, key0, key1, w0, w1, w2, w3);
+            }
+            const uint4 th = *reinterpret_cast<const uint4 *>(tm1 + s0);
+            hits = (s0 + 0u < P.n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < P.n_noise && w1 <= th.y ? 2u : 0u) |
+                   (s0 + 2u < P.n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < P.n_noise && w3 <= th.w ? 8u : 0u);
+            next_hit = first_hit(hits, nz_cb);
+            tot.noise += min(256u, P.n_noise - nz_cb);
+        };
+        // Decode the pending hit at slot next_hit into sign-flip masks (or a
+        // record flip, returned; kNoHit otherwise) and move to the next hit.
+        auto take_hit = [&](uint64_t &dD, uint64_t &dS) -> uint32_t {
+            const uint32_t L = (next_hit - nz_cb) >> 2, b = next_hit & 3u;
+            const uint32_t pick = b == 0u ? w0 : b == 1u ? w1 : b == 2u ? w2 : w3;
+            const uint64_t wv = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)L);
+            const NoiseLoc &NL = nz[next_hit];
+            const uint32_t nkind = NL.kind;
+            uint32_t fr = kNoHit;
+            dD = 0;
+            dS = 0;
+            if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR) {
+                uint32_t ca, cb = 0;
+                if (nkind == NZ_DEP1) {
+                    ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
+                } else if (nkind == NZ_DEP2) {
+                    const uint32_t code = (uint32_t)((15ull * wv) / NL.thr) + 1u;
+                    ca = code >> 2;
+                    cb = code & 3u;
+                } else {
+                    ca = 1u;
+                }
+                // Pauli codes: 1 = X, 2 = Y, 3 = Z
+                if (ca == 1u || ca == 2u) { dD ^= NL.masks[0]; dS ^= NL.masks[1]; }
+                if (ca == 3u || ca == 2u) { dD ^= NL.masks[2]; dS ^= NL.masks[3]; }
+                if (cb == 1u || cb == 2u) { dD ^= NL.masks[4]; dS ^= NL.masks[5]; }
+                if (cb == 3u || cb == 2u) { dD ^= NL.masks[6]; dS ^= NL.masks[7]; }
+            } else if (nkind == NZ_FLIP) {
+                fr = NL.rec;
+            }
+            if (lane == L) hits &= ~(1u << b);
+            next_hit = first_hit(hits, nz_cb);
+            return fr;
+        };
         // Event e sits in evc, one dword per lane; event e + 1 is loaded while
         // event e runs (the list ends with two END events).
         evc = ev32[lane];
         for (uint32_t e = 0;; ++e) {
-            const uint32_t evx = ev32[(uint64_t)(e + 1u) * 64u + lane];
+            uint32_t evx = ev32[(uint64_t)(e + 1u) * 64u + lane];
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
@@ -375,52 +436,14 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             const uint32_t nend = EV32(noise_end);
             while (true) {
                 while (next_hit < nend) {
-                    const uint32_t L = (next_hit - nz_cb) >> 2, b = next_hit & 3u;
-                    const uint32_t pick = b == 0u ? w0 : b == 1u ? w1 : b == 2u ? w2 : w3;
-                    const uint64_t wv = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)L);
-                    const NoiseLoc &NL = nz[next_hit];
-                    const uint32_t nkind = NL.kind;
-                    if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR) {
-                        uint32_t ca, cb = 0;
-                        if (nkind == NZ_DEP1) {
-                            ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
-                        } else if (nkind == NZ_DEP2) {
-                            const uint32_t code = (uint32_t)((15ull * wv) / NL.thr) + 1u;
-                            ca = code >> 2;
-                            cb = code & 3u;
-                        } else {
-                            ca = 1u;
-                        }
-                        // Pauli codes: 1 = X, 2 = Y, 3 = Z
-                        if (ca == 1u || ca == 2u) { rD ^= NL.masks[0]; rS ^= NL.masks[1]; }
-                        if (ca == 3u || ca == 2u) { rD ^= NL.masks[2]; rS ^= NL.masks[3]; }
-                        if (cb == 1u || cb == 2u) { rD ^= NL.masks[4]; rS ^= NL.masks[5]; }
-                        if (cb == 3u || cb == 2u) { rD ^= NL.masks[6]; rS ^= NL.masks[7]; }
-                    } else if (nkind == NZ_FLIP) {
-                        const uint32_t r = NL.rec;
-                        rec_toggle(r >> 5, 1u << (r & 31u));
-                    }
-                    if (lane == L) hits &= ~(1u << b);
-                    next_hit = first_hit(hits, nz_cb);
+                    uint64_t dD, dS;
+                    const uint32_t fr = take_hit(dD, dS);
+                    rD ^= dD;
+                    rS ^= dS;
+                    if (fr != kNoHit) rec_toggle(fr >> 5, 1u << (fr & 31u));
                 }
                 if (nend <= nz_drawn || nz_drawn >= P.n_noise) break;
-                // draw the next 256 slots: one Philox block of 4 words per lane
-                nz_cb = nz_drawn;
-                nz_drawn += 256u;
-                const uint32_t s0 = nz_cb + 4u * lane;
-                if (EXPL) {
-                    w0 = s0 + 0u < P.n_noise ? wrow[s0 + 0u] : 0u;
-                    w1 = s0 + 1u < P.n_noise ? wrow[s0 + 1u] : 0u;
-                    w2 = s0 + 2u < P.n_noise ? wrow[s0 + 2u] : 0u;
-                    w3 = s0 + 3u < P.n_noise ? wrow[s0 + 3u] : 0u;
-                } else {
-                    philox10(s0 >> 2, s_lo, s_hi, 0u, key0, key1, w0, w1, w2, w3);
-                }
-                const uint4 th = *reinterpret_cast<const uint4 *>(tm1 + s0);
-                hits = (s0 + 0u < P.n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < P.n_noise && w1 <= th.y ? 2u : 0u) |
-                       (s0 + 2u < P.n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < P.n_noise && w3 <= th.w ? 8u : 0u);
-                next_hit = first_hit(hits, nz_cb);
-                tot.noise += min(256u, P.n_noise - nz_cb);
+                draw_chunk();
             }
             // ---- Cliffords since the previous event: one XOR ----
             rD ^= EV64(cliffD);
@@ -488,6 +511,87 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     after = 1;
                     break;
                 }
+            } else if (kind == EV_M_DET && (EV32(flags) & EVF_BATCH) && !tracing) {
+                // ---- a run of outcome-fixed measurements, one member per lane ----
+                // Member i sees the signs rD, rS of the first member, the
+                // Clifford flips since then (cumD, cumS) and the noise hits
+                // before its own noise_end; its outcome is c times the sign of
+                // the product of the rows that make up the measured Pauli.
+                const uint32_t m = EV32(bcnt);
+                const uint32_t li = lane < m ? lane : m - 1u;
+                const uint4 *bp = reinterpret_cast<const uint4 *>(bm) + (size_t)(EV32(boff) + li) * 5u;
+                const uint4 q0 = bp[0], q1 = bp[1], q3 = bp[3], q4 = bp[4];
+                uint64_t myD = rD ^ (((uint64_t)q1.y << 32) | q1.x);
+                uint64_t myS = rS ^ (((uint64_t)q1.w << 32) | q1.z);
+                const uint32_t my_nend = q3.x;
+                const uint32_t nlast = (uint32_t)__builtin_amdgcn_readlane((int)my_nend, (int)(m - 1u));
+                while (true) {
+                    while (next_hit < nlast) {
+                        const uint32_t s = next_hit;
+                        uint64_t dD, dS;
+                        (void)take_hit(dD, dS);  // the compiler keeps record flips out of runs
+                        if (s < my_nend) {
+                            myD ^= dD;
+                            myS ^= dS;
+                        }
+                    }
+                    if (nlast <= nz_drawn || nz_drawn >= P.n_noise) break;
+                    draw_chunk();
+                }
+                const uint64_t beta = ((uint64_t)q0.y << 32) | q0.x, gamma = ((uint64_t)q0.w << 32) | q0.z;
+                const uint32_t info = q3.y;
+                const uint32_t bit =
+                    ((info & BM_CSIGN) ? 1u : 0u) ^ par64(myD & beta) ^ par64(myS & gamma) ^ par64(gamma & a);
+                // folded checks read record bits from before the run, plus their own
+                uint32_t chk = 0;
+                if (info & BM_CHECK) {
+                    const uint32_t w = q3.z;
+                    const uint32_t rw = w == 0u ? rr0 : w == 1u ? rr1 : w == 2u ? rr2 : w == 3u ? rr3 : rec[w];
+                    chk = ((info & BM_EXPECT) ? 1u : 0u) ^ par32(rw & q3.w) ^ ((info & BM_OWN) ? bit : 0u);
+                }
+                const uint64_t fails = __ballot(lane < m && chk != 0u);
+                const uint32_t L = fails ? (uint32_t)__builtin_ctzll(fails) : m - 1u;  // last member executed
+                const uint64_t upto = L >= 63u ? ~0ull : ((2ull << L) - 1ull);
+                const uint32_t rl = uni(q4.z), rc = rl >> 8;
+                if (rc) {
+                    const uint32_t rl0 = rl & 255u, r0 = uni(q4.y);
+                    uint64_t bits = (__ballot((info & BM_RECORD) != 0u && bit != 0u) & upto) >> rl0;
+                    if (rc < 64u) bits &= (1ull << rc) - 1ull;
+                    if (bits) {
+                        const uint32_t w = r0 >> 5, sh = r0 & 31u;
+                        const uint32_t lo = (uint32_t)bits, hi = (uint32_t)(bits >> 32);
+                        const uint32_t t0 = lo << sh;
+                        const uint32_t t1 = sh ? (hi << sh) | (lo >> (32u - sh)) : hi;
+                        const uint32_t t2 = sh ? hi >> (32u - sh) : 0u;
+                        if (t0) rec_toggle(w, t0);
+                        if (t1) rec_toggle(w + 1u, t1);
+                        if (t2) rec_toggle(w + 2u, t2);
+                    }
+                }
+                // signs after member L: its own view, plus the resets that fired
+                uint64_t rsl = __ballot((info & BM_RESET) != 0u && bit != 0u) & upto;
+                rD = lane64(myD, L);
+                rS = lane64(myS, L);
+                if (rsl) {
+                    const uint4 q2 = bp[2];
+                    const uint64_t xD = ((uint64_t)q2.y << 32) | q2.x, xS = ((uint64_t)q2.w << 32) | q2.z;
+                    while (rsl) {
+                        const uint32_t l = (uint32_t)__builtin_ctzll(rsl);
+                        rsl &= rsl - 1ull;
+                        rD ^= lane64(xD, l);
+                        rS ^= lane64(xS, l);
+                    }
+                }
+                tot.events += L + 1u;
+                if (fails) {
+                    status = ST_DISCARDED;
+                    abort_src = (uint32_t)__builtin_amdgcn_readlane((int)q4.x, (int)L);
+                    term = e + L;
+                    after = 1;
+                    break;
+                }
+                e += m - 1u;
+                evx = ev32[(uint64_t)(e + 1u) * 64u + lane];
             } else if (kind <= EV_M_MERGE) {
                 // ---- measurement ----
                 // The uniform is drawn only when the outcome is random.  Philox
@@ -721,11 +825,11 @@ hipError_t launch_reset(unsigned long long *counters, unsigned long long *next, 
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
     const bool expl = p.words != nullptr;
     if (fp64) {
-        if (expl) hipLaunchKernelGGL((k_sample<double, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
-        else hipLaunchKernelGGL((k_sample<double, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
+        if (expl) hipLaunchKernelGGL((k_sample<double, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+        else hipLaunchKernelGGL((k_sample<double, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
     } else {
-        if (expl) hipLaunchKernelGGL((k_sample<float, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
-        else hipLaunchKernelGGL((k_sample<float, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p);
+        if (expl) hipLaunchKernelGGL((k_sample<float, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+        else hipLaunchKernelGGL((k_sample<float, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
     }
     return hipGetLastError();
 }

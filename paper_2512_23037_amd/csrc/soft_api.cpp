@@ -63,6 +63,7 @@ struct soft_ctx {
     DevBuf<Event> d_ev;
     DevBuf<NoiseLoc> d_nz;
     DevBuf<uint32_t> d_tm1, d_det;
+    DevBuf<BatchMember> d_bm;
     unsigned long long *d_counters = nullptr;  // C_COUNT + 1 (work cursor)
     double *d_phase = nullptr;                 // cos/sin of k pi/8, k = 0..15
 
@@ -148,7 +149,8 @@ int prepare(soft_ctx *c) {
     if ((rc = ensure(c, c->d_ev, c->prog.events.size())) ||
         (rc = ensure(c, c->d_nz, std::max<size_t>(c->prog.noise.size(), 1))) ||
         (rc = ensure(c, c->d_tm1, c->prog.noise_tm1.size())) ||
-        (rc = ensure(c, c->d_det, std::max<size_t>(c->prog.det_pairs.size(), 2))))
+        (rc = ensure(c, c->d_det, std::max<size_t>(c->prog.det_pairs.size(), 2))) ||
+        (rc = ensure(c, c->d_bm, std::max<size_t>(c->prog.batch.size(), 1))))
         return rc;
     HIPCHK(c, hipMemcpy(c->d_ev.p, c->prog.events.data(), c->prog.events.size() * sizeof(Event), hipMemcpyHostToDevice));
     if (!c->prog.noise.empty())
@@ -156,6 +158,8 @@ int prepare(soft_ctx *c) {
     HIPCHK(c, hipMemcpy(c->d_tm1.p, c->prog.noise_tm1.data(), c->prog.noise_tm1.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     if (!c->prog.det_pairs.empty())
         HIPCHK(c, hipMemcpy(c->d_det.p, c->prog.det_pairs.data(), c->prog.det_pairs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!c->prog.batch.empty())
+        HIPCHK(c, hipMemcpy(c->d_bm.p, c->prog.batch.data(), c->prog.batch.size() * sizeof(BatchMember), hipMemcpyHostToDevice));
     c->dirty = false;
     drop_graph(c);
     return SOFT_OK;
@@ -242,6 +246,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.nz = c->d_nz.p;
     rp.tm1 = c->d_tm1.p;
     rp.det = c->d_det.p;
+    rp.bm = c->d_bm.p;
     rp.words = c->words_dev;
     rp.phase_tab = c->d_phase;
     rp.word_stride = (uint64_t)c->prog.n_noise + c->prog.n_meas;
@@ -439,6 +444,7 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_nz);
     release(c->d_tm1);
     release(c->d_det);
+    release(c->d_bm);
     release(c->d_keep_meta);
     release(c->d_keep_v);
     release(c->d_trace_meta);

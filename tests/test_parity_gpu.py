@@ -88,6 +88,32 @@ def test_cultivation_15q_full():
     assert list(hist[:16]) == c["support_hist"]
 
 
+@pytest.mark.parametrize("workload,rate", [("cultivation_15q", 0.03), ("cultivation_15q", 0.004),
+                                           ("cultivation_42q", 0.002)])
+def test_measurement_runs_with_dense_noise(workload, rate):
+    # Runs of outcome-fixed measurements (checks and resets) are evaluated one
+    # member per lane; noise hits between members must reach exactly the
+    # members after them, and a failing check inside a run must end the shot
+    # there.  Explicit words put a hit on each noise slot with probability
+    # `rate`, far above the model's p, so most runs see hits inside them.
+    w = workloads.config(workload, seed=1)
+    circ = oracle.Circuit(w.text, w.noise)
+    N = 4096
+    rng = np.random.default_rng([len(workload), int(rate * 1e4)])
+    thr = int(w.noise["p1"] * 2**32)  # every slot of these circuits has p = p1
+    hit = rng.random((N, circ.n_noise_slots)) < rate
+    nw = np.where(hit, rng.integers(0, thr, size=hit.shape), rng.integers(thr, 2**32, size=hit.shape))
+    mw = rng.integers(0, 2**32, size=(N, circ.n_meas_slots))
+    words = np.concatenate([nw, mw], axis=1).astype(np.uint32)
+    ctx = make_ctx(w.text, w.noise, keep=(0, 256))
+    gpu = run_gpu(ctx, 0, N, words)
+    ref = circ.batch(0, 0, N, words=words)
+    compare_batch(gpu, ref)
+    compare_kept(ctx, circ, 0, range(256), words=words[:256])
+    # shots end at many different checks, not only the first
+    assert len(np.unique(ref["abort_op"])) > 5
+
+
 @pytest.mark.parametrize("bits,tol", [(64, 1e-10), (32, 1e-5)])
 def test_cultivation_42q_subset(bits, tol):
     w = workloads.config("cultivation_42q", seed=1)
