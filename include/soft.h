@@ -95,8 +95,22 @@ const char *soft_last_error(const soft_ctx *ctx);
  * exceeds the largest tile the library supports. */
 int soft_load_circuit(soft_ctx *ctx, const char *text, size_t len);
 
-/* Set the noise model inserted around the circuit's ops (default: none). */
+/* Set the noise model inserted around the circuit's ops (default: none).
+ * ESTATE while a mixture is loaded (each variant has its own model). */
 int soft_load_noise(soft_ctx *ctx, const soft_noise *model);
+
+/* Load a mixture: n_variants (1..64) circuits, each with its own noise model,
+ * sampled together in one launch by soft_run.  Variant v owns the global
+ * shot indices [shot_ends[v-1], shot_ends[v]) (shot_ends[-1] = 0; the ends
+ * strictly increase), and a shot of variant v has the same result as the
+ * same shot index of a context holding only that circuit and model.
+ * texts[v] (lens[v] bytes, copied) use the soft_load_circuit format;
+ * models[v] as soft_load_noise.  On failure the message names the variant
+ * and the previous contents stay loaded.  soft_load_circuit returns the
+ * context to a single circuit.  Explicit uniforms (soft_set_uniforms) are
+ * not available for mixtures (EUNSUPPORTED at soft_run). */
+int soft_load_mixture(soft_ctx *ctx, uint32_t n_variants, const char *const *texts, const size_t *lens,
+                      const soft_noise *models, const uint64_t *shot_ends);
 
 /* Key of the per-shot Philox4x32-10 streams (Salmon et al., SC'11).  Noise
  * slot s of shot t uses word s%4 of the block at counter
@@ -128,9 +142,17 @@ int soft_set_prune(soft_ctx *ctx, double tau);
 int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
                   uint32_t blocks_per_cu, uint32_t grab);
 
-/* Time a grid of launch shapes on `sample_shots` shots (outputs discarded)
- * and keep the fastest for this circuit, noise model and precision.  Runs on
- * hip_stream and synchronizes it. */
+/* Where the per-wave coefficient tile lives: 0 = automatic (LDS when one
+ * wave's tile fits in a block's LDS, else device memory), 1 = LDS, 2 = device
+ * memory (HBM; one slab of 2^k_max entries per resident wave, allocated by the
+ * library on first use).  LDS is the fast place; device memory lifts the LDS
+ * size limit on the span dimension (up to k_max = 20). */
+int soft_set_tile_memory(soft_ctx *ctx, int mode);
+
+/* Time a grid of launch shapes (and, in automatic tile mode, both tile
+ * placements) on `sample_shots` shots spread over the variants (outputs
+ * discarded) and keep the fastest for this circuit, noise model and
+ * precision.  Runs on hip_stream and synchronizes it. */
 int soft_autotune(soft_ctx *ctx, uint64_t sample_shots, void *hip_stream);
 
 /* Keep the final state of shots [shot_lo, shot_lo + count) of later runs for
@@ -145,13 +167,18 @@ int soft_set_keep(soft_ctx *ctx, uint64_t shot_lo, uint32_t count);
  *   status_dev:   uint32 [n_shots] SOFT_PASSED/DISCARDED/OVERFLOW/NUMERIC;
  *   abort_op_dev: uint32 [n_shots] op index that ended the shot
  *                 (0xffffffff if it passed), or NULL;
- *   obs_dev:      uint32 [n_shots], bit j = observable j, or NULL. */
+ *   obs_dev:      uint32 [n_shots], bit j = observable j, or NULL.
+ * EINVAL if the shots reach past the last variant's range of a mixture. */
 int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes_dev,
              uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev,
              void *hip_stream);
 
 /* Aggregates of the last run; synchronizes that run's stream. */
 int soft_read_counters(soft_ctx *ctx, soft_counters *out);
+
+/* Aggregates of the last run over the shots of one variant of a mixture
+ * (variant 0 of a single circuit is the whole run).  Synchronizes. */
+int soft_read_variant_counters(soft_ctx *ctx, uint32_t variant, soft_counters *out);
 
 /* Final coefficients of a kept shot of the last run, sorted by alpha (bit k =
  * destabilizer d_k), entries below the pruning threshold left out.  Up to
@@ -180,12 +207,17 @@ int soft_read_trace(soft_ctx *ctx, uint32_t step, uint64_t info[6], uint64_t *x,
 
 /* Facts about the loaded circuit: info[0..7] = qubits, records, noise slots,
  * measurement slots, observables, events, largest span dimension k_max,
- * record words. */
+ * record words.  For a mixture, each entry is the largest over the variants
+ * (the record words size soft_run's outcome planes). */
 int soft_circuit_info(soft_ctx *ctx, uint64_t info[8]);
 
-/* Launch shape used by the next run: out[0..3] = waves_per_block,
- * blocks_per_cu, grab, LDS bytes per wave. */
-int soft_launch_shape(soft_ctx *ctx, uint32_t out[4]);
+/* The same facts for variant `variant` of a mixture. */
+int soft_variant_info(soft_ctx *ctx, uint32_t variant, uint64_t info[8]);
+
+/* Launch shape used by the next run: out[0..4] = waves_per_block,
+ * blocks_per_cu, grab, LDS bytes per wave, 1 if the tiles are in device
+ * memory. */
+int soft_launch_shape(soft_ctx *ctx, uint32_t out[5]);
 
 #ifdef __cplusplus
 }

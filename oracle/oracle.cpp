@@ -19,7 +19,9 @@
 //   * entries with |v|^2 < tau^2 * sum|v|^2 are dropped after every T and
 //     measurement;
 //   * noise: DEP1 picks X/Y/Z with p/3 each, DEP2 one of the 15 non-identity
-//     two-qubit Paulis with p/15 each, XERR an X, FLIP a classical record flip.
+//     two-qubit Paulis with p/15 each, XERR an X, ZERR a Z, FLIP a classical
+//     record flip; X-basis readouts and resets (MX, RX, MRX) take ZERR where
+//     Z-basis ones take XERR.
 #include "oracle.h"
 
 #include <algorithm>
@@ -76,10 +78,11 @@ uint32_t philox_word(uint64_t seed, uint64_t shot, uint32_t stream, uint64_t slo
 // Circuit representation after parsing and noise insertion.
 // ---------------------------------------------------------------------------
 enum Kind {
-    K_H, K_S, K_SDG, K_X, K_Y, K_Z, K_CX, K_CZ, K_T, K_TDG,
-    K_M, K_MPP, K_R,
-    K_DEP1, K_DEP2, K_XERR, K_FLIP,
-    K_DETECTOR, K_OBSERVABLE
+    K_H, K_S, K_SDG, K_X, K_Y, K_Z, K_CX, K_CZ, K_T, K_TDG, K_HXY, K_HNXY,
+    K_M, K_MPP, K_R, K_MX, K_RX, K_MR, K_MRX,
+    K_DEP1, K_DEP2, K_XERR, K_ZERR, K_FLIP,
+    K_DETECTOR, K_OBSERVABLE,
+    K_FEEDBACK  // Pauli `b` (1 X, 2 Y, 3 Z) on qubit a when record bit `rec` is 1
 };
 
 struct Op {
@@ -177,10 +180,10 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             continue;
         }
         int src = c.n_src++;
-        static const char *one_q[] = {"H", "S", "SDG", "X", "Y", "Z", "T", "TDG"};
-        static const Kind one_k[] = {K_H, K_S, K_SDG, K_X, K_Y, K_Z, K_T, K_TDG};
+        static const char *one_q[] = {"H", "S", "SDG", "X", "Y", "Z", "T", "TDG", "H_XY", "H_NXY"};
+        static const Kind one_k[] = {K_H, K_S, K_SDG, K_X, K_Y, K_Z, K_T, K_TDG, K_HXY, K_HNXY};
         bool done = false;
-        for (int i = 0; i < 8 && !done; ++i) {
+        for (int i = 0; i < 10 && !done; ++i) {
             if (name == one_q[i]) {
                 if (tok.size() != 2) throw ParseError{line, name + " takes one qubit"};
                 Op o;
@@ -217,6 +220,34 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             c.ops.push_back(o);
             active[q] = 1;
             add_noise(K_XERR, nm.p_reset, q, -1, src);
+        } else if (name == "MX" || name == "RX" || name == "MR" || name == "MRX") {
+            // X-basis measurement / reset to |+>, and measure-then-reset.  The
+            // measurement-error flip before a readout and the reset-error flip
+            // after a reset anticommute with the measured Pauli: X for Z-basis
+            // ops, Z for X-basis ops.
+            if (tok.size() != 2) throw ParseError{line, name + " takes one qubit"};
+            int q = qubit(tok[1]);
+            const bool xb = name == "MX" || name == "RX" || name == "MRX";
+            const bool readout = name != "RX", reset = name != "MX";
+            const Kind flip = xb ? K_ZERR : K_XERR;
+            if (readout) add_noise(flip, nm.p_meas, q, -1, src);
+            Op o;
+            o.kind = name == "MX" ? K_MX : name == "RX" ? K_RX : name == "MR" ? K_MR : K_MRX;
+            o.a = q; o.src = src; o.slot = c.n_meas++;
+            if (readout) o.rec = c.n_rec++;
+            c.ops.push_back(o);
+            active[q] = 1;
+            if (reset) add_noise(flip, nm.p_reset, q, -1, src);
+        } else if (name == "XIF" || name == "YIF" || name == "ZIF") {
+            // classically controlled Pauli: apply it when the record bit is 1
+            if (tok.size() != 3) throw ParseError{line, name + " takes a record index and a qubit"};
+            Op o;
+            o.kind = K_FEEDBACK; o.src = src;
+            o.rec = to_int(tok[1], line);
+            if (o.rec >= c.n_rec) throw ParseError{line, "record index not yet measured"};
+            o.a = qubit(tok[2]);
+            o.b = name == "XIF" ? 1 : name == "YIF" ? 2 : 3;
+            c.ops.push_back(o);
         } else if (name == "MPP") {
             if (tok.size() != 2) throw ParseError{line, "MPP takes one Pauli product"};
             Op o;
@@ -242,11 +273,11 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             o.rec = c.n_rec++;
             c.ops.push_back(o);
             add_flip(nm.p_mpp, o.rec, src);
-        } else if (name == "DEP1" || name == "XERR") {
+        } else if (name == "DEP1" || name == "XERR" || name == "ZERR") {
             if (tok.size() < 3) throw ParseError{line, name + " takes p and qubits"};
             double p = to_prob(tok[1], line);
-            for (size_t i = 2; i < tok.size(); ++i)
-                add_noise(name == "DEP1" ? K_DEP1 : K_XERR, p, qubit(tok[i]), -1, src);
+            const Kind k = name == "DEP1" ? K_DEP1 : name == "XERR" ? K_XERR : K_ZERR;
+            for (size_t i = 2; i < tok.size(); ++i) add_noise(k, p, qubit(tok[i]), -1, src);
         } else if (name == "DEP2") {
             if (tok.size() < 4 || (tok.size() - 2) % 2 != 0) throw ParseError{line, "DEP2 takes p and qubit pairs"};
             double p = to_prob(tok[1], line);
@@ -356,6 +387,16 @@ void apply_clifford(ShotState &st, Kind k, int a, int b) {
                 break;
             case K_SDG:
                 st.r[i] ^= xa & (za ^ 1);
+                set_bit(st.z[i], a, za ^ xa);
+                break;
+            case K_HXY:
+                // (X + Y)/sqrt2: X -> Y, Y -> X, Z -> -Z
+                st.r[i] ^= za & (xa ^ 1);
+                set_bit(st.z[i], a, za ^ xa);
+                break;
+            case K_HNXY:
+                // (X - Y)/sqrt2: X -> -Y, Y -> -X, Z -> -Z
+                st.r[i] ^= xa | za;
                 set_bit(st.z[i], a, za ^ xa);
                 break;
             case K_X: st.r[i] ^= za; break;
@@ -579,8 +620,12 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
 
     for (const Op &o : c.ops) {
         switch (o.kind) {
-            case K_H: case K_S: case K_SDG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ:
+            case K_H: case K_S: case K_SDG: case K_X: case K_Y: case K_Z: case K_CX: case K_CZ: case K_HXY:
+            case K_HNXY:
                 apply_clifford(st, o.kind, o.a, o.b);
+                break;
+            case K_FEEDBACK:
+                if (rec_bit(o.rec)) apply_pauli_code(st, o.b, o.a);
                 break;
             case K_T: case K_TDG: {
                 Pauli Z;
@@ -599,9 +644,11 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 }
                 break;
             }
-            case K_M: case K_MPP: case K_R: {
+            case K_M: case K_MPP: case K_R: case K_MX: case K_RX: case K_MR: case K_MRX: {
+                const bool xb = o.kind == K_MX || o.kind == K_RX || o.kind == K_MRX;
                 Pauli P;
                 if (o.kind == K_MPP) { P.x = o.px; P.z = o.pz; }
+                else if (xb) P.x = 1ULL << o.a;
                 else P.z = 1ULL << o.a;
                 res.info.m_entries += st.v.size();
                 res.info.events++;
@@ -614,15 +661,14 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                     res.info.norm2 = norm2(st.v);
                     return;
                 }
-                if (o.kind == K_R) {
-                    if (b) apply_clifford(st, K_X, o.a, -1);
-                } else if (b) {
-                    res.record[o.rec >> 5] |= 1u << (o.rec & 31);
-                }
+                if (b && o.rec >= 0) res.record[o.rec >> 5] |= 1u << (o.rec & 31);
+                // resets bring outcome 1 back to the +1 eigenstate of the measured Pauli
+                if (b && (o.kind == K_R || o.kind == K_MR)) apply_clifford(st, K_X, o.a, -1);
+                if (b && (o.kind == K_RX || o.kind == K_MRX)) apply_clifford(st, K_Z, o.a, -1);
                 note_support();
                 break;
             }
-            case K_DEP1: case K_DEP2: case K_XERR: case K_FLIP: {
+            case K_DEP1: case K_DEP2: case K_XERR: case K_ZERR: case K_FLIP: {
                 res.info.noise_slots++;
                 uint32_t w = noise_word(o.slot);
                 if ((uint64_t)w >= o.thr) break;
@@ -635,6 +681,8 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                     apply_pauli_code(st, code & 3, o.b);
                 } else if (o.kind == K_XERR) {
                     apply_pauli_code(st, 1, o.a);
+                } else if (o.kind == K_ZERR) {
+                    apply_pauli_code(st, 3, o.a);
                 } else {
                     res.record[o.rec >> 5] ^= 1u << (o.rec & 31);
                 }

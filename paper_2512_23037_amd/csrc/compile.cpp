@@ -58,6 +58,7 @@ struct RowMask {
     uint64_t d = 0, s = 0;
     RowMask operator^(const RowMask &o) const { return {d ^ o.d, s ^ o.s}; }
     RowMask operator&(const RowMask &o) const { return {d & o.d, s & o.s}; }
+    RowMask operator|(const RowMask &o) const { return {d | o.d, s | o.s}; }
     RowMask &operator^=(const RowMask &o) { d ^= o.d; s ^= o.s; return *this; }
 };
 
@@ -77,6 +78,17 @@ class FrameCompiler {
     void sdg(int a) {
         RowMask notz = {~cz_[a].d, ~cz_[a].s};
         acc_ ^= cx_[a] & notz;
+        cz_[a] ^= cx_[a];
+    }
+    // (X + Y)/sqrt2: X -> Y, Y -> X, Z -> -Z
+    void hxy(int a) {
+        RowMask notx = {~cx_[a].d, ~cx_[a].s};
+        acc_ ^= cz_[a] & notx;
+        cz_[a] ^= cx_[a];
+    }
+    // (X - Y)/sqrt2: X -> -Y, Y -> -X, Z -> -Z
+    void hnxy(int a) {
+        acc_ ^= cx_[a] | cz_[a];
         cz_[a] ^= cx_[a];
     }
     void px(int a) { acc_ ^= cz_[a]; }
@@ -164,7 +176,8 @@ class FrameCompiler {
     }
 
     // Measurement of P (Hermitian, sign +); reset adds a conditional X_q.
-    void measure(const PauliStr &P, uint32_t mslot, int rec, int reset_q, uint32_t src) {
+    // reset_z: the reset flips with Z_q (X-basis reset) instead of X_q.
+    void measure(const PauliStr &P, uint32_t mslot, int rec, int reset_q, uint32_t src, bool reset_z = false) {
         Event E = begin(src);
         uint64_t beta, gamma;
         int cexp;
@@ -245,10 +258,11 @@ class FrameCompiler {
             set_row(false, p, sp.x, sp.z);
             set_row(true, p, P.x, P.z);
         }
-        if (reset_q >= 0) {
+        if (reset_q >= 0) {  // rows anticommuting with the flip, in the frame after the measurement
             E.flags |= EVF_RESET;
-            E.xD = cz_[reset_q].d;
-            E.xS = cz_[reset_q].s;
+            const RowMask &m = reset_z ? cx_[reset_q] : cz_[reset_q];
+            E.xD = m.d;
+            E.xS = m.s;
         }
         finish(E);
     }
@@ -293,6 +307,19 @@ class FrameCompiler {
         E.kind = detector ? EV_DETECTOR : EV_OBSERVABLE;
         E.rec = obs;
         fill(E);
+        finish(E);
+    }
+
+    // Pauli (1 X, 2 Y, 3 Z) on qubit q when record bit `rec` is 1.
+    void feedback(int pauli, int q, uint32_t rec, uint32_t src) {
+        Event E = begin(src);
+        E.kind = EV_FEEDBACK;
+        E.rec = rec;
+        RowMask m;
+        if (pauli == 1 || pauli == 2) m ^= cz_[q];
+        if (pauli == 3 || pauli == 2) m ^= cx_[q];
+        E.xD = m.d;
+        E.xS = m.s;
         finish(E);
     }
 
@@ -591,11 +618,13 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
             if (tok.size() != k) throw CompileError{ln, op + ": wrong number of arguments"};
         };
         if (op == "H" || op == "S" || op == "SDG" || op == "X" || op == "Y" || op == "Z" || op == "T" ||
-            op == "TDG") {
+            op == "TDG" || op == "H_XY" || op == "H_NXY") {
             want(2);
             int q = qubit(tok[1]);
             busy[q] = 1;
             if (op == "H") fc.h(q);
+            else if (op == "H_XY") fc.hxy(q);
+            else if (op == "H_NXY") fc.hnxy(q);
             else if (op == "S") fc.s(q);
             else if (op == "SDG") fc.sdg(q);
             else if (op == "X") fc.px(q);
@@ -624,6 +653,27 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
                 fc.measure(Z, out.n_meas++, -1, q, src);
                 fc.noise(NZ_XERR, nm.p_reset, q, -1, 0);
             }
+        } else if (op == "MX" || op == "RX" || op == "MR" || op == "MRX") {
+            // X-basis readout / reset to |+>, measure-then-reset; the error
+            // flips anticommute with the measured Pauli (Z for the X basis)
+            want(2);
+            int q = qubit(tok[1]);
+            busy[q] = 1;
+            const bool xb = op != "MR", readout = op != "RX", reset = op != "MX";
+            const uint32_t flip = xb ? NZ_ZERR : NZ_XERR;
+            PauliStr P;
+            if (xb) P.x = bitq(q);
+            else P.z = bitq(q);
+            if (readout) fc.noise(flip, nm.p_meas, q, -1, 0);
+            const int rec = readout ? (int)out.n_rec++ : -1;
+            fc.measure(P, out.n_meas++, rec, reset ? q : -1, src, xb);
+            if (reset) fc.noise(flip, nm.p_reset, q, -1, 0);
+        } else if (op == "XIF" || op == "YIF" || op == "ZIF") {
+            want(3);
+            int r = parse_uint(tok[1], ln);
+            if ((uint32_t)r >= out.n_rec) throw CompileError{ln, "record index not yet measured"};
+            int q = qubit(tok[2]);
+            fc.feedback(op == "XIF" ? 1 : op == "YIF" ? 2 : 3, q, (uint32_t)r, src);
         } else if (op == "MPP") {
             want(2);
             PauliStr P;
@@ -648,10 +698,11 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
             uint32_t rec = out.n_rec++;
             fc.measure(P, out.n_meas++, (int)rec, -1, src);
             fc.noise(NZ_FLIP, nm.p_mpp, -1, -1, rec);
-        } else if (op == "DEP1" || op == "XERR") {
+        } else if (op == "DEP1" || op == "XERR" || op == "ZERR") {
             if (tok.size() < 3) throw CompileError{ln, op + ": wrong number of arguments"};
             double p = parse_prob(tok[1], ln);
-            for (size_t i = 2; i < tok.size(); ++i) fc.noise(op == "DEP1" ? NZ_DEP1 : NZ_XERR, p, qubit(tok[i]), -1, 0);
+            const uint32_t k = op == "DEP1" ? NZ_DEP1 : op == "XERR" ? NZ_XERR : NZ_ZERR;
+            for (size_t i = 2; i < tok.size(); ++i) fc.noise(k, p, qubit(tok[i]), -1, 0);
         } else if (op == "DEP2") {
             if (tok.size() < 4 || tok.size() % 2 != 0) throw CompileError{ln, "DEP2: wrong number of arguments"};
             double p = parse_prob(tok[1], ln);

@@ -41,6 +41,7 @@ enum EvKind : uint32_t {
     EV_M_MERGE,      // beta != 0 inside the span: pairs merge, k -> k-1
     EV_DETECTOR,     // parity check of record bits, abort on failure
     EV_OBSERVABLE,   // parity of record bits, stored as an observable bit
+    EV_FEEDBACK,     // Pauli flip (masks xD/xS) when record bit `rec` is 1
     EV_END
 };
 
@@ -84,7 +85,7 @@ struct alignas(16) Event {
     uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products
-    uint64_t xD, xS;          // reset: rows anticommuting with X_q afterwards
+    uint64_t xD, xS;          // reset / feedback: rows anticommuting with the flip Pauli
     double Are, Aim;          // T_PHASE: e^{i s pi/4}; branching T: cos(pi/8), 0
     double Bre, Bim;          // branching T: sin(pi/8), 0 (the weight of the partner term)
     float Afr, Afi, Bfr, Bfi; // the same in single precision
@@ -124,7 +125,19 @@ struct alignas(16) BatchMember {
 static_assert(sizeof(BatchMember) == 80, "batch member layout");
 constexpr uint32_t kBatchMax = 64;
 
-enum NoiseKind : uint32_t { NZ_NONE = 0, NZ_DEP1, NZ_DEP2, NZ_XERR, NZ_FLIP };
+// A mixture runs several compiled circuits in one launch: global shot indices
+// [previous shot_end, shot_end) belong to the variant, whose events, noise
+// locations and thresholds sit at the given offsets of the shared tables.
+struct alignas(16) VariantDesc {
+    uint64_t shot_end;
+    uint32_t ev_off, nz_off, tm1_off;  // tm1_off is a multiple of 256
+    uint32_t n_noise;
+    uint32_t pad[2];
+};
+static_assert(sizeof(VariantDesc) == 32, "variant layout");
+constexpr uint32_t kMaxVariants = 64;
+
+enum NoiseKind : uint32_t { NZ_NONE = 0, NZ_DEP1, NZ_DEP2, NZ_XERR, NZ_FLIP, NZ_ZERR };
 
 // One noise location (one random word).  masks[0..3] = rows anticommuting
 // with X_a (D, S) and with Z_a (D, S); masks[4..7] the same for qubit b.
@@ -139,7 +152,7 @@ static_assert(sizeof(NoiseLoc) == 80, "noise layout");
 // Per-shot status codes (low byte of the status word).
 enum Status : uint32_t { ST_PASSED = 0, ST_DISCARDED = 1, ST_OVERFLOW = 2, ST_NUMERIC = 3 };
 
-// Device counters, all 64-bit.
+// Device counters, all 64-bit: one row of C_COUNT per variant.
 enum Counter {
     C_SHOTS = 0, C_PASSED, C_DISCARDED, C_OVERFLOW, C_NUMERIC, C_LOGICAL,
     C_ENTRIES_T, C_ENTRIES_M, C_NOISE, C_EVENTS, C_NORMDEV_BITS,
@@ -150,7 +163,7 @@ enum Counter {
 // Per kept shot (and per traced step): meta words, and separately the dense
 // coefficient tile as double pairs.  KM_VALID holds kStateValid once written.
 enum KeepMeta {
-    KM_STATUS = 0, KM_ABORT, KM_TERM_EV, KM_AFTER, KM_RD, KM_RS, KM_A, KM_K, KM_NRM2, KM_VALID, KM_COUNT
+    KM_STATUS = 0, KM_ABORT, KM_TERM_EV, KM_AFTER, KM_RD, KM_RS, KM_A, KM_K, KM_NRM2, KM_VALID, KM_VAR, KM_COUNT
 };
 
 constexpr unsigned long long kStateValid = 0x5f7a7e5f7a7e0001ull;

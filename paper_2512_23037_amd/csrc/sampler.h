@@ -13,29 +13,31 @@ struct RunParams {
     const uint32_t *tm1;      // per noise slot: threshold - 1 (padded to 256)
     const uint32_t *det;      // DETECTOR/OBSERVABLE (word, mask) pairs
     const BatchMember *bm;    // members of side-by-side measurement runs
+    const VariantDesc *vars;  // shot ranges of the circuits in this run
     const uint32_t *words;    // explicit uniforms [n_shots][word_stride] or null
     const double *phase_tab;  // cos(k pi/8) for k = 0..15, then sin(k pi/8)
     uint32_t *outcomes;       // [rec_words][n_shots] or null
     uint32_t *status;         // [n_shots]
     uint32_t *abort_op;       // [n_shots] or null
     uint32_t *obs;            // [n_shots] or null
-    unsigned long long *counters;  // C_COUNT words
+    unsigned long long *counters;  // [variants][C_COUNT]
     unsigned long long *next;      // work-stealing cursor
     unsigned long long *keep_meta; // [keep_n][KM_COUNT] or null
     double *keep_v;                // [keep_n][tile_entries][2] or null
     unsigned long long *trace_meta;  // [trace_n][KM_COUNT] or null
     double *trace_v;                 // [trace_n][tile_entries][2] or null
+    void *gtile;              // device-memory tiles, one slab of tile_entries per wave, or null (LDS tiles)
     uint64_t trace_shot;
     uint64_t seed, shot0, n_shots, keep_lo;
     uint64_t word_stride;
-    uint32_t keep_n, n_noise, rec_words, support_cap;
+    uint32_t keep_n, n_vars, rec_words, support_cap;
     uint32_t trace_n, pad_;
     uint32_t wave_bytes, tile_bytes, tile_entries, grab;
     double tau2;              // pruning threshold squared
 };
 
-// Zero the counters and the work cursor (a kernel, so it can live in a graph).
-hipError_t launch_reset(unsigned long long *counters, unsigned long long *next, hipStream_t stream);
+// Zero `n` counters and the work cursor (a kernel, so it can live in a graph).
+hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long long *next, hipStream_t stream);
 
 // The persistent sampler: grid x block threads, `lds` bytes of dynamic LDS.
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream);

@@ -128,7 +128,7 @@ template <typename C>
 __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const C *v, uint32_t lane,
                                            uint32_t tile_entries, uint32_t status, uint32_t abort_src, uint32_t term,
                                            uint32_t after, uint64_t rD, uint64_t rS, uint64_t a, uint32_t k,
-                                           double nrm2, const double *phase_tab, uint32_t phase8) {
+                                           double nrm2, const double *phase_tab, uint32_t phase8, uint32_t var) {
     if (lane == 0) {
         m[KM_STATUS] = status;
         m[KM_ABORT] = abort_src;
@@ -140,6 +140,7 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
         m[KM_K] = k;
         m[KM_NRM2] = (unsigned long long)__double_as_longlong(nrm2);
         m[KM_VALID] = kStateValid;
+        m[KM_VAR] = var;
     }
     const double pc = phase_tab[phase8], ps = phase_tab[16u + phase8];
     const uint32_t cnt = 1u << k;
@@ -282,23 +283,56 @@ struct WaveTotals {
 #define EVF(f) __uint_as_float(EV32(f))
 #define EVD(f) __longlong_as_double((long long)EV64(f))
 
-template <typename R, bool EXPL>
+template <typename R, bool EXPL, bool GT>
 __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
                                                 const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
                                                 const uint32_t *__restrict__ words,
                                                 const BatchMember *__restrict__ bm, RunParams P) {
     typedef typename Cx<R>::T C;
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t *ev32 = reinterpret_cast<const uint32_t *>(ev);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    C *v = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
-    uint32_t *rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes + P.tile_bytes);
+    // The coefficient tile lives in LDS, or (GT) in a per-wave slab of
+    // device memory for spans whose tile does not fit in LDS.  The record
+    // words are always in LDS.
+    C *v;
+    uint32_t *rec;
+    if (GT) {
+        v = reinterpret_cast<C *>(P.gtile) + (size_t)(blockIdx.x * (blockDim.x >> 6) + wave) * P.tile_entries;
+        rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes);
+    } else {
+        v = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
+        rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes + P.tile_bytes);
+    }
+    // Lanes read entries that other lanes wrote in the previous pass: with a
+    // device-memory tile, each pass ends with a fence (LDS keeps a wave's
+    // accesses in order by itself).
+    auto tile_sync = [&]() {
+        if (GT) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    };
     const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
     const double tau2 = P.tau2;
 
     WaveTotals tot;
-    uint64_t myc = 0;  // counter number `lane` of this wave
+    uint64_t myc = 0;  // counter number `lane` of this wave, for variant `var`
+
+    // Circuit of the current shot.  A wave's shots come in increasing order,
+    // so the variant index only moves forward.
+    uint32_t var = 0;
+    bool var_ok = false;
+    uint64_t var_end = 0;
+    const uint32_t *ev32 = nullptr;
+    auto flush_counters = [&]() {
+        unsigned long long *row = P.counters + (size_t)var * C_COUNT;
+        myc += lane == C_ENTRIES_T ? tot.entries_t : 0ull;
+        myc += lane == C_ENTRIES_M ? tot.entries_m : 0ull;
+        myc += lane == C_NOISE ? tot.noise : 0ull;
+        myc += lane == C_EVENTS ? tot.events : 0ull;
+        if (lane < (uint32_t)C_COUNT && lane != (uint32_t)C_NORMDEV_BITS && myc) atomicAdd(row + lane, (unsigned long long)myc);
+        if (lane == (uint32_t)C_NORMDEV_BITS) atomicMax(row + lane, (unsigned long long)__double_as_longlong(tot.maxdev));
+        myc = 0;
+        tot = WaveTotals();
+    };
 
     // Work stealing by groups of `grab` (<= 64) consecutive shots.  Lane g keeps
     // the output words of the group's g-th shot, so each output plane is
@@ -322,6 +356,14 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         const uint64_t i = group_base + group_pos;
         const uint64_t shot = P.shot0 + i;
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
+        if (!var_ok || shot >= var_end) {
+            if (var_ok) flush_counters();
+            while (P.vars[var].shot_end <= shot) ++var;
+            const VariantDesc &VD = P.vars[var];
+            var_end = VD.shot_end;
+            ev32 = reinterpret_cast<const uint32_t *>(ev + VD.ev_off);
+            var_ok = true;
+        }
         const uint32_t *wrow = EXPL ? words + i * P.word_stride : nullptr;
 
         // ---- shot start: d_i = +X_i, s_i = +Z_i, v = {0: 1} ----
@@ -354,6 +396,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             return uni(pbits);
         };
         if (lane == 0) v[0] = mk<C>(1.0, 0.0);
+        tile_sync();
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
         uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
@@ -367,25 +410,28 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
         const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
+        // noise tables of this variant (read where used: the draws are rare)
+        const VariantDesc *vdp = P.vars + var;
 
         // Draw the next 256 noise slots: one Philox block of 4 words per lane.
         auto draw_chunk = [&]() {
+            const uint32_t n_noise = vdp->n_noise;
             nz_cb = nz_drawn;
             nz_drawn += 256u;
             const uint32_t s0 = nz_cb + 4u * lane;
             if (EXPL) {
-                w0 = s0 + 0u < P.n_noise ? wrow[s0 + 0u] : 0u;
-                w1 = s0 + 1u < P.n_noise ? wrow[s0 + 1u] : 0u;
-                w2 = s0 + 2u < P.n_noise ? wrow[s0 + 2u] : 0u;
-                w3 = s0 + 3u < P.n_noise ? wrow[s0 + 3u] : 0u;
+                w0 = s0 + 0u < n_noise ? wrow[s0 + 0u] : 0u;
+                w1 = s0 + 1u < n_noise ? wrow[s0 + 1u] : 0u;
+                w2 = s0 + 2u < n_noise ? wrow[s0 + 2u] : 0u;
+                w3 = s0 + 3u < n_noise ? wrow[s0 + 3u] : 0u;
             } else {
                 philox10(s0 >> 2, s_lo, s_hi, 0u, key0, key1, w0, w1, w2, w3);
             }
-            const uint4 th = *reinterpret_cast<const uint4 *>(tm1 + s0);
-            hits = (s0 + 0u < P.n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < P.n_noise && w1 <= th.y ? 2u : 0u) |
-                   (s0 + 2u < P.n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < P.n_noise && w3 <= th.w ? 8u : 0u);
+            const uint4 th = *reinterpret_cast<const uint4 *>(tm1 + vdp->tm1_off + s0);
+            hits = (s0 + 0u < n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < n_noise && w1 <= th.y ? 2u : 0u) |
+                   (s0 + 2u < n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < n_noise && w3 <= th.w ? 8u : 0u);
             next_hit = first_hit(hits, nz_cb);
-            tot.noise += min(256u, P.n_noise - nz_cb);
+            tot.noise += min(256u, n_noise - nz_cb);
         };
         // Decode the pending hit at slot next_hit into sign-flip masks (or a
         // record flip, returned; kNoHit otherwise) and move to the next hit.
@@ -393,12 +439,12 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             const uint32_t L = (next_hit - nz_cb) >> 2, b = next_hit & 3u;
             const uint32_t pick = b == 0u ? w0 : b == 1u ? w1 : b == 2u ? w2 : w3;
             const uint64_t wv = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)L);
-            const NoiseLoc &NL = nz[next_hit];
+            const NoiseLoc &NL = nz[vdp->nz_off + next_hit];
             const uint32_t nkind = NL.kind;
             uint32_t fr = kNoHit;
             dD = 0;
             dS = 0;
-            if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR) {
+            if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR || nkind == NZ_ZERR) {
                 uint32_t ca, cb = 0;
                 if (nkind == NZ_DEP1) {
                     ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
@@ -407,7 +453,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     ca = code >> 2;
                     cb = code & 3u;
                 } else {
-                    ca = 1u;
+                    ca = nkind == NZ_XERR ? 1u : 3u;
                 }
                 // Pauli codes: 1 = X, 2 = Y, 3 = Z
                 if (ca == 1u || ca == 2u) { dD ^= NL.masks[0]; dS ^= NL.masks[1]; }
@@ -429,7 +475,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
-                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8);
+                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var);
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
@@ -442,7 +488,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     rS ^= dS;
                     if (fr != kNoHit) rec_toggle(fr >> 5, 1u << (fr & 31u));
                 }
-                if (nend <= nz_drawn || nz_drawn >= P.n_noise) break;
+                if (nend <= nz_drawn || nz_drawn >= vdp->n_noise) break;
                 draw_chunk();
             }
             // ---- Cliffords since the previous event: one XOR ----
@@ -535,7 +581,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                             myS ^= dS;
                         }
                     }
-                    if (nlast <= nz_drawn || nz_drawn >= P.n_noise) break;
+                    if (nlast <= nz_drawn || nz_drawn >= vdp->n_noise) break;
                     draw_chunk();
                 }
                 const uint64_t beta = ((uint64_t)q0.y << 32) | q0.x, gamma = ((uint64_t)q0.w << 32) | q0.z;
@@ -602,7 +648,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const uint32_t ms = EV32(mslot);
                     uint32_t mw;
                     if (EXPL) {
-                        mw = wrow[P.n_noise + ms];
+                        mw = wrow[vdp->n_noise + ms];
                     } else {
                         if (ms < m_base || ms - m_base >= 256u) {
                             m_base = ms & ~255u;
@@ -755,6 +801,13 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         break;
                     }
                 }
+            } else if (kind == EV_FEEDBACK) {
+                // ---- classically controlled Pauli ----
+                const uint32_t r = EV32(rec);
+                if ((rec_read(r >> 5) >> (r & 31u)) & 1u) {
+                    rD ^= EV64(xD);
+                    rS ^= EV64(xS);
+                }
             } else {
                 // ---- DETECTOR / OBSERVABLE ----
                 const uint32_t pbits = parity_check();
@@ -769,8 +822,10 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     obs |= pbits << EV32(rec);
                 }
             }
+            tile_sync();
             evc = evx;
         }
+        tile_sync();
 
         // ---- shot end: norm check, outputs, kept states, counters ----
         const uint32_t cnt = 1u << k;
@@ -792,54 +847,63 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
             const uint64_t kk = shot - P.keep_lo;
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
-                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8);
+                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var);
         }
         if (tracing && term < P.trace_n)
             dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
-                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8);
+                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var);
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
     }
-    myc += lane == C_ENTRIES_T ? tot.entries_t : 0ull;
-    myc += lane == C_ENTRIES_M ? tot.entries_m : 0ull;
-    myc += lane == C_NOISE ? tot.noise : 0ull;
-    myc += lane == C_EVENTS ? tot.events : 0ull;
-    if (lane < (uint32_t)C_COUNT && lane != (uint32_t)C_NORMDEV_BITS && myc) atomicAdd(P.counters + lane, (unsigned long long)myc);
-    if (lane == (uint32_t)C_NORMDEV_BITS) atomicMax(P.counters + lane, (unsigned long long)__double_as_longlong(tot.maxdev));
+    if (var_ok) flush_counters();
 }
 
-__global__ void k_reset(unsigned long long *counters, unsigned long long *next) {
-    const uint32_t t = threadIdx.x;
-    if (t < (uint32_t)C_COUNT) counters[t] = 0ull;
-    if (t == 0) *next = 0ull;
+__global__ void k_reset(unsigned long long *counters, uint32_t n, unsigned long long *next) {
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) counters[t] = 0ull;
+    if (threadIdx.x == 0) *next = 0ull;
+}
+
+template <typename R, bool EXPL, bool GT> const void *kernel_ptr() { return (const void *)k_sample<R, EXPL, GT>; }
+
+template <typename R, bool EXPL, bool GT>
+void launch_one(const RunParams &p, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL((k_sample<R, EXPL, GT>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
 }
 
 }  // namespace
 
-hipError_t launch_reset(unsigned long long *counters, unsigned long long *next, hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, counters, next);
+hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long long *next, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, stream, counters, n, next);
     return hipGetLastError();
 }
 
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
-    const bool expl = p.words != nullptr;
-    if (fp64) {
-        if (expl) hipLaunchKernelGGL((k_sample<double, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
-        else hipLaunchKernelGGL((k_sample<double, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
-    } else {
-        if (expl) hipLaunchKernelGGL((k_sample<float, true>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
-        else hipLaunchKernelGGL((k_sample<float, false>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+    const bool expl = p.words != nullptr, gt = p.gtile != nullptr;
+    const int sel = (fp64 ? 4 : 0) | (expl ? 2 : 0) | (gt ? 1 : 0);
+    switch (sel) {
+        case 0: launch_one<float, false, false>(p, grid, block, lds, stream); break;
+        case 1: launch_one<float, false, true>(p, grid, block, lds, stream); break;
+        case 2: launch_one<float, true, false>(p, grid, block, lds, stream); break;
+        case 3: launch_one<float, true, true>(p, grid, block, lds, stream); break;
+        case 4: launch_one<double, false, false>(p, grid, block, lds, stream); break;
+        case 5: launch_one<double, false, true>(p, grid, block, lds, stream); break;
+        case 6: launch_one<double, true, false>(p, grid, block, lds, stream); break;
+        default: launch_one<double, true, true>(p, grid, block, lds, stream); break;
     }
     return hipGetLastError();
 }
 
 hipError_t sampler_set_lds_limit(int bytes) {
-    hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)k_sample<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void *)k_sample<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void *)k_sample<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_sample<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *ks[8] = {kernel_ptr<float, false, false>(), kernel_ptr<float, false, true>(),
+                         kernel_ptr<float, true, false>(),  kernel_ptr<float, true, true>(),
+                         kernel_ptr<double, false, false>(), kernel_ptr<double, false, true>(),
+                         kernel_ptr<double, true, false>(),  kernel_ptr<double, true, true>()};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace soft

@@ -29,7 +29,17 @@ thread_local std::string g_create_error;
 
 struct Shape {
     uint32_t wpb = 0, bpc = 0, grab = 0;
+    uint32_t gt = 0;  // 1: coefficient tiles in device memory instead of LDS
 };
+
+struct Variant {
+    std::string text;
+    NoiseModel noise;
+    uint64_t shot_end = ~0ull;  // global shots [previous end, shot_end)
+    Program prog;
+};
+
+constexpr size_t kCounterWords = (size_t)kMaxVariants * C_COUNT + 1;
 
 template <typename T> struct DevBuf {
     T *p = nullptr;
@@ -45,10 +55,12 @@ struct soft_ctx {
     std::string err;
 
     bool have_text = false;
-    std::string text;
-    NoiseModel noise;
-    bool dirty = true;  // program must be recompiled
-    Program prog;
+    bool mixture = false;
+    NoiseModel noise;            // model of a single loaded circuit
+    std::vector<Variant> vars;   // the circuit, or the circuits of a mixture
+    bool dirty = true;           // device tables must be rebuilt
+    uint32_t kmax = 0, rec_words = 0;  // largest over the variants
+    uint64_t hash = 0;           // of every variant and its shot range
 
     uint64_t seed = 0;
     const uint32_t *words_dev = nullptr;
@@ -57,14 +69,17 @@ struct soft_ctx {
     int bits = 64;
     double tau = -1.0;
     uint32_t support_cap = 0;
+    int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory
     Shape user;                               // explicit launch shape parts
-    std::map<std::tuple<uint64_t, int, double, uint32_t>, Shape> tuned;
+    std::map<std::tuple<uint64_t, int, double, uint32_t, int>, Shape> tuned;
 
     DevBuf<Event> d_ev;
     DevBuf<NoiseLoc> d_nz;
     DevBuf<uint32_t> d_tm1, d_det;
     DevBuf<BatchMember> d_bm;
-    unsigned long long *d_counters = nullptr;  // C_COUNT + 1 (work cursor)
+    DevBuf<VariantDesc> d_vars;
+    DevBuf<unsigned char> d_gtile;            // device-memory tiles
+    unsigned long long *d_counters = nullptr;  // kMaxVariants rows of C_COUNT, then the work cursor
     double *d_phase = nullptr;                 // cos/sin of k pi/8, k = 0..15
 
     uint64_t keep_lo = 0;
@@ -120,10 +135,14 @@ template <typename T> void release(DevBuf<T> &b) {
 
 double tau_of(const soft_ctx *c) { return c->tau >= 0.0 ? c->tau : (c->bits == 32 ? 1e-6 : 1e-12); }
 
-uint32_t tile_entries(const soft_ctx *c) { return 1u << c->prog.kmax; }
-uint32_t rec_words(const soft_ctx *c) { return (c->prog.n_rec + 31u) / 32u; }
+uint32_t tile_entries(const soft_ctx *c) { return 1u << c->kmax; }
+uint32_t rec_words(const soft_ctx *c) { return c->rec_words; }
 uint32_t tile_bytes(const soft_ctx *c) { return tile_entries(c) * (c->bits == 64 ? 16u : 8u); }
-uint32_t wave_bytes(const soft_ctx *c) { return ((tile_bytes(c) + 15u) & ~15u) + ((rec_words(c) * 4u + 15u) & ~15u); }
+// LDS bytes per wave: the tile (unless it lives in device memory) and the record.
+uint32_t wave_bytes(const soft_ctx *c, bool gt) {
+    const uint32_t recb = std::max<uint32_t>(16u, (rec_words(c) * 4u + 15u) & ~15u);
+    return gt ? recb : ((tile_bytes(c) + 15u) & ~15u) + recb;
+}
 
 void drop_graph(soft_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -131,35 +150,69 @@ void drop_graph(soft_ctx *c) {
     c->gkey.clear();
 }
 
-// Compile the text (if changed) and upload the program.
-int prepare(soft_ctx *c) {
-    if (!c->have_text) return fail(c, SOFT_ESTATE, "no circuit loaded");
-    if (!c->dirty) return SOFT_OK;
-    Program p;
+int compile_into(soft_ctx *c, const std::string &text, const NoiseModel &nm, Program &out) {
     try {
-        compile_circuit(c->text, c->noise, p);
+        compile_circuit(text, nm, out);
     } catch (const CompileError &e) {
         return fail(c, e.line > 0 ? SOFT_EPARSE : SOFT_ECAPACITY,
                     e.line > 0 ? "line " + std::to_string(e.line) + ": " + e.msg : e.msg);
     } catch (const std::bad_alloc &) {
         return fail(c, SOFT_ECAPACITY, "out of host memory while compiling");
     }
-    c->prog = std::move(p);
+    return SOFT_OK;
+}
+
+// Upload the compiled variants as one set of tables: each variant's events,
+// noise locations, thresholds, check pairs and run members are appended, and
+// its references into the shared tables are rebased.
+int prepare(soft_ctx *c) {
+    if (!c->have_text) return fail(c, SOFT_ESTATE, "no circuit loaded");
+    if (!c->dirty) return SOFT_OK;
+    std::vector<Event> ev;
+    std::vector<NoiseLoc> nz;
+    std::vector<uint32_t> tm1, det;
+    std::vector<BatchMember> bm;
+    std::vector<VariantDesc> vd;
+    c->kmax = 0;
+    c->rec_words = 0;
+    uint64_t h = 1469598103934665603ULL;
+    for (const Variant &V : c->vars) {
+        const Program &P = V.prog;
+        VariantDesc D;
+        std::memset(&D, 0, sizeof(D));
+        D.shot_end = V.shot_end;
+        D.ev_off = (uint32_t)ev.size();
+        D.nz_off = (uint32_t)nz.size();
+        D.tm1_off = (uint32_t)tm1.size();
+        D.n_noise = P.n_noise;
+        const uint32_t det_base = (uint32_t)(det.size() / 2), bm_base = (uint32_t)bm.size();
+        for (Event E : P.events) {
+            E.det_off += det_base;
+            if (E.flags & EVF_BATCH) E.boff += bm_base;
+            ev.push_back(E);
+        }
+        nz.insert(nz.end(), P.noise.begin(), P.noise.end());
+        tm1.insert(tm1.end(), P.noise_tm1.begin(), P.noise_tm1.end());
+        det.insert(det.end(), P.det_pairs.begin(), P.det_pairs.end());
+        bm.insert(bm.end(), P.batch.begin(), P.batch.end());
+        vd.push_back(D);
+        c->kmax = std::max(c->kmax, P.kmax);
+        c->rec_words = std::max(c->rec_words, (P.n_rec + 31u) / 32u);
+        h = (h ^ P.hash) * 1099511628211ULL;
+        h = (h ^ V.shot_end) * 1099511628211ULL;
+    }
+    c->hash = h;
     int rc;
-    if ((rc = ensure(c, c->d_ev, c->prog.events.size())) ||
-        (rc = ensure(c, c->d_nz, std::max<size_t>(c->prog.noise.size(), 1))) ||
-        (rc = ensure(c, c->d_tm1, c->prog.noise_tm1.size())) ||
-        (rc = ensure(c, c->d_det, std::max<size_t>(c->prog.det_pairs.size(), 2))) ||
-        (rc = ensure(c, c->d_bm, std::max<size_t>(c->prog.batch.size(), 1))))
+    if ((rc = ensure(c, c->d_ev, ev.size())) || (rc = ensure(c, c->d_nz, std::max<size_t>(nz.size(), 1))) ||
+        (rc = ensure(c, c->d_tm1, tm1.size())) || (rc = ensure(c, c->d_det, std::max<size_t>(det.size(), 2))) ||
+        (rc = ensure(c, c->d_bm, std::max<size_t>(bm.size(), 1))) || (rc = ensure(c, c->d_vars, vd.size())))
         return rc;
-    HIPCHK(c, hipMemcpy(c->d_ev.p, c->prog.events.data(), c->prog.events.size() * sizeof(Event), hipMemcpyHostToDevice));
-    if (!c->prog.noise.empty())
-        HIPCHK(c, hipMemcpy(c->d_nz.p, c->prog.noise.data(), c->prog.noise.size() * sizeof(NoiseLoc), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->d_tm1.p, c->prog.noise_tm1.data(), c->prog.noise_tm1.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    if (!c->prog.det_pairs.empty())
-        HIPCHK(c, hipMemcpy(c->d_det.p, c->prog.det_pairs.data(), c->prog.det_pairs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    if (!c->prog.batch.empty())
-        HIPCHK(c, hipMemcpy(c->d_bm.p, c->prog.batch.data(), c->prog.batch.size() * sizeof(BatchMember), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_ev.p, ev.data(), ev.size() * sizeof(Event), hipMemcpyHostToDevice));
+    if (!nz.empty()) HIPCHK(c, hipMemcpy(c->d_nz.p, nz.data(), nz.size() * sizeof(NoiseLoc), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_tm1.p, tm1.data(), tm1.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!det.empty()) HIPCHK(c, hipMemcpy(c->d_det.p, det.data(), det.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!bm.empty()) HIPCHK(c, hipMemcpy(c->d_bm.p, bm.data(), bm.size() * sizeof(BatchMember), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_vars.p, vd.data(), vd.size() * sizeof(VariantDesc), hipMemcpyHostToDevice));
     c->dirty = false;
     drop_graph(c);
     return SOFT_OK;
@@ -171,10 +224,23 @@ constexpr uint32_t kMaxWavesPerCu = 32u;
 
 // Untuned launch shape: as many resident waves per CU as the LDS tiles allow
 // (at most 32), two waves per block when that still leaves >= 16 waves.
+// Device-memory tiles are used when asked for, or (auto) when one wave's LDS
+// tile does not fit in a block's LDS.
+bool tiles_in_memory(const soft_ctx *c) {
+    if (c->tile_mode == 2) return true;
+    if (c->tile_mode == 1) return false;
+    return wave_bytes(c, false) > (uint32_t)c->max_lds_block;
+}
+
+// Resident waves per CU when the tile is not the limit (4 waves per SIMD).
+constexpr uint32_t kMemTileWavesPerCu = 16u;
+
 Shape default_shape(const soft_ctx *c) {
     Shape s;
-    const uint32_t wb = wave_bytes(c);
-    const uint32_t waves_cu = std::max<uint32_t>(1u, std::min<uint32_t>(kMaxWavesPerCu, kLdsPerCu / wb));
+    s.gt = tiles_in_memory(c) ? 1u : 0u;
+    const uint32_t wb = wave_bytes(c, s.gt);
+    const uint32_t cap = s.gt ? kMemTileWavesPerCu : kMaxWavesPerCu;
+    const uint32_t waves_cu = std::max<uint32_t>(1u, std::min<uint32_t>(cap, kLdsPerCu / wb));
     s.wpb = (waves_cu >= 16u && 2u * wb <= (uint32_t)c->max_lds_block) ? 2u : 1u;
     while (s.wpb > 1 && s.wpb * wb > (uint32_t)c->max_lds_block) s.wpb /= 2;
     s.bpc = std::max<uint32_t>(1u, waves_cu / s.wpb);
@@ -184,8 +250,9 @@ Shape default_shape(const soft_ctx *c) {
 
 Shape current_shape(const soft_ctx *c) {
     Shape s = default_shape(c);
-    auto it = c->tuned.find(std::make_tuple(c->prog.hash, c->bits, tau_of(c), c->support_cap));
+    auto it = c->tuned.find(std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode));
     if (it != c->tuned.end()) s = it->second;
+    if (c->tile_mode) s.gt = c->tile_mode == 2 ? 1u : 0u;
     if (c->user.wpb) s.wpb = c->user.wpb;
     if (c->user.bpc) s.bpc = c->user.bpc;
     if (c->user.grab) s.grab = c->user.grab;
@@ -193,22 +260,29 @@ Shape current_shape(const soft_ctx *c) {
 }
 
 int check_shape(soft_ctx *c, const Shape &s) {
-    const uint64_t lds = (uint64_t)s.wpb * wave_bytes(c);
+    const uint64_t lds = (uint64_t)s.wpb * wave_bytes(c, s.gt);
     if (s.wpb < 1 || s.wpb > 4) return fail(c, SOFT_EINVAL, "waves_per_block must be 1..4");
     if (lds > (uint64_t)c->max_lds_block)
         return fail(c, SOFT_ECAPACITY, "coefficient tile needs " + std::to_string(lds) + " bytes of LDS per block; the device allows " +
-                                           std::to_string(c->max_lds_block) + " (span dimension " + std::to_string(c->prog.kmax) + ")");
+                                           std::to_string(c->max_lds_block) + " (span dimension " + std::to_string(c->kmax) + ")");
     if (s.bpc < 1 || s.grab < 1 || s.grab > 64) return fail(c, SOFT_EINVAL, "blocks_per_cu must be >= 1 and grab in 1..64");
     return SOFT_OK;
 }
 
 // Launch reset + sampler on `stream` through a cached hipGraph.
-int launch(soft_ctx *c, const RunParams &rp, const Shape &s, uint64_t n_shots, hipStream_t stream) {
-    const uint32_t wb = wave_bytes(c);
+int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStream_t stream) {
+    const uint32_t wb = wave_bytes(c, s.gt);
     const size_t lds = (size_t)s.wpb * wb;
     uint64_t blocks_needed = (n_shots + s.wpb - 1) / s.wpb;
     uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cus * s.bpc, std::max<uint64_t>(blocks_needed, 1));
     const dim3 g((uint32_t)grid), b(64u * s.wpb);
+    rp.wave_bytes = wb;
+    rp.gtile = nullptr;
+    if (s.gt) {  // one slab per wave of the grid
+        int rc = ensure(c, c->d_gtile, (size_t)grid * s.wpb * tile_bytes(c));
+        if (rc) return rc;
+        rp.gtile = c->d_gtile.p;
+    }
     std::vector<unsigned char> key(sizeof(RunParams) + 3 * sizeof(uint64_t) + sizeof(int));
     unsigned char *kp = key.data();
     std::memcpy(kp, &rp, sizeof(RunParams));
@@ -219,7 +293,7 @@ int launch(soft_ctx *c, const RunParams &rp, const Shape &s, uint64_t n_shots, h
         drop_graph(c);
         hipGraph_t graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = launch_reset(rp.counters, rp.next, c->capture_stream);
+        hipError_t e1 = launch_reset(rp.counters, rp.n_vars * (uint32_t)C_COUNT, rp.next, c->capture_stream);
         hipError_t e2 = e1 == hipSuccess ? launch_sampler(rp, c->bits == 64, g, b, lds, c->capture_stream) : e1;
         hipError_t e3 = hipStreamEndCapture(c->capture_stream, &graph);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -247,24 +321,24 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.tm1 = c->d_tm1.p;
     rp.det = c->d_det.p;
     rp.bm = c->d_bm.p;
+    rp.vars = c->d_vars.p;
+    rp.n_vars = (uint32_t)c->vars.size();
     rp.words = c->words_dev;
     rp.phase_tab = c->d_phase;
-    rp.word_stride = (uint64_t)c->prog.n_noise + c->prog.n_meas;
+    rp.word_stride = (uint64_t)c->vars[0].prog.n_noise + c->vars[0].prog.n_meas;
     rp.outcomes = outcomes;
     rp.status = status;
     rp.abort_op = abort_op;
     rp.obs = obs;
     rp.counters = c->d_counters;
-    rp.next = c->d_counters + C_COUNT;
+    rp.next = c->d_counters + kCounterWords - 1;
     rp.seed = c->seed;
     rp.shot0 = shot0;
     rp.n_shots = n_shots;
-    rp.n_noise = c->prog.n_noise;
     rp.rec_words = rec_words(c);
     rp.support_cap = c->support_cap ? c->support_cap : 0xFFFFFFFFu;
     rp.tile_entries = tile_entries(c);
     rp.tile_bytes = tile_bytes(c);
-    rp.wave_bytes = wave_bytes(c);
     const double t = tau_of(c);
     rp.tau2 = t * t;
     rp.grab = 1;
@@ -311,6 +385,17 @@ int run_impl(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, 
     return SOFT_OK;
 }
 
+// Frame (x/z bits and span basis) in which a dumped state is expressed.
+const Frame *frame_of(soft_ctx *c, const std::vector<unsigned long long> &meta, int &rc) {
+    const uint64_t v = meta[KM_VAR], term = meta[KM_TERM_EV];
+    if (v >= c->vars.size() || term >= c->vars[v].prog.events.size()) {
+        rc = fail(c, SOFT_EDEVICE, "corrupt dumped state");
+        return nullptr;
+    }
+    const Program &P = c->vars[v].prog;
+    return meta[KM_AFTER] ? &P.after[term] : &P.before[term];
+}
+
 const Frame *kept_frame(soft_ctx *c, uint64_t shot, std::vector<unsigned long long> &meta, std::vector<double> &tile, int &rc) {
     rc = SOFT_OK;
     if (!c->ran) { rc = fail(c, SOFT_ESTATE, "no run yet"); return nullptr; }
@@ -328,9 +413,7 @@ const Frame *kept_frame(soft_ctx *c, uint64_t shot, std::vector<unsigned long lo
     if (e == hipSuccess)
         e = hipMemcpy(tile.data(), c->d_keep_v.p + kk * (uint64_t)c->keep_tile * 2, tile.size() * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) { rc = fail(c, SOFT_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e)); return nullptr; }
-    const uint64_t term = meta[KM_TERM_EV];
-    if (term >= c->prog.events.size()) { rc = fail(c, SOFT_EDEVICE, "corrupt kept state"); return nullptr; }
-    return meta[KM_AFTER] ? &c->prog.after[term] : &c->prog.before[term];
+    return frame_of(c, meta, rc);
 }
 
 // Coefficients of a dumped state: alpha(j) = a ^ sum_t j_t b_t over the
@@ -366,9 +449,9 @@ int decode_coeffs(soft_ctx *c, const Frame &f, const std::vector<unsigned long l
 }
 
 // Tableau rows of a dumped state: x/z from the frame, signs from the shot.
-void decode_tableau(const soft_ctx *c, const Frame &f, const std::vector<unsigned long long> &meta, uint64_t *x,
+void decode_tableau(const Frame &f, const std::vector<unsigned long long> &meta, uint64_t *x,
                     uint64_t *z, uint8_t *r) {
-    const int n = c->prog.n;
+    const int n = (int)f.xd.size();
     for (int i = 0; i < n; ++i) {
         uint64_t xd = 0, zd = 0, xs = 0, zs = 0;
         for (int q = 0; q < n; ++q) {
@@ -418,9 +501,9 @@ int soft_create(soft_ctx **out, int hip_device) {
         (void)hipGetLastError();
         c->max_lds_block = std::min(lds, 65536);
     }
-    if ((e = hipMalloc((void **)&c->d_counters, (C_COUNT + 1) * sizeof(unsigned long long))) != hipSuccess)
+    if ((e = hipMalloc((void **)&c->d_counters, kCounterWords * sizeof(unsigned long long))) != hipSuccess)
         return bad(e, "hipMalloc");
-    if ((e = hipMemset(c->d_counters, 0, (C_COUNT + 1) * sizeof(unsigned long long))) != hipSuccess) return bad(e, "hipMemset");
+    if ((e = hipMemset(c->d_counters, 0, kCounterWords * sizeof(unsigned long long))) != hipSuccess) return bad(e, "hipMemset");
     if ((e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess) return bad(e, "hipStreamCreate");
     {
         double tab[32];
@@ -445,6 +528,8 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_tm1);
     release(c->d_det);
     release(c->d_bm);
+    release(c->d_vars);
+    release(c->d_gtile);
     release(c->d_keep_meta);
     release(c->d_keep_v);
     release(c->d_trace_meta);
@@ -459,17 +544,15 @@ const char *soft_last_error(const soft_ctx *c) { return c ? c->err.c_str() : g_c
 
 int soft_load_circuit(soft_ctx *c, const char *text, size_t len) {
     if (!c || (!text && len)) return fail(c, SOFT_EINVAL, "null argument");
-    std::string t(text ? text : "", len);
-    // validate now so that errors surface at load time
-    Program p;
-    try {
-        compile_circuit(t, c->noise, p);
-    } catch (const CompileError &e) {
-        return fail(c, e.line > 0 ? SOFT_EPARSE : SOFT_ECAPACITY,
-                    e.line > 0 ? "line " + std::to_string(e.line) + ": " + e.msg : e.msg);
-    }
-    c->text = std::move(t);
+    Variant V;
+    V.text.assign(text ? text : "", len);
+    V.noise = c->noise;
+    int rc = compile_into(c, V.text, V.noise, V.prog);
+    if (rc) return rc;
+    c->vars.clear();
+    c->vars.push_back(std::move(V));
     c->have_text = true;
+    c->mixture = false;
     c->dirty = true;
     (void)hipSetDevice(c->device);
     return prepare(c);
@@ -477,17 +560,59 @@ int soft_load_circuit(soft_ctx *c, const char *text, size_t len) {
 
 int soft_load_noise(soft_ctx *c, const soft_noise *m) {
     if (!c || !m) return fail(c, SOFT_EINVAL, "null argument");
-    const double ps[6] = {m->p1, m->p2, m->p_idle, m->p_meas, m->p_reset, m->p_mpp};
+    if (c->mixture) return fail(c, SOFT_ESTATE, "a mixture carries one noise model per variant; load it again instead");
+    NoiseModel nm;
+    nm.p1 = m->p1;
+    nm.p2 = m->p2;
+    nm.p_idle = m->p_idle;
+    nm.p_meas = m->p_meas;
+    nm.p_reset = m->p_reset;
+    nm.p_mpp = m->p_mpp;
+    const double ps[6] = {nm.p1, nm.p2, nm.p_idle, nm.p_meas, nm.p_reset, nm.p_mpp};
     for (double p : ps)
         if (!(p >= 0.0 && p <= 1.0)) return fail(c, SOFT_EINVAL, "noise probability out of [0,1]");
-    c->noise.p1 = m->p1;
-    c->noise.p2 = m->p2;
-    c->noise.p_idle = m->p_idle;
-    c->noise.p_meas = m->p_meas;
-    c->noise.p_reset = m->p_reset;
-    c->noise.p_mpp = m->p_mpp;
-    c->dirty = true;
+    if (c->have_text) {
+        Program P;
+        int rc = compile_into(c, c->vars[0].text, nm, P);
+        if (rc) return rc;
+        c->vars[0].noise = nm;
+        c->vars[0].prog = std::move(P);
+        c->dirty = true;
+    }
+    c->noise = nm;
     if (!c->have_text) return SOFT_OK;
+    (void)hipSetDevice(c->device);
+    return prepare(c);
+}
+
+int soft_load_mixture(soft_ctx *c, uint32_t n_variants, const char *const *texts, const size_t *lens,
+                      const soft_noise *models, const uint64_t *shot_ends) {
+    if (!c || !texts || !lens || !models || !shot_ends) return fail(c, SOFT_EINVAL, "null argument");
+    if (n_variants < 1 || n_variants > kMaxVariants)
+        return fail(c, SOFT_EINVAL, "n_variants must be in 1.." + std::to_string(kMaxVariants));
+    std::vector<Variant> vs(n_variants);
+    for (uint32_t v = 0; v < n_variants; ++v) {
+        if (!texts[v] && lens[v]) return fail(c, SOFT_EINVAL, "null circuit text");
+        if (shot_ends[v] == 0 || (v > 0 && shot_ends[v] <= shot_ends[v - 1]))
+            return fail(c, SOFT_EINVAL, "shot_ends must be positive and strictly increasing");
+        const soft_noise &m = models[v];
+        NoiseModel nm;
+        nm.p1 = m.p1;
+        nm.p2 = m.p2;
+        nm.p_idle = m.p_idle;
+        nm.p_meas = m.p_meas;
+        nm.p_reset = m.p_reset;
+        nm.p_mpp = m.p_mpp;
+        vs[v].text.assign(texts[v] ? texts[v] : "", lens[v]);
+        vs[v].noise = nm;
+        vs[v].shot_end = shot_ends[v];
+        int rc = compile_into(c, vs[v].text, nm, vs[v].prog);
+        if (rc) return fail(c, rc, "variant " + std::to_string(v) + ": " + c->err);
+    }
+    c->vars = std::move(vs);
+    c->have_text = true;
+    c->mixture = true;
+    c->dirty = true;
     (void)hipSetDevice(c->device);
     return prepare(c);
 }
@@ -539,6 +664,13 @@ int soft_set_caps(soft_ctx *c, uint32_t support_cap, uint32_t wpb, uint32_t bpc,
     return SOFT_OK;
 }
 
+int soft_set_tile_memory(soft_ctx *c, int mode) {
+    if (!c) return SOFT_EINVAL;
+    if (mode < 0 || mode > 2) return fail(c, SOFT_EINVAL, "tile memory mode must be 0 (auto), 1 (LDS) or 2 (device memory)");
+    c->tile_mode = mode;
+    return SOFT_OK;
+}
+
 int soft_set_keep(soft_ctx *c, uint64_t shot_lo, uint32_t count) {
     if (!c) return SOFT_EINVAL;
     if (count > 4096) return fail(c, SOFT_ECAPACITY, "at most 4096 kept shots");
@@ -555,38 +687,63 @@ int soft_run(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, 
     int rc = prepare(c);
     if (rc) return rc;
     if (c->words_dev) {
-        if (c->words_noise != c->prog.n_noise || c->words_meas != c->prog.n_meas)
-            return fail(c, SOFT_EINVAL, "explicit words: expected " + std::to_string(c->prog.n_noise) + " noise and " +
-                                            std::to_string(c->prog.n_meas) + " measurement slots per shot");
+        if (c->mixture) return fail(c, SOFT_EUNSUPPORTED, "explicit words are for a single circuit, not a mixture");
+        const Program &P = c->vars[0].prog;
+        if (c->words_noise != P.n_noise || c->words_meas != P.n_meas)
+            return fail(c, SOFT_EINVAL, "explicit words: expected " + std::to_string(P.n_noise) + " noise and " +
+                                            std::to_string(P.n_meas) + " measurement slots per shot");
         if (n_shots > c->words_n) return fail(c, SOFT_EINVAL, "explicit words: fewer rows than shots");
     }
+    if (shot0 + n_shots < shot0 || shot0 + n_shots > c->vars.back().shot_end)
+        return fail(c, SOFT_EINVAL, "shots beyond the last variant's range");
     if (n_shots == 0) return SOFT_OK;
     Shape s = current_shape(c);
     if ((rc = check_shape(c, s))) return rc;
     return run_impl(c, shot0, n_shots, outcomes, status, abort_op, obs, (hipStream_t)hip_stream, s);
 }
 
-int soft_read_counters(soft_ctx *c, soft_counters *out) {
-    if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
+namespace {
+// Sum of the counter rows [v0, v1) (maximum for the norm deviation).
+int read_rows(soft_ctx *c, uint32_t v0, uint32_t v1, soft_counters *out) {
     if (!c->ran) return fail(c, SOFT_ESTATE, "no run yet");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->last_stream));
-    unsigned long long h[C_COUNT];
-    HIPCHK(c, hipMemcpy(h, c->d_counters, sizeof(h), hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> h((size_t)(v1 - v0) * C_COUNT);
+    HIPCHK(c, hipMemcpy(h.data(), c->d_counters + (size_t)v0 * C_COUNT, h.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
-    out->shots = h[C_SHOTS];
-    out->passed = h[C_PASSED];
-    out->discarded = h[C_DISCARDED];
-    out->overflow = h[C_OVERFLOW];
-    out->numeric = h[C_NUMERIC];
-    out->logical_errors = h[C_LOGICAL];
-    out->entries_t = h[C_ENTRIES_T];
-    out->entries_m = h[C_ENTRIES_M];
-    out->noise_slots = h[C_NOISE];
-    out->events = h[C_EVENTS];
-    for (int b = 0; b < 16; ++b) out->support_hist[b] = h[C_HIST0 + b];
-    std::memcpy(&out->max_norm_dev, &h[C_NORMDEV_BITS], sizeof(double));
+    double dev = 0.0;
+    for (uint32_t v = 0; v < v1 - v0; ++v) {
+        const unsigned long long *r = h.data() + (size_t)v * C_COUNT;
+        out->shots += r[C_SHOTS];
+        out->passed += r[C_PASSED];
+        out->discarded += r[C_DISCARDED];
+        out->overflow += r[C_OVERFLOW];
+        out->numeric += r[C_NUMERIC];
+        out->logical_errors += r[C_LOGICAL];
+        out->entries_t += r[C_ENTRIES_T];
+        out->entries_m += r[C_ENTRIES_M];
+        out->noise_slots += r[C_NOISE];
+        out->events += r[C_EVENTS];
+        for (int b = 0; b < 16; ++b) out->support_hist[b] += r[C_HIST0 + b];
+        double d;
+        std::memcpy(&d, &r[C_NORMDEV_BITS], sizeof(double));
+        dev = std::max(dev, d);
+    }
+    out->max_norm_dev = dev;
     return SOFT_OK;
+}
+}  // namespace
+
+int soft_read_counters(soft_ctx *c, soft_counters *out) {
+    if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
+    return read_rows(c, 0, (uint32_t)c->vars.size(), out);
+}
+
+int soft_read_variant_counters(soft_ctx *c, uint32_t variant, soft_counters *out) {
+    if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
+    if (variant >= c->vars.size()) return fail(c, SOFT_EINVAL, "no such variant");
+    return read_rows(c, variant, variant + 1, out);
 }
 
 int soft_read_coeffs(soft_ctx *c, uint64_t shot, uint64_t *alpha, double *re, double *im, uint32_t cap, uint32_t *count) {
@@ -608,7 +765,7 @@ int soft_read_tableau(soft_ctx *c, uint64_t shot, uint64_t *x, uint64_t *z, uint
     int rc;
     const Frame *f = kept_frame(c, shot, meta, tile, rc);
     if (!f) return rc;
-    decode_tableau(c, *f, meta, x, z, r);
+    decode_tableau(*f, meta, x, z, r);
     return SOFT_OK;
 }
 
@@ -636,39 +793,59 @@ int soft_read_trace(soft_ctx *c, uint32_t step, uint64_t info[6], uint64_t *x, u
     if (meta[KM_VALID] != kStateValid) return SOFT_OK;
     HIPCHK(c, hipMemcpy(tile.data(), c->d_trace_v.p + (uint64_t)step * c->trace_tile * 2, tile.size() * sizeof(double),
                         hipMemcpyDeviceToHost));
-    const uint64_t term = meta[KM_TERM_EV];
-    if (term >= c->prog.events.size()) return fail(c, SOFT_EDEVICE, "corrupt trace entry");
-    const Frame &f = meta[KM_AFTER] ? c->prog.after[term] : c->prog.before[term];
+    int rc = SOFT_OK;
+    const Frame *f = frame_of(c, meta, rc);
+    if (!f) return rc;
+    const Event &E = c->vars[meta[KM_VAR]].prog.events[meta[KM_TERM_EV]];
     info[0] = 1;
-    info[1] = (meta[KM_STATUS] != ST_PASSED && meta[KM_ABORT] != 0xFFFFFFFFull) ? meta[KM_ABORT] : c->prog.events[term].src;
+    info[1] = (meta[KM_STATUS] != ST_PASSED && meta[KM_ABORT] != 0xFFFFFFFFull) ? meta[KM_ABORT] : E.src;
     info[2] = meta[KM_STATUS];
     info[3] = meta[KM_K];
     info[4] = meta[KM_NRM2];
-    info[5] = (meta[KM_STATUS] != ST_PASSED || c->prog.events[term].kind == EV_END) ? 1 : 0;
-    decode_tableau(c, f, meta, x, z, r);
+    info[5] = (meta[KM_STATUS] != ST_PASSED || E.kind == EV_END) ? 1 : 0;
+    decode_tableau(*f, meta, x, z, r);
     uint32_t cnt = 0;
-    int rc = decode_coeffs(c, f, meta, tile, alpha, re, im, cap, &cnt);
+    rc = decode_coeffs(c, *f, meta, tile, alpha, re, im, cap, &cnt);
     if (count) *count = cnt;
     return rc;
 }
+
+namespace {
+void program_info(const Program &P, uint64_t info[8]) {
+    info[0] = (uint64_t)P.n;
+    info[1] = P.n_rec;
+    info[2] = P.n_noise;
+    info[3] = P.n_meas;
+    info[4] = P.n_obs;
+    info[5] = P.events.size();
+    info[6] = P.kmax;
+    info[7] = (P.n_rec + 31u) / 32u;
+}
+}  // namespace
 
 int soft_circuit_info(soft_ctx *c, uint64_t info[8]) {
     if (!c || !info) return fail(c, SOFT_EINVAL, "null argument");
     (void)hipSetDevice(c->device);
     int rc = prepare(c);
     if (rc) return rc;
-    info[0] = (uint64_t)c->prog.n;
-    info[1] = c->prog.n_rec;
-    info[2] = c->prog.n_noise;
-    info[3] = c->prog.n_meas;
-    info[4] = c->prog.n_obs;
-    info[5] = c->prog.events.size();
-    info[6] = c->prog.kmax;
-    info[7] = rec_words(c);
+    for (int i = 0; i < 8; ++i) info[i] = 0;
+    for (const Variant &V : c->vars) {
+        uint64_t vi[8];
+        program_info(V.prog, vi);
+        for (int i = 0; i < 8; ++i) info[i] = std::max(info[i], vi[i]);
+    }
     return SOFT_OK;
 }
 
-int soft_launch_shape(soft_ctx *c, uint32_t out[4]) {
+int soft_variant_info(soft_ctx *c, uint32_t variant, uint64_t info[8]) {
+    if (!c || !info) return fail(c, SOFT_EINVAL, "null argument");
+    if (!c->have_text) return fail(c, SOFT_ESTATE, "no circuit loaded");
+    if (variant >= c->vars.size()) return fail(c, SOFT_EINVAL, "no such variant");
+    program_info(c->vars[variant].prog, info);
+    return SOFT_OK;
+}
+
+int soft_launch_shape(soft_ctx *c, uint32_t out[5]) {
     if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
     (void)hipSetDevice(c->device);
     int rc = prepare(c);
@@ -677,7 +854,8 @@ int soft_launch_shape(soft_ctx *c, uint32_t out[4]) {
     out[0] = s.wpb;
     out[1] = s.bpc;
     out[2] = s.grab;
-    out[3] = wave_bytes(c);
+    out[3] = wave_bytes(c, s.gt);
+    out[4] = s.gt;
     return SOFT_OK;
 }
 
@@ -688,47 +866,77 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     int rc = prepare(c);
     if (rc) return rc;
     if (c->words_dev) return fail(c, SOFT_ESTATE, "autotune runs on Philox draws; clear explicit uniforms first");
+    uint32_t *d_status_holder = nullptr;
     hipStream_t st = (hipStream_t)hip_stream;
+    // The sample: the first shots of each variant's range, sample_shots in all.
+    std::vector<std::pair<uint64_t, uint64_t>> seg;
+    {
+        const uint64_t per = std::max<uint64_t>(1, sample_shots / c->vars.size());
+        uint64_t lo = 0;
+        for (const Variant &V : c->vars) {
+            seg.push_back({lo, std::min<uint64_t>(per, V.shot_end - lo)});
+            lo = V.shot_end;
+        }
+    }
+    uint64_t seg_max = 0;
+    for (auto &g : seg) seg_max = std::max(seg_max, g.second);
+    auto sample_pass = [&](const Shape &s) {
+        int r = SOFT_OK;
+        for (auto &g : seg)
+            if (!r) r = run_impl(c, g.first, g.second, nullptr, d_status_holder, nullptr, nullptr, st, s);
+        return r;
+    };
     uint32_t *d_status = nullptr;
-    HIPCHK(c, hipMalloc((void **)&d_status, sample_shots * sizeof(uint32_t)));
+    HIPCHK(c, hipMalloc((void **)&d_status, seg_max * sizeof(uint32_t)));
+    d_status_holder = d_status;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     HIPCHK(c, hipEventCreate(&t0));
     HIPCHK(c, hipEventCreate(&t1));
     const uint32_t keep_n = c->keep_n;
     c->keep_n = 0;
-    const uint32_t wb = wave_bytes(c);
     Shape best;
     float best_ms = 1e30f;
     const uint32_t wpbs[3] = {1, 2, 4};
     const uint32_t grabs[2] = {16, 64};
-    for (uint32_t wpb : wpbs) {
-        if (wpb * wb > (uint32_t)c->max_lds_block) continue;
-        const uint32_t occ = std::min<uint32_t>(std::max<uint32_t>(1u, kLdsPerCu / (wpb * wb)), kMaxWavesPerCu / wpb);
-        std::vector<uint32_t> bpcs;
-        for (uint32_t d : {4u, 2u, 1u}) {
-            uint32_t v = std::max<uint32_t>(1u, occ / d);
-            if (std::find(bpcs.begin(), bpcs.end(), v) == bpcs.end()) bpcs.push_back(v);
-        }
-        for (uint32_t bpc : bpcs) {
-            for (uint32_t grab : grabs) {
-                Shape s;
-                s.wpb = wpb;
-                s.bpc = bpc;
-                s.grab = grab;
-                float ms = 0.0f;
-                // one untimed run, then one timed run
-                rc = run_impl(c, 0, sample_shots, nullptr, d_status, nullptr, nullptr, st, s);
-                hipError_t e = rc ? hipSuccess : hipEventRecord(t0, st);
-                if (!rc && e == hipSuccess) rc = run_impl(c, 0, sample_shots, nullptr, d_status, nullptr, nullptr, st, s);
-                if (!rc && e == hipSuccess) e = hipEventRecord(t1, st);
-                if (!rc && e == hipSuccess) e = hipEventSynchronize(t1);
-                if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                if (!rc && e != hipSuccess) rc = fail(c, SOFT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
-                if (rc) break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = s;
+    // Tile placements to try: the forced one, or LDS (if it fits) and device memory.
+    std::vector<uint32_t> gts;
+    if (c->tile_mode == 1) gts = {0u};
+    else if (c->tile_mode == 2) gts = {1u};
+    else gts = tiles_in_memory(c) ? std::vector<uint32_t>{1u} : std::vector<uint32_t>{0u, 1u};
+    for (uint32_t gt : gts) {
+        const uint32_t wb = wave_bytes(c, gt != 0);
+        for (uint32_t wpb : wpbs) {
+            if (wpb * wb > (uint32_t)c->max_lds_block) continue;
+            const uint32_t cap = gt ? kMemTileWavesPerCu : kMaxWavesPerCu;
+            const uint32_t occ = std::max<uint32_t>(1u, std::min<uint32_t>(kLdsPerCu / (wpb * wb), cap / wpb));
+            std::vector<uint32_t> bpcs;
+            for (uint32_t d : {4u, 2u, 1u}) {
+                uint32_t v = std::max<uint32_t>(1u, occ / d);
+                if (std::find(bpcs.begin(), bpcs.end(), v) == bpcs.end()) bpcs.push_back(v);
+            }
+            for (uint32_t bpc : bpcs) {
+                for (uint32_t grab : grabs) {
+                    Shape s;
+                    s.wpb = wpb;
+                    s.bpc = bpc;
+                    s.grab = grab;
+                    s.gt = gt;
+                    float ms = 0.0f;
+                    // one untimed run, then one timed run
+                    rc = sample_pass(s);
+                    hipError_t e = rc ? hipSuccess : hipEventRecord(t0, st);
+                    if (!rc && e == hipSuccess) rc = sample_pass(s);
+                    if (!rc && e == hipSuccess) e = hipEventRecord(t1, st);
+                    if (!rc && e == hipSuccess) e = hipEventSynchronize(t1);
+                    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                    if (!rc && e != hipSuccess) rc = fail(c, SOFT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+                    if (rc) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = s;
+                    }
                 }
+                if (rc) break;
             }
             if (rc) break;
         }
@@ -740,7 +948,7 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     (void)hipStreamSynchronize(st);
     (void)hipFree(d_status);
     if (rc) return rc;
-    c->tuned[std::make_tuple(c->prog.hash, c->bits, tau_of(c), c->support_cap)] = best;
+    c->tuned[std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode)] = best;
     c->ran = false;  // counters of the last sample run are not a user run
     return SOFT_OK;
 }

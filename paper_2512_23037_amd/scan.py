@@ -1,0 +1,59 @@
+"""Command line for long runs: a noise scan with logical error rates and
+intervals, or a throughput-against-batch-size sweep.
+
+  python -m paper_2512_23037_amd.scan --circuit FILE --p 2.5e-4,5e-4,1e-3 \\
+         --shots-per-p 1000000000 --batch 10000000 --bits 32
+  python -m paper_2512_23037_amd.scan --circuit FILE --p 1e-3 --sweep 4096,65536,1048576
+
+One JSON line per noise rate (or per batch size) on stdout, progress on
+stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2512_23037_amd.scan")
+    ap.add_argument("--circuit", required=True, help="circuit text file")
+    ap.add_argument("--p", default="1e-3", help="comma-separated circuit-level noise rates")
+    ap.add_argument("--shots-per-p", type=float, default=1e7)
+    ap.add_argument("--batch", type=float, default=1e7)
+    ap.add_argument("--bits", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sweep", default="", help="comma-separated shots per launch: throughput sweep instead of a scan")
+    args = ap.parse_args(argv)
+    text = open(args.circuit).read()
+    ps = [float(x) for x in args.p.split(",") if x]
+
+    import torch  # noqa: F401  (loads the HIP runtime before the library)
+
+    from . import soft, stats
+
+    if args.sweep:
+        sizes = [int(float(x)) for x in args.sweep.split(",") if x]
+        ctx = soft.Context(0)
+        ctx.load_noise(**{k: ps[0] for k in ("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp")})
+        ctx.load_circuit(text)
+        ctx.set_rng(args.seed)
+        ctx.set_precision(args.bits)
+        for row in stats.batch_sweep(ctx, sizes):
+            row.update({"p": ps[0], "bits": args.bits})
+            print(json.dumps(row), flush=True)
+        return 0
+
+    def progress(done, total, secs):
+        print("scan: %d / %d shots, %.1f s" % (done, total, secs), file=sys.stderr, flush=True)
+
+    rows = stats.noise_scan(text, ps, int(args.shots_per_p), int(args.batch), bits=args.bits, seed=args.seed,
+                            progress=progress)
+    for r in rows:
+        r["bits"] = args.bits
+        print(json.dumps(r), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

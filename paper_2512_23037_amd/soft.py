@@ -23,7 +23,8 @@ ERROR_NAMES = {SOFT_EINVAL: "EINVAL", SOFT_EPARSE: "EPARSE", SOFT_ECAPACITY: "EC
 EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit", "soft_load_noise",
            "soft_set_rng", "soft_set_uniforms", "soft_set_precision", "soft_set_prune", "soft_set_caps",
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
-           "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace")
+           "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
+           "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory")
 
 
 class SoftError(RuntimeError):
@@ -83,6 +84,10 @@ def load_library(path: str = LIB_PATH):
         "soft_launch_shape": (I, [P, P]),
         "soft_set_trace": (I, [P, U64, U32]),
         "soft_read_trace": (I, [P, U32, P, P, P, P, P, P, P, U32, ctypes.POINTER(U32)]),
+        "soft_load_mixture": (I, [P, U32, P, P, P, P]),
+        "soft_read_variant_counters": (I, [P, U32, ctypes.POINTER(soft_counters)]),
+        "soft_variant_info": (I, [P, U32, P]),
+        "soft_set_tile_memory": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -119,6 +124,7 @@ class Context:
             raise SoftError(rc, (self._lib.soft_last_error(None) or b"").decode())
         self._h = h
         self.device = device
+        self._ends = None  # shot ranges of a loaded mixture
 
     def close(self):
         if getattr(self, "_h", None):
@@ -139,6 +145,32 @@ class Context:
     def load_circuit(self, text: str):
         b = text.encode()
         self._check(self._lib.soft_load_circuit(self._h, b, len(b)))
+        self._ends = None
+
+    def load_mixture(self, texts, models, shot_ends):
+        """Variant v = (texts[v], models[v] as a dict of soft_noise fields)
+        owns the global shots [shot_ends[v-1], shot_ends[v])."""
+        import numpy as np
+        n = len(texts)
+        if not (len(models) == n == len(shot_ends)):
+            raise ValueError("texts, models and shot_ends differ in length")
+        bufs = [t.encode() for t in texts]
+        tarr = (ctypes.c_char_p * n)(*bufs)
+        larr = (ctypes.c_size_t * n)(*[len(b) for b in bufs])
+        marr = (soft_noise * n)(*[soft_noise(*(float(m.get(k, 0.0)) for k, _ in soft_noise._fields_)) for m in models])
+        ends = np.ascontiguousarray(shot_ends, dtype=np.uint64)
+        self._check(self._lib.soft_load_mixture(self._h, n, ctypes.cast(tarr, ctypes.c_void_p),
+                                                ctypes.cast(larr, ctypes.c_void_p), ctypes.cast(marr, ctypes.c_void_p),
+                                                _ptr(ends)))
+        self._ends = [int(x) for x in ends]
+
+    def variant_of(self, shot: int) -> int:
+        if self._ends is None:
+            return 0
+        for v, e in enumerate(self._ends):
+            if shot < e:
+                return v
+        raise ValueError("shot beyond the mixture's ranges")
 
     def load_noise(self, p1=0.0, p2=0.0, p_idle=0.0, p_meas=0.0, p_reset=0.0, p_mpp=0.0):
         m = soft_noise(p1, p2, p_idle, p_meas, p_reset, p_mpp)
@@ -159,6 +191,10 @@ class Context:
     def set_caps(self, support_cap=0, waves_per_block=0, blocks_per_cu=0, grab=0):
         self._check(self._lib.soft_set_caps(self._h, support_cap, waves_per_block, blocks_per_cu, grab))
 
+    def set_tile_memory(self, mode: int):
+        """0 automatic, 1 LDS, 2 device memory (HBM)."""
+        self._check(self._lib.soft_set_tile_memory(self._h, mode))
+
     def set_keep(self, shot_lo: int, count: int):
         self._check(self._lib.soft_set_keep(self._h, shot_lo, count))
 
@@ -172,9 +208,13 @@ class Context:
         self._check(self._lib.soft_run(self._h, shot0, n_shots, _ptr(outcomes), _ptr(status), _ptr(abort_op),
                                        _ptr(obs), _stream_handle(stream)))
 
-    def counters(self) -> dict:
+    def counters(self, variant: int | None = None) -> dict:
+        """Aggregates of the last run (of one variant's shots if given)."""
         c = soft_counters()
-        self._check(self._lib.soft_read_counters(self._h, ctypes.byref(c)))
+        if variant is None:
+            self._check(self._lib.soft_read_counters(self._h, ctypes.byref(c)))
+        else:
+            self._check(self._lib.soft_read_variant_counters(self._h, variant, ctypes.byref(c)))
         out = {f: getattr(c, f) for f, _ in soft_counters._fields_ if f != "support_hist"}
         out["support_hist"] = list(c.support_hist)
         return out
@@ -191,7 +231,7 @@ class Context:
 
     def read_tableau(self, shot: int):
         import numpy as np
-        n = self.info()["qubits"]
+        n = self.info(self.variant_of(shot))["qubits"]
         x = np.zeros(2 * n, dtype=np.uint64)
         z = np.zeros(2 * n, dtype=np.uint64)
         r = np.zeros(2 * n, dtype=np.uint8)
@@ -200,12 +240,13 @@ class Context:
 
     def set_trace(self, shot: int, steps: int):
         self._check(self._lib.soft_set_trace(self._h, shot, steps))
+        self._trace_shot = shot
 
     def read_trace(self, step: int, cap: int = 1 << 16):
         """State after event `step` of the traced shot: None if not reached,
         else a dict with op, status, k, norm2, final, tableau and coeffs."""
         import numpy as np
-        n = self.info()["qubits"]
+        n = self.info(self.variant_of(getattr(self, "_trace_shot", 0)))["qubits"]
         info = np.zeros(6, dtype=np.uint64)
         x = np.zeros(2 * n, dtype=np.uint64)
         z = np.zeros(2 * n, dtype=np.uint64)
@@ -224,18 +265,24 @@ class Context:
                 "final": bool(info[5]), "x": x, "z": z, "r": r,
                 "coeffs": {int(al[i]): complex(re[i], im[i]) for i in range(k)}}
 
-    def info(self) -> dict:
+    def info(self, variant: int | None = None) -> dict:
+        """Facts about the circuit (largest over a mixture's variants), or
+        about one variant."""
         import numpy as np
         a = np.zeros(8, dtype=np.uint64)
-        self._check(self._lib.soft_circuit_info(self._h, _ptr(a)))
+        if variant is None:
+            self._check(self._lib.soft_circuit_info(self._h, _ptr(a)))
+        else:
+            self._check(self._lib.soft_variant_info(self._h, variant, _ptr(a)))
         keys = ("qubits", "records", "noise_slots", "meas_slots", "observables", "events", "k_max", "record_words")
         return {k: int(v) for k, v in zip(keys, a)}
 
     def launch_shape(self) -> dict:
         import numpy as np
-        a = np.zeros(4, dtype=np.uint32)
+        a = np.zeros(5, dtype=np.uint32)
         self._check(self._lib.soft_launch_shape(self._h, _ptr(a)))
-        return dict(zip(("waves_per_block", "blocks_per_cu", "grab", "lds_bytes_per_wave"), (int(x) for x in a)))
+        return dict(zip(("waves_per_block", "blocks_per_cu", "grab", "lds_bytes_per_wave", "tiles_in_memory"),
+                        (int(x) for x in a)))
 
 
 def sample(ctx: Context, shot0: int, n_shots: int, stream=None):

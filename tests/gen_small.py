@@ -6,8 +6,14 @@ import numpy as np
 
 def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: float = 0.08,
                    p_mpp: float = 0.04, p_reset: float = 0.03, p_pauli: float = 0.08,
-                   clifford_only: bool = False, allow_mpp: bool = True, gates=("H", "S", "SDG", "CX", "CZ")):
+                   clifford_only: bool = False, allow_mpp: bool = True, gates=("H", "S", "SDG", "CX", "CZ"),
+                   p_msc: float = 0.0):
+    """Random circuit text and its measurement-slot count.  With p_msc > 0, a
+    fraction p_msc of the ops come from the extended set: H_XY, H_NXY, MX,
+    RX, MR, MRX and record-controlled Paulis XIF/YIF/ZIF."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    msc = rng if p_msc > 0 else None
+    n_rec = 0
     if clifford_only:
         p_t = 0.0
     if not allow_mpp:
@@ -15,17 +21,32 @@ def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: fl
     lines = ["QUBITS %d" % n]
     n_meas_slots = 0
     for _ in range(length):
+        if msc is not None and msc.random() < p_msc:
+            kind = int(msc.integers(7))
+            q = int(msc.integers(n))
+            if kind == 0:
+                lines.append("%s %d" % ("H_XY" if msc.integers(2) == 0 else "H_NXY", q))
+            elif kind <= 4:
+                op = ("MX", "RX", "MR", "MRX")[kind - 1]
+                lines.append("%s %d" % (op, q))
+                n_meas_slots += 1
+                n_rec += op != "RX"
+            elif n_rec:
+                lines.append("%sIF %d %d" % ("XYZ"[int(msc.integers(3))], int(msc.integers(n_rec)), q))
+            continue
         u = rng.random()
         if u < p_t:
             lines.append("%s %d" % ("T" if rng.integers(2) == 0 else "TDG", rng.integers(n)))
         elif u < p_t + p_meas:
             lines.append("M %d" % rng.integers(n))
             n_meas_slots += 1
+            n_rec += 1
         elif u < p_t + p_meas + p_mpp:
             k = int(rng.integers(1, n + 1))
             qs = rng.choice(n, size=k, replace=False)
             lines.append("MPP " + "*".join("%s%d" % ("XYZ"[rng.integers(3)], q) for q in qs))
             n_meas_slots += 1
+            n_rec += 1
         elif u < p_t + p_meas + p_mpp + p_reset:
             lines.append("R %d" % rng.integers(n))
             n_meas_slots += 1

@@ -1,7 +1,8 @@
 """Dense statevector checker for the oracle (test code, numpy, <= ~12 qubits).
 
 It runs a circuit on a plain 2^n statevector with the textbook gate matrices
-(H, S = diag(1, i), T = diag(1, e^{i pi/4}), CNOT, CZ, Paulis) and, beside it,
+(H, S = diag(1, i), T = diag(1, e^{i pi/4}), CNOT, CZ, Paulis, (X +- Y)/sqrt2)
+and, beside it,
 a "shadow" copy of the stabilizer state |psi_S> whose global phase follows the
 same reading the oracle uses: Cliffords and Paulis act on it as matrices, T
 leaves it alone, and a measurement that is random on |psi_S> replaces it by
@@ -27,6 +28,8 @@ MATS = {
     "Z": np.diag([1, -1]).astype(complex),
     "T": np.diag([1, np.exp(1j * np.pi / 4)]),
     "TDG": np.diag([1, np.exp(-1j * np.pi / 4)]),
+    "H_XY": np.array([[0, 1 - 1j], [1 + 1j, 0]], dtype=complex) * SQ2,   # (X + Y)/sqrt2
+    "H_NXY": np.array([[0, 1 + 1j], [1 - 1j, 0]], dtype=complex) * SQ2,  # (X - Y)/sqrt2
 }
 
 
@@ -105,7 +108,7 @@ def run(text, meas_words):
     slot = 0
     for tok in ops:
         g = tok[0]
-        if g in ("H", "S", "SDG", "X", "Y", "Z"):
+        if g in ("H", "S", "SDG", "X", "Y", "Z", "H_XY", "H_NXY"):
             q = int(tok[1])
             phi = apply_1q(phi, MATS[g], q, n)
             shadow = apply_1q(shadow, MATS[g], q, n)
@@ -117,9 +120,17 @@ def run(text, meas_words):
         elif g == "CZ":
             phi = apply_cz(phi, int(tok[1]), int(tok[2]), n)
             shadow = apply_cz(shadow, int(tok[1]), int(tok[2]), n)
-        elif g in ("M", "R", "MPP"):
+        elif g in ("XIF", "YIF", "ZIF"):
+            # classically controlled Pauli
+            if record[int(tok[1])]:
+                q = int(tok[2])
+                phi = apply_1q(phi, MATS[g[0]], q, n)
+                shadow = apply_1q(shadow, MATS[g[0]], q, n)
+        elif g in ("M", "R", "MPP", "MX", "RX", "MR", "MRX"):
             if g == "MPP":
                 x, z = mpp_pauli(tok[1])
+            elif g in ("MX", "RX", "MRX"):
+                x, z = 1 << int(tok[1]), 0
             else:
                 x, z = 0, 1 << int(tok[1])
             Pphi = pauli_apply(phi, x, z, 0, n)
@@ -139,12 +150,13 @@ def run(text, meas_words):
             else:
                 raise AssertionError("shadow is not a stabilizer state")
             bit = 0 if m == 1 else 1
-            if g == "R":
-                if bit:
-                    phi = apply_1q(phi, MATS["X"], int(tok[1]), n)
-                    shadow = apply_1q(shadow, MATS["X"], int(tok[1]), n)
-            else:
+            if g not in ("R", "RX"):
                 record.append(bit)
+            if bit and g in ("R", "MR", "RX", "MRX"):
+                # back to the +1 eigenstate: X flips Z_q, Z flips X_q
+                F = MATS["X"] if g in ("R", "MR") else MATS["Z"]
+                phi = apply_1q(phi, F, int(tok[1]), n)
+                shadow = apply_1q(shadow, F, int(tok[1]), n)
         elif g in ("DETECTOR", "OBSERVABLE", "TICK"):
             pass
         else:

@@ -138,6 +138,32 @@ def test_every_gate_rule_matches_dense_conjugation(seed):
             assert np.allclose(got, want, atol=1e-12)
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_hxy_gate_rules_match_dense_conjugation(seed):
+    n = 2
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(10):
+        g = ["H_XY", "H_NXY", "H", "S", "CX"][int(rng.integers(5))]
+        ops.append("CX 0 1" if g == "CX" else "%s %d" % (g, int(rng.integers(2))))
+    text = "QUBITS 2\n" + "\n".join(ops) + "\n"
+    r = oracle.Circuit(text).shot(0, 0)
+    U = _unitary(text, n)
+    for i in range(n):
+        for P0, row in ((_pauli_matrix(1 << i, 0, 0, n), i), (_pauli_matrix(0, 1 << i, 0, n), n + i)):
+            want = U @ P0 @ U.conj().T
+            got = _pauli_matrix(int(r.tab_x[row]), int(r.tab_z[row]), 2 * int(r.tab_r[row]), n)
+            assert np.allclose(got, want, atol=1e-12), text
+
+
+def test_hxy_single_qubit_images():
+    # (X+Y)/sqrt2: X -> Y, Z -> -Z;  (X-Y)/sqrt2: X -> -Y, Z -> -Z
+    for g, sx in (("H_XY", 0), ("H_NXY", 1)):
+        r = oracle.Circuit("QUBITS 1\n%s 0\n" % g).shot(0, 0)
+        assert (int(r.tab_x[0]), int(r.tab_z[0]), int(r.tab_r[0])) == (1, 1, sx)   # d_0 = X image
+        assert (int(r.tab_x[1]), int(r.tab_z[1]), int(r.tab_r[1])) == (0, 1, 1)    # s_0 = Z image
+
+
 # ---------------------------------------------------------------------------
 # Dense statevector with phase-tracked shadow
 # ---------------------------------------------------------------------------
@@ -172,6 +198,66 @@ def test_every_prefix_matches_dense(seed):
     lines = text.strip().splitlines()
     for k in range(2, len(lines) + 1):
         _check_dense("\n".join(lines[:k]) + "\n", seed)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_msc_ops_match_dense(seed):
+    # X-basis readouts and resets, measure-and-reset, H_XY / H_NXY and
+    # record-controlled Paulis mixed into random Clifford+T circuits
+    n = 1 + seed % 5
+    text, _ = random_circuit(7000 + seed, n, 45, p_msc=0.3)
+    _check_dense(text, seed)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_msc_ops_every_prefix_matches_dense(seed):
+    text, _ = random_circuit(7700 + seed, 3, 30, p_msc=0.35)
+    lines = text.strip().splitlines()
+    for k in range(2, len(lines) + 1):
+        _check_dense("\n".join(lines[:k]) + "\n", seed)
+
+
+def test_x_basis_reset_and_readout():
+    # RX prepares |+>: an MX right after reads 0 with certainty, M reads 50/50
+    c = oracle.Circuit("QUBITS 1\nH 0\nS 0\nRX 0\nMX 0\n")
+    for w in (0, 1 << 31, 0xFFFFFFFF):
+        r = c.shot(0, 0, words=np.array([w, w], dtype=np.uint32))
+        assert r.record == [0]
+    c = oracle.Circuit("QUBITS 1\nRX 0\nM 0\n")
+    r = c.shot(0, 0, words=np.array([5, 5], dtype=np.uint32))
+    assert abs(r.p0[1] - 0.5) < 1e-15
+    # MR leaves |0>: a second M reads 0 whatever the first read
+    c = oracle.Circuit("QUBITS 1\nH 0\nMR 0\nM 0\n")
+    for w in (0, 0xFFFFFFFF):
+        r = c.shot(0, 0, words=np.array([w, 3], dtype=np.uint32))
+        assert r.record[1] == 0 and r.record[0] == (0 if w == 0 else 1)
+
+
+def test_feedback_applies_pauli_on_record():
+    # M of |+> gives a random bit b; XIF b then M again reads 0 for b = 0 and
+    # 1 (X on |1> after the collapse gives |0>) -- in both cases the second
+    # readout is 0 after X-correction of a Z-basis collapse.
+    c = oracle.Circuit("QUBITS 1\nH 0\nM 0\nXIF 0 0\nM 0\n")
+    for w in (0, 0xFFFFFFFF):
+        r = c.shot(0, 0, words=np.array([w, 3], dtype=np.uint32))
+        assert r.record[1] == 0
+    # ZIF acts on the X basis the same way
+    c = oracle.Circuit("QUBITS 1\nMX 0\nZIF 0 0\nMX 0\n")
+    for w in (0, 0xFFFFFFFF):
+        r = c.shot(0, 0, words=np.array([w, 3], dtype=np.uint32))
+        assert r.record[1] == 0
+
+
+def test_msc_model_noise_matches_explicit_noise_ops():
+    # X-basis readouts take a Z flip before, X-basis resets a Z flip after
+    text = "QUBITS 2\nMX 0\nRX 1\nMR 0\nMRX 1\n"
+    explicit = ("QUBITS 2\nZERR 0.4 0\nMX 0\nRX 1\nZERR 0.5 1\nXERR 0.4 0\nMR 0\nXERR 0.5 0\n"
+                "ZERR 0.4 1\nMRX 1\nZERR 0.5 1\n")
+    model = {"p1": 0.0, "p2": 0.0, "p_idle": 0.0, "p_meas": 0.4, "p_reset": 0.5, "p_mpp": 0.0}
+    a = oracle.Circuit(text, model).batch(5, 0, 2000)
+    b = oracle.Circuit(explicit).batch(5, 0, 2000)
+    assert (a["outcomes"] == b["outcomes"]).all()
+    assert a["outcomes"].any()
 
 
 def test_dense_on_larger_register():
@@ -458,7 +544,7 @@ def test_forced_noise_words():
     ("H 0\n", "line 1"), ("QUBITS 2\nH 2\n", "line 2"), ("QUBITS 2\nCX 1 1\n", "line 2"),
     ("QUBITS 2\nFOO 1\n", "unknown"), ("QUBITS 2\nDETECTOR 0 0\n", "record"),
     ("QUBITS 2\nDEP1 1.5 0\n", "probability"), ("QUBITS 2\nMPP X0*X0\n", "repeated"),
-    ("QUBITS 65\n", "QUBITS"),
+    ("QUBITS 65\n", "QUBITS"), ("QUBITS 2\nXIF 0 1\n", "record"), ("QUBITS 2\nM 0\nZIF 0\n", "record index"),
 ])
 def test_parse_errors(text, frag):
     with pytest.raises(ValueError, match=frag):

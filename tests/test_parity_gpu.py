@@ -35,6 +35,41 @@ def test_random_circuits_explicit_words(seed):
 
 
 @pytest.mark.parametrize("seed", range(16))
+def test_msc_ops_explicit_words(seed):
+    # X-basis readouts and resets, measure-and-reset, H_XY / H_NXY and
+    # record-controlled Paulis, with explicit noise ops and words
+    n = 1 + seed % 6
+    text, _ = random_circuit(61000 + seed, n, 90, p_msc=0.25)
+    if seed % 2:
+        lines = text.strip().split("\n")
+        noisy = [lines[0]]
+        for ln in lines[1:]:
+            noisy.append(ln)
+            q = ln.split()[-1]
+            if q.isdigit():
+                noisy.append("ZERR 0.05 %s" % q if seed % 4 == 1 else "DEP1 0.05 %s" % q)
+        text = "\n".join(noisy) + "\n"
+    circ = oracle.Circuit(text)
+    N = 256
+    words = _words(circ, N, seed)
+    ctx = make_ctx(text, keep=(0, N))
+    gpu = run_gpu(ctx, 0, N, words)
+    compare_batch(gpu, circ.batch(0, 0, N, words=words))
+    compare_kept(ctx, circ, 0, range(N), words=words)
+
+
+def test_msc_ops_model_noise_philox():
+    text, _ = random_circuit(62000, 5, 200, p_msc=0.2)
+    noise = {"p1": 2e-3, "p2": 4e-3, "p_idle": 1e-3, "p_meas": 5e-3, "p_reset": 5e-3, "p_mpp": 5e-3}
+    circ = oracle.Circuit(text, noise)
+    N = 20000
+    ctx = make_ctx(text, noise, seed=8, keep=(0, 128))
+    gpu = run_gpu(ctx, 0, N)
+    compare_batch(gpu, circ.batch(8, 0, N))
+    compare_kept(ctx, circ, 8, range(128))
+
+
+@pytest.mark.parametrize("seed", range(16))
 def test_random_noisy_circuits_philox(seed):
     n = 2 + seed % 6
     text, _ = random_circuit(32000 + seed, n, 80)
@@ -226,7 +261,7 @@ def test_trace_matches_oracle_step_by_step(seed):
     # The paper's step-by-step cross-check (Sec. V-B): after every event the
     # GPU tableau and coefficient vector equal the oracle's for the same prefix.
     n = 2 + seed % 5
-    text, _ = random_circuit(41000 + seed, n, 70)
+    text, _ = random_circuit(41000 + seed, n, 70, p_msc=0.15 if seed >= 4 else 0.0)
     lines = text.strip().split("\n")
     circ = oracle.Circuit(text)
     words = random_words(seed, circ.words_per_shot)

@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "random_clifford_t", "cultivation_shaped", "config", "circuit_stats"]
+__all__ = ["Workload", "random_clifford_t", "cultivation_shaped", "config", "mixture", "circuit_stats"]
 
 
 @dataclass
@@ -297,6 +297,7 @@ def config(name: str, seed: int = 1, p: float | None = None) -> Workload:
     ``clifford_t_8q``   -- 8 qubits, 200 Cliffords, 6 T/T†, 8 measurements (p=1e-3)
     ``cultivation_15q`` -- 7 data + 8 ancilla, two transversal brackets (28 T/T†)
     ``cultivation_42q`` -- 19 data + 23 ancilla, brackets 19+7+5+5 (72 T/T†)
+    ``cultivation_42q_k12`` -- the same family with 7 Z checks: support up to 2^12
     """
     if name == "clifford_t_8q":
         return random_clifford_t(seed, p=1e-3 if p is None else p)
@@ -306,7 +307,37 @@ def config(name: str, seed: int = 1, p: float | None = None) -> Workload:
     if name == "cultivation_42q":
         return cultivation_shaped(seed, 19, 23, 9, [19, 7, 5, 5], check_weight=6, p=1e-3 if p is None else p,
                                   name="cultivation_42q_72T")
+    if name == "cultivation_42q_k12":
+        return cultivation_shaped(seed, 19, 23, 7, [19, 7, 5, 5], check_weight=6, p=1e-3 if p is None else p,
+                                  name="cultivation_42q_72T_k12")
     raise KeyError(name)
+
+
+# The eight generated companions of the 15-qubit circuit in the mixed run:
+# (data qubits, ancillas, Z-check rank, bracket sizes).  Qubits 12..20, 16..40
+# T/T-dagger; the 12- and 13-data-qubit codes reach span dimension 10.
+MIX_SHAPES = [(9, 5, 3, [9]), (10, 6, 3, [10, 4]), (11, 7, 3, [11, 5]), (12, 8, 2, [12, 4]),
+              (8, 4, 3, [8, 8]), (13, 7, 3, [13, 7]), (10, 8, 4, [10, 5, 3]), (9, 7, 2, [9])]
+MIX_P = (5e-4, 1e-3, 2e-3)
+
+
+def mixture(seed: int = 1, total_shots: int = 10_000_000) -> dict:
+    """Many circuits in one launch: the 15-qubit cultivation circuit plus the
+    eight shapes of MIX_SHAPES, each at every p of MIX_P (27 variants), with
+    the shots split evenly into consecutive global ranges.  Returns the
+    variants' workloads, their noise dicts and the exclusive range ends."""
+    circuits = [config("cultivation_15q", seed=seed)]
+    for i, (nd, na, rz, br) in enumerate(MIX_SHAPES):
+        circuits.append(cultivation_shaped(seed * 1000 + i, nd, na, rz, br, check_weight=min(5, nd - 2),
+                                           name="mix%d_%dq_%dT" % (i, nd + na, 2 * sum(min(b, nd) for b in br))))
+    works, models = [], []
+    for w in circuits:
+        for p in MIX_P:
+            works.append(w)
+            models.append({k: p for k in ("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp")})
+    nv = len(works)
+    ends = [total_shots * (v + 1) // nv for v in range(nv)]
+    return {"workloads": works, "models": models, "shot_ends": ends}
 
 
 def circuit_stats(text: str) -> dict:
