@@ -315,6 +315,9 @@ class FrameCompiler {
         Event E = begin(src);
         E.kind = EV_FEEDBACK;
         E.rec = rec;
+        E.det_cnt = 1;  // the record bit, read as a parity check
+        E.dw0 = rec >> 5;
+        E.dm0 = 1u << (rec & 31u);
         RowMask m;
         if (pauli == 1 || pauli == 2) m ^= cz_[q];
         if (pauli == 3 || pauli == 2) m ^= cx_[q];

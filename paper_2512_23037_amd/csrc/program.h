@@ -41,7 +41,7 @@ enum EvKind : uint32_t {
     EV_M_MERGE,      // beta != 0 inside the span: pairs merge, k -> k-1
     EV_DETECTOR,     // parity check of record bits, abort on failure
     EV_OBSERVABLE,   // parity of record bits, stored as an observable bit
-    EV_FEEDBACK,     // Pauli flip (masks xD/xS) when record bit `rec` is 1
+    EV_FEEDBACK,     // Pauli flip (masks xD/xS) when record bit `rec` is 1 (as the check dw0/dm0)
     EV_END
 };
 

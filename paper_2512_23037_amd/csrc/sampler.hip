@@ -37,6 +37,15 @@ __device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t h) {
     return ((p ^ lo) << 1) | lo;
 }
 
+// A lane-parallel pass over indices [0, cnt) with cnt a power of two: a
+// uniform trip count, and when cnt < 64 the lanes past the end sit out.
+template <typename F> __device__ __forceinline__ void lane_pass(uint32_t cnt, uint32_t lane, F &&f) {
+    const uint32_t iters = (cnt + 63u) >> 6;
+#pragma unroll 1
+    for (uint32_t it = 0; it < iters; ++it)
+        if (cnt >= 64u || lane < cnt) f((it << 6) | lane);
+}
+
 // readfirstlane yields a signed int: widen through uint32_t, never directly.
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
@@ -144,7 +153,7 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
     }
     const double pc = phase_tab[phase8], ps = phase_tab[16u + phase8];
     const uint32_t cnt = 1u << k;
-    for (uint32_t j = lane; j < tile_entries; j += 64u) {
+    lane_pass(tile_entries, lane, [&](uint32_t j) {
         double x = 0.0, y = 0.0;
         if (j < cnt) {
             const C e = v[j];
@@ -153,7 +162,7 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
         }
         dst[2u * j] = x * pc - y * ps;
         dst[2u * j + 1u] = x * ps + y * pc;
-    }
+    });
 }
 
 constexpr uint32_t kNoHit = 0xFFFFFFFFu;
@@ -479,6 +488,9 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
+            // k changes only in uniform branches; say so, or the compiler
+            // lowers every pass over the tile as a divergent loop
+            k = uni(k);
             const uint32_t nend = EV32(noise_end);
             while (true) {
                 while (next_hit < nend) {
@@ -508,7 +520,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 const R fr = (R)EVD(Are), fi = (R)EVD(Aim);
                 const uint32_t cnt = 1u << k;
                 if (g != 0u || sig) {
-                    for (uint32_t j = lane; j < cnt; j += 64u) {
+                    lane_pass(cnt, lane, [&](uint32_t j) {
                         if (sig ^ par32(g & j)) {
                             C x = v[j];
                             C y;
@@ -516,7 +528,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                             y.y = x.x * fi + x.y * fr;
                             v[j] = y;
                         }
-                    }
+                    });
                 }
                 tot.events++;
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
@@ -669,11 +681,11 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
                     const uint32_t cnt = 1u << k;
                     double n0 = 0.0, n1 = 0.0;
-                    for (uint32_t j = lane; j < cnt; j += 64u) {
+                    lane_pass(cnt, lane, [&](uint32_t j) {
                         const double q = nrm<R>(v[j]);
                         if (par32(g & j)) n1 += q;
                         else n0 += q;
-                    }
+                    });
                     n0 = wave_sum(n0);
                     n1 = wave_sum(n1);
                     const double Np = sig ? n1 : n0, Nm = sig ? n0 : n1;
@@ -692,7 +704,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const uint32_t ts = EV32(tstar), half = cnt >> 1;
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
-                    for (uint32_t jp = lane; jp < half; jp += 64u) {
+                    lane_pass(half, lane, [&](uint32_t jp) {
                         uint32_t j = ins0(jp, ts);
                         if (par32(g & j) != bsel) j |= 1u << ts;
                         C x = scale(v[j], s);
@@ -701,7 +713,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         if (!keep) x = z;
                         nn += keep ? q : 0.0;
                         v[jp] = x;
-                    }
+                    });
                     nrm2 = wave_sum(nn);
                     --k;
                     if (bsel) a ^= EV64(avec);
@@ -714,7 +726,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const R s = (R)(1.0 / sqrt(nrm2));
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
-                    for (uint32_t j = lane; j < cnt; j += 64u) {
+                    lane_pass(cnt, lane, [&](uint32_t j) {
                         C x = v[j];
                         if (ap ^ par32(pm & j)) x = rot(x, q0 + 2u * (fs ^ par32(g & j)));
                         x = scale(x, s);
@@ -723,7 +735,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         if (!keep) x = z;
                         nn += keep ? q : 0.0;
                         v[j] = x;
-                    }
+                    });
                     nrm2 = wave_sum(nn);
                     tot.entries_m += cnt;
                 } else {  // EV_M_MERGE
@@ -732,7 +744,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const uint32_t npairs = 1u << (k - 1u), mu = EV32(mu), h = EV32(tstar), pm = EV32(pm);
                     const uint32_t fs0 = sc ^ ga;
                     double np = 0.0, nm = 0.0;
-                    for (uint32_t p = lane; p < npairs; p += 64u) {
+                    lane_pass(npairs, lane, [&](uint32_t p) {
                         const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
                         const uint32_t a0 = ap ^ par32(pm & j0);
                         const uint32_t x = a0 ? j1 : j0, y = a0 ? j0 : j1;
@@ -742,7 +754,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         const double mx = (double)vx.x - (double)fy.x, my = (double)vx.y - (double)fy.y;
                         np += px * px + py * py;
                         nm += mx * mx + my * my;
-                    }
+                    });
                     np = 0.5 * wave_sum(np);
                     nm = 0.5 * wave_sum(nm);
                     const double p0 = np / (np + nm);
@@ -758,7 +770,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const R s = (R)(1.0 / sqrt(2.0 * Ns));
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
-                    for (uint32_t p = lane; p < npairs; p += 64u) {
+                    lane_pass(npairs, lane, [&](uint32_t p) {
                         const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
                         const uint32_t a0 = ap ^ par32(pm & j0);
                         const uint32_t x = a0 ? j1 : j0, y = a0 ? j0 : j1;
@@ -773,7 +785,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         if (!keep) o = z;
                         nn += keep ? q : 0.0;
                         v[p] = o;
-                    }
+                    });
                     nrm2 = wave_sum(nn);
                     --k;
                 }
@@ -802,9 +814,8 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     }
                 }
             } else if (kind == EV_FEEDBACK) {
-                // ---- classically controlled Pauli ----
-                const uint32_t r = EV32(rec);
-                if ((rec_read(r >> 5) >> (r & 31u)) & 1u) {
+                // ---- classically controlled Pauli: the record bit is a one-pair check ----
+                if (parity_check()) {
                     rD ^= EV64(xD);
                     rS ^= EV64(xS);
                 }
@@ -830,7 +841,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         // ---- shot end: norm check, outputs, kept states, counters ----
         const uint32_t cnt = 1u << k;
         double nn = 0.0;
-        for (uint32_t j = lane; j < cnt; j += 64u) nn += nrm<R>(v[j]);
+        lane_pass(cnt, lane, [&](uint32_t j) { nn += nrm<R>(v[j]); });
         nn = wave_sum(nn);
         tot.maxdev = fmax(tot.maxdev, fabs(nn - 1.0));
         if (lane == group_pos) {
