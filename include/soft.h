@@ -173,6 +173,19 @@ int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes
              uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev,
              void *hip_stream);
 
+/* Sample an explicit list of global shot indices: shots_dev (device, uint64,
+ * 8-byte aligned) holds n_shots indices in any order; output row i (of
+ * outcomes_dev, status_dev, ...) belongs to shots_dev[i], with the layout of
+ * soft_run.  A shot's result depends only on its index, so this re-runs
+ * chosen shots exactly: e.g. the shots a capped run flagged SOFT_OVERFLOW,
+ * after raising the cap (soft_set_caps) or moving the tile to device memory
+ * (soft_set_tile_memory) -- the overflow re-run of a production sweep.  Kept
+ * shots (soft_set_keep) are matched by shot index.  A mixture's index outside
+ * every range runs as the last variant.  Explicit uniforms are for soft_run
+ * only (EUNSUPPORTED here). */
+int soft_run_list(soft_ctx *ctx, const uint64_t *shots_dev, uint64_t n_shots, uint32_t *outcomes_dev,
+                  uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev, void *hip_stream);
+
 /* Aggregates of the last run; synchronizes that run's stream. */
 int soft_read_counters(soft_ctx *ctx, soft_counters *out);
 

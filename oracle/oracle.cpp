@@ -220,6 +220,32 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             c.ops.push_back(o);
             active[q] = 1;
             add_noise(K_XERR, nm.p_reset, q, -1, src);
+        } else if (name == "CCZ" || name == "CCX") {
+            // CCZ = exp(i pi x_a x_b x_c) in the computational basis, and
+            // 4 xyz = x + y + z - (x^y) - (x^z) - (y^z) + (x^y^z), so CCZ is T
+            // (diag(1, e^{i pi/4})) on a, b, c and on a^b^c, and T-dagger on
+            // a^b, a^c, b^c; a parity is formed on a target by CNOTs and undone
+            // after.  CCX conjugates the target by H.
+            if (tok.size() != 4) throw ParseError{line, name + " takes three qubits"};
+            int a = qubit(tok[1]), b = qubit(tok[2]), t = qubit(tok[3]);
+            if (a == b || a == t || b == t) throw ParseError{line, name + " on repeated qubits"};
+            auto gate = [&](Kind k, int q0, int q1) {
+                Op o;
+                o.kind = k; o.a = q0; o.b = q1; o.src = src;
+                c.ops.push_back(o);
+            };
+            if (name == "CCX") gate(K_H, t, -1);
+            gate(K_T, a, -1);
+            gate(K_T, b, -1);
+            gate(K_T, t, -1);
+            gate(K_CX, a, b); gate(K_TDG, b, -1); gate(K_CX, a, b);              // a^b
+            gate(K_CX, a, t); gate(K_TDG, t, -1); gate(K_CX, a, t);              // a^t
+            gate(K_CX, b, t); gate(K_TDG, t, -1); gate(K_CX, b, t);              // b^t
+            gate(K_CX, a, t); gate(K_CX, b, t); gate(K_T, t, -1);                // a^b^t
+            gate(K_CX, b, t); gate(K_CX, a, t);
+            if (name == "CCX") gate(K_H, t, -1);
+            active[a] = active[b] = active[t] = 1;
+            for (int q : {a, b, t}) add_noise(K_DEP1, nm.p1, q, -1, src);
         } else if (name == "MX" || name == "RX" || name == "MR" || name == "MRX") {
             // X-basis measurement / reset to |+>, and measure-then-reset.  The
             // measurement-error flip before a readout and the reset-error flip

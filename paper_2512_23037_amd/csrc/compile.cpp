@@ -656,6 +656,27 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
                 fc.measure(Z, out.n_meas++, -1, q, src);
                 fc.noise(NZ_XERR, nm.p_reset, q, -1, 0);
             }
+        } else if (op == "CCZ" || op == "CCX") {
+            // CCZ multiplies |x> by (-1)^{x_a x_b x_c}; with
+            // 4xyz = x + y + z - (x^y) - (x^z) - (y^z) + (x^y^z) it is
+            // T on a, b, c and on a^b^c, T-dagger on a^b, a^c, b^c (T = diag(1,
+            // e^{i pi/4})), each parity formed on one of the qubits by CNOTs and
+            // undone.  At most three new span coordinates, support at most 8x
+            // (Proposition 1).  CCX = H_t CCZ H_t.
+            want(4);
+            int a = qubit(tok[1]), b = qubit(tok[2]), t = qubit(tok[3]);
+            if (a == b || a == t || b == t) throw CompileError{ln, op + " on repeated qubits"};
+            busy[a] = busy[b] = busy[t] = 1;
+            if (op == "CCX") fc.h(t);
+            fc.t_gate(a, false, src);
+            fc.t_gate(b, false, src);
+            fc.t_gate(t, false, src);
+            fc.cnot(a, b); fc.t_gate(b, true, src); fc.cnot(a, b);
+            fc.cnot(a, t); fc.t_gate(t, true, src); fc.cnot(a, t);
+            fc.cnot(b, t); fc.t_gate(t, true, src); fc.cnot(b, t);
+            fc.cnot(a, t); fc.cnot(b, t); fc.t_gate(t, false, src); fc.cnot(b, t); fc.cnot(a, t);
+            if (op == "CCX") fc.h(t);
+            for (int q : {a, b, t}) fc.noise(NZ_DEP1, nm.p1, q, -1, 0);
         } else if (op == "MX" || op == "RX" || op == "MR" || op == "MRX") {
             // X-basis readout / reset to |+>, measure-then-reset; the error
             // flips anticommute with the measured Pauli (Z for the X basis)

@@ -15,6 +15,7 @@ struct RunParams {
     const BatchMember *bm;    // members of side-by-side measurement runs
     const VariantDesc *vars;  // shot ranges of the circuits in this run
     const uint32_t *words;    // explicit uniforms [n_shots][word_stride] or null
+    const uint64_t *shot_list;  // global shot index of each run position, or null (shot0 + i)
     const double *phase_tab;  // cos(k pi/8) for k = 0..15, then sin(k pi/8)
     uint32_t *outcomes;       // [rec_words][n_shots] or null
     uint32_t *status;         // [n_shots]

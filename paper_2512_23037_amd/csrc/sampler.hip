@@ -279,9 +279,10 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
     return cnt;
 }
 
-struct WaveTotals {
-    uint64_t entries_t = 0, entries_m = 0, noise = 0, events = 0;
-    double maxdev = 0.0;
+// Work counted during one shot (32 bits suffice per shot); added to the
+// lane-held 64-bit counters when the shot ends.
+struct ShotTotals {
+    uint32_t entries_t = 0, entries_m = 0, noise = 0, events = 0;
 };
 
 // Fields of the current event (held one dword per lane in `evc`).
@@ -322,25 +323,22 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
     const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
     const double tau2 = P.tau2;
 
-    WaveTotals tot;
+    double maxdev = 0.0;  // largest norm deviation of this wave's shots
     uint64_t myc = 0;  // counter number `lane` of this wave, for variant `var`
 
-    // Circuit of the current shot.  A wave's shots come in increasing order,
-    // so the variant index only moves forward.
+    // Circuit of the current shot: variant `var` owns shots [var_lo, var_end).
+    // A wave's shots usually come in increasing order, so the range is looked
+    // up again only when a shot leaves it.
     uint32_t var = 0;
     bool var_ok = false;
-    uint64_t var_end = 0;
+    uint64_t var_lo = 0, var_end = 0;
     const uint32_t *ev32 = nullptr;
     auto flush_counters = [&]() {
         unsigned long long *row = P.counters + (size_t)var * C_COUNT;
-        myc += lane == C_ENTRIES_T ? tot.entries_t : 0ull;
-        myc += lane == C_ENTRIES_M ? tot.entries_m : 0ull;
-        myc += lane == C_NOISE ? tot.noise : 0ull;
-        myc += lane == C_EVENTS ? tot.events : 0ull;
         if (lane < (uint32_t)C_COUNT && lane != (uint32_t)C_NORMDEV_BITS && myc) atomicAdd(row + lane, (unsigned long long)myc);
-        if (lane == (uint32_t)C_NORMDEV_BITS) atomicMax(row + lane, (unsigned long long)__double_as_longlong(tot.maxdev));
+        if (lane == (uint32_t)C_NORMDEV_BITS) atomicMax(row + lane, (unsigned long long)__double_as_longlong(maxdev));
         myc = 0;
-        tot = WaveTotals();
+        maxdev = 0.0;
     };
 
     // Work stealing by groups of `grab` (<= 64) consecutive shots.  Lane g keeps
@@ -363,12 +361,15 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             group_pos = 0;
         }
         const uint64_t i = group_base + group_pos;
-        const uint64_t shot = P.shot0 + i;
+        const uint64_t shot = P.shot_list ? P.shot_list[i] : P.shot0 + i;
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
-        if (!var_ok || shot >= var_end) {
+        if (!var_ok || shot >= var_end || shot < var_lo) {
             if (var_ok) flush_counters();
-            while (P.vars[var].shot_end <= shot) ++var;
+            // shots past the last range (possible only in a shot list) run as the last variant
+            var = 0;
+            while (var + 1u < P.n_vars && P.vars[var].shot_end <= shot) ++var;
             const VariantDesc &VD = P.vars[var];
+            var_lo = var ? P.vars[var - 1u].shot_end : 0ull;
             var_end = VD.shot_end;
             ev32 = reinterpret_cast<const uint32_t *>(ev + VD.ev_off);
             var_ok = true;
@@ -419,6 +420,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
         const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
+        ShotTotals tot;
         // noise tables of this variant (read where used: the draws are rare)
         const VariantDesc *vdp = P.vars + var;
 
@@ -843,7 +845,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         double nn = 0.0;
         lane_pass(cnt, lane, [&](uint32_t j) { nn += nrm<R>(v[j]); });
         nn = wave_sum(nn);
-        tot.maxdev = fmax(tot.maxdev, fabs(nn - 1.0));
+        maxdev = fmax(maxdev, fabs(nn - 1.0));
         if (lane == group_pos) {
             o_status = status;
             o_abort = abort_src;
@@ -866,6 +868,8 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
+        myc += lane == C_ENTRIES_T ? tot.entries_t : lane == C_ENTRIES_M ? tot.entries_m
+             : lane == C_NOISE ? tot.noise : lane == C_EVENTS ? tot.events : 0u;
     }
     if (var_ok) flush_counters();
 }

@@ -101,6 +101,7 @@ struct soft_ctx {
     bool ran = false;
     hipStream_t last_stream = nullptr;
     uint64_t last_shot0 = 0, last_n = 0;
+    bool last_list = false;  // the last run sampled a shot list
 };
 
 namespace {
@@ -370,11 +371,12 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
 }
 
 int run_impl(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, uint32_t *status, uint32_t *abort_op,
-             uint32_t *obs, hipStream_t stream, const Shape &s) {
+             uint32_t *obs, hipStream_t stream, const Shape &s, const uint64_t *shot_list = nullptr) {
     RunParams rp;
     int rc = make_params(c, shot0, n_shots, outcomes, status, abort_op, obs, rp);
     if (rc) return rc;
     rp.grab = s.grab;
+    rp.shot_list = shot_list;
     if (c->trace_n)  // outside the graph: mark every trace step unwritten
         HIPCHK(c, hipMemsetAsync(c->d_trace_meta.p, 0, (size_t)c->trace_n * KM_COUNT * sizeof(unsigned long long), stream));
     if ((rc = launch(c, rp, s, n_shots, stream))) return rc;
@@ -382,6 +384,7 @@ int run_impl(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, 
     c->last_stream = stream;
     c->last_shot0 = shot0;
     c->last_n = n_shots;
+    c->last_list = shot_list != nullptr;
     return SOFT_OK;
 }
 
@@ -399,8 +402,8 @@ const Frame *frame_of(soft_ctx *c, const std::vector<unsigned long long> &meta, 
 const Frame *kept_frame(soft_ctx *c, uint64_t shot, std::vector<unsigned long long> &meta, std::vector<double> &tile, int &rc) {
     rc = SOFT_OK;
     if (!c->ran) { rc = fail(c, SOFT_ESTATE, "no run yet"); return nullptr; }
-    if (!c->keep_n || shot < c->keep_lo || shot - c->keep_lo >= c->keep_n || shot < c->last_shot0 ||
-        shot - c->last_shot0 >= c->last_n) {
+    if (!c->keep_n || shot < c->keep_lo || shot - c->keep_lo >= c->keep_n ||
+        (!c->last_list && (shot < c->last_shot0 || shot - c->last_shot0 >= c->last_n))) {
         rc = fail(c, SOFT_EINVAL, "shot was not kept by the last run (see soft_set_keep)");
         return nullptr;
     }
@@ -734,6 +737,22 @@ int read_rows(soft_ctx *c, uint32_t v0, uint32_t v1, soft_counters *out) {
     return SOFT_OK;
 }
 }  // namespace
+
+int soft_run_list(soft_ctx *c, const uint64_t *shots_dev, uint64_t n_shots, uint32_t *outcomes, uint32_t *status,
+                  uint32_t *abort_op, uint32_t *obs, void *hip_stream) {
+    if (!c) return SOFT_EINVAL;
+    if (!status && n_shots) return fail(c, SOFT_EINVAL, "status_dev is required");
+    if (!shots_dev && n_shots) return fail(c, SOFT_EINVAL, "shots_dev is required");
+    if (((uintptr_t)shots_dev & 7u) != 0) return fail(c, SOFT_EINVAL, "shots_dev must be 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = prepare(c);
+    if (rc) return rc;
+    if (c->words_dev) return fail(c, SOFT_EUNSUPPORTED, "explicit words are for soft_run");
+    if (n_shots == 0) return SOFT_OK;
+    Shape s = current_shape(c);
+    if ((rc = check_shape(c, s))) return rc;
+    return run_impl(c, 0, n_shots, outcomes, status, abort_op, obs, (hipStream_t)hip_stream, s, shots_dev);
+}
 
 int soft_read_counters(soft_ctx *c, soft_counters *out) {
     if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");

@@ -3,7 +3,9 @@ intervals, or a throughput-against-batch-size sweep.
 
   python -m paper_2512_23037_amd.scan --circuit FILE --p 2.5e-4,5e-4,1e-3 \\
          --shots-per-p 1000000000 --batch 10000000 --bits 32
-  python -m paper_2512_23037_amd.scan --circuit FILE --p 1e-3 --sweep 4096,65536,1048576
+  python -m paper_2512_23037_amd.scan --workload cultivation_42q --p 1e-3 --sweep 4096,65536,1048576
+
+(--workload names a generator of the repository's `workloads` module.)
 
 One JSON line per noise rate (or per batch size) on stdout, progress on
 stderr.
@@ -17,7 +19,9 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2512_23037_amd.scan")
-    ap.add_argument("--circuit", required=True, help="circuit text file")
+    src = ap.add_mutually_exclusive_group(required=True)
+    src.add_argument("--circuit", help="circuit text file")
+    src.add_argument("--workload", help="name of a seeded generator in the workloads module (seed 1)")
     ap.add_argument("--p", default="1e-3", help="comma-separated circuit-level noise rates")
     ap.add_argument("--shots-per-p", type=float, default=1e7)
     ap.add_argument("--batch", type=float, default=1e7)
@@ -25,7 +29,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sweep", default="", help="comma-separated shots per launch: throughput sweep instead of a scan")
     args = ap.parse_args(argv)
-    text = open(args.circuit).read()
+    if args.circuit:
+        text = open(args.circuit).read()
+    else:
+        import workloads
+        text = workloads.config(args.workload, seed=1).text
     ps = [float(x) for x in args.p.split(",") if x]
 
     import torch  # noqa: F401  (loads the HIP runtime before the library)

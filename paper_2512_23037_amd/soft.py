@@ -24,7 +24,8 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_set_rng", "soft_set_uniforms", "soft_set_precision", "soft_set_prune", "soft_set_caps",
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
-           "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory")
+           "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
+           "soft_run_list")
 
 
 class SoftError(RuntimeError):
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "soft_read_variant_counters": (I, [P, U32, ctypes.POINTER(soft_counters)]),
         "soft_variant_info": (I, [P, U32, P]),
         "soft_set_tile_memory": (I, [P, I]),
+        "soft_run_list": (I, [P, P, U64, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -207,6 +209,12 @@ class Context:
         of the documented shapes (outcomes [record_words, n_shots])."""
         self._check(self._lib.soft_run(self._h, shot0, n_shots, _ptr(outcomes), _ptr(status), _ptr(abort_op),
                                        _ptr(obs), _stream_handle(stream)))
+
+    def run_list(self, shots, outcomes=None, status=None, abort_op=None, obs=None, stream=None):
+        """Sample the global shot indices in `shots` (an int64 CUDA tensor);
+        row i of every output belongs to shots[i].  Asynchronous on `stream`."""
+        self._check(self._lib.soft_run_list(self._h, _ptr(shots), int(shots.numel()), _ptr(outcomes), _ptr(status),
+                                            _ptr(abort_op), _ptr(obs), _stream_handle(stream)))
 
     def counters(self, variant: int | None = None) -> dict:
         """Aggregates of the last run (of one variant's shots if given)."""

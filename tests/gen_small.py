@@ -7,12 +7,14 @@ import numpy as np
 def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: float = 0.08,
                    p_mpp: float = 0.04, p_reset: float = 0.03, p_pauli: float = 0.08,
                    clifford_only: bool = False, allow_mpp: bool = True, gates=("H", "S", "SDG", "CX", "CZ"),
-                   p_msc: float = 0.0):
+                   p_msc: float = 0.0, p_ccz: float = 0.0):
     """Random circuit text and its measurement-slot count.  With p_msc > 0, a
     fraction p_msc of the ops come from the extended set: H_XY, H_NXY, MX,
-    RX, MR, MRX and record-controlled Paulis XIF/YIF/ZIF."""
+    RX, MR, MRX and record-controlled Paulis XIF/YIF/ZIF; with p_ccz > 0 (and
+    n >= 3) a fraction p_ccz are CCZ / CCX on three distinct qubits."""
     rng = np.random.Generator(np.random.PCG64(seed))
     msc = rng if p_msc > 0 else None
+    ccz = rng if p_ccz > 0 and n >= 3 else None
     n_rec = 0
     if clifford_only:
         p_t = 0.0
@@ -21,6 +23,10 @@ def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: fl
     lines = ["QUBITS %d" % n]
     n_meas_slots = 0
     for _ in range(length):
+        if ccz is not None and ccz.random() < p_ccz:
+            a, b, t = (int(x) for x in ccz.choice(n, size=3, replace=False))
+            lines.append("%s %d %d %d" % ("CCZ" if ccz.integers(2) == 0 else "CCX", a, b, t))
+            continue
         if msc is not None and msc.random() < p_msc:
             kind = int(msc.integers(7))
             q = int(msc.integers(n))

@@ -120,6 +120,16 @@ def run(text, meas_words):
         elif g == "CZ":
             phi = apply_cz(phi, int(tok[1]), int(tok[2]), n)
             shadow = apply_cz(shadow, int(tok[1]), int(tok[2]), n)
+        elif g in ("CCZ", "CCX"):
+            # diag(..., -1 on x_a = x_b = x_t = 1); CCX flips t there instead.
+            # Non-Clifford: the shadow stays.
+            a, b, t = int(tok[1]), int(tok[2]), int(tok[3])
+            idx = np.arange(1 << n, dtype=np.uint64)
+            on = ((idx >> np.uint64(a)) & (idx >> np.uint64(b)) & np.uint64(1)).astype(bool)
+            if g == "CCZ":
+                phi = np.where(on & ((idx >> np.uint64(t)) & np.uint64(1)).astype(bool), -phi, phi)
+            else:
+                phi = phi[np.where(on, idx ^ (np.uint64(1) << np.uint64(t)), idx)]
         elif g in ("XIF", "YIF", "ZIF"):
             # classically controlled Pauli
             if record[int(tok[1])]:

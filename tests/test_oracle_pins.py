@@ -260,6 +260,40 @@ def test_msc_model_noise_matches_explicit_noise_ops():
     assert a["outcomes"].any()
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_ccz_ccx_match_dense(seed):
+    # CCZ / CCX (Toffoli) mixed into random Clifford+T circuits with
+    # measurements, against the dense statevector
+    n = 3 + seed % 4
+    text, _ = random_circuit(8100 + seed, n, 40, p_ccz=0.15)
+    assert "CC" in text
+    _check_dense(text, seed)
+
+
+def test_ccz_closed_forms():
+    # CCZ|+++> = (1/sqrt8) sum_x (-1)^{x0 x1 x2}|x>: the X-basis readouts of the
+    # three qubits are correlated exactly as that state predicts, and the
+    # support after one CCZ is at most 8 (Proposition 1, |Q| - r_Q = 3)
+    c = oracle.Circuit("QUBITS 3\nH 0\nH 1\nH 2\nCCZ 0 1 2\n")
+    r = c.shot(0, 0)
+    assert 1 < len(r.coeffs) <= 8
+    c = oracle.Circuit("QUBITS 3\nH 0\nH 1\nH 2\nCCZ 0 1 2\nMPP X0*X1*X2\n")
+    r = c.shot(0, 0, words=np.array([0], dtype=np.uint32))
+    # <X X X> on CCZ|+++> = 1/2 (the -1 sign on one of 8 amplitudes): P(+1) = 3/4
+    assert abs(r.p0[0] - 0.75) < 1e-12
+    # CCZ twice is the identity on the coefficients
+    a = oracle.Circuit("QUBITS 3\nH 0\nH 1\nT 2\nH 2\nCCZ 0 1 2\nCCZ 0 1 2\n").shot(0, 0)
+    b = oracle.Circuit("QUBITS 3\nH 0\nH 1\nT 2\nH 2\n").shot(0, 0)
+    keys = set(a.coeffs) | set(b.coeffs)
+    assert max(abs(a.coeffs.get(k, 0) - b.coeffs.get(k, 0)) for k in keys) < 1e-12
+    # Toffoli truth table on basis inputs
+    for x in range(8):
+        prep = "".join("X %d\n" % q for q in range(3) if (x >> q) & 1)
+        r = oracle.Circuit("QUBITS 3\n" + prep + "CCX 0 1 2\nM 0\nM 1\nM 2\n").shot(0, 0)
+        want = x ^ (4 if (x & 3) == 3 else 0)
+        assert r.record == [(want >> q) & 1 for q in range(3)]
+
+
 def test_dense_on_larger_register():
     text, _ = random_circuit(77, 10, 120, p_t=0.1)
     _check_dense(text, 77, tol=1e-11)
@@ -545,6 +579,7 @@ def test_forced_noise_words():
     ("QUBITS 2\nFOO 1\n", "unknown"), ("QUBITS 2\nDETECTOR 0 0\n", "record"),
     ("QUBITS 2\nDEP1 1.5 0\n", "probability"), ("QUBITS 2\nMPP X0*X0\n", "repeated"),
     ("QUBITS 65\n", "QUBITS"), ("QUBITS 2\nXIF 0 1\n", "record"), ("QUBITS 2\nM 0\nZIF 0\n", "record index"),
+    ("QUBITS 3\nCCZ 0 1 1\n", "repeated"),
 ])
 def test_parse_errors(text, frag):
     with pytest.raises(ValueError, match=frag):

@@ -58,8 +58,23 @@ def test_msc_ops_explicit_words(seed):
     compare_kept(ctx, circ, 0, range(N), words=words)
 
 
+@pytest.mark.parametrize("seed", range(10))
+def test_ccz_ccx_explicit_words(seed):
+    # CCZ / Toffoli lowered to their phase polynomial of seven T/T-dagger
+    n = 3 + seed % 5
+    text, _ = random_circuit(63000 + seed, n, 70, p_ccz=0.12)
+    circ = oracle.Circuit(text)
+    N = 256
+    words = _words(circ, N, seed)
+    ctx = make_ctx(text, keep=(0, N))
+    gpu = run_gpu(ctx, 0, N, words)
+    compare_batch(gpu, circ.batch(0, 0, N, words=words))
+    compare_kept(ctx, circ, 0, range(N), words=words)
+
+
 def test_msc_ops_model_noise_philox():
-    text, _ = random_circuit(62000, 5, 200, p_msc=0.2)
+    text, _ = random_circuit(62000, 5, 200, p_msc=0.2, p_ccz=0.03)
+    assert "CC" in text
     noise = {"p1": 2e-3, "p2": 4e-3, "p_idle": 1e-3, "p_meas": 5e-3, "p_reset": 5e-3, "p_mpp": 5e-3}
     circ = oracle.Circuit(text, noise)
     N = 20000
