@@ -222,13 +222,24 @@ __device__ __forceinline__ C t_out(C a, C b, R cs, R c, R thr, bool &keep) {
 
 // Branching T on an existing coordinate: pairs (j0, j1 = j0 ^ mu), j0 with
 // bit h clear.  v'_j0 = cs v_j0 + sn i^Q (-1)^(sig ^ g.j1) v_j1 and the same
-// with j0, j1 exchanged.  j0 = ins0(lane, h) | ins0(64 it, h): the lane part
-// and its sign parity are fixed for the event, the rest is uniform.
+// with j0, j1 exchanged.  j0 = ins0(lane, h) | ins0(64 it, h): the lane bits and
+// the iteration bits of a coordinate are disjoint, so each lane keeps two base
+// pointers for the event (j0's and j1's lane parts, h set in j1's) and an
+// iteration adds one uniform byte offset to each.
 template <uint32_t Q, typename R, typename C>
 __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
                                            uint32_t sig, R cs, R sn, R thr) {
     const uint32_t npairs = 1u << (k - 1u);
-    const uint32_t lc = ins0(lane, h);
+    // With fewer than 64 pairs the spare lanes repeat a live lane's pair (same
+    // values to the same addresses) and are left out of the counts, so the
+    // loop body needs no divergent branch.
+    const uint32_t lp = npairs >= 64u ? lane : (lane & (npairs - 1u));
+    const uint64_t live = npairs >= 64u ? ~0ull : ((1ull << npairs) - 1ull);
+    const uint32_t lc = ins0(lp, h);
+    const uint32_t lmask = ins0(63u, h), hb = 1u << h;  // mu's top bit is h
+    const uint32_t mu_l = mu & lmask, mu_i = mu & ~(lmask | hb);
+    char *const p0 = reinterpret_cast<char *>(v + lc);
+    char *const p1 = reinterpret_cast<char *>(v + ((lc ^ mu_l) | hb));
     const R base1 = ((sig ^ par32(g & lc)) != 0u) ? -sn : sn;   // weight of v_j0 in v'_j1
     const R base0 = par32(g & mu) ? -base1 : base1;             // weight of v_j1 in v'_j0
     uint32_t cnt = 0;
@@ -236,17 +247,16 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     for (uint32_t it = 0; it < iters; ++it) {
         const uint32_t J = ins0(it << 6, h);
         const bool flip = par32(g & J) != 0u;
-        if (npairs >= 64u || lane < npairs) {
-            const uint32_t j0 = lc | J, j1 = j0 ^ mu;
-            const C v0 = v[j0], v1 = v[j1];
-            const R c1 = flip ? -base1 : base1, c0 = flip ? -base0 : base0;
-            bool k0, k1;
-            const C o0 = t_out<Q, R, C>(v0, v1, cs, c0, thr, k0);
-            const C o1 = t_out<Q, R, C>(v1, v0, cs, c1, thr, k1);
-            cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
-            v[j0] = o0;
-            v[j1] = o1;
-        }
+        C *const r0 = reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
+        C *const r1 = reinterpret_cast<C *>(p1 + (J ^ mu_i) * (uint32_t)sizeof(C));
+        const C v0 = *r0, v1 = *r1;
+        const R c1 = flip ? -base1 : base1, c0 = flip ? -base0 : base0;
+        bool k0, k1;
+        const C o0 = t_out<Q, R, C>(v0, v1, cs, c0, thr, k0);
+        const C o1 = t_out<Q, R, C>(v1, v0, cs, c1, thr, k1);
+        cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
+        *r0 = o0;
+        *r1 = o1;
     }
     return cnt;
 }
@@ -257,24 +267,28 @@ template <uint32_t Q, typename R, typename C>
 __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R cs, R sn,
                                              R thr) {
     const uint32_t half = 1u << k;
-    const R base = ((sig ^ par32(g & lane)) != 0u) ? -sn : sn;
+    // spare lanes repeat a live lane (see t_bfly)
+    const uint32_t lp = half >= 64u ? lane : (lane & (half - 1u));
+    const uint64_t live = half >= 64u ? ~0ull : ((1ull << half) - 1ull);
+    const R base = ((sig ^ par32(g & lp)) != 0u) ? -sn : sn;
     const C z = {0, 0};
+    char *const p0 = reinterpret_cast<char *>(v + lp);
+    char *const p1 = reinterpret_cast<char *>(v + half + lp);
     uint32_t cnt = 0;
     const uint32_t iters = (half + 63u) >> 6;
     for (uint32_t it = 0; it < iters; ++it) {
         const uint32_t J = it << 6;
         const bool flip = par32(g & J) != 0u;
-        if (half >= 64u || lane < half) {
-            const uint32_t j = J | lane;
-            const C v0 = v[j];
-            const R c1 = flip ? -base : base;
-            bool k0, k1;
-            const C o0 = t_out<0, R, C>(v0, z, cs, (R)0, thr, k0);
-            const C o1 = t_out<Q, R, C>(z, v0, (R)0, c1, thr, k1);
-            cnt += (uint32_t)__popcll(__ballot(k0)) + (uint32_t)__popcll(__ballot(k1));
-            v[j] = o0;
-            v[j + half] = o1;
-        }
+        C *const r0 = reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
+        C *const r1 = reinterpret_cast<C *>(p1 + J * (uint32_t)sizeof(C));
+        const C v0 = *r0;
+        const R c1 = flip ? -base : base;
+        bool k0, k1;
+        const C o0 = t_out<0, R, C>(v0, z, cs, (R)0, thr, k0);
+        const C o1 = t_out<Q, R, C>(z, v0, (R)0, c1, thr, k1);
+        cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
+        *r0 = o0;
+        *r1 = o1;
     }
     return cnt;
 }

@@ -40,20 +40,23 @@ def test_overflow_rerun_without_the_cap():
     N = 50_000
     ctx = make_ctx(w.text, w.noise, seed=41, cap=8)
     capped = _run_range(ctx, 0, N)
-    over = np.nonzero(capped["status"] == soft.SOFT_OVERFLOW)[0]
+    over = np.nonzero(capped["status"] == soft.OVERFLOW)[0]
     assert len(over) > 100
     ref_capped = circ.batch(41, 0, N, cap=8)
     assert (capped["status"] == ref_capped["status"]).all()
     # the re-run: same shot indices, no cap, kept states for a few of them
     ctx.set_caps(0)
-    ctx.set_keep(int(over[0]), int(over[-1] - over[0] + 1))
+    lo = int(over[0])
+    ctx.set_keep(lo, 4096)
     again = _run_list(ctx, over)
-    assert (again["status"] != soft.SOFT_OVERFLOW).all()
+    assert (again["status"] != soft.OVERFLOW).all()
     full = circ.batch(41, 0, N)
     for key in ("status", "abort_op", "obs"):
         assert (again[key] == full[key][over]).all(), key
     assert (again["outcomes"] == full["outcomes"][:, over]).all()
-    for shot in over[:20]:
+    kept = [int(x) for x in over if x < lo + 4096][:20]
+    assert len(kept) >= 5
+    for shot in kept:
         r = circ.shot(41, int(shot))
         x, z, rr = ctx.read_tableau(int(shot))
         assert (x == r.tab_x).all() and (z == r.tab_z).all() and (rr == r.tab_r).all()
