@@ -168,4 +168,8 @@ enum KeepMeta {
 
 constexpr unsigned long long kStateValid = 0x5f7a7e5f7a7e0001ull;
 
+// Measurement-record words a shot keeps in scalar registers; a circuit with
+// at most this many words needs no LDS for its record.
+constexpr uint32_t kRecSgpr = 4;
+
 }  // namespace soft

@@ -34,6 +34,8 @@ struct RunParams {
     uint32_t keep_n, n_vars, rec_words, support_cap;
     uint32_t trace_n, pad_;
     uint32_t wave_bytes, tile_bytes, tile_entries, grab;
+    uint32_t rec_off, pad2_;  // byte offset of the record in a wave's LDS slot (LDS tiles; 0 when the
+                              // record fits in scalar registers and never touches LDS)
     double tau2;              // pruning threshold squared
 };
 
@@ -42,6 +44,10 @@ hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long 
 
 // The persistent sampler: grid x block threads, `lds` bytes of dynamic LDS.
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream);
+
+// Blocks of `block` threads with `lds` bytes of dynamic LDS that one CU keeps
+// resident (registers and LDS).
+hipError_t sampler_occupancy(bool fp64, bool expl, bool gt, int block, size_t lds, int *blocks_per_cu);
 
 // Raise the dynamic-LDS limit of every sampler instantiation (called once).
 hipError_t sampler_set_lds_limit(int bytes);

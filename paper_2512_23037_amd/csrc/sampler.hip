@@ -179,8 +179,6 @@ __device__ __forceinline__ uint32_t first_hit(uint32_t hits, uint32_t cb) {
 
 // Record words per shot held in lanes until the group is written.
 constexpr uint32_t kRecRegs = 8;
-// Record words kept in scalar registers during a shot.
-constexpr uint32_t kRecSgpr = 4;
 
 // Write the outputs of shots [base, base + len) held by lanes 0..len-1.
 __device__ __forceinline__ void flush_group(const RunParams &P, uint64_t base, uint32_t len, uint32_t lane,
@@ -326,7 +324,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes);
     } else {
         v = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
-        rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes + P.tile_bytes);
+        rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes + P.rec_off);
     }
     // Lanes read entries that other lanes wrote in the previous pass: with a
     // device-memory tile, each pass ends with a fence (LDS keeps a wave's
@@ -921,6 +919,15 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
         default: launch_one<double, true, true>(p, grid, block, lds, stream); break;
     }
     return hipGetLastError();
+}
+
+hipError_t sampler_occupancy(bool fp64, bool expl, bool gt, int block, size_t lds, int *blocks_per_cu) {
+    const void *ks[8] = {kernel_ptr<float, false, false>(), kernel_ptr<float, false, true>(),
+                         kernel_ptr<float, true, false>(),  kernel_ptr<float, true, true>(),
+                         kernel_ptr<double, false, false>(), kernel_ptr<double, false, true>(),
+                         kernel_ptr<double, true, false>(),  kernel_ptr<double, true, true>()};
+    const int sel = (fp64 ? 4 : 0) | (expl ? 2 : 0) | (gt ? 1 : 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ks[sel], block, lds);
 }
 
 hipError_t sampler_set_lds_limit(int bytes) {

@@ -140,9 +140,10 @@ uint32_t tile_entries(const soft_ctx *c) { return 1u << c->kmax; }
 uint32_t rec_words(const soft_ctx *c) { return c->rec_words; }
 uint32_t tile_bytes(const soft_ctx *c) { return tile_entries(c) * (c->bits == 64 ? 16u : 8u); }
 // LDS bytes per wave: the tile (unless it lives in device memory) and the record.
+// A record of at most kRecSgpr words stays in scalar registers and takes no LDS.
 uint32_t wave_bytes(const soft_ctx *c, bool gt) {
-    const uint32_t recb = std::max<uint32_t>(16u, (rec_words(c) * 4u + 15u) & ~15u);
-    return gt ? recb : ((tile_bytes(c) + 15u) & ~15u) + recb;
+    const uint32_t recb = rec_words(c) > kRecSgpr ? (rec_words(c) * 4u + 15u) & ~15u : 0u;
+    return gt ? std::max<uint32_t>(16u, recb) : ((tile_bytes(c) + 15u) & ~15u) + recb;
 }
 
 void drop_graph(soft_ctx *c) {
@@ -245,6 +246,13 @@ Shape default_shape(const soft_ctx *c) {
     s.wpb = (waves_cu >= 16u && 2u * wb <= (uint32_t)c->max_lds_block) ? 2u : 1u;
     while (s.wpb > 1 && s.wpb * wb > (uint32_t)c->max_lds_block) s.wpb /= 2;
     s.bpc = std::max<uint32_t>(1u, waves_cu / s.wpb);
+    // no more blocks than stay resident (registers can be the tighter limit)
+    int res = 0;
+    if (sampler_occupancy(c->bits == 64, c->words_dev != nullptr, s.gt != 0, (int)(64u * s.wpb), (size_t)s.wpb * wb,
+                          &res) == hipSuccess && res > 0)
+        s.bpc = std::min<uint32_t>(s.bpc, (uint32_t)res);
+    else
+        (void)hipGetLastError();
     s.grab = 16;
     return s;
 }
@@ -278,6 +286,7 @@ int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStrea
     uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cus * s.bpc, std::max<uint64_t>(blocks_needed, 1));
     const dim3 g((uint32_t)grid), b(64u * s.wpb);
     rp.wave_bytes = wb;
+    rp.rec_off = (!s.gt && rec_words(c) > kRecSgpr) ? ((tile_bytes(c) + 15u) & ~15u) : 0u;
     rp.gtile = nullptr;
     if (s.gt) {  // one slab per wave of the grid
         int rc = ensure(c, c->d_gtile, (size_t)grid * s.wpb * tile_bytes(c));

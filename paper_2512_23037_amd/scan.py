@@ -28,6 +28,7 @@ def main(argv=None):
     ap.add_argument("--bits", type=int, default=32)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sweep", default="", help="comma-separated shots per launch: throughput sweep instead of a scan")
+    ap.add_argument("--autotune", type=float, default=0, help="tune the launch shape on this many shots first")
     args = ap.parse_args(argv)
     if args.circuit:
         text = open(args.circuit).read()
@@ -56,7 +57,7 @@ def main(argv=None):
         print("scan: %d / %d shots, %.1f s" % (done, total, secs), file=sys.stderr, flush=True)
 
     rows = stats.noise_scan(text, ps, int(args.shots_per_p), int(args.batch), bits=args.bits, seed=args.seed,
-                            progress=progress)
+                            progress=progress, autotune=int(args.autotune))
     for r in rows:
         r["bits"] = args.bits
         print(json.dumps(r), flush=True)

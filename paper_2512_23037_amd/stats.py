@@ -112,9 +112,12 @@ def rates(c: dict) -> dict:
 
 
 def noise_scan(text: str, ps, shots_per_p: int, batch: int, bits: int = 32, seed: int = 0,
-               noise_keys=("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp"), progress=None) -> list[dict]:
+               noise_keys=("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp"), progress=None,
+               autotune: int = 0) -> list[dict]:
     """One circuit at each rate of `ps` (uniform circuit-level noise), run as
-    the variants of one mixture over consecutive global shot ranges."""
+    the variants of one mixture over consecutive global shot ranges.  With
+    autotune > 0 the launch shape and tile placement are tuned on that many
+    shots first (outside the timed scan)."""
     from . import soft
 
     ctx = soft.Context(0)
@@ -122,6 +125,9 @@ def noise_scan(text: str, ps, shots_per_p: int, batch: int, bits: int = 32, seed
     ctx.load_mixture([text] * len(ps), [{k: p for k in noise_keys} for p in ps], ends)
     ctx.set_rng(seed)
     ctx.set_precision(bits)
+    if autotune:
+        ctx.autotune(autotune)
+    shape = ctx.launch_shape()
     res = run_batches(ctx, 0, shots_per_p * len(ps), batch, progress=progress)
     rows = []
     for p, c in zip(ps, res["variants"]):
@@ -131,6 +137,7 @@ def noise_scan(text: str, ps, shots_per_p: int, batch: int, bits: int = 32, seed
     total = shots_per_p * len(ps)
     for r in rows:
         r["scan_shots_per_s"] = total / res["seconds"]
+        r["launch"] = shape
     ctx.close()
     return rows
 

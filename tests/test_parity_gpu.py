@@ -72,6 +72,37 @@ def test_ccz_ccx_explicit_words(seed):
     compare_kept(ctx, circ, 0, range(N), words=words)
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_long_records_in_lds(seed):
+    # More than 128 record bits: words beyond the four scalar-register words
+    # live in LDS, and beyond eight words the outputs go out directly;
+    # detectors and feedback read bits across all of them.
+    rng = np.random.default_rng(seed)
+    text, _ = random_circuit(64000 + seed, 4, 700, p_meas=0.5, p_t=0.05, p_mpp=0.02, p_reset=0.0)
+    lines = text.strip().split("\n")
+    out, n_rec = [lines[0]], 0
+    for ln in lines[1:]:
+        out.append(ln)
+        if ln.startswith(("M ", "MPP ")):
+            n_rec += 1
+            if n_rec > 10 and rng.random() < 0.04:
+                r = sorted(rng.choice(n_rec, size=3, replace=False))
+                out.append("DETECTOR %d %s" % (int(rng.integers(2)), " ".join(str(x) for x in r)))
+            if n_rec > 5 and rng.random() < 0.05:
+                out.append("XIF %d %d" % (int(rng.integers(n_rec)), int(rng.integers(4))))
+    out.append("OBSERVABLE 0 %s" % " ".join(str(x) for x in range(0, n_rec, 7)))
+    text = "\n".join(out) + "\n"
+    circ = oracle.Circuit(text)
+    assert circ.n_records > 300
+    N = 512
+    words = _words(circ, N, seed)
+    ctx = make_ctx(text, keep=(0, 64))
+    assert ctx.info()["record_words"] > 8
+    gpu = run_gpu(ctx, 0, N, words)
+    compare_batch(gpu, circ.batch(0, 0, N, words=words))
+    compare_kept(ctx, circ, 0, range(64), words=words)
+
+
 def test_msc_ops_model_noise_philox():
     text, _ = random_circuit(62000, 5, 200, p_msc=0.2, p_ccz=0.03)
     assert "CC" in text
