@@ -89,6 +89,48 @@ def cpu_baseline(w, shots_sample: int):
                       % (shots_sample - 1, SEED_RNG, threads, dt)}, r["work"], shots_sample
 
 
+def bench_mixture(torch, workloads, soft, args):
+    """The batching configuration: the 15-qubit circuit and eight generated
+    shapes (12-20 qubits, 16-40 T/T-dagger) at p in {5e-4, 1e-3, 2e-3}, all
+    in one persistent launch per step; FP64 coefficients."""
+    shots = args.shots
+    m = workloads.mixture(seed=SEED_CIRCUIT, total_shots=shots)
+    ctx = soft.Context(0)
+    ctx.load_mixture([w.text for w in m["workloads"]], m["models"], m["shot_ends"])
+    ctx.set_rng(SEED_RNG)
+    if args.autotune:
+        ctx.autotune(args.autotune)
+    dev = torch.device("cuda", 0)
+    nw = ctx.info()["record_words"]
+    bufs = (torch.zeros((nw, shots), dtype=torch.int32, device=dev), torch.zeros(shots, dtype=torch.int32, device=dev),
+            torch.zeros(shots, dtype=torch.int32, device=dev), torch.zeros(shots, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.run(0, shots, *bufs, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):  # the ranges are fixed: every step runs the same global shots
+        ctx.run(0, shots, *bufs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    c = ctx.counters()
+    per = []
+    for v, (w, mod) in enumerate(zip(m["workloads"], m["models"])):
+        cv = ctx.counters(v)
+        per.append({"circuit": w.name, "p": mod["p1"], "shots": cv["shots"], "passed": cv["passed"],
+                    "logical_errors": cv["logical_errors"]})
+    print(json.dumps({"metric": "shots/sec on 1 MI355X, mixed launch (27 circuit/noise variants)", "value": shots / (ms / 1e3),
+                      "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "mixture: cultivation_15q + 8 generated shapes x p in {5e-4, 1e-3, 2e-3}, "
+                                             "%d shots per launch" % shots, "launch": ctx.launch_shape()},
+                      "stats": {"passed": c["passed"], "discarded": c["discarded"], "support_hist": c["support_hist"]},
+                      "variants": per}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +143,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=0, help="sample shots for the autotuner (0 = library default shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy 3 times (HBM counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--mixture", action="store_true",
+                    help="instead: the batching run (27 circuit/noise variants, --shots in one launch per step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the sampler shards shot ranges across GPUs by design, "
@@ -118,6 +162,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}))
+        return
+
+    if args.mixture:
+        bench_mixture(torch, workloads, soft, args)
         return
 
     w = workloads.config(WORKLOAD, seed=SEED_CIRCUIT)

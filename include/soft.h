@@ -149,10 +149,12 @@ int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
  * size limit on the span dimension (up to k_max = 20). */
 int soft_set_tile_memory(soft_ctx *ctx, int mode);
 
-/* Time a grid of launch shapes (and, in automatic tile mode, both tile
- * placements) on `sample_shots` shots spread over the variants (outputs
- * discarded) and keep the fastest for this circuit, noise model and
- * precision.  Runs on hip_stream and synchronizes it. */
+/* Time the default launch shape and a grid of others (and, in automatic tile
+ * mode, both tile placements) on `sample_shots` shots spread over the
+ * variants, in one launch each (outputs discarded; the better of two timings
+ * counts), and keep the fastest for this circuit, noise model and precision.
+ * Samples of 10^6 shots or more rank shapes reliably; small samples measure
+ * launch overhead.  Runs on hip_stream and synchronizes it. */
 int soft_autotune(soft_ctx *ctx, uint64_t sample_shots, void *hip_stream);
 
 /* Keep the final state of shots [shot_lo, shot_lo + count) of later runs for

@@ -896,37 +896,43 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     if (c->words_dev) return fail(c, SOFT_ESTATE, "autotune runs on Philox draws; clear explicit uniforms first");
     uint32_t *d_status_holder = nullptr;
     hipStream_t st = (hipStream_t)hip_stream;
-    // The sample: the first shots of each variant's range, sample_shots in all.
-    std::vector<std::pair<uint64_t, uint64_t>> seg;
+    // The sample: the first shots of each variant's range, sample_shots in all,
+    // as one shot list so that every timing is a single launch.
+    std::vector<uint64_t> list;
     {
         const uint64_t per = std::max<uint64_t>(1, sample_shots / c->vars.size());
         uint64_t lo = 0;
         for (const Variant &V : c->vars) {
-            seg.push_back({lo, std::min<uint64_t>(per, V.shot_end - lo)});
+            const uint64_t n = std::min<uint64_t>(per, V.shot_end - lo);
+            for (uint64_t i = 0; i < n; ++i) list.push_back(lo + i);
             lo = V.shot_end;
         }
     }
-    uint64_t seg_max = 0;
-    for (auto &g : seg) seg_max = std::max(seg_max, g.second);
-    auto sample_pass = [&](const Shape &s) {
-        int r = SOFT_OK;
-        for (auto &g : seg)
-            if (!r) r = run_impl(c, g.first, g.second, nullptr, d_status_holder, nullptr, nullptr, st, s);
-        return r;
-    };
     uint32_t *d_status = nullptr;
-    HIPCHK(c, hipMalloc((void **)&d_status, seg_max * sizeof(uint32_t)));
+    uint64_t *d_list = nullptr;
+    HIPCHK(c, hipMalloc((void **)&d_status, list.size() * sizeof(uint32_t)));
     d_status_holder = d_status;
+    if (hipMalloc((void **)&d_list, list.size() * sizeof(uint64_t)) != hipSuccess ||
+        hipMemcpy(d_list, list.data(), list.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d_status);
+        if (d_list) (void)hipFree(d_list);
+        return fail(c, SOFT_EDEVICE, "autotune: could not stage the shot list");
+    }
+    auto sample_pass = [&](const Shape &s) {
+        return run_impl(c, 0, list.size(), nullptr, d_status_holder, nullptr, nullptr, st, s, d_list);
+    };
     hipEvent_t t0 = nullptr, t1 = nullptr;
     HIPCHK(c, hipEventCreate(&t0));
     HIPCHK(c, hipEventCreate(&t1));
     const uint32_t keep_n = c->keep_n;
     c->keep_n = 0;
-    Shape best;
-    float best_ms = 1e30f;
+    // Candidates: the default shape first, then a grid of shapes per tile
+    // placement.  Each is run once untimed and twice timed; the faster timing
+    // counts, so one noisy launch cannot pick a worse shape than the default.
+    std::vector<Shape> cands;
+    cands.push_back(default_shape(c));
     const uint32_t wpbs[3] = {1, 2, 4};
     const uint32_t grabs[2] = {16, 64};
-    // Tile placements to try: the forced one, or LDS (if it fits) and device memory.
     std::vector<uint32_t> gts;
     if (c->tile_mode == 1) gts = {0u};
     else if (c->tile_mode == 2) gts = {1u};
@@ -942,39 +948,45 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
                 uint32_t v = std::max<uint32_t>(1u, occ / d);
                 if (std::find(bpcs.begin(), bpcs.end(), v) == bpcs.end()) bpcs.push_back(v);
             }
-            for (uint32_t bpc : bpcs) {
+            for (uint32_t bpc : bpcs)
                 for (uint32_t grab : grabs) {
-                    Shape s;
-                    s.wpb = wpb;
-                    s.bpc = bpc;
-                    s.grab = grab;
-                    s.gt = gt;
-                    float ms = 0.0f;
-                    // one untimed run, then one timed run
-                    rc = sample_pass(s);
-                    hipError_t e = rc ? hipSuccess : hipEventRecord(t0, st);
-                    if (!rc && e == hipSuccess) rc = sample_pass(s);
-                    if (!rc && e == hipSuccess) e = hipEventRecord(t1, st);
-                    if (!rc && e == hipSuccess) e = hipEventSynchronize(t1);
-                    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                    if (!rc && e != hipSuccess) rc = fail(c, SOFT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
-                    if (rc) break;
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = s;
-                    }
+                    Shape sh;
+                    sh.wpb = wpb;
+                    sh.bpc = bpc;
+                    sh.grab = grab;
+                    sh.gt = gt;
+                    cands.push_back(sh);
                 }
-                if (rc) break;
-            }
-            if (rc) break;
+        }
+    }
+    Shape best = cands[0];
+    float best_ms = 1e30f;
+    for (const Shape &sh : cands) {
+        if (check_shape(c, sh) != SOFT_OK) continue;
+        rc = sample_pass(sh);  // untimed: graph capture, caches
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            float t = 0.0f;
+            hipError_t e = hipEventRecord(t0, st);
+            if (e == hipSuccess) rc = sample_pass(sh);
+            if (!rc && e == hipSuccess) e = hipEventRecord(t1, st);
+            if (!rc && e == hipSuccess) e = hipEventSynchronize(t1);
+            if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, t0, t1);
+            if (!rc && e != hipSuccess) rc = fail(c, SOFT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+            if (!rc) ms = std::min(ms, t);
         }
         if (rc) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
     }
     c->keep_n = keep_n;
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     (void)hipStreamSynchronize(st);
     (void)hipFree(d_status);
+    (void)hipFree(d_list);
     if (rc) return rc;
     c->tuned[std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode)] = best;
     c->ran = false;  // counters of the last sample run are not a user run
