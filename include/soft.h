@@ -67,6 +67,9 @@ typedef struct {
     uint64_t events;             /* T/T-dagger and measurements executed      */
     uint64_t support_hist[16];   /* shots by floor(log2(max |v|)), last bin 15+ */
     double max_norm_dev;         /* max over shots of |sum |v|^2 - 1| at the end */
+    uint64_t restarts;           /* shots re-run on the full event list: the speculative
+                                    list's span truncation found amplitude left (noise
+                                    broke a T / T-dagger cancellation) */
 } soft_counters;
 
 /* Create a context on HIP device `hip_device` (made current for the call).
@@ -141,6 +144,18 @@ int soft_set_prune(soft_ctx *ctx, double tau);
  * together): launch shape, 0 = the autotuned or default value. */
 int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
                   uint32_t blocks_per_cu, uint32_t grab);
+
+/* Speculative span truncation (on by default): where every T of a run since
+ * a checkpoint meets its inverse on the same qubit with nothing in between
+ * that fails to commute with its Z (T and T-dagger layers around commuting
+ * check rounds), the product of the pairs is the identity, so a shot whose
+ * noise left the pairs intact has its coefficients back on the checkpoint's
+ * span.  The compiler then emits a second event list that truncates the span
+ * there; the kernel verifies that the dropped coordinates hold exact zeros
+ * and otherwise restarts the shot on the full list (counted in
+ * soft_counters.restarts).  Results are the full list's either way (up to
+ * rounding order in the FP64 sums).  on = 0 runs the full list only. */
+int soft_set_speculation(soft_ctx *ctx, int on);
 
 /* Where the per-wave coefficient tile lives: 0 = automatic (LDS when one
  * wave's tile fits in a block's LDS, else device memory), 1 = LDS, 2 = device

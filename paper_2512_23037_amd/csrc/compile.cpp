@@ -65,7 +65,7 @@ struct RowMask {
 // The shot-independent tableau, by column, plus the span and the event list.
 class FrameCompiler {
   public:
-    FrameCompiler(int n, Program &prog) : n_(n), P_(prog), cx_(n), cz_(n) {
+    FrameCompiler(int n, Program &prog, bool speculate) : n_(n), P_(prog), cx_(n), cz_(n), spec_(speculate) {
         for (int q = 0; q < n; ++q) {
             cx_[q].d = bitq(q);  // d_q = X_q
             cz_[q].s = bitq(q);  // s_q = Z_q
@@ -73,7 +73,11 @@ class FrameCompiler {
     }
 
     // ---- Cliffords: x/z columns move, sign flips accumulate in acc_ ----
-    void h(int a) { acc_ ^= cx_[a] & cz_[a]; std::swap(cx_[a], cz_[a]); }
+    void h(int a) {
+        spec_touch(a);
+        acc_ ^= cx_[a] & cz_[a];
+        std::swap(cx_[a], cz_[a]);
+    }
     void s(int a) { acc_ ^= cx_[a] & cz_[a]; cz_[a] ^= cx_[a]; }
     void sdg(int a) {
         RowMask notz = {~cz_[a].d, ~cz_[a].s};
@@ -82,19 +86,28 @@ class FrameCompiler {
     }
     // (X + Y)/sqrt2: X -> Y, Y -> X, Z -> -Z
     void hxy(int a) {
+        spec_touch(a);
         RowMask notx = {~cx_[a].d, ~cx_[a].s};
         acc_ ^= cz_[a] & notx;
         cz_[a] ^= cx_[a];
     }
     // (X - Y)/sqrt2: X -> -Y, Y -> -X, Z -> -Z
     void hnxy(int a) {
+        spec_touch(a);
         acc_ ^= cx_[a] | cz_[a];
         cz_[a] ^= cx_[a];
     }
-    void px(int a) { acc_ ^= cz_[a]; }
+    void px(int a) {
+        spec_touch(a);
+        acc_ ^= cz_[a];
+    }
     void pz(int a) { acc_ ^= cx_[a]; }
-    void py(int a) { acc_ ^= cx_[a] ^ cz_[a]; }
+    void py(int a) {
+        spec_touch(a);
+        acc_ ^= cx_[a] ^ cz_[a];
+    }
     void cnot(int a, int b) {
+        spec_touch(b);  // Z_a commutes with CNOT(a -> b), Z_b does not
         RowMask t = cx_[b] ^ cz_[a];
         RowMask nt = {~t.d, ~t.s};
         acc_ ^= cx_[a] & cz_[b] & nt;
@@ -131,6 +144,7 @@ class FrameCompiler {
     void t_gate(int q, bool dagger, uint32_t src) {
         PauliStr Z;
         Z.z = bitq(q);
+        const uint32_t k_before = (uint32_t)basis_.size();
         Event E = begin(src);
         uint64_t beta, gamma;
         int cexp;
@@ -173,11 +187,13 @@ class FrameCompiler {
         }
         E.Afr = (float)E.Are; E.Afi = (float)E.Aim; E.Bfr = (float)E.Bre; E.Bfi = (float)E.Bim;
         finish(E);
+        spec_after_t(q, dagger, k_before, src);
     }
 
     // Measurement of P (Hermitian, sign +); reset adds a conditional X_q.
     // reset_z: the reset flips with Z_q (X-basis reset) instead of X_q.
     void measure(const PauliStr &P, uint32_t mslot, int rec, int reset_q, uint32_t src, bool reset_z = false) {
+        if ((P.x & open_mask_) || (reset_q >= 0 && !reset_z && ((open_mask_ >> reset_q) & 1ull))) spec_reset();
         Event E = begin(src);
         uint64_t beta, gamma;
         int cexp;
@@ -258,6 +274,7 @@ class FrameCompiler {
             set_row(false, p, sp.x, sp.z);
             set_row(true, p, P.x, P.z);
         }
+        if (E.kind != EV_M_DET) spec_reset();  // the span changed
         if (reset_q >= 0) {  // rows anticommuting with the flip, in the frame after the measurement
             E.flags |= EVF_RESET;
             const RowMask &m = reset_z ? cx_[reset_q] : cz_[reset_q];
@@ -312,6 +329,7 @@ class FrameCompiler {
 
     // Pauli (1 X, 2 Y, 3 Z) on qubit q when record bit `rec` is 1.
     void feedback(int pauli, int q, uint32_t rec, uint32_t src) {
+        if (pauli != 3) spec_touch(q);
         Event E = begin(src);
         E.kind = EV_FEEDBACK;
         E.rec = rec;
@@ -338,6 +356,52 @@ class FrameCompiler {
     }
 
   private:
+    // ---- speculative span truncation ----
+    // T gates opened since a checkpoint (a point with span dimension ckpt_k_).
+    // When every one of them has met its inverse on the same qubit, with
+    // nothing in between that fails to commute with its Z, the product of the
+    // pairs is the identity, so a shot whose noise did not break a pair has its
+    // coefficients back on coordinates < ckpt_k_: a DROP event returns the span
+    // to that dimension (the kernel checks the entries above are zero and
+    // restarts the shot on the full event list otherwise).
+    struct OpenT {
+        int q;
+        bool dagger;
+    };
+    bool spec_;
+    std::vector<OpenT> open_;
+    uint64_t open_mask_ = 0;
+    uint32_t ckpt_k_ = 0;
+
+    void spec_reset() {
+        open_.clear();
+        open_mask_ = 0;
+    }
+    void spec_touch(int q) {
+        if ((open_mask_ >> q) & 1ull) spec_reset();
+    }
+    void spec_after_t(int q, bool dagger, uint32_t k_before, uint32_t src) {
+        if (!spec_) return;
+        for (size_t i = open_.size(); i-- > 0;) {
+            if (open_[i].q == q && open_[i].dagger != dagger) {
+                open_.erase(open_.begin() + (long)i);
+                open_mask_ = 0;
+                for (const OpenT &o : open_) open_mask_ |= bitq(o.q);
+                if (open_.empty() && basis_.size() > ckpt_k_) {
+                    Event D = begin(src);
+                    D.kind = EV_DROP;
+                    D.mu = ckpt_k_;
+                    basis_.resize(ckpt_k_);
+                    finish(D);
+                }
+                return;
+            }
+        }
+        if (open_.empty()) ckpt_k_ = k_before;
+        open_.push_back({q, dagger});
+        open_mask_ |= bitq(q);
+    }
+
     int n_;
     Program &P_;
     std::vector<RowMask> cx_, cz_;
@@ -592,7 +656,7 @@ uint64_t fnv1a(const void *data, size_t len, uint64_t h) {
 
 }  // namespace
 
-void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out) {
+void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out, bool speculate) {
     out = Program();
     const double probs[6] = {nm.p1, nm.p2, nm.p_idle, nm.p_meas, nm.p_reset, nm.p_mpp};
     for (double p : probs)
@@ -605,7 +669,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     const int n = parse_uint(tok[1], cur.line);
     if (n < 1 || n > 64) throw CompileError{cur.line, "QUBITS must be in 1..64"};
     out.n = n;
-    FrameCompiler fc(n, out);
+    FrameCompiler fc(n, out, speculate);
     std::vector<char> busy(n, 0);
     uint32_t src = 0;
 

@@ -43,7 +43,10 @@ struct CompileError {
 // Largest span dimension the compiler accepts.
 constexpr uint32_t kMaxSpanDim = 20;
 
-// Throws CompileError.
-void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out);
+// Throws CompileError.  With `speculate`, the event list also carries DROP
+// events that return the span to its size before a run of T gates once all of
+// them have met their inverses (the full list has none; both assign the same
+// noise and measurement slots and records).
+void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out, bool speculate = false);
 
 }  // namespace soft

@@ -42,6 +42,7 @@ enum EvKind : uint32_t {
     EV_DETECTOR,     // parity check of record bits, abort on failure
     EV_OBSERVABLE,   // parity of record bits, stored as an observable bit
     EV_FEEDBACK,     // Pauli flip (masks xD/xS) when record bit `rec` is 1 (as the check dw0/dm0)
+    EV_DROP,         // speculative: coordinates >= mu carry no amplitude; k -> mu
     EV_END
 };
 
@@ -132,7 +133,8 @@ struct alignas(16) VariantDesc {
     uint64_t shot_end;
     uint32_t ev_off, nz_off, tm1_off;  // tm1_off is a multiple of 256
     uint32_t n_noise;
-    uint32_t pad[2];
+    uint32_t ev_off_full;  // the full event list (ev_off: the speculative one, or the same)
+    uint32_t pad;
 };
 static_assert(sizeof(VariantDesc) == 32, "variant layout");
 constexpr uint32_t kMaxVariants = 64;
@@ -156,6 +158,7 @@ enum Status : uint32_t { ST_PASSED = 0, ST_DISCARDED = 1, ST_OVERFLOW = 2, ST_NU
 enum Counter {
     C_SHOTS = 0, C_PASSED, C_DISCARDED, C_OVERFLOW, C_NUMERIC, C_LOGICAL,
     C_ENTRIES_T, C_ENTRIES_M, C_NOISE, C_EVENTS, C_NORMDEV_BITS,
+    C_RESTARTS,              // shots restarted on the full list after a failed DROP check
     C_HIST0,                 // 16 buckets of floor(log2(max |v|))
     C_COUNT = C_HIST0 + 16
 };
@@ -163,7 +166,8 @@ enum Counter {
 // Per kept shot (and per traced step): meta words, and separately the dense
 // coefficient tile as double pairs.  KM_VALID holds kStateValid once written.
 enum KeepMeta {
-    KM_STATUS = 0, KM_ABORT, KM_TERM_EV, KM_AFTER, KM_RD, KM_RS, KM_A, KM_K, KM_NRM2, KM_VALID, KM_VAR, KM_COUNT
+    KM_STATUS = 0, KM_ABORT, KM_TERM_EV, KM_AFTER, KM_RD, KM_RS, KM_A, KM_K, KM_NRM2, KM_VALID, KM_VAR, KM_PROG,
+    KM_COUNT
 };
 
 constexpr unsigned long long kStateValid = 0x5f7a7e5f7a7e0001ull;

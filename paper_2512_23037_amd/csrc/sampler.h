@@ -34,8 +34,9 @@ struct RunParams {
     uint32_t keep_n, n_vars, rec_words, support_cap;
     uint32_t trace_n, pad_;
     uint32_t wave_bytes, tile_bytes, tile_entries, grab;
-    uint32_t rec_off, pad2_;  // byte offset of the record in a wave's LDS slot (LDS tiles; 0 when the
+    uint32_t rec_off;         // byte offset of the record in a wave's LDS slot (LDS tiles; 0 when the
                               // record fits in scalar registers and never touches LDS)
+    uint32_t speculate;       // 1: run the speculative event list first
     double tau2;              // pruning threshold squared
 };
 

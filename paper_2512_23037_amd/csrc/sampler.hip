@@ -137,7 +137,8 @@ template <typename C>
 __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const C *v, uint32_t lane,
                                            uint32_t tile_entries, uint32_t status, uint32_t abort_src, uint32_t term,
                                            uint32_t after, uint64_t rD, uint64_t rS, uint64_t a, uint32_t k,
-                                           double nrm2, const double *phase_tab, uint32_t phase8, uint32_t var) {
+                                           double nrm2, const double *phase_tab, uint32_t phase8, uint32_t var,
+                                           uint32_t full) {
     if (lane == 0) {
         m[KM_STATUS] = status;
         m[KM_ABORT] = abort_src;
@@ -150,6 +151,7 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
         m[KM_NRM2] = (unsigned long long)__double_as_longlong(nrm2);
         m[KM_VALID] = kStateValid;
         m[KM_VAR] = var;
+        m[KM_PROG] = full;
     }
     const double pc = phase_tab[phase8], ps = phase_tab[16u + phase8];
     const uint32_t cnt = 1u << k;
@@ -178,7 +180,7 @@ __device__ __forceinline__ uint32_t first_hit(uint32_t hits, uint32_t cb) {
 }
 
 // Record words per shot held in lanes until the group is written.
-constexpr uint32_t kRecRegs = 8;
+constexpr uint32_t kRecRegs = 4;
 
 // Write the outputs of shots [base, base + len) held by lanes 0..len-1.
 __device__ __forceinline__ void flush_group(const RunParams &P, uint64_t base, uint32_t len, uint32_t lane,
@@ -294,7 +296,7 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
 // Work counted during one shot (32 bits suffice per shot); added to the
 // lane-held 64-bit counters when the shot ends.
 struct ShotTotals {
-    uint32_t entries_t = 0, entries_m = 0, noise = 0, events = 0;
+    uint32_t entries_t = 0, entries_m = 0, noise = 0, events = 0, restarts = 0;
 };
 
 // Fields of the current event (held one dword per lane in `evc`).
@@ -344,7 +346,6 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
     uint32_t var = 0;
     bool var_ok = false;
     uint64_t var_lo = 0, var_end = 0;
-    const uint32_t *ev32 = nullptr;
     auto flush_counters = [&]() {
         unsigned long long *row = P.counters + (size_t)var * C_COUNT;
         if (lane < (uint32_t)C_COUNT && lane != (uint32_t)C_NORMDEV_BITS && myc) atomicAdd(row + lane, (unsigned long long)myc);
@@ -383,13 +384,11 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             const VariantDesc &VD = P.vars[var];
             var_lo = var ? P.vars[var - 1u].shot_end : 0ull;
             var_end = VD.shot_end;
-            ev32 = reinterpret_cast<const uint32_t *>(ev + VD.ev_off);
             var_ok = true;
         }
         const uint32_t *wrow = EXPL ? words + i * P.word_stride : nullptr;
 
-        // ---- shot start: d_i = +X_i, s_i = +Z_i, v = {0: 1} ----
-        for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64) rec[w] = 0u;
+        // ---- per-shot state (set at the start of each attempt below) ----
         // record words 0..3 live in scalar registers, the rest in LDS
         uint32_t rr0 = 0, rr1 = 0, rr2 = 0, rr3 = 0;
         auto rec_read = [&](uint32_t w) -> uint32_t {
@@ -417,8 +416,6 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             }
             return uni(pbits);
         };
-        if (lane == 0) v[0] = mk<C>(1.0, 0.0);
-        tile_sync();
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
         uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
@@ -490,15 +487,40 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             next_hit = first_hit(hits, nz_cb);
             return fr;
         };
+        // The speculative event list runs first (a traced shot takes the full
+        // list, so that every trace step exists); a failed DROP check restarts
+        // the shot on the full list.  A shot's draws depend only on its slots,
+        // so the restarted shot is the one the full list gives.
+        bool full = tracing || !P.speculate || vdp->ev_off_full == vdp->ev_off;
+        for (;;) {
+        const uint32_t *evl = reinterpret_cast<const uint32_t *>(ev + (full ? vdp->ev_off_full : vdp->ev_off));
+        for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64) rec[w] = 0u;
+        rr0 = rr1 = rr2 = rr3 = 0u;
+        if (lane == 0) v[0] = mk<C>(1.0, 0.0);
+        tile_sync();
+        rD = rS = a = 0ull;
+        k = 0;
+        phase8 = 0;
+        nrm2 = 1.0;
+        status = ST_PASSED;
+        abort_src = 0xFFFFFFFFu;
+        obs = 0;
+        maxsup = 1;
+        term = after = 0;
+        nz_cb = nz_drawn = 0;
+        next_hit = kNoHit;
+        hits = 0;
+        m_base = 0xFFFFFF00u;
+        bool restart = false;
         // Event e sits in evc, one dword per lane; event e + 1 is loaded while
         // event e runs (the list ends with two END events).
-        evc = ev32[lane];
+        evc = evl[lane];
         for (uint32_t e = 0;; ++e) {
-            uint32_t evx = ev32[(uint64_t)(e + 1u) * 64u + lane];
+            uint32_t evx = evl[(uint64_t)(e + 1u) * 64u + lane];
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
-                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var);
+                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u);
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
@@ -663,7 +685,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     break;
                 }
                 e += m - 1u;
-                evx = ev32[(uint64_t)(e + 1u) * 64u + lane];
+                evx = evl[(uint64_t)(e + 1u) * 64u + lane];
             } else if (kind <= EV_M_MERGE) {
                 // ---- measurement ----
                 // The uniform is drawn only when the outcome is random.  Philox
@@ -827,6 +849,28 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         break;
                     }
                 }
+            } else if (kind == EV_DROP) {
+                // ---- speculative span truncation: coordinates >= k0 must be empty ----
+                const uint32_t k0 = EV32(mu), cnt = 1u << k;
+                bool live = false;
+                for (uint32_t j = (1u << k0) + lane; j < cnt; j += 64u) {
+                    const C x = v[j];
+                    live = live || x.x != (R)0 || x.y != (R)0;
+                }
+                if (__ballot(live) != 0ull) {
+                    restart = true;
+                    break;
+                }
+                k = k0;
+                if (k0 == 0u) {
+                    // One entry is left and the exact state has unit norm: rescale
+                    // it in FP64 (the cuts the full list runs next do the same).
+                    const C x = v[0];
+                    const double q = nrm<R>(x);
+                    const R sc = (R)(1.0 / sqrt(q));
+                    if (lane == 0) v[0] = scale(x, sc);
+                    nrm2 = q * (double)sc * (double)sc;
+                }
             } else if (kind == EV_FEEDBACK) {
                 // ---- classically controlled Pauli: the record bit is a one-pair check ----
                 if (parity_check()) {
@@ -851,6 +895,10 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             evc = evx;
         }
         tile_sync();
+        if (!restart) break;
+        full = true;
+        ++tot.restarts;
+        }
 
         // ---- shot end: norm check, outputs, kept states, counters ----
         const uint32_t cnt = 1u << k;
@@ -872,16 +920,17 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
             const uint64_t kk = shot - P.keep_lo;
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
-                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var);
+                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u);
         }
         if (tracing && term < P.trace_n)
             dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
-                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var);
+                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u);
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
         myc += lane == C_ENTRIES_T ? tot.entries_t : lane == C_ENTRIES_M ? tot.entries_m
-             : lane == C_NOISE ? tot.noise : lane == C_EVENTS ? tot.events : 0u;
+             : lane == C_NOISE ? tot.noise : lane == C_EVENTS ? tot.events
+             : lane == C_RESTARTS ? tot.restarts : 0u;
     }
     if (var_ok) flush_counters();
 }

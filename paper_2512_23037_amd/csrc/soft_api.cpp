@@ -36,7 +36,9 @@ struct Variant {
     std::string text;
     NoiseModel noise;
     uint64_t shot_end = ~0ull;  // global shots [previous end, shot_end)
-    Program prog;
+    Program prog;               // the full event list
+    Program fast;               // the speculative list with DROP events (empty: none found)
+    bool has_fast = false;
 };
 
 constexpr size_t kCounterWords = (size_t)kMaxVariants * C_COUNT + 1;
@@ -70,6 +72,7 @@ struct soft_ctx {
     double tau = -1.0;
     uint32_t support_cap = 0;
     int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory
+    bool speculate = true;                    // run speculative event lists where compiled
     Shape user;                               // explicit launch shape parts
     std::map<std::tuple<uint64_t, int, double, uint32_t, int>, Shape> tuned;
 
@@ -152,15 +155,29 @@ void drop_graph(soft_ctx *c) {
     c->gkey.clear();
 }
 
-int compile_into(soft_ctx *c, const std::string &text, const NoiseModel &nm, Program &out) {
+int compile_into(soft_ctx *c, const std::string &text, const NoiseModel &nm, Program &out, bool speculate = false) {
     try {
-        compile_circuit(text, nm, out);
+        compile_circuit(text, nm, out, speculate);
     } catch (const CompileError &e) {
         return fail(c, e.line > 0 ? SOFT_EPARSE : SOFT_ECAPACITY,
                     e.line > 0 ? "line " + std::to_string(e.line) + ": " + e.msg : e.msg);
     } catch (const std::bad_alloc &) {
         return fail(c, SOFT_ECAPACITY, "out of host memory while compiling");
     }
+    return SOFT_OK;
+}
+
+// Compile a variant's full event list and, when the circuit offers span
+// truncations, its speculative list.
+int compile_variant(soft_ctx *c, Variant &V) {
+    int rc = compile_into(c, V.text, V.noise, V.prog);
+    if (rc) return rc;
+    V.has_fast = false;
+    V.fast = Program();
+    if ((rc = compile_into(c, V.text, V.noise, V.fast, true))) return rc;
+    for (const Event &E : V.fast.events)
+        if (E.kind == EV_DROP) V.has_fast = true;
+    if (!V.has_fast) V.fast = Program();
     return SOFT_OK;
 }
 
@@ -183,20 +200,26 @@ int prepare(soft_ctx *c) {
         VariantDesc D;
         std::memset(&D, 0, sizeof(D));
         D.shot_end = V.shot_end;
-        D.ev_off = (uint32_t)ev.size();
         D.nz_off = (uint32_t)nz.size();
         D.tm1_off = (uint32_t)tm1.size();
         D.n_noise = P.n_noise;
-        const uint32_t det_base = (uint32_t)(det.size() / 2), bm_base = (uint32_t)bm.size();
-        for (Event E : P.events) {
-            E.det_off += det_base;
-            if (E.flags & EVF_BATCH) E.boff += bm_base;
-            ev.push_back(E);
-        }
+        // each event list with its own check pairs and run members
+        auto append = [&](const Program &Q) {
+            const uint32_t off = (uint32_t)ev.size();
+            const uint32_t det_base = (uint32_t)(det.size() / 2), bm_base = (uint32_t)bm.size();
+            for (Event E : Q.events) {
+                E.det_off += det_base;
+                if (E.flags & EVF_BATCH) E.boff += bm_base;
+                ev.push_back(E);
+            }
+            det.insert(det.end(), Q.det_pairs.begin(), Q.det_pairs.end());
+            bm.insert(bm.end(), Q.batch.begin(), Q.batch.end());
+            return off;
+        };
+        D.ev_off_full = append(P);
+        D.ev_off = V.has_fast ? append(V.fast) : D.ev_off_full;
         nz.insert(nz.end(), P.noise.begin(), P.noise.end());
         tm1.insert(tm1.end(), P.noise_tm1.begin(), P.noise_tm1.end());
-        det.insert(det.end(), P.det_pairs.begin(), P.det_pairs.end());
-        bm.insert(bm.end(), P.batch.begin(), P.batch.end());
         vd.push_back(D);
         c->kmax = std::max(c->kmax, P.kmax);
         c->rec_words = std::max(c->rec_words, (P.n_rec + 31u) / 32u);
@@ -331,6 +354,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.tm1 = c->d_tm1.p;
     rp.det = c->d_det.p;
     rp.bm = c->d_bm.p;
+    rp.speculate = c->speculate ? 1u : 0u;
     rp.vars = c->d_vars.p;
     rp.n_vars = (uint32_t)c->vars.size();
     rp.words = c->words_dev;
@@ -397,14 +421,24 @@ int run_impl(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, 
     return SOFT_OK;
 }
 
+// The event list that produced a dumped state.
+const Program &program_of(const soft_ctx *c, const std::vector<unsigned long long> &meta) {
+    const Variant &V = c->vars[meta[KM_VAR]];
+    return (meta[KM_PROG] || !V.has_fast) ? V.prog : V.fast;
+}
+
 // Frame (x/z bits and span basis) in which a dumped state is expressed.
 const Frame *frame_of(soft_ctx *c, const std::vector<unsigned long long> &meta, int &rc) {
     const uint64_t v = meta[KM_VAR], term = meta[KM_TERM_EV];
-    if (v >= c->vars.size() || term >= c->vars[v].prog.events.size()) {
+    if (v >= c->vars.size()) {
         rc = fail(c, SOFT_EDEVICE, "corrupt dumped state");
         return nullptr;
     }
-    const Program &P = c->vars[v].prog;
+    const Program &P = program_of(c, meta);
+    if (term >= P.events.size()) {
+        rc = fail(c, SOFT_EDEVICE, "corrupt dumped state");
+        return nullptr;
+    }
     return meta[KM_AFTER] ? &P.after[term] : &P.before[term];
 }
 
@@ -559,7 +593,7 @@ int soft_load_circuit(soft_ctx *c, const char *text, size_t len) {
     Variant V;
     V.text.assign(text ? text : "", len);
     V.noise = c->noise;
-    int rc = compile_into(c, V.text, V.noise, V.prog);
+    int rc = compile_variant(c, V);
     if (rc) return rc;
     c->vars.clear();
     c->vars.push_back(std::move(V));
@@ -584,11 +618,12 @@ int soft_load_noise(soft_ctx *c, const soft_noise *m) {
     for (double p : ps)
         if (!(p >= 0.0 && p <= 1.0)) return fail(c, SOFT_EINVAL, "noise probability out of [0,1]");
     if (c->have_text) {
-        Program P;
-        int rc = compile_into(c, c->vars[0].text, nm, P);
+        Variant V;
+        V.text = c->vars[0].text;
+        V.noise = nm;
+        int rc = compile_variant(c, V);
         if (rc) return rc;
-        c->vars[0].noise = nm;
-        c->vars[0].prog = std::move(P);
+        c->vars[0] = std::move(V);
         c->dirty = true;
     }
     c->noise = nm;
@@ -618,7 +653,7 @@ int soft_load_mixture(soft_ctx *c, uint32_t n_variants, const char *const *texts
         vs[v].text.assign(texts[v] ? texts[v] : "", lens[v]);
         vs[v].noise = nm;
         vs[v].shot_end = shot_ends[v];
-        int rc = compile_into(c, vs[v].text, nm, vs[v].prog);
+        int rc = compile_variant(c, vs[v]);
         if (rc) return fail(c, rc, "variant " + std::to_string(v) + ": " + c->err);
     }
     c->vars = std::move(vs);
@@ -673,6 +708,12 @@ int soft_set_caps(soft_ctx *c, uint32_t support_cap, uint32_t wpb, uint32_t bpc,
     c->user.wpb = wpb;
     c->user.bpc = bpc;
     c->user.grab = grab;
+    return SOFT_OK;
+}
+
+int soft_set_speculation(soft_ctx *c, int on) {
+    if (!c) return SOFT_EINVAL;
+    c->speculate = on != 0;
     return SOFT_OK;
 }
 
@@ -737,6 +778,7 @@ int read_rows(soft_ctx *c, uint32_t v0, uint32_t v1, soft_counters *out) {
         out->entries_m += r[C_ENTRIES_M];
         out->noise_slots += r[C_NOISE];
         out->events += r[C_EVENTS];
+        out->restarts += r[C_RESTARTS];
         for (int b = 0; b < 16; ++b) out->support_hist[b] += r[C_HIST0 + b];
         double d;
         std::memcpy(&d, &r[C_NORMDEV_BITS], sizeof(double));
@@ -824,7 +866,7 @@ int soft_read_trace(soft_ctx *c, uint32_t step, uint64_t info[6], uint64_t *x, u
     int rc = SOFT_OK;
     const Frame *f = frame_of(c, meta, rc);
     if (!f) return rc;
-    const Event &E = c->vars[meta[KM_VAR]].prog.events[meta[KM_TERM_EV]];
+    const Event &E = program_of(c, meta).events[meta[KM_TERM_EV]];
     info[0] = 1;
     info[1] = (meta[KM_STATUS] != ST_PASSED && meta[KM_ABORT] != 0xFFFFFFFFull) ? meta[KM_ABORT] : E.src;
     info[2] = meta[KM_STATUS];

@@ -25,7 +25,7 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
            "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
-           "soft_run_list")
+           "soft_run_list", "soft_set_speculation")
 
 
 class SoftError(RuntimeError):
@@ -42,7 +42,8 @@ class soft_counters(ctypes.Structure):
     _fields_ = [("shots", ctypes.c_uint64), ("passed", ctypes.c_uint64), ("discarded", ctypes.c_uint64),
                 ("overflow", ctypes.c_uint64), ("numeric", ctypes.c_uint64), ("logical_errors", ctypes.c_uint64),
                 ("entries_t", ctypes.c_uint64), ("entries_m", ctypes.c_uint64), ("noise_slots", ctypes.c_uint64),
-                ("events", ctypes.c_uint64), ("support_hist", ctypes.c_uint64 * 16), ("max_norm_dev", ctypes.c_double)]
+                ("events", ctypes.c_uint64), ("support_hist", ctypes.c_uint64 * 16), ("max_norm_dev", ctypes.c_double),
+                ("restarts", ctypes.c_uint64)]
 
 
 _lib = None
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "soft_variant_info": (I, [P, U32, P]),
         "soft_set_tile_memory": (I, [P, I]),
         "soft_run_list": (I, [P, P, U64, P, P, P, P, P]),
+        "soft_set_speculation": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -192,6 +194,10 @@ class Context:
 
     def set_caps(self, support_cap=0, waves_per_block=0, blocks_per_cu=0, grab=0):
         self._check(self._lib.soft_set_caps(self._h, support_cap, waves_per_block, blocks_per_cu, grab))
+
+    def set_speculation(self, on: bool):
+        """Run the speculative (span-truncating) event lists first (default)."""
+        self._check(self._lib.soft_set_speculation(self._h, 1 if on else 0))
 
     def set_tile_memory(self, mode: int):
         """0 automatic, 1 LDS, 2 device memory (HBM)."""

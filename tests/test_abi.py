@@ -42,12 +42,14 @@ def test_struct_layout_matches_binding(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "soft.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(soft_noise), sizeof(soft_counters),'
-                   ' offsetof(soft_counters, support_hist), offsetof(soft_counters, max_norm_dev));return 0;}\n')
+                   ' offsetof(soft_counters, support_hist), offsetof(soft_counters, max_norm_dev));'
+                   ' printf("%zu\\n", offsetof(soft_counters, restarts));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [ctypes.sizeof(soft.soft_noise), ctypes.sizeof(soft.soft_counters),
-                   soft.soft_counters.support_hist.offset, soft.soft_counters.max_norm_dev.offset]
+                   soft.soft_counters.support_hist.offset, soft.soft_counters.max_norm_dev.offset,
+                   soft.soft_counters.restarts.offset]
 
 
 def test_header_compiles_as_c_and_cxx(tmp_path):

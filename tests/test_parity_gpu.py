@@ -193,6 +193,48 @@ def test_measurement_runs_with_dense_noise(workload, rate):
     compare_kept(ctx, circ, 0, range(256), words=words[:256])
     # shots end at many different checks, not only the first
     assert len(np.unique(ref["abort_op"])) > 5
+    # the dense noise breaks T / T-dagger cancellations: restarted shots
+    assert ctx.counters()["restarts"] > 0
+
+
+@pytest.mark.parametrize("workload,bits", [("cultivation_15q", 64), ("cultivation_42q", 64), ("cultivation_42q", 32)])
+def test_speculative_lists_equal_full_lists(workload, bits):
+    # The span-truncating event list (with restarts where noise broke a
+    # cancellation) gives the full list's results: records, statuses, abort
+    # ops and observables bit for bit, kept coefficients to rounding.
+    w = workloads.config(workload, seed=1)
+    N = 200_000
+    outs, kept = {}, {}
+    for spec in (True, False):
+        ctx = make_ctx(w.text, w.noise, seed=31, bits=bits, keep=(0, 128))
+        ctx.set_speculation(spec)
+        outs[spec] = run_gpu(ctx, 0, N)
+        kept[spec] = [ctx.read_coeffs(s_) for s_ in range(128)]
+        c = ctx.counters()
+        if spec:
+            assert 0 < c["restarts"] < N // 10
+        else:
+            assert c["restarts"] == 0
+        ctx.close()
+    diff = (outs[True]["status"] != outs[False]["status"]) | (outs[True]["outcomes"] != outs[False]["outcomes"]).any(axis=0)
+    # FP32: an outcome may flip only at a near-tie of the two summation orders
+    assert diff.sum() == 0 if bits == 64 else diff.sum() <= 2
+    keep = ~diff
+    for key in ("abort_op", "obs"):
+        assert (outs[True][key][keep] == outs[False][key][keep]).all()
+    tol = 1e-10 if bits == 64 else 1e-5
+    for s_ in range(128):
+        if keep[s_]:
+            from tests.gpu_helpers import coeff_error
+            assert coeff_error(kept[True][s_], kept[False][s_]) < tol
+
+
+def test_speculation_noiseless_never_restarts():
+    w = workloads.config("cultivation_42q", seed=1)
+    ctx = make_ctx(w.text, None, seed=2)
+    gpu = run_gpu(ctx, 0, 100_000)
+    assert (gpu["status"] == 0).all() and (gpu["obs"] == 0).all()
+    assert ctx.counters()["restarts"] == 0
 
 
 @pytest.mark.parametrize("bits,tol", [(64, 1e-10), (32, 1e-5)])
