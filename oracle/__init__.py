@@ -66,6 +66,8 @@ def _load():
         lib.oracle_batch.restype = ctypes.c_int
         lib.oracle_batch.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, P, ctypes.c_double,
                                      ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, P]
+        lib.oracle_set_noise_mode.restype = ctypes.c_int
+        lib.oracle_set_noise_mode.argtypes = [P, ctypes.c_int]
         lib.oracle_philox.argtypes = [P, P, P]
         lib.oracle_pauli_mul.argtypes = [P, P, P]
         _lib = lib
@@ -115,7 +117,7 @@ class ShotResult:
 class Circuit:
     """A parsed and noise-lowered circuit held by the oracle."""
 
-    def __init__(self, text: str, noise: dict | None = None):
+    def __init__(self, text: str, noise: dict | None = None, noise_mode: int = 0):
         lib = _load()
         nz = _Noise(**(noise or {}))
         err = ctypes.create_string_buffer(512)
@@ -127,6 +129,9 @@ class Circuit:
         lib.oracle_counts(h, _ptr(counts))
         (self.n_qubits, self.n_ops, self.n_records, self.n_noise_slots,
          self.n_meas_slots, self.n_observables, self.n_lowered) = (int(x) for x in counts)
+        if lib.oracle_set_noise_mode(h, int(noise_mode)) != 0:
+            raise ValueError(f"bad noise mode {noise_mode}")
+        self.noise_mode = int(noise_mode)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -92,6 +92,7 @@ struct Op {
     std::vector<int> recs;    // DETECTOR / OBSERVABLE record indices
     int expect = 0;           // DETECTOR / OBSERVABLE constant
     uint64_t thr = 0;         // noise threshold floor(p * 2^32)
+    double p = 0.0;           // noise probability
     int src = -1;             // index of the source op it came from
     int slot = -1;            // noise slot (noise ops) or measurement slot
     int rec = -1;             // record written (M, MPP) or flipped (FLIP)
@@ -104,6 +105,11 @@ struct oracle_circuit {
     int n = 0;
     int n_src = 0, n_rec = 0, n_noise = 0, n_meas = 0, n_obs = 0;
     std::vector<Op> ops;
+    // Noise sampling: mode 0 draws one word per noise slot; mode 1 draws
+    // geometric gaps between candidate slots (see gap_of) and thins them.
+    int noise_mode = 0;
+    std::vector<uint64_t> gap_thr;   // [g] = floor(q^g 2^32), g = 0..n_noise, q = 1 - p_max
+    std::vector<uint64_t> accept;    // per slot: floor(p / p_max * 2^32)
 };
 
 namespace {
@@ -150,14 +156,14 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
     auto add_noise = [&](Kind k, double p, int a, int b, int src) {
         if (p <= 0.0) return;
         Op o;
-        o.kind = k; o.a = a; o.b = b; o.thr = threshold_of(p); o.src = src;
+        o.kind = k; o.a = a; o.b = b; o.thr = threshold_of(p); o.p = p; o.src = src;
         o.slot = c.n_noise++;
         c.ops.push_back(o);
     };
     auto add_flip = [&](double p, int rec, int src) {
         if (p <= 0.0) return;
         Op o;
-        o.kind = K_FLIP; o.rec = rec; o.thr = threshold_of(p); o.src = src;
+        o.kind = K_FLIP; o.rec = rec; o.thr = threshold_of(p); o.p = p; o.src = src;
         o.slot = c.n_noise++;
         c.ops.push_back(o);
     };
@@ -636,6 +642,34 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
     auto noise_word = [&](int slot) {
         return words ? words[slot] : philox_word(seed, shot, 0, (uint64_t)slot);
     };
+    // Mode 1: a Bernoulli(p_slot) hit on every slot, drawn as a Bernoulli(p_max)
+    // candidate process thinned by p_slot / p_max.  Candidates: the gap G
+    // before the next one has P(G >= g) = q^g, drawn from one word w as the
+    // number of g >= 1 with w < floor(q^g 2^32); a second word a accepts the
+    // candidate iff a < floor(p_slot / p_max 2^32) and then picks its Pauli
+    // the way mode 0 uses its word.  Words come from stream 2 in order.
+    uint64_t draw = 0;
+    int64_t cand = -1;          // last candidate slot
+    int next_hit = -1;          // pending accepted slot (mode 1), -1 = none left
+    uint32_t hit_word = 0;
+    auto advance = [&]() {
+        next_hit = -1;
+        while (true) {
+            const uint32_t w = philox_word(seed, shot, 2, draw++);
+            int64_t g = 0;
+            while (g + 1 <= c.n_noise && (uint64_t)w < c.gap_thr[g + 1]) ++g;
+            cand += 1 + g;
+            if (cand >= c.n_noise) return;
+            const uint32_t a = philox_word(seed, shot, 2, draw++);
+            if ((uint64_t)a < c.accept[cand]) {
+                next_hit = (int)cand;
+                hit_word = a;
+                return;
+            }
+        }
+    };
+    const bool gaps = c.noise_mode == 1 && !words;
+    if (gaps) advance();
     auto meas_word = [&](int slot) {
         return words ? words[c.n_noise + slot] : philox_word(seed, shot, 1, (uint64_t)slot);
     };
@@ -696,13 +730,23 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
             }
             case K_DEP1: case K_DEP2: case K_XERR: case K_ZERR: case K_FLIP: {
                 res.info.noise_slots++;
-                uint32_t w = noise_word(o.slot);
-                if ((uint64_t)w >= o.thr) break;
+                uint32_t w;
+                uint64_t thr;
+                if (gaps) {
+                    if (o.slot != next_hit) break;
+                    w = hit_word;
+                    thr = c.accept[o.slot];
+                    advance();
+                } else {
+                    w = noise_word(o.slot);
+                    thr = o.thr;
+                    if ((uint64_t)w >= thr) break;
+                }
                 if (o.kind == K_DEP1) {
-                    int idx = (int)((3ULL * w) / o.thr);  // 0,1,2 -> X,Y,Z
+                    int idx = (int)((3ULL * w) / thr);  // 0,1,2 -> X,Y,Z
                     apply_pauli_code(st, idx + 1, o.a);
                 } else if (o.kind == K_DEP2) {
-                    int code = (int)((15ULL * w) / o.thr) + 1;  // 1..15
+                    int code = (int)((15ULL * w) / thr) + 1;  // 1..15
                     apply_pauli_code(st, code >> 2, o.a);
                     apply_pauli_code(st, code & 3, o.b);
                 } else if (o.kind == K_XERR) {
@@ -761,6 +805,37 @@ oracle_circuit *oracle_compile(const char *text, const oracle_noise *noise, char
 }
 
 void oracle_free(oracle_circuit *c) { delete c; }
+
+int oracle_set_noise_mode(oracle_circuit *c, int mode) {
+    if (!c || mode < 0 || mode > 1) return -1;
+    c->noise_mode = mode;
+    c->gap_thr.clear();
+    c->accept.clear();
+    if (mode == 1) {
+        // a slot whose threshold floor(p 2^32) is 0 is never hit in mode 0;
+        // it takes no part here either (acceptance 0, no say in p_max)
+        auto live = [](const Op &o) {
+            return o.slot >= 0 && o.thr > 0 &&
+                   (o.kind == K_DEP1 || o.kind == K_DEP2 || o.kind == K_XERR || o.kind == K_ZERR || o.kind == K_FLIP);
+        };
+        double pmax = 0.0;
+        for (const Op &o : c->ops)
+            if (live(o)) pmax = std::max(pmax, o.p);
+        c->accept.assign(c->n_noise, 0);
+        for (const Op &o : c->ops)
+            if (live(o)) c->accept[o.slot] = (uint64_t)std::floor(o.p / pmax * 4294967296.0);
+        // q^g by repeated multiplication (the same IEEE products on every machine)
+        const double q = 1.0 - pmax;
+        c->gap_thr.assign(c->n_noise + 1, 0);
+        double t = 1.0;
+        c->gap_thr[0] = 1ull << 32;
+        for (int g = 1; g <= c->n_noise; ++g) {
+            t *= q;
+            c->gap_thr[g] = (uint64_t)std::floor(t * 4294967296.0);
+        }
+    }
+    return 0;
+}
 
 void oracle_counts(const oracle_circuit *c, uint64_t counts[7]) {
     counts[0] = c->n;

@@ -50,6 +50,12 @@ oracle_circuit *oracle_compile(const char *text, const oracle_noise *noise,
                                char *err, int errlen);
 void oracle_free(oracle_circuit *c);
 
+/* Noise sampling mode: 0 (default) one word per noise slot from stream 0;
+ * 1 geometric gaps between candidate slots from stream 2, thinned by
+ * p_slot / p_max (the same hit distribution, different draws).  Explicit
+ * words always use mode 0.  Returns 0, or -1 for a bad mode. */
+int oracle_set_noise_mode(oracle_circuit *c, int mode);
+
 /* counts[0..6] = n_qubits, n_source_ops, n_records, n_noise_slots,
  *                n_meas_slots, n_observables, n_lowered_ops */
 void oracle_counts(const oracle_circuit *c, uint64_t counts[7]);
