@@ -50,12 +50,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_ctx(soft, w, bits):
+def make_ctx(soft, w, bits, noise_mode):
     ctx = soft.Context(0)
     ctx.load_noise(**w.noise)
     ctx.load_circuit(w.text)
     ctx.set_rng(SEED_RNG)
     ctx.set_precision(bits)
+    ctx.set_noise_mode(noise_mode)
     return ctx
 
 
@@ -76,10 +77,10 @@ def time_steps(torch, ctx, shots, steps, warmup, bufs):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(w, shots_sample: int):
+def cpu_baseline(w, shots_sample: int, noise_mode: int):
     import oracle
     oracle.build(force=False)
-    circ = oracle.Circuit(w.text, w.noise)
+    circ = oracle.Circuit(w.text, w.noise, noise_mode=noise_mode)
     threads = max(1, min(len(os.sched_getaffinity(0)), 64))
     t0 = time.perf_counter()
     r = circ.batch(SEED_RNG, 0, shots_sample, threads=threads)
@@ -98,6 +99,7 @@ def bench_mixture(torch, workloads, soft, args):
     ctx = soft.Context(0)
     ctx.load_mixture([w.text for w in m["workloads"]], m["models"], m["shot_ends"])
     ctx.set_rng(SEED_RNG)
+    ctx.set_noise_mode(args.noise_mode)
     if args.autotune:
         ctx.autotune(args.autotune)
     dev = torch.device("cuda", 0)
@@ -126,7 +128,8 @@ def bench_mixture(torch, workloads, soft, args):
                       "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
                       "higher_is_better": True, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "mixture: cultivation_15q + 8 generated shapes x p in {5e-4, 1e-3, 2e-3}, "
-                                             "%d shots per launch" % shots, "launch": ctx.launch_shape()},
+                                             "%d shots per launch" % shots, "launch": ctx.launch_shape(),
+                                 "noise_draws": ["a word per noise location", "gap sampling"][args.noise_mode]},
                       "stats": {"passed": c["passed"], "discarded": c["discarded"], "support_hist": c["support_hist"]},
                       "variants": per}))
 
@@ -143,6 +146,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=0, help="sample shots for the autotuner (0 = library default shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy 3 times (HBM counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--noise-mode", type=int, default=0, choices=(0, 1),
+                    help="0: one noise word per location; 1: gap sampling (same distribution)")
     ap.add_argument("--mixture", action="store_true",
                     help="instead: the batching run (27 circuit/noise variants, --shots in one launch per step)")
     args = ap.parse_args()
@@ -175,7 +180,7 @@ def main():
 
     results = {}
     for bits in ([32] if args.no_fp64 else [32, 64]):
-        ctx = make_ctx(soft, w, bits)
+        ctx = make_ctx(soft, w, bits, args.noise_mode)
         if args.autotune:
             ctx.autotune(args.autotune)
         nw = ctx.info()["record_words"]
@@ -207,6 +212,7 @@ def main():
         "config": {"workload": "cultivation-shaped 42q/72T circuit (19 data + 23 ancilla, brackets 19+7+5+5, "
                                "seed %d), circuit-level depolarizing p=1e-3, %d shots per step" % (SEED_CIRCUIT, shots),
                    "coefficients": "fp32 complex; fp64 probabilities, renormalisation, norm check",
+                   "noise_draws": ["a word per noise location", "gap sampling"][args.noise_mode],
                    "circuit": stats_tab, "launch": r32["shape"]},
         "stats": {"passed": c["passed"], "discarded": c["discarded"], "overflow": c["overflow"],
                   "numeric": c["numeric"], "logical_errors": c["logical_errors"],
@@ -234,7 +240,7 @@ def main():
     # ---- roofline: algorithmic VALU work per launch over the measured time ----
     work = None
     if not args.no_cpu_baseline:
-        base, work, nsample = cpu_baseline(w, args.cpu_sample)
+        base, work, nsample = cpu_baseline(w, args.cpu_sample, args.noise_mode)
         out["cpu_baseline"] = base
     if work is not None:
         per_shot = {k: v / nsample for k, v in work.items()}

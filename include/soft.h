@@ -157,6 +157,19 @@ int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
  * rounding order in the FP64 sums).  on = 0 runs the full list only. */
 int soft_set_speculation(soft_ctx *ctx, int on);
 
+/* How noise hits are drawn (the same distribution either way: every noise
+ * location hit independently with its probability, its Pauli uniform over the
+ * channel's list).  mode 0 (default): one Philox word of stream 0 per noise
+ * location, hit iff word < floor(p 2^32).  mode 1 (gap sampling): candidate
+ * locations form a Bernoulli(p_max) process, p_max the largest location
+ * probability of the circuit; the gap to the next candidate comes from one
+ * word of stream 2 and the gap table floor((1 - p_max)^g 2^32), and a second
+ * word accepts the candidate with probability floor(p / p_max 2^32) 2^-32,
+ * its Pauli picked from that word.  Mode 1 draws about 2 n p_max words per
+ * shot instead of n.  Explicit words (soft_set_words) always use mode 0.
+ * Returns SOFT_EINVAL for another mode. */
+int soft_set_noise_mode(soft_ctx *ctx, int mode);
+
 /* Where the per-wave coefficient tile lives: 0 = automatic (LDS when one
  * wave's tile fits in a block's LDS, else device memory), 1 = LDS, 2 = device
  * memory (HBM; one slab of 2^k_max entries per resident wave, allocated by the

@@ -9,6 +9,7 @@
 // that work that is the same for every shot (see program.h).
 #include "compile.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -65,7 +66,7 @@ struct RowMask {
 // The shot-independent tableau, by column, plus the span and the event list.
 class FrameCompiler {
   public:
-    FrameCompiler(int n, Program &prog, bool speculate) : n_(n), P_(prog), cx_(n), cz_(n), spec_(speculate) {
+    FrameCompiler(int n, Program &prog, bool speculate) : spec_(speculate), n_(n), P_(prog), cx_(n), cz_(n) {
         for (int q = 0; q < n; ++q) {
             cx_[q].d = bitq(q);  // d_q = X_q
             cz_[q].s = bitq(q);  // s_q = Z_q
@@ -137,6 +138,7 @@ class FrameCompiler {
             L.masks[6] = cx_[b].d; L.masks[7] = cx_[b].s;
         }
         P_.noise.push_back(L);
+        P_.noise_p.push_back(p);
         P_.noise_tm1.push_back(L.thr == 0 ? 0u : (uint32_t)(L.thr - 1));
     }
 
@@ -171,6 +173,9 @@ class FrameCompiler {
             E.Aim = 0.0;
             E.Bre = sn;
             E.Bim = 0.0;
+            E.Tn = sn / cs;
+            E.Cs2 = cs * cs;
+            E.Tnf = (float)E.Tn;
             E.qb = (uint32_t)((cexp + (dagger ? 1 : 3)) & 3);
             uint32_t mu;
             if (coords(beta, mu)) {
@@ -656,6 +661,28 @@ uint64_t fnv1a(const void *data, size_t len, uint64_t h) {
 
 }  // namespace
 
+// Gap sampling tables (see NoiseLoc): acceptance per slot and the gap table
+// floor(q^g 2^32), q^g formed by repeated multiplication.  Slots with thr = 0
+// take no part (acc = 0) and do not set p_max.  Without live slots every
+// acceptance is 0, and the table content does not matter.
+static void gap_tables(Program &out) {
+    const size_t n = out.noise.size();
+    double pmax = 0.0;
+    for (size_t s = 0; s < n; ++s)
+        if (out.noise[s].thr) pmax = std::max(pmax, out.noise_p[s]);
+    for (size_t s = 0; s < n; ++s)
+        out.noise[s].acc = out.noise[s].thr ? (uint64_t)std::floor(out.noise_p[s] / pmax * 4294967296.0) : 0u;
+    out.gap.assign(n, 0xFFFFFFFFu);
+    if (pmax > 0.0) {
+        const double q = 1.0 - pmax;
+        double t = 1.0;
+        for (size_t g = 1; g <= n; ++g) {
+            t *= q;
+            out.gap[g - 1] = (uint32_t)std::floor(t * 4294967296.0);
+        }
+    }
+}
+
 void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out, bool speculate) {
     out = Program();
     const double probs[6] = {nm.p1, nm.p2, nm.p_idle, nm.p_meas, nm.p_reset, nm.p_mpp};
@@ -829,6 +856,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     form_batches(out);
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
+    gap_tables(out);
     // pad the threshold table to whole 256-slot chunks
     while (out.noise_tm1.size() % 256) out.noise_tm1.push_back(0);
     if (out.noise_tm1.empty()) out.noise_tm1.assign(256, 0);

@@ -28,6 +28,8 @@ struct Program {
     std::vector<Event> events;
     std::vector<NoiseLoc> noise;
     std::vector<uint32_t> noise_tm1;  // per slot: thr-1 (hit iff word <= it), padded
+    std::vector<double> noise_p;      // per slot: probability
+    std::vector<uint32_t> gap;        // gap sampling: [g - 1] = floor(q^g 2^32), g = 1..n_noise
     std::vector<uint32_t> det_pairs;  // (record word, mask) pairs
     std::vector<BatchMember> batch;   // members of side-by-side measurement runs
     std::vector<Frame> before;        // frame when event e starts

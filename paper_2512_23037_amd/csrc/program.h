@@ -21,8 +21,10 @@
 //
 // A branching T^s multiplies the whole state by e^{i s pi/8} (Eqs. 1-2); that
 // factor is kept as an exact per-shot count of eighth turns and applied only
-// when a state is read out, so the tile update is
-//   v'_j = cos(pi/8) v_j + sin(pi/8) i^qb (-1)^(...) v_{j^mu}.
+// when a state is read out.  The tile also holds the state up to a real
+// per-shot factor: the cos(pi/8) of each branching T joins it (measurements
+// renormalise the tile and reset it), so the tile update is
+//   v'_j = v_j + tan(pi/8) i^qb (-1)^(...) v_{j^mu}.
 //
 // Sign vectors are two 64-bit words: bit i of the D word is the sign of
 // destabilizer d_i, bit i of the S word the sign of stabilizer s_i (n <= 64).
@@ -90,7 +92,13 @@ struct alignas(16) Event {
     double Are, Aim;          // T_PHASE: e^{i s pi/4}; branching T: cos(pi/8), 0
     double Bre, Bim;          // branching T: sin(pi/8), 0 (the weight of the partner term)
     float Afr, Afi, Bfr, Bfi; // the same in single precision
-    uint32_t pad1[6];
+    // Branching T on a tile that carries the state up to a per-shot real
+    // factor: v'_j = v_j + tan(pi/8) i^qb c' v_partner, and cos^2(pi/8) joins
+    // the factor's square.
+    double Tn;                // tan(pi/8)
+    double Cs2;               // cos^2(pi/8)
+    float Tnf;                // Tn in single precision
+    uint32_t pad1;
 };
 static_assert(sizeof(Event) == 256, "event layout");
 
@@ -134,7 +142,7 @@ struct alignas(16) VariantDesc {
     uint32_t ev_off, nz_off, tm1_off;  // tm1_off is a multiple of 256
     uint32_t n_noise;
     uint32_t ev_off_full;  // the full event list (ev_off: the speculative one, or the same)
-    uint32_t pad;
+    uint32_t gap_off;      // gap-sampling threshold table of this variant (n_noise entries)
 };
 static_assert(sizeof(VariantDesc) == 32, "variant layout");
 constexpr uint32_t kMaxVariants = 64;
@@ -143,13 +151,32 @@ enum NoiseKind : uint32_t { NZ_NONE = 0, NZ_DEP1, NZ_DEP2, NZ_XERR, NZ_FLIP, NZ_
 
 // One noise location (one random word).  masks[0..3] = rows anticommuting
 // with X_a (D, S) and with Z_a (D, S); masks[4..7] the same for qubit b.
+//
+// Two ways to draw the hits, with the same distribution (each slot hit
+// independently with its probability p):
+//  * per slot: slot s takes word s of stream 0 and is hit iff word < thr;
+//  * gap sampling: candidates form a Bernoulli(p_max) process over the slots,
+//    p_max the largest slot probability.  The gap G before the next candidate
+//    has P(G >= g) = q^g (q = 1 - p_max); one word w of stream 2 gives
+//    G = #{g >= 1 : w < floor(q^g 2^32)} from the variant's gap table, and the
+//    next word a accepts the candidate iff a < acc = floor(p / p_max 2^32).
+//    Words of stream 2 are taken in order, two per candidate (one past the
+//    last slot).  A slot with thr = 0 is never hit in either way.
+// A hit's Pauli comes from its word the same way in both: w / thr (per slot)
+// or a / acc (gap sampling) split into 3 (DEP1) or 15 (DEP2) equal parts.
 struct alignas(16) NoiseLoc {
     uint32_t kind;
     uint32_t rec;     // FLIP: record bit to flip
     uint64_t thr;     // floor(p * 2^32), 0..2^32
     uint64_t masks[8];
+    uint64_t acc;     // gap sampling: floor(p / p_max * 2^32), 0 when thr = 0
+    uint64_t pad;
 };
-static_assert(sizeof(NoiseLoc) == 80, "noise layout");
+static_assert(sizeof(NoiseLoc) == 96, "noise layout");
+
+// How a launch draws its noise hits (NoiseLoc): per slot, explicit words
+// (per slot, words given by the caller) or gap sampling.
+enum NoiseSource : uint32_t { NS_SLOTS = 0, NS_EXPLICIT = 1, NS_GAPS = 2 };
 
 // Per-shot status codes (low byte of the status word).
 enum Status : uint32_t { ST_PASSED = 0, ST_DISCARDED = 1, ST_OVERFLOW = 2, ST_NUMERIC = 3 };

@@ -11,6 +11,7 @@ struct RunParams {
     const Event *ev;
     const NoiseLoc *nz;
     const uint32_t *tm1;      // per noise slot: threshold - 1 (padded to 256)
+    const uint32_t *gaps;     // gap sampling tables of the variants (VariantDesc::gap_off)
     const uint32_t *det;      // DETECTOR/OBSERVABLE (word, mask) pairs
     const BatchMember *bm;    // members of side-by-side measurement runs
     const VariantDesc *vars;  // shot ranges of the circuits in this run
@@ -37,6 +38,8 @@ struct RunParams {
     uint32_t rec_off;         // byte offset of the record in a wave's LDS slot (LDS tiles; 0 when the
                               // record fits in scalar registers and never touches LDS)
     uint32_t speculate;       // 1: run the speculative event list first
+    uint32_t noise_mode;      // 0: a word per noise slot, 1: gap sampling (ignored with explicit words)
+    uint32_t pad2_;
     double tau2;              // pruning threshold squared
 };
 
@@ -48,7 +51,7 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
 
 // Blocks of `block` threads with `lds` bytes of dynamic LDS that one CU keeps
 // resident (registers and LDS).
-hipError_t sampler_occupancy(bool fp64, bool expl, bool gt, int block, size_t lds, int *blocks_per_cu);
+hipError_t sampler_occupancy(bool fp64, uint32_t noise_source, bool gt, int block, size_t lds, int *blocks_per_cu);
 
 // Raise the dynamic-LDS limit of every sampler instantiation (called once).
 hipError_t sampler_set_lds_limit(int bytes);

@@ -18,6 +18,8 @@
 // renormalisation accumulated in FP64; Pauli noise per shot as sign flips.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "program.h"
 #include "sampler.h"
 
@@ -128,17 +130,16 @@ template <typename C, typename R> __device__ __forceinline__ C scale(C a, R s) {
     return a;
 }
 
-// Write one shot's state (status, signs, offset, span dimension, carried norm
-// and the coefficient tile widened to double) for the readout calls.
 // Write one shot's state for the readout calls: status, signs, offset, span
 // dimension, carried norm, and the coefficient tile widened to double with the
-// counted global phase e^{i pi phase8 / 8} applied.
+// counted global phase e^{i pi phase8 / 8} and the tile's real factor
+// sqrt(tscale2) applied.
 template <typename C>
 __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const C *v, uint32_t lane,
                                            uint32_t tile_entries, uint32_t status, uint32_t abort_src, uint32_t term,
                                            uint32_t after, uint64_t rD, uint64_t rS, uint64_t a, uint32_t k,
                                            double nrm2, const double *phase_tab, uint32_t phase8, uint32_t var,
-                                           uint32_t full) {
+                                           uint32_t full, double tscale2) {
     if (lane == 0) {
         m[KM_STATUS] = status;
         m[KM_ABORT] = abort_src;
@@ -153,7 +154,8 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
         m[KM_VAR] = var;
         m[KM_PROG] = full;
     }
-    const double pc = phase_tab[phase8], ps = phase_tab[16u + phase8];
+    const double f = sqrt(tscale2);
+    const double pc = f * phase_tab[phase8], ps = f * phase_tab[16u + phase8];
     const uint32_t cnt = 1u << k;
     lane_pass(tile_entries, lane, [&](uint32_t j) {
         double x = 0.0, y = 0.0;
@@ -208,27 +210,64 @@ template <uint32_t Q, typename C> __device__ __forceinline__ C rotc(C a) {
     return r;
 }
 
-// out = cs * a + c * i^Q b, then drop it below the pruning level.
+// out = a + c * i^Q b, then drop it below the pruning level.
 template <uint32_t Q, typename R, typename C>
-__device__ __forceinline__ C t_out(C a, C b, R cs, R c, R thr, bool &keep) {
+__device__ __forceinline__ C t_out(C a, C b, R c, R thr, bool &keep) {
     const C w = rotc<Q>(b);
     C o;
-    o.x = fma(c, w.x, cs * a.x);
-    o.y = fma(c, w.y, cs * a.y);
+    o.x = fma(c, w.x, a.x);
+    o.y = fma(c, w.y, a.y);
     keep = fma(o.x, o.x, o.y * o.y) >= thr;
     if (!keep) { o.x = 0; o.y = 0; }
     return o;
 }
 
+// a, dropped below the pruning level.
+template <typename R, typename C> __device__ __forceinline__ C t_keep(C a, R thr, bool &keep) {
+    keep = fma(a.x, a.x, a.y * a.y) >= thr;
+    if (!keep) { a.x = 0; a.y = 0; }
+    return a;
+}
+
+// c * i^Q b, dropped below the pruning level.
+template <uint32_t Q, typename R, typename C> __device__ __forceinline__ C t_new(C b, R c, R thr, bool &keep) {
+    const C w = rotc<Q>(b);
+    C o;
+    o.x = c * w.x;
+    o.y = c * w.y;
+    return t_keep<R, C>(o, thr, keep);
+}
+
+// The tile holds the state up to a real per-shot factor, so a branching T
+// is v' = v + tn i^Q (+-1) v_partner with tn = tan(pi/8) (its cos(pi/8) goes
+// into the factor).
+//
+// The iterations of a pass cover 64 lanes each; iteration `it` adds the
+// uniform coordinate bits J(it), and the sign (-1)^(g.J(it)) is the same for
+// the whole wave.  A sign -1 is i^2, i.e. the Q + 2 form of the update.  If
+// no iteration bit of J meets g, every iteration takes the Q form.
+// Otherwise, with t the lowest iteration bit whose coordinate bit is in g,
+// iterations it and it ^ 2^t have opposite signs: each such pair runs one Q
+// and one Q + 2 update, and which is which is a scalar choice.
+//
+// Pair the iterations on bit t when it lies in [0, log2(iters)); returns
+// 1 << t, or 0 when every iteration has sign +1.  `pos` maps iteration bit
+// u to its coordinate bit.
+template <typename Pos> __device__ __forceinline__ uint32_t pair_bit(uint32_t g, uint32_t iters, Pos &&pos) {
+    for (uint32_t u = 0; (1u << u) < iters; ++u)
+        if ((g >> pos(u)) & 1u) return 1u << u;
+    return 0u;
+}
+
 // Branching T on an existing coordinate: pairs (j0, j1 = j0 ^ mu), j0 with
-// bit h clear.  v'_j0 = cs v_j0 + sn i^Q (-1)^(sig ^ g.j1) v_j1 and the same
+// bit h clear.  v'_j0 = v_j0 + tn i^Q (-1)^(sig ^ g.j1) v_j1 and the same
 // with j0, j1 exchanged.  j0 = ins0(lane, h) | ins0(64 it, h): the lane bits and
 // the iteration bits of a coordinate are disjoint, so each lane keeps two base
 // pointers for the event (j0's and j1's lane parts, h set in j1's) and an
 // iteration adds one uniform byte offset to each.
 template <uint32_t Q, typename R, typename C>
 __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
-                                           uint32_t sig, R cs, R sn, R thr) {
+                                           uint32_t sig, R tn, R thr) {
     const uint32_t npairs = 1u << (k - 1u);
     // With fewer than 64 pairs the spare lanes repeat a live lane's pair (same
     // values to the same addresses) and are left out of the counts, so the
@@ -240,55 +279,77 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     const uint32_t mu_l = mu & lmask, mu_i = mu & ~(lmask | hb);
     char *const p0 = reinterpret_cast<char *>(v + lc);
     char *const p1 = reinterpret_cast<char *>(v + ((lc ^ mu_l) | hb));
-    const R base1 = ((sig ^ par32(g & lc)) != 0u) ? -sn : sn;   // weight of v_j0 in v'_j1
-    const R base0 = par32(g & mu) ? -base1 : base1;             // weight of v_j1 in v'_j0
+    const R c1 = ((sig ^ par32(g & lc)) != 0u) ? -tn : tn;   // weight of v_j0 in v'_j1
+    const R c0 = par32(g & mu) ? -c1 : c1;                   // weight of v_j1 in v'_j0
     uint32_t cnt = 0;
     const uint32_t iters = (npairs + 63u) >> 6;
-    for (uint32_t it = 0; it < iters; ++it) {
-        const uint32_t J = ins0(it << 6, h);
-        const bool flip = par32(g & J) != 0u;
+    // one iteration with the Q or (S = 2) the Q + 2 form
+    auto step = [&](uint32_t J, auto S) {
+        constexpr uint32_t QS = (Q + decltype(S)::value) & 3u;
         C *const r0 = reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
         C *const r1 = reinterpret_cast<C *>(p1 + (J ^ mu_i) * (uint32_t)sizeof(C));
         const C v0 = *r0, v1 = *r1;
-        const R c1 = flip ? -base1 : base1, c0 = flip ? -base0 : base0;
         bool k0, k1;
-        const C o0 = t_out<Q, R, C>(v0, v1, cs, c0, thr, k0);
-        const C o1 = t_out<Q, R, C>(v1, v0, cs, c1, thr, k1);
+        const C o0 = t_out<QS, R, C>(v0, v1, c0, thr, k0);
+        const C o1 = t_out<QS, R, C>(v1, v0, c1, thr, k1);
         cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
         *r0 = o0;
         *r1 = o1;
+    };
+    const uint32_t tb = pair_bit(g, iters, [&](uint32_t u) { return u + 6u < h ? u + 6u : u + 7u; });
+    if (tb == 0u) {
+        for (uint32_t it = 0; it < iters; ++it) step(ins0(it << 6, h), std::integral_constant<uint32_t, 0>());
+    } else {
+        const uint32_t t = (uint32_t)__builtin_ctz(tb);
+        for (uint32_t i2 = 0; i2 < (iters >> 1); ++i2) {
+            const uint32_t it = ins0(i2, t);
+            const uint32_t JA = ins0(it << 6, h), JB = ins0((it | tb) << 6, h);
+            const bool fa = par32(g & JA) != 0u;
+            step(fa ? JB : JA, std::integral_constant<uint32_t, 0>());
+            step(fa ? JA : JB, std::integral_constant<uint32_t, 2>());
+        }
     }
     return cnt;
 }
 
-// Branching T on a new coordinate (k -> k+1): v'_j = cs v_j and
-// v'_{j+2^k} = sn i^Q (-1)^(sig ^ g.j) v_j.
+// Branching T on a new coordinate (k -> k+1): v'_j = v_j and
+// v'_{j+2^k} = tn i^Q (-1)^(sig ^ g.j) v_j.
 template <uint32_t Q, typename R, typename C>
-__device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R cs, R sn,
+__device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R tn,
                                              R thr) {
     const uint32_t half = 1u << k;
     // spare lanes repeat a live lane (see t_bfly)
     const uint32_t lp = half >= 64u ? lane : (lane & (half - 1u));
     const uint64_t live = half >= 64u ? ~0ull : ((1ull << half) - 1ull);
-    const R base = ((sig ^ par32(g & lp)) != 0u) ? -sn : sn;
-    const C z = {0, 0};
+    const R c1 = ((sig ^ par32(g & lp)) != 0u) ? -tn : tn;
     char *const p0 = reinterpret_cast<char *>(v + lp);
     char *const p1 = reinterpret_cast<char *>(v + half + lp);
     uint32_t cnt = 0;
     const uint32_t iters = (half + 63u) >> 6;
-    for (uint32_t it = 0; it < iters; ++it) {
-        const uint32_t J = it << 6;
-        const bool flip = par32(g & J) != 0u;
+    auto step = [&](uint32_t J, auto S) {
+        constexpr uint32_t QS = (Q + decltype(S)::value) & 3u;
         C *const r0 = reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
         C *const r1 = reinterpret_cast<C *>(p1 + J * (uint32_t)sizeof(C));
         const C v0 = *r0;
-        const R c1 = flip ? -base : base;
         bool k0, k1;
-        const C o0 = t_out<0, R, C>(v0, z, cs, (R)0, thr, k0);
-        const C o1 = t_out<Q, R, C>(z, v0, (R)0, c1, thr, k1);
+        const C o0 = t_keep<R, C>(v0, thr, k0);
+        const C o1 = t_new<QS, R, C>(v0, c1, thr, k1);
         cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
         *r0 = o0;
         *r1 = o1;
+    };
+    const uint32_t tb = pair_bit(g, iters, [](uint32_t u) { return u + 6u; });
+    if (tb == 0u) {
+        for (uint32_t it = 0; it < iters; ++it) step(it << 6, std::integral_constant<uint32_t, 0>());
+    } else {
+        const uint32_t t = (uint32_t)__builtin_ctz(tb);
+        for (uint32_t i2 = 0; i2 < (iters >> 1); ++i2) {
+            const uint32_t it = ins0(i2, t);
+            const uint32_t JA = it << 6, JB = (it | tb) << 6;
+            const bool fa = par32(g & JA) != 0u;
+            step(fa ? JB : JA, std::integral_constant<uint32_t, 0>());
+            step(fa ? JA : JB, std::integral_constant<uint32_t, 2>());
+        }
     }
     return cnt;
 }
@@ -307,12 +368,13 @@ struct ShotTotals {
 #define EVF(f) __uint_as_float(EV32(f))
 #define EVD(f) __longlong_as_double((long long)EV64(f))
 
-template <typename R, bool EXPL, bool GT>
-__global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
-                                                const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
-                                                const uint32_t *__restrict__ words,
-                                                const BatchMember *__restrict__ bm, RunParams P) {
+template <typename R, uint32_t NS, bool GT>
+__device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
+                                             const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
+                                             const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
+                                             const RunParams &P) {
     typedef typename Cx<R>::T C;
+    constexpr bool EXPL = NS == NS_EXPLICIT, GAPS = NS == NS_GAPS;
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
@@ -420,11 +482,16 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         uint32_t k = 0;
         uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
         double nrm2 = 1.0;
+        double tscale2 = 1.0;  // |state|^2 = tscale2 |tile|^2 (branching T leave cos(pi/8) out)
         uint32_t status = ST_PASSED, abort_src = 0xFFFFFFFFu, obs = 0, maxsup = 1;
         uint32_t term = 0, after = 0;
-        // noise: 256 slots per chunk, 4 consecutive slots (one Philox block) per lane
+        // noise per slot: 256 slots per chunk, 4 consecutive slots (one Philox
+        // block) per lane; nz_drawn = slots drawn.  Gap sampling: lanes hold
+        // 256 words of stream 2 starting at word nz_cb, gd is the next word,
+        // nz_drawn = slots decided, hw the word of the pending hit.
         uint32_t nz_cb = 0, nz_drawn = 0, next_hit = kNoHit;
         uint32_t hits = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        uint32_t gd = 0, hw = 0;
         // measurement words: slots [m_base, m_base + 256), one Philox block per lane
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
@@ -453,13 +520,62 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             next_hit = first_hit(hits, nz_cb);
             tot.noise += min(256u, n_noise - nz_cb);
         };
+        // Gap sampling: decide the slots up to the next candidate.  A
+        // candidate takes words gd, gd + 1 of stream 2 (gap, then acceptance;
+        // gd is even, so both sit in one Philox block, 64 blocks = 256 words
+        // held one block per lane).  The gap G = #{j : w < gap[j]} (a prefix,
+        // the table falls with j) is found 64 entries apart, then entry by
+        // entry, one entry per lane; entries past the last slot count as false.
+        auto draw_gap = [&]() {
+            if ((gd & ~255u) != nz_cb) {
+                nz_cb = gd & ~255u;
+                philox10((nz_cb >> 2) + lane, s_lo, s_hi, 2u, key0, key1, w0, w1, w2, w3);
+            }
+            const uint32_t L = (gd - nz_cb) >> 2;
+            const bool hi = (gd & 2u) != 0u;
+            const uint32_t w = uni((uint32_t)__builtin_amdgcn_readlane((int)(hi ? w2 : w0), (int)L));
+            const uint32_t aw = uni((uint32_t)__builtin_amdgcn_readlane((int)(hi ? w3 : w1), (int)L));
+            gd += 2u;
+            const uint32_t lim = vdp->n_noise - nz_drawn;
+            const uint32_t *tb = P.gaps + vdp->gap_off;
+            uint32_t G = 0;
+            for (;;) {
+                const uint32_t j1 = G + 64u * lane;
+                const uint32_t n1 = (uint32_t)__builtin_popcountll(__ballot(j1 < lim && w < tb[j1]));
+                if (n1 == 0u) break;
+                const uint32_t b2 = G + 64u * (n1 - 1u) + 1u;
+                const uint32_t j2 = b2 + lane;
+                const uint32_t n2 = (uint32_t)__builtin_popcountll(__ballot(lane < 63u && j2 < lim && w < tb[j2]));
+                G = b2 + n2;
+                if (n1 < 64u || n2 < 63u) break;
+            }
+            G = uni(G);
+            if (G >= lim) {
+                tot.noise += lim;
+                nz_drawn = vdp->n_noise;
+                return;
+            }
+            tot.noise += G + 1u;
+            const uint32_t cslot = nz_drawn + G;
+            nz_drawn = cslot + 1u;
+            if ((uint64_t)aw < nz[vdp->nz_off + cslot].acc) {
+                next_hit = cslot;
+                hw = aw;
+            }
+        };
         // Decode the pending hit at slot next_hit into sign-flip masks (or a
         // record flip, returned; kNoHit otherwise) and move to the next hit.
         auto take_hit = [&](uint64_t &dD, uint64_t &dS) -> uint32_t {
             const uint32_t L = (next_hit - nz_cb) >> 2, b = next_hit & 3u;
-            const uint32_t pick = b == 0u ? w0 : b == 1u ? w1 : b == 2u ? w2 : w3;
-            const uint64_t wv = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)L);
+            uint64_t wv;
+            if (GAPS) {
+                wv = hw;
+            } else {
+                const uint32_t pick = b == 0u ? w0 : b == 1u ? w1 : b == 2u ? w2 : w3;
+                wv = (uint32_t)__builtin_amdgcn_readlane((int)pick, (int)L);
+            }
             const NoiseLoc &NL = nz[vdp->nz_off + next_hit];
+            const uint64_t thr = GAPS ? NL.acc : NL.thr;
             const uint32_t nkind = NL.kind;
             uint32_t fr = kNoHit;
             dD = 0;
@@ -467,9 +583,9 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR || nkind == NZ_ZERR) {
                 uint32_t ca, cb = 0;
                 if (nkind == NZ_DEP1) {
-                    ca = (uint32_t)((3ull * wv) / NL.thr) + 1u;
+                    ca = (uint32_t)((3ull * wv) / thr) + 1u;
                 } else if (nkind == NZ_DEP2) {
-                    const uint32_t code = (uint32_t)((15ull * wv) / NL.thr) + 1u;
+                    const uint32_t code = (uint32_t)((15ull * wv) / thr) + 1u;
                     ca = code >> 2;
                     cb = code & 3u;
                 } else {
@@ -483,8 +599,12 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             } else if (nkind == NZ_FLIP) {
                 fr = NL.rec;
             }
-            if (lane == L) hits &= ~(1u << b);
-            next_hit = first_hit(hits, nz_cb);
+            if (GAPS) {
+                next_hit = kNoHit;
+            } else {
+                if (lane == L) hits &= ~(1u << b);
+                next_hit = first_hit(hits, nz_cb);
+            }
             return fr;
         };
         // The speculative event list runs first (a traced shot takes the full
@@ -502,14 +622,17 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         k = 0;
         phase8 = 0;
         nrm2 = 1.0;
+        tscale2 = 1.0;
         status = ST_PASSED;
         abort_src = 0xFFFFFFFFu;
         obs = 0;
         maxsup = 1;
         term = after = 0;
-        nz_cb = nz_drawn = 0;
+        nz_cb = GAPS ? 0xFFFFFFFFu : 0u;
+        nz_drawn = 0;
         next_hit = kNoHit;
         hits = 0;
+        gd = 0;
         m_base = 0xFFFFFF00u;
         bool restart = false;
         // Event e sits in evc, one dword per lane; event e + 1 is loaded while
@@ -520,7 +643,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
-                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u);
+                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
@@ -537,7 +660,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     if (fr != kNoHit) rec_toggle(fr >> 5, 1u << (fr & 31u));
                 }
                 if (nend <= nz_drawn || nz_drawn >= vdp->n_noise) break;
-                draw_chunk();
+                if (GAPS) draw_gap(); else draw_chunk();
             }
             // ---- Cliffords since the previous event: one XOR ----
             rD ^= EV64(cliffD);
@@ -568,29 +691,30 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                 }
                 tot.events++;
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
-                const R cs = sizeof(R) == 4 ? (R)EVF(Afr) : (R)EVD(Are);
-                const R sn = sizeof(R) == 4 ? (R)EVF(Bfr) : (R)EVD(Bre);
+                const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
                 const uint32_t sig = sc ^ ga;
-                // T is unitary: the carried norm stays, and it sets the pruning level
-                const R thr = (R)(tau2 * nrm2);
+                // T is unitary: the carried norm stays, and it sets the pruning
+                // level, on the tile's scale once cos^2(pi/8) joins the factor
+                tscale2 *= EVD(Cs2);
+                const R thr = (R)(tau2 * nrm2 / tscale2);
                 const uint32_t qb = EV32(qb);
                 uint32_t cnt;
                 if (kind == EV_T_DOUBLE) {
                     switch (qb) {
-                        case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
-                        case 1: cnt = t_double<1, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
-                        case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
-                        default: cnt = t_double<3, R, C>(v, lane, k, g, sig, cs, sn, thr); break;
+                        case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, tn, thr); break;
+                        case 1: cnt = t_double<1, R, C>(v, lane, k, g, sig, tn, thr); break;
+                        case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, tn, thr); break;
+                        default: cnt = t_double<3, R, C>(v, lane, k, g, sig, tn, thr); break;
                     }
                     tot.entries_t += 2u << k;
                     ++k;
                 } else {
                     const uint32_t mu = EV32(mu), h = EV32(tstar);
                     switch (qb) {
-                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
-                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
-                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
-                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, cs, sn, thr); break;
+                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
+                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
+                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
+                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
                     }
                     tot.entries_t += 1u << k;
                 }
@@ -630,7 +754,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         }
                     }
                     if (nlast <= nz_drawn || nz_drawn >= vdp->n_noise) break;
-                    draw_chunk();
+                    if (GAPS) draw_gap(); else draw_chunk();
                 }
                 const uint64_t beta = ((uint64_t)q0.y << 32) | q0.x, gamma = ((uint64_t)q0.w << 32) | q0.z;
                 const uint32_t info = q3.y;
@@ -751,6 +875,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         v[jp] = x;
                     });
                     nrm2 = wave_sum(nn);
+                    tscale2 = 1.0;
                     --k;
                     if (bsel) a ^= EV64(avec);
                 } else if (kind == EV_M_SPLIT) {
@@ -759,7 +884,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const uint32_t fs = bit ^ sc ^ ga ^ EV32(gbeta);
                     const uint32_t q0 = (4u - EV32(cexp)) & 3u;
                     const uint32_t cnt = 1u << k, pm = EV32(pm);
-                    const R s = (R)(1.0 / sqrt(nrm2));
+                    const R s = (R)sqrt(tscale2 / nrm2);
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
                     lane_pass(cnt, lane, [&](uint32_t j) {
@@ -773,6 +898,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         v[j] = x;
                     });
                     nrm2 = wave_sum(nn);
+                    tscale2 = 1.0;
                     tot.entries_m += cnt;
                 } else {  // EV_M_MERGE
                     const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
@@ -823,6 +949,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                         v[p] = o;
                     });
                     nrm2 = wave_sum(nn);
+                    tscale2 = 1.0;
                     --k;
                 }
                 if (kind == EV_M_SPLIT || kind == EV_M_MERGE) {
@@ -870,6 +997,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
                     const R sc = (R)(1.0 / sqrt(q));
                     if (lane == 0) v[0] = scale(x, sc);
                     nrm2 = q * (double)sc * (double)sc;
+                    tscale2 = 1.0;
                 }
             } else if (kind == EV_FEEDBACK) {
                 // ---- classically controlled Pauli: the record bit is a one-pair check ----
@@ -905,7 +1033,7 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         double nn = 0.0;
         lane_pass(cnt, lane, [&](uint32_t j) { nn += nrm<R>(v[j]); });
         nn = wave_sum(nn);
-        maxdev = fmax(maxdev, fabs(nn - 1.0));
+        maxdev = fmax(maxdev, fabs(nn * tscale2 - 1.0));
         if (lane == group_pos) {
             o_status = status;
             o_abort = abort_src;
@@ -920,11 +1048,11 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
         if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
             const uint64_t kk = shot - P.keep_lo;
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
-                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u);
+                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
         }
         if (tracing && term < P.trace_n)
             dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
-                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u);
+                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
@@ -935,17 +1063,59 @@ __global__ void __launch_bounds__(256) k_sample(const Event *__restrict__ ev, co
     if (var_ok) flush_counters();
 }
 
+// An FP32 tile of a 2^10 span takes 8 KiB of LDS, so LDS holds 5 waves per
+// SIMD; the register budget is set to match.  What no longer fits in
+// registers is what lives across a whole shot (group outputs, shot
+// constants), never the event loop's working set.  FP64 tiles are twice as
+// large: LDS, not registers, sets their occupancy.
+template <uint32_t NS, bool GT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_sample_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
+             const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
+             RunParams P) {
+    sample_shots<float, NS, GT>(ev, nz, tm1, det, words, bm, P);
+}
+
+template <uint32_t NS, bool GT>
+__global__ void __launch_bounds__(256)
+k_sample_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
+             const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
+             RunParams P) {
+    sample_shots<double, NS, GT>(ev, nz, tm1, det, words, bm, P);
+}
+
 __global__ void k_reset(unsigned long long *counters, uint32_t n, unsigned long long *next) {
     for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) counters[t] = 0ull;
     if (threadIdx.x == 0) *next = 0ull;
 }
 
-template <typename R, bool EXPL, bool GT> const void *kernel_ptr() { return (const void *)k_sample<R, EXPL, GT>; }
-
-template <typename R, bool EXPL, bool GT>
-void launch_one(const RunParams &p, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((k_sample<R, EXPL, GT>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+template <typename R, uint32_t NS, bool GT> const void *kernel_ptr() {
+    if (sizeof(R) == 4) return (const void *)k_sample_f32<NS, GT>;
+    return (const void *)k_sample_f64<NS, GT>;
 }
+
+template <typename R, uint32_t NS, bool GT>
+void launch_one(const RunParams &p, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
+    if (sizeof(R) == 4)
+        hipLaunchKernelGGL((k_sample_f32<NS, GT>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+    else
+        hipLaunchKernelGGL((k_sample_f64<NS, GT>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+}
+
+// The 12 instantiations, indexed by fp64 * 6 + source * 2 + gt.
+template <typename R, uint32_t NS> void kernels_of(const void **out) {
+    out[0] = kernel_ptr<R, NS, false>();
+    out[1] = kernel_ptr<R, NS, true>();
+}
+void all_kernels(const void **ks) {
+    kernels_of<float, NS_SLOTS>(ks + 0);
+    kernels_of<float, NS_EXPLICIT>(ks + 2);
+    kernels_of<float, NS_GAPS>(ks + 4);
+    kernels_of<double, NS_SLOTS>(ks + 6);
+    kernels_of<double, NS_EXPLICIT>(ks + 8);
+    kernels_of<double, NS_GAPS>(ks + 10);
+}
+int kernel_index(bool fp64, uint32_t ns, bool gt) { return (fp64 ? 6 : 0) + 2 * (int)ns + (gt ? 1 : 0); }
 
 }  // namespace
 
@@ -955,35 +1125,34 @@ hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long 
 }
 
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
-    const bool expl = p.words != nullptr, gt = p.gtile != nullptr;
-    const int sel = (fp64 ? 4 : 0) | (expl ? 2 : 0) | (gt ? 1 : 0);
-    switch (sel) {
-        case 0: launch_one<float, false, false>(p, grid, block, lds, stream); break;
-        case 1: launch_one<float, false, true>(p, grid, block, lds, stream); break;
-        case 2: launch_one<float, true, false>(p, grid, block, lds, stream); break;
-        case 3: launch_one<float, true, true>(p, grid, block, lds, stream); break;
-        case 4: launch_one<double, false, false>(p, grid, block, lds, stream); break;
-        case 5: launch_one<double, false, true>(p, grid, block, lds, stream); break;
-        case 6: launch_one<double, true, false>(p, grid, block, lds, stream); break;
-        default: launch_one<double, true, true>(p, grid, block, lds, stream); break;
+    const uint32_t ns = p.words != nullptr ? NS_EXPLICIT : (p.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
+    const bool gt = p.gtile != nullptr;
+    switch (kernel_index(fp64, ns, gt)) {
+        case 0: launch_one<float, NS_SLOTS, false>(p, grid, block, lds, stream); break;
+        case 1: launch_one<float, NS_SLOTS, true>(p, grid, block, lds, stream); break;
+        case 2: launch_one<float, NS_EXPLICIT, false>(p, grid, block, lds, stream); break;
+        case 3: launch_one<float, NS_EXPLICIT, true>(p, grid, block, lds, stream); break;
+        case 4: launch_one<float, NS_GAPS, false>(p, grid, block, lds, stream); break;
+        case 5: launch_one<float, NS_GAPS, true>(p, grid, block, lds, stream); break;
+        case 6: launch_one<double, NS_SLOTS, false>(p, grid, block, lds, stream); break;
+        case 7: launch_one<double, NS_SLOTS, true>(p, grid, block, lds, stream); break;
+        case 8: launch_one<double, NS_EXPLICIT, false>(p, grid, block, lds, stream); break;
+        case 9: launch_one<double, NS_EXPLICIT, true>(p, grid, block, lds, stream); break;
+        case 10: launch_one<double, NS_GAPS, false>(p, grid, block, lds, stream); break;
+        default: launch_one<double, NS_GAPS, true>(p, grid, block, lds, stream); break;
     }
     return hipGetLastError();
 }
 
-hipError_t sampler_occupancy(bool fp64, bool expl, bool gt, int block, size_t lds, int *blocks_per_cu) {
-    const void *ks[8] = {kernel_ptr<float, false, false>(), kernel_ptr<float, false, true>(),
-                         kernel_ptr<float, true, false>(),  kernel_ptr<float, true, true>(),
-                         kernel_ptr<double, false, false>(), kernel_ptr<double, false, true>(),
-                         kernel_ptr<double, true, false>(),  kernel_ptr<double, true, true>()};
-    const int sel = (fp64 ? 4 : 0) | (expl ? 2 : 0) | (gt ? 1 : 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ks[sel], block, lds);
+hipError_t sampler_occupancy(bool fp64, uint32_t ns, bool gt, int block, size_t lds, int *blocks_per_cu) {
+    const void *ks[12];
+    all_kernels(ks);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ks[kernel_index(fp64, ns, gt)], block, lds);
 }
 
 hipError_t sampler_set_lds_limit(int bytes) {
-    const void *ks[8] = {kernel_ptr<float, false, false>(), kernel_ptr<float, false, true>(),
-                         kernel_ptr<float, true, false>(),  kernel_ptr<float, true, true>(),
-                         kernel_ptr<double, false, false>(), kernel_ptr<double, false, true>(),
-                         kernel_ptr<double, true, false>(),  kernel_ptr<double, true, true>()};
+    const void *ks[12];
+    all_kernels(ks);
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;

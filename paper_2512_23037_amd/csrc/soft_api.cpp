@@ -73,12 +73,13 @@ struct soft_ctx {
     uint32_t support_cap = 0;
     int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory
     bool speculate = true;                    // run speculative event lists where compiled
+    int noise_mode = 0;                       // 0 a word per noise slot, 1 gap sampling
     Shape user;                               // explicit launch shape parts
-    std::map<std::tuple<uint64_t, int, double, uint32_t, int>, Shape> tuned;
+    std::map<std::tuple<uint64_t, int, double, uint32_t, int, int>, Shape> tuned;
 
     DevBuf<Event> d_ev;
     DevBuf<NoiseLoc> d_nz;
-    DevBuf<uint32_t> d_tm1, d_det;
+    DevBuf<uint32_t> d_tm1, d_det, d_gap;
     DevBuf<BatchMember> d_bm;
     DevBuf<VariantDesc> d_vars;
     DevBuf<unsigned char> d_gtile;            // device-memory tiles
@@ -189,7 +190,7 @@ int prepare(soft_ctx *c) {
     if (!c->dirty) return SOFT_OK;
     std::vector<Event> ev;
     std::vector<NoiseLoc> nz;
-    std::vector<uint32_t> tm1, det;
+    std::vector<uint32_t> tm1, det, gap;
     std::vector<BatchMember> bm;
     std::vector<VariantDesc> vd;
     c->kmax = 0;
@@ -203,6 +204,7 @@ int prepare(soft_ctx *c) {
         D.nz_off = (uint32_t)nz.size();
         D.tm1_off = (uint32_t)tm1.size();
         D.n_noise = P.n_noise;
+        D.gap_off = (uint32_t)gap.size();
         // each event list with its own check pairs and run members
         auto append = [&](const Program &Q) {
             const uint32_t off = (uint32_t)ev.size();
@@ -220,6 +222,7 @@ int prepare(soft_ctx *c) {
         D.ev_off = V.has_fast ? append(V.fast) : D.ev_off_full;
         nz.insert(nz.end(), P.noise.begin(), P.noise.end());
         tm1.insert(tm1.end(), P.noise_tm1.begin(), P.noise_tm1.end());
+        gap.insert(gap.end(), P.gap.begin(), P.gap.end());
         vd.push_back(D);
         c->kmax = std::max(c->kmax, P.kmax);
         c->rec_words = std::max(c->rec_words, (P.n_rec + 31u) / 32u);
@@ -230,8 +233,10 @@ int prepare(soft_ctx *c) {
     int rc;
     if ((rc = ensure(c, c->d_ev, ev.size())) || (rc = ensure(c, c->d_nz, std::max<size_t>(nz.size(), 1))) ||
         (rc = ensure(c, c->d_tm1, tm1.size())) || (rc = ensure(c, c->d_det, std::max<size_t>(det.size(), 2))) ||
-        (rc = ensure(c, c->d_bm, std::max<size_t>(bm.size(), 1))) || (rc = ensure(c, c->d_vars, vd.size())))
+        (rc = ensure(c, c->d_bm, std::max<size_t>(bm.size(), 1))) || (rc = ensure(c, c->d_vars, vd.size())) ||
+        (rc = ensure(c, c->d_gap, std::max<size_t>(gap.size(), 1))))
         return rc;
+    if (!gap.empty()) HIPCHK(c, hipMemcpy(c->d_gap.p, gap.data(), gap.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_ev.p, ev.data(), ev.size() * sizeof(Event), hipMemcpyHostToDevice));
     if (!nz.empty()) HIPCHK(c, hipMemcpy(c->d_nz.p, nz.data(), nz.size() * sizeof(NoiseLoc), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_tm1.p, tm1.data(), tm1.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -251,6 +256,11 @@ constexpr uint32_t kMaxWavesPerCu = 32u;
 // (at most 32), two waves per block when that still leaves >= 16 waves.
 // Device-memory tiles are used when asked for, or (auto) when one wave's LDS
 // tile does not fit in a block's LDS.
+// Noise source of the next launch (explicit words use the per-slot form).
+uint32_t noise_source(const soft_ctx *c) {
+    return c->words_dev != nullptr ? NS_EXPLICIT : (c->noise_mode == 1 ? NS_GAPS : NS_SLOTS);
+}
+
 bool tiles_in_memory(const soft_ctx *c) {
     if (c->tile_mode == 2) return true;
     if (c->tile_mode == 1) return false;
@@ -271,7 +281,7 @@ Shape default_shape(const soft_ctx *c) {
     s.bpc = std::max<uint32_t>(1u, waves_cu / s.wpb);
     // no more blocks than stay resident (registers can be the tighter limit)
     int res = 0;
-    if (sampler_occupancy(c->bits == 64, c->words_dev != nullptr, s.gt != 0, (int)(64u * s.wpb), (size_t)s.wpb * wb,
+    if (sampler_occupancy(c->bits == 64, noise_source(c), s.gt != 0, (int)(64u * s.wpb), (size_t)s.wpb * wb,
                           &res) == hipSuccess && res > 0)
         s.bpc = std::min<uint32_t>(s.bpc, (uint32_t)res);
     else
@@ -282,7 +292,7 @@ Shape default_shape(const soft_ctx *c) {
 
 Shape current_shape(const soft_ctx *c) {
     Shape s = default_shape(c);
-    auto it = c->tuned.find(std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode));
+    auto it = c->tuned.find(std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode, c->noise_mode));
     if (it != c->tuned.end()) s = it->second;
     if (c->tile_mode) s.gt = c->tile_mode == 2 ? 1u : 0u;
     if (c->user.wpb) s.wpb = c->user.wpb;
@@ -355,6 +365,8 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.det = c->d_det.p;
     rp.bm = c->d_bm.p;
     rp.speculate = c->speculate ? 1u : 0u;
+    rp.gaps = c->d_gap.p;
+    rp.noise_mode = (uint32_t)c->noise_mode;
     rp.vars = c->d_vars.p;
     rp.n_vars = (uint32_t)c->vars.size();
     rp.words = c->words_dev;
@@ -572,6 +584,7 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_ev);
     release(c->d_nz);
     release(c->d_tm1);
+    release(c->d_gap);
     release(c->d_det);
     release(c->d_bm);
     release(c->d_vars);
@@ -714,6 +727,13 @@ int soft_set_caps(soft_ctx *c, uint32_t support_cap, uint32_t wpb, uint32_t bpc,
 int soft_set_speculation(soft_ctx *c, int on) {
     if (!c) return SOFT_EINVAL;
     c->speculate = on != 0;
+    return SOFT_OK;
+}
+
+int soft_set_noise_mode(soft_ctx *c, int mode) {
+    if (!c) return SOFT_EINVAL;
+    if (mode < 0 || mode > 1) return fail(c, SOFT_EINVAL, "noise mode must be 0 (a word per slot) or 1 (gap sampling)");
+    c->noise_mode = mode;
     return SOFT_OK;
 }
 
@@ -1030,7 +1050,7 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     (void)hipFree(d_status);
     (void)hipFree(d_list);
     if (rc) return rc;
-    c->tuned[std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode)] = best;
+    c->tuned[std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode, c->noise_mode)] = best;
     c->ran = false;  // counters of the last sample run are not a user run
     return SOFT_OK;
 }

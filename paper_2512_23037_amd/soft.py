@@ -25,7 +25,7 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
            "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
-           "soft_run_list", "soft_set_speculation")
+           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode")
 
 
 class SoftError(RuntimeError):
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "soft_set_tile_memory": (I, [P, I]),
         "soft_run_list": (I, [P, P, U64, P, P, P, P, P]),
         "soft_set_speculation": (I, [P, I]),
+        "soft_set_noise_mode": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -198,6 +199,10 @@ class Context:
     def set_speculation(self, on: bool):
         """Run the speculative (span-truncating) event lists first (default)."""
         self._check(self._lib.soft_set_speculation(self._h, 1 if on else 0))
+
+    def set_noise_mode(self, mode: int):
+        """0: one word per noise location (default); 1: gap sampling."""
+        self._check(self._lib.soft_set_noise_mode(self._h, mode))
 
     def set_tile_memory(self, mode: int):
         """0 automatic, 1 LDS, 2 device memory (HBM)."""
