@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--autotune", type=int, default=0, help="sample shots for the autotuner (0 = library default shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy 3 times (HBM counter calibration for rocprofv3 --pmc)")
-    ap.add_argument("--noise-mode", type=int, default=0, choices=(0, 1),
+    ap.add_argument("--noise-mode", type=int, default=1, choices=(0, 1),
                     help="0: one noise word per location; 1: gap sampling (same distribution)")
     ap.add_argument("--mixture", action="store_true",
                     help="instead: the batching run (27 circuit/noise variants, --shots in one launch per step)")
@@ -245,7 +245,7 @@ def main():
     if work is not None:
         per_shot = {k: v / nsample for k, v in work.items()}
         ops = (OPS_T_BRANCH * per_shot["t_entries"] + OPS_T_PHASE * per_shot["t_phase_entries"] +
-               OPS_M * per_shot["m_entries"] + OPS_NOISE * per_shot["noise_slots"]) * shots
+               OPS_M * per_shot["m_entries"] + OPS_NOISE * per_shot["noise_words"]) * shots
         achieved = ops / (r32["ms"] / 1e3) / 1e12
         traffic = None
         if os.path.exists(PROFILE_TRAFFIC):
@@ -263,7 +263,7 @@ def main():
                            "ops_per_launch": ops, "work_per_shot": per_shot,
                            "executed": {"ops_per_launch": ex_ops, "achieved": ex_rate, "frac": ex_rate / VALU_PEAK_TOPS,
                                         "per_shot": {"t_entries": c["entries_t"] / shots, "m_entries": c["entries_m"] / shots,
-                                                     "noise_slots": c["noise_slots"] / shots}},
+                                                     "noise_words": c["noise_slots"] / shots}},
                            "kernel_ms": r32["ms"], "kernel_hash": kernel_hash()}
     print(json.dumps(out))
 

@@ -63,7 +63,7 @@ typedef struct {
     uint64_t logical_errors;     /* passed shots with a nonzero observable   */
     uint64_t entries_t;          /* coefficient entries written by T/T-dagger */
     uint64_t entries_m;          /* coefficient entries read by measurements */
-    uint64_t noise_slots;        /* noise words drawn                          */
+    uint64_t noise_slots;        /* noise words drawn (256 per Philox refill of a wave) */
     uint64_t events;             /* T/T-dagger and measurements executed      */
     uint64_t support_hist[16];   /* shots by floor(log2(max |v|)), last bin 15+ */
     double max_norm_dev;         /* max over shots of |sum |v|^2 - 1| at the end */

@@ -43,7 +43,7 @@ class _ShotInfo(ctypes.Structure):
                 ("obs", ctypes.c_uint32), ("max_support", ctypes.c_uint32),
                 ("t_entries", ctypes.c_uint64), ("t_phase_entries", ctypes.c_uint64),
                 ("m_entries", ctypes.c_uint64), ("noise_slots", ctypes.c_uint64),
-                ("events", ctypes.c_uint64), ("norm2", ctypes.c_double)]
+                ("events", ctypes.c_uint64), ("norm2", ctypes.c_double), ("noise_words", ctypes.c_uint64)]
 
 
 _lib = None
@@ -171,7 +171,7 @@ class Circuit:
         bits = [int((rec[i >> 5] >> (i & 31)) & 1) for i in range(self.n_records)]
         coeffs = {int(al[i]): complex(re[i], im[i]) for i in range(k)}
         work = {f: int(getattr(info, f)) for f in ("t_entries", "t_phase_entries", "m_entries",
-                                                   "noise_slots", "events")}
+                                                   "noise_slots", "events", "noise_words")}
         return ShotResult(bits, info.status, info.abort_op, info.obs, info.max_support, tx, tz, tr,
                           coeffs, p0[: self.n_meas_slots], work, info.norm2)
 
@@ -186,7 +186,7 @@ class Circuit:
         abort_op = np.zeros(n, dtype=np.uint32)
         obs = np.zeros(n, dtype=np.uint32)
         maxs = np.zeros(n, dtype=np.uint32)
-        work = np.zeros(5, dtype=np.uint64)
+        work = np.zeros(6, dtype=np.uint64)
         w = None
         if words is not None:
             w = np.ascontiguousarray(words, dtype=np.uint32)
@@ -198,5 +198,6 @@ class Circuit:
             raise RuntimeError("oracle_batch failed")
         return {"outcomes": outcomes[:nw], "status": status, "abort_op": abort_op, "obs": obs,
                 "max_support": maxs, "threads": threads,
-                "work": dict(zip(("t_entries", "t_phase_entries", "m_entries", "noise_slots", "events"),
+                "work": dict(zip(("t_entries", "t_phase_entries", "m_entries", "noise_slots", "events",
+                                  "noise_words"),
                                  (int(x) for x in work)))}

@@ -656,11 +656,13 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
         next_hit = -1;
         while (true) {
             const uint32_t w = philox_word(seed, shot, 2, draw++);
+            ++res.info.noise_words;
             int64_t g = 0;
             while (g + 1 <= c.n_noise && (uint64_t)w < c.gap_thr[g + 1]) ++g;
             cand += 1 + g;
             if (cand >= c.n_noise) return;
             const uint32_t a = philox_word(seed, shot, 2, draw++);
+            ++res.info.noise_words;
             if ((uint64_t)a < c.accept[cand]) {
                 next_hit = (int)cand;
                 hit_word = a;
@@ -739,6 +741,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                     advance();
                 } else {
                     w = noise_word(o.slot);
+                    ++res.info.noise_words;
                     thr = o.thr;
                     if ((uint64_t)w >= thr) break;
                 }
@@ -882,7 +885,7 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
     if (threads < 1) threads = 1;
     const uint64_t stride = (uint64_t)c->n_noise + c->n_meas;
     const int nw = (c->n_rec + 31) / 32;
-    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(5, 0));
+    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(6, 0));
     auto worker = [&](int t) {
         uint64_t lo = n * t / threads, hi = n * (t + 1) / threads;
         ShotState st;
@@ -900,6 +903,7 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
             part[t][2] += res.info.m_entries;
             part[t][3] += res.info.noise_slots;
             part[t][4] += res.info.events;
+            part[t][5] += res.info.noise_words;
         }
     };
     std::vector<std::thread> pool;
@@ -907,7 +911,7 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
     worker(0);
     for (auto &th : pool) th.join();
     if (work)
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 6; ++k) {
             work[k] = 0;
             for (int t = 0; t < threads; ++t) work[k] += part[t][k];
         }

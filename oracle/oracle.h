@@ -74,6 +74,7 @@ typedef struct {
     uint64_t noise_slots; /* noise slots drawn before the shot ended           */
     uint64_t events;      /* T/TDG + measurements executed                       */
     double   norm2;       /* sum |v|^2 at the end                                */
+    uint64_t noise_words; /* random words drawn for noise (one per slot in mode 0) */
 } oracle_shot_info;
 
 /* Run one shot.  words: NULL for Philox4x32-10 draws keyed by (seed, shot),
@@ -95,8 +96,9 @@ int oracle_shot(const oracle_circuit *c, uint64_t seed, uint64_t shot,
 /* Run shots [shot0, shot0+n) on `threads` host threads.
  * words: NULL, or explicit words laid out [n][n_noise_slots + n_meas_slots].
  * outcomes: bit-planes [ceil(n_records/32)][n]; status/abort_op/obs: [n].
- * max_support: [n] or NULL.  work: NULL or 5 sums of the oracle_shot_info
- * counters (t_entries, t_phase_entries, m_entries, noise_slots, events). */
+ * max_support: [n] or NULL.  work: NULL or 6 sums of the oracle_shot_info
+ * counters (t_entries, t_phase_entries, m_entries, noise_slots, events,
+ * noise_words). */
 int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0,
                  uint64_t n, const uint32_t *words, double tau, uint32_t cap,
                  int threads, uint32_t *outcomes, uint32_t *status,

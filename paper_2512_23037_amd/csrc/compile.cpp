@@ -169,10 +169,6 @@ class FrameCompiler {
             // T^s = e^{i s theta}(cos theta - i s sin theta Z_q).  The global
             // factor e^{i s theta} is counted per shot; the rest is
             // cos theta v + sin theta i^qb c' v_partner with i^qb = (-i s) i^cexp.
-            E.Are = cs;
-            E.Aim = 0.0;
-            E.Bre = sn;
-            E.Bim = 0.0;
             E.Tn = sn / cs;
             E.Cs2 = cs * cs;
             E.Tnf = (float)E.Tn;
@@ -190,7 +186,6 @@ class FrameCompiler {
                 if (basis_.size() > P_.kmax) P_.kmax = (uint32_t)basis_.size();
             }
         }
-        E.Afr = (float)E.Are; E.Afi = (float)E.Aim; E.Bfr = (float)E.Bre; E.Bfi = (float)E.Bim;
         finish(E);
         spec_after_t(q, dagger, k_before, src);
     }
@@ -661,6 +656,27 @@ uint64_t fnv1a(const void *data, size_t len, uint64_t h) {
 
 }  // namespace
 
+// Running work counts of the event list (see Event::cum_t): the span
+// dimension before each event is the same in every shot, so the work of a
+// shot that stops after event e is the sum over the events up to e.
+static void work_sums(Program &out) {
+    uint64_t t = 0, m = 0;
+    uint32_t n = 0;
+    for (Event &E : out.events) {
+        E.cum_t = t;
+        E.cum_m = m;
+        E.cum_e = n;
+        switch (E.kind) {
+            case EV_T_PHASE: ++n; break;
+            case EV_T_DOUBLE: t += 2ull << E.k; ++n; break;
+            case EV_T_BFLY: t += 1ull << E.k; ++n; break;
+            case EV_M_DET: ++n; break;
+            case EV_M_CUT: case EV_M_SPLIT: case EV_M_MERGE: m += 1ull << E.k; ++n; break;
+            default: break;
+        }
+    }
+}
+
 // Gap sampling tables (see NoiseLoc): acceptance per slot and the gap table
 // floor(q^g 2^32), q^g formed by repeated multiplication.  Slots with thr = 0
 // take no part (acc = 0) and do not set p_max.  Without live slots every
@@ -856,6 +872,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     form_batches(out);
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
+    work_sums(out);
     gap_tables(out);
     // pad the threshold table to whole 256-slot chunks
     while (out.noise_tm1.size() % 256) out.noise_tm1.push_back(0);

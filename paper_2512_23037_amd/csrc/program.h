@@ -89,16 +89,20 @@ struct alignas(16) Event {
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products
     uint64_t xD, xS;          // reset / feedback: rows anticommuting with the flip Pauli
-    double Are, Aim;          // T_PHASE: e^{i s pi/4}; branching T: cos(pi/8), 0
-    double Bre, Bim;          // branching T: sin(pi/8), 0 (the weight of the partner term)
-    float Afr, Afi, Bfr, Bfi; // the same in single precision
+    double Are, Aim;          // T_PHASE: e^{i s pi/4}
     // Branching T on a tile that carries the state up to a per-shot real
     // factor: v'_j = v_j + tan(pi/8) i^qb c' v_partner, and cos^2(pi/8) joins
     // the factor's square.
     double Tn;                // tan(pi/8)
     double Cs2;               // cos^2(pi/8)
+    // Work of the list's events before this one, so a shot's counters come
+    // from the event after the last one it ran: tile entries written by
+    // branching T, tile entries read by measurement passes, T and measurement
+    // events.
+    uint64_t cum_t, cum_m;
     float Tnf;                // Tn in single precision
-    uint32_t pad1;
+    uint32_t cum_e;
+    uint32_t pad1[4];
 };
 static_assert(sizeof(Event) == 256, "event layout");
 

@@ -181,24 +181,8 @@ __device__ __forceinline__ uint32_t first_hit(uint32_t hits, uint32_t cb) {
     return cb + 4u * L + (uint32_t)__builtin_ctz(m);
 }
 
-// Record words per shot held in lanes until the group is written.
-constexpr uint32_t kRecRegs = 4;
-
-// Write the outputs of shots [base, base + len) held by lanes 0..len-1.
-__device__ __forceinline__ void flush_group(const RunParams &P, uint64_t base, uint32_t len, uint32_t lane,
-                                            uint32_t st, uint32_t ab, uint32_t ob, const uint32_t (&rec)[kRecRegs]) {
-    if (lane < len) {
-        const uint64_t i = base + lane;
-        P.status[i] = st;
-        if (P.abort_op) P.abort_op[i] = ab;
-        if (P.obs) P.obs[i] = ob;
-        if (P.outcomes) {
-#pragma unroll
-            for (uint32_t w = 0; w < kRecRegs; ++w)
-                if (w < P.rec_words) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
-        }
-    }
-}
+// The record words 0..kRecSgpr-1 of a shot live in one vector register, word
+// w in lane w (kRecSgpr <= 64); the rest in LDS.
 
 // i^Q * a for a compile-time Q: only register moves and sign modifiers.
 template <uint32_t Q, typename C> __device__ __forceinline__ C rotc(C a) {
@@ -354,11 +338,6 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
     return cnt;
 }
 
-// Work counted during one shot (32 bits suffice per shot); added to the
-// lane-held 64-bit counters when the shot ends.
-struct ShotTotals {
-    uint32_t entries_t = 0, entries_m = 0, noise = 0, events = 0, restarts = 0;
-};
 
 // Fields of the current event (held one dword per lane in `evc`).
 #define EV32(f) ((uint32_t)__builtin_amdgcn_readlane((int)evc, (int)(offsetof(Event, f) / 4u)))
@@ -416,18 +395,25 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         maxdev = 0.0;
     };
 
-    // Work stealing by groups of `grab` (<= 64) consecutive shots.  Lane g keeps
-    // the output words of the group's g-th shot, so each output plane is
-    // written as one contiguous store per group.
+    // Work stealing by groups of `grab` (<= 64) consecutive shots.  A wave
+    // writes its shots' output words one shot after the other, so L2 gathers
+    // each output plane's words of a group into whole lines.
     uint64_t group_base = 0;
     uint32_t group_len = 0, group_pos = 0;
-    uint32_t o_status = 0, o_abort = 0, o_obs = 0;
-    uint32_t o_rec[kRecRegs];
-#pragma unroll
-    for (uint32_t w = 0; w < kRecRegs; ++w) o_rec[w] = 0u;
+    // Output plane of this lane: record word `lane` (lanes below kRecSgpr),
+    // then status, abort op and observables; null when the caller did not ask.
+    uint32_t *out_plane = nullptr;
+    if (lane < kRecSgpr) {
+        if (P.outcomes && lane < P.rec_words) out_plane = P.outcomes + (uint64_t)lane * P.n_shots;
+    } else if (lane == kRecSgpr) {
+        out_plane = P.status;
+    } else if (lane == kRecSgpr + 1u) {
+        out_plane = P.abort_op;
+    } else if (lane == kRecSgpr + 2u) {
+        out_plane = P.obs;
+    }
     while (true) {
         if (group_pos == group_len) {
-            if (group_len) flush_group(P, group_base, group_len, lane, o_status, o_abort, o_obs, o_rec);
             unsigned long long got = 0;
             if (lane == 0) got = atomicAdd(P.next, (unsigned long long)P.grab);
             group_base = uni64(__shfl((unsigned long long)got, 0, 64));
@@ -436,31 +422,29 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             group_pos = 0;
         }
         const uint64_t i = group_base + group_pos;
-        const uint64_t shot = P.shot_list ? P.shot_list[i] : P.shot0 + i;
+        // a vector load of a uniform address: say that the result is uniform
+        const uint64_t shot = uni64(P.shot_list ? P.shot_list[i] : P.shot0 + i);
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
         if (!var_ok || shot >= var_end || shot < var_lo) {
             if (var_ok) flush_counters();
             // shots past the last range (possible only in a shot list) run as the last variant
             var = 0;
             while (var + 1u < P.n_vars && P.vars[var].shot_end <= shot) ++var;
-            const VariantDesc &VD = P.vars[var];
-            var_lo = var ? P.vars[var - 1u].shot_end : 0ull;
-            var_end = VD.shot_end;
+            var = uni(var);
+            var_lo = uni64(var ? P.vars[var - 1u].shot_end : 0ull);
+            var_end = uni64(P.vars[var].shot_end);
             var_ok = true;
         }
         const uint32_t *wrow = EXPL ? words + i * P.word_stride : nullptr;
 
         // ---- per-shot state (set at the start of each attempt below) ----
         // record words 0..3 live in scalar registers, the rest in LDS
-        uint32_t rr0 = 0, rr1 = 0, rr2 = 0, rr3 = 0;
+        uint32_t rrv = 0;  // record word `lane` for lanes below kRecSgpr
         auto rec_read = [&](uint32_t w) -> uint32_t {
-            return w == 0u ? rr0 : w == 1u ? rr1 : w == 2u ? rr2 : w == 3u ? rr3 : rec[w];
+            return w < kRecSgpr ? (uint32_t)__builtin_amdgcn_readlane((int)rrv, (int)w) : rec[w];
         };
         auto rec_toggle = [&](uint32_t w, uint32_t m) {
-            if (w == 0u) rr0 ^= m;
-            else if (w == 1u) rr1 ^= m;
-            else if (w == 2u) rr2 ^= m;
-            else if (w == 3u) rr3 ^= m;
+            if (w < kRecSgpr) rrv ^= lane == w ? m : 0u;
             else if (lane == 0) rec[w] ^= m;
         };
         // expect ^ XOR of the listed record bits for the current event (the
@@ -496,7 +480,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
         const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
-        ShotTotals tot;
         // noise tables of this variant (read where used: the draws are rare)
         const VariantDesc *vdp = P.vars + var;
 
@@ -518,7 +501,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             hits = (s0 + 0u < n_noise && w0 <= th.x ? 1u : 0u) | (s0 + 1u < n_noise && w1 <= th.y ? 2u : 0u) |
                    (s0 + 2u < n_noise && w2 <= th.z ? 4u : 0u) | (s0 + 3u < n_noise && w3 <= th.w ? 8u : 0u);
             next_hit = first_hit(hits, nz_cb);
-            tot.noise += min(256u, n_noise - nz_cb);
         };
         // Gap sampling: decide the slots up to the next candidate.  A
         // candidate takes words gd, gd + 1 of stream 2 (gap, then acceptance;
@@ -551,11 +533,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             }
             G = uni(G);
             if (G >= lim) {
-                tot.noise += lim;
                 nz_drawn = vdp->n_noise;
                 return;
             }
-            tot.noise += G + 1u;
             const uint32_t cslot = nz_drawn + G;
             nz_drawn = cslot + 1u;
             if ((uint64_t)aw < nz[vdp->nz_off + cslot].acc) {
@@ -615,7 +595,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         for (;;) {
         const uint32_t *evl = reinterpret_cast<const uint32_t *>(ev + (full ? vdp->ev_off_full : vdp->ev_off));
         for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64) rec[w] = 0u;
-        rr0 = rr1 = rr2 = rr3 = 0u;
+        rrv = 0u;
         if (lane == 0) v[0] = mk<C>(1.0, 0.0);
         tile_sync();
         rD = rS = a = 0ull;
@@ -638,7 +618,8 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // Event e sits in evc, one dword per lane; event e + 1 is loaded while
         // event e runs (the list ends with two END events).
         evc = evl[lane];
-        for (uint32_t e = 0;; ++e) {
+        uint32_t e = 0;  // after the loop: the last event run
+        for (;; ++e) {
             uint32_t evx = evl[(uint64_t)(e + 1u) * 64u + lane];
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
@@ -689,7 +670,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         }
                     });
                 }
-                tot.events++;
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
                 const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
                 const uint32_t sig = sc ^ ga;
@@ -706,7 +686,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, tn, thr); break;
                         default: cnt = t_double<3, R, C>(v, lane, k, g, sig, tn, thr); break;
                     }
-                    tot.entries_t += 2u << k;
                     ++k;
                 } else {
                     const uint32_t mu = EV32(mu), h = EV32(tstar);
@@ -716,12 +695,10 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
                         default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
                     }
-                    tot.entries_t += 1u << k;
                 }
                 phase8 = (phase8 + ((EV32(flags) & EVF_TDG) ? 15u : 1u)) & 15u;
                 cnt = uni(cnt);
                 maxsup = max(maxsup, cnt);
-                tot.events++;
                 if (cnt > P.support_cap) {
                     status = ST_OVERFLOW;
                     abort_src = EV32(src);
@@ -762,9 +739,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     ((info & BM_CSIGN) ? 1u : 0u) ^ par64(myD & beta) ^ par64(myS & gamma) ^ par64(gamma & a);
                 // folded checks read record bits from before the run, plus their own
                 uint32_t chk = 0;
+                // (the lane shuffle runs on every lane: a source lane must be active)
+                const uint32_t rlane = (uint32_t)__shfl((int)rrv, (int)(q3.z & 63u), 64);
                 if (info & BM_CHECK) {
                     const uint32_t w = q3.z;
-                    const uint32_t rw = w == 0u ? rr0 : w == 1u ? rr1 : w == 2u ? rr2 : w == 3u ? rr3 : rec[w];
+                    const uint32_t rw = w < kRecSgpr ? rlane : rec[w];
                     chk = ((info & BM_EXPECT) ? 1u : 0u) ^ par32(rw & q3.w) ^ ((info & BM_OWN) ? bit : 0u);
                 }
                 const uint64_t fails = __ballot(lane < m && chk != 0u);
@@ -800,12 +779,12 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         rS ^= lane64(xS, l);
                     }
                 }
-                tot.events += L + 1u;
                 if (fails) {
                     status = ST_DISCARDED;
                     abort_src = (uint32_t)__builtin_amdgcn_readlane((int)q4.x, (int)L);
                     term = e + L;
                     after = 1;
+                    e += L;  // the last event run
                     break;
                 }
                 e += m - 1u;
@@ -834,7 +813,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     u = ((double)mw + 0.5) * (1.0 / 4294967296.0);
                 }
                 uint32_t bit = 0;
-                tot.events++;
                 if (kind == EV_M_DET) {
                     bit = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
                 } else if (kind == EV_M_CUT) {
@@ -853,7 +831,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     bit = u < p0 ? 0u : 1u;
                     const uint32_t bsel = sig ^ bit;
                     const double Ns = bsel ? n1 : n0;
-                    tot.entries_m += cnt;
                     if (!(Ns > 1e-300)) {
                         status = ST_NUMERIC;
                         abort_src = EV32(src);
@@ -899,7 +876,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     });
                     nrm2 = wave_sum(nn);
                     tscale2 = 1.0;
-                    tot.entries_m += cnt;
                 } else {  // EV_M_MERGE
                     const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
                     const uint32_t q0 = (4u - EV32(cexp)) & 3u;
@@ -922,7 +898,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     const double p0 = np / (np + nm);
                     bit = u < p0 ? 0u : 1u;
                     const double Ns = bit ? nm : np;
-                    tot.entries_m += 2u * npairs;
                     if (!(Ns > 1e-300)) {
                         status = ST_NUMERIC;
                         abort_src = EV32(src);
@@ -1023,9 +998,19 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             evc = evx;
         }
         tile_sync();
+        {
+            // work of this attempt: the list's running sums at the event after
+            // the last one run, and the noise words drawn
+            const Event *nx = reinterpret_cast<const Event *>(evl) + e + 1u;
+            const uint64_t wt = uni64(nx->cum_t), wm = uni64(nx->cum_m);
+            const uint32_t we = uni(nx->cum_e);
+            const uint32_t wn = GAPS ? ((gd + 255u) & ~255u) : min(nz_drawn, vdp->n_noise);
+            myc += lane == (uint32_t)C_ENTRIES_T ? wt : lane == (uint32_t)C_ENTRIES_M ? wm
+                 : lane == (uint32_t)C_EVENTS ? (uint64_t)we : lane == (uint32_t)C_NOISE ? (uint64_t)wn : 0ull;
+        }
         if (!restart) break;
         full = true;
-        ++tot.restarts;
+        myc += lane == (uint32_t)C_RESTARTS ? 1u : 0u;
         }
 
         // ---- shot end: norm check, outputs, kept states, counters ----
@@ -1034,16 +1019,15 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         lane_pass(cnt, lane, [&](uint32_t j) { nn += nrm<R>(v[j]); });
         nn = wave_sum(nn);
         maxdev = fmax(maxdev, fabs(nn * tscale2 - 1.0));
-        if (lane == group_pos) {
-            o_status = status;
-            o_abort = abort_src;
-            o_obs = obs;
-#pragma unroll
-            for (uint32_t w = 0; w < kRecRegs; ++w)
-                if (w < P.rec_words) o_rec[w] = rec_read(w);
+        {
+            // one store for the record words held in scalar registers and the
+            // three per-shot words; record words in LDS follow
+            const uint32_t val = lane < kRecSgpr ? rrv : lane == kRecSgpr ? status
+                               : lane == kRecSgpr + 1u ? abort_src : obs;
+            if (out_plane) out_plane[i] = val;
         }
-        if (P.outcomes)  // record words beyond the lane-held ones go out directly
-            for (uint32_t w = kRecRegs + lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
+        if (P.outcomes)
+            for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
         ++group_pos;
         if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
             const uint64_t kk = shot - P.keep_lo;
@@ -1056,9 +1040,6 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
-        myc += lane == C_ENTRIES_T ? tot.entries_t : lane == C_ENTRIES_M ? tot.entries_m
-             : lane == C_NOISE ? tot.noise : lane == C_EVENTS ? tot.events
-             : lane == C_RESTARTS ? tot.restarts : 0u;
     }
     if (var_ok) flush_counters();
 }
