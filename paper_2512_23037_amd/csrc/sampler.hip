@@ -233,15 +233,19 @@ template <uint32_t Q, typename R, typename C> __device__ __forceinline__ C t_new
 // Otherwise, with t the lowest iteration bit whose coordinate bit is in g,
 // iterations it and it ^ 2^t have opposite signs: each such pair runs one Q
 // and one Q + 2 update, and which is which is a scalar choice.
-//
-// Pair the iterations on bit t when it lies in [0, log2(iters)); returns
-// 1 << t, or 0 when every iteration has sign +1.  `pos` maps iteration bit
-// u to its coordinate bit.
+// The coordinate bit that pairs the iterations: the lowest coordinate bit in
+// g that some iteration sets, or 0 when every iteration has sign +1.  `pos`
+// maps iteration bit u to its coordinate bit.
 template <typename Pos> __device__ __forceinline__ uint32_t pair_bit(uint32_t g, uint32_t iters, Pos &&pos) {
     for (uint32_t u = 0; (1u << u) < iters; ++u)
-        if ((g >> pos(u)) & 1u) return 1u << u;
+        if ((g >> pos(u)) & 1u) return 1u << pos(u);
     return 0u;
 }
+
+// The iterations' coordinate bits J run over the values with the bits of M
+// clear (M holds the lane bits and any skipped bit): J -> ((J | M) + 1) & ~M
+// steps to the next one in increasing order.
+__device__ __forceinline__ uint32_t next_j(uint32_t J, uint32_t M) { return ((J | M) + 1u) & ~M; }
 
 // Branching T on an existing coordinate: pairs (j0, j1 = j0 ^ mu), j0 with
 // bit h clear.  v'_j0 = v_j0 + tn i^Q (-1)^(sig ^ g.j1) v_j1 and the same
@@ -267,30 +271,46 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     const R c0 = par32(g & mu) ? -c1 : c1;                   // weight of v_j1 in v'_j0
     uint32_t cnt = 0;
     const uint32_t iters = (npairs + 63u) >> 6;
-    // one iteration with the Q or (S = 2) the Q + 2 form
-    auto step = [&](uint32_t J, auto S) {
+    // one iteration with the Q or (S = 2) the Q + 2 form, in two halves so
+    // that a pair of iterations issues all its LDS reads before any write
+    // (the iterations of a pass touch disjoint entries)
+    auto addr0 = [&](uint32_t J) { return reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C)); };
+    auto addr1 = [&](uint32_t J) { return reinterpret_cast<C *>(p1 + (J ^ mu_i) * (uint32_t)sizeof(C)); };
+    auto finish = [&](uint32_t J, C v0, C v1, auto S) {
         constexpr uint32_t QS = (Q + decltype(S)::value) & 3u;
-        C *const r0 = reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
-        C *const r1 = reinterpret_cast<C *>(p1 + (J ^ mu_i) * (uint32_t)sizeof(C));
-        const C v0 = *r0, v1 = *r1;
         bool k0, k1;
         const C o0 = t_out<QS, R, C>(v0, v1, c0, thr, k0);
         const C o1 = t_out<QS, R, C>(v1, v0, c1, thr, k1);
         cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
-        *r0 = o0;
-        *r1 = o1;
+        *addr0(J) = o0;
+        *addr1(J) = o1;
     };
-    const uint32_t tb = pair_bit(g, iters, [&](uint32_t u) { return u + 6u < h ? u + 6u : u + 7u; });
-    if (tb == 0u) {
-        for (uint32_t it = 0; it < iters; ++it) step(ins0(it << 6, h), std::integral_constant<uint32_t, 0>());
+    auto step = [&](uint32_t J, auto S) { finish(J, *addr0(J), *addr1(J), S); };
+    // the iterations' coordinate bits J = ins0(64 it, h): everything outside
+    // the lane bits and bit h
+    const uint32_t pb = pair_bit(g, iters, [&](uint32_t u) { return u + 6u < h ? u + 6u : u + 7u; });
+    uint32_t J = 0;
+    if (pb == 0u) {
+        if (iters == 1u) {
+            step(J, std::integral_constant<uint32_t, 0>());
+        } else {
+            for (uint32_t it = 0; it < iters; it += 2u) {  // iters is a power of two
+                const uint32_t JB = next_j(J, lmask | hb);
+                const C a0 = *addr0(J), a1 = *addr1(J), b0 = *addr0(JB), b1 = *addr1(JB);
+                finish(J, a0, a1, std::integral_constant<uint32_t, 0>());
+                finish(JB, b0, b1, std::integral_constant<uint32_t, 0>());
+                J = next_j(JB, lmask | hb);
+            }
+        }
     } else {
-        const uint32_t t = (uint32_t)__builtin_ctz(tb);
         for (uint32_t i2 = 0; i2 < (iters >> 1); ++i2) {
-            const uint32_t it = ins0(i2, t);
-            const uint32_t JA = ins0(it << 6, h), JB = ins0((it | tb) << 6, h);
-            const bool fa = par32(g & JA) != 0u;
-            step(fa ? JB : JA, std::integral_constant<uint32_t, 0>());
-            step(fa ? JA : JB, std::integral_constant<uint32_t, 2>());
+            const uint32_t JB = J | pb;
+            const bool fa = par32(g & J) != 0u;
+            const uint32_t Jp = fa ? JB : J, Jm = fa ? J : JB;  // sign +1, sign -1
+            const C a0 = *addr0(Jp), a1 = *addr1(Jp), b0 = *addr0(Jm), b1 = *addr1(Jm);
+            finish(Jp, a0, a1, std::integral_constant<uint32_t, 0>());
+            finish(Jm, b0, b1, std::integral_constant<uint32_t, 2>());
+            J = next_j(J, lmask | hb | pb);
         }
     }
     return cnt;
@@ -310,29 +330,37 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
     char *const p1 = reinterpret_cast<char *>(v + half + lp);
     uint32_t cnt = 0;
     const uint32_t iters = (half + 63u) >> 6;
-    auto step = [&](uint32_t J, auto S) {
+    // as in t_bfly: a pair of iterations reads before it writes
+    auto addr0 = [&](uint32_t J) { return reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C)); };
+    auto addr1 = [&](uint32_t J) { return reinterpret_cast<C *>(p1 + J * (uint32_t)sizeof(C)); };
+    auto finish = [&](uint32_t J, C v0, auto S) {
         constexpr uint32_t QS = (Q + decltype(S)::value) & 3u;
-        C *const r0 = reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
-        C *const r1 = reinterpret_cast<C *>(p1 + J * (uint32_t)sizeof(C));
-        const C v0 = *r0;
         bool k0, k1;
         const C o0 = t_keep<R, C>(v0, thr, k0);
         const C o1 = t_new<QS, R, C>(v0, c1, thr, k1);
         cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
-        *r0 = o0;
-        *r1 = o1;
+        *addr0(J) = o0;
+        *addr1(J) = o1;
     };
-    const uint32_t tb = pair_bit(g, iters, [](uint32_t u) { return u + 6u; });
-    if (tb == 0u) {
-        for (uint32_t it = 0; it < iters; ++it) step(it << 6, std::integral_constant<uint32_t, 0>());
+    const uint32_t pb = pair_bit(g, iters, [](uint32_t u) { return u + 6u; });
+    if (iters == 1u) {
+        finish(0u, *addr0(0u), std::integral_constant<uint32_t, 0>());
+    } else if (pb == 0u) {
+        for (uint32_t J = 0; J < (iters << 6); J += 128u) {
+            const C a = *addr0(J), b = *addr0(J + 64u);
+            finish(J, a, std::integral_constant<uint32_t, 0>());
+            finish(J + 64u, b, std::integral_constant<uint32_t, 0>());
+        }
     } else {
-        const uint32_t t = (uint32_t)__builtin_ctz(tb);
+        uint32_t J = 0;
         for (uint32_t i2 = 0; i2 < (iters >> 1); ++i2) {
-            const uint32_t it = ins0(i2, t);
-            const uint32_t JA = it << 6, JB = (it | tb) << 6;
-            const bool fa = par32(g & JA) != 0u;
-            step(fa ? JB : JA, std::integral_constant<uint32_t, 0>());
-            step(fa ? JA : JB, std::integral_constant<uint32_t, 2>());
+            const uint32_t JB = J | pb;
+            const bool fa = par32(g & J) != 0u;
+            const uint32_t Jp = fa ? JB : J, Jm = fa ? J : JB;
+            const C a = *addr0(Jp), b = *addr0(Jm);
+            finish(Jp, a, std::integral_constant<uint32_t, 0>());
+            finish(Jm, b, std::integral_constant<uint32_t, 2>());
+            J = next_j(J, 63u | pb);
         }
     }
     return cnt;
