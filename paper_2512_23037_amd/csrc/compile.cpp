@@ -348,11 +348,14 @@ class FrameCompiler {
         Event E = begin(src);
         E.kind = EV_END;
         finish(E);
-        // one more END so that the kernel may always load event e + 1
-        Event pad = E;
-        P_.events.push_back(pad);
-        P_.before.push_back(P_.before.back());
-        P_.after.push_back(P_.after.back());
+        // two more END events so that the kernel may always load events e + 1
+        // and e + 2
+        for (int i = 0; i < 2; ++i) {
+            Event pad = E;
+            P_.events.push_back(pad);
+            P_.before.push_back(P_.before.back());
+            P_.after.push_back(P_.after.back());
+        }
     }
 
   private:

@@ -303,14 +303,29 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
             }
         }
     } else {
-        for (uint32_t i2 = 0; i2 < (iters >> 1); ++i2) {
+        // two pairs per trip: eight reads in flight before the writes
+        const uint32_t M = lmask | hb | pb, npair = iters >> 1;
+        uint32_t i2 = 0;
+        for (; i2 + 2u <= npair; i2 += 2u) {
+            const uint32_t J2 = next_j(J, M);
+            const bool fa = par32(g & J) != 0u, fb = par32(g & J2) != 0u;
+            const uint32_t Jp = fa ? (J | pb) : J, Jm = fa ? J : (J | pb);
+            const uint32_t Kp = fb ? (J2 | pb) : J2, Km = fb ? J2 : (J2 | pb);
+            const C a0 = *addr0(Jp), a1 = *addr1(Jp), b0 = *addr0(Jm), b1 = *addr1(Jm);
+            const C e0 = *addr0(Kp), e1 = *addr1(Kp), d0 = *addr0(Km), d1 = *addr1(Km);
+            finish(Jp, a0, a1, std::integral_constant<uint32_t, 0>());
+            finish(Jm, b0, b1, std::integral_constant<uint32_t, 2>());
+            finish(Kp, e0, e1, std::integral_constant<uint32_t, 0>());
+            finish(Km, d0, d1, std::integral_constant<uint32_t, 2>());
+            J = next_j(J2, M);
+        }
+        if (i2 < npair) {
             const uint32_t JB = J | pb;
             const bool fa = par32(g & J) != 0u;
-            const uint32_t Jp = fa ? JB : J, Jm = fa ? J : JB;  // sign +1, sign -1
+            const uint32_t Jp = fa ? JB : J, Jm = fa ? J : JB;
             const C a0 = *addr0(Jp), a1 = *addr1(Jp), b0 = *addr0(Jm), b1 = *addr1(Jm);
             finish(Jp, a0, a1, std::integral_constant<uint32_t, 0>());
             finish(Jm, b0, b1, std::integral_constant<uint32_t, 2>());
-            J = next_j(J, lmask | hb | pb);
         }
     }
     return cnt;
@@ -643,12 +658,14 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         gd = 0;
         m_base = 0xFFFFFF00u;
         bool restart = false;
-        // Event e sits in evc, one dword per lane; event e + 1 is loaded while
-        // event e runs (the list ends with two END events).
+        // Event e sits in evc, one dword per lane; event e + 1 is in evx, and
+        // event e + 2 is loaded while event e runs (the list ends with three
+        // END events).
         evc = evl[lane];
+        uint32_t evx = evl[64u + lane];
         uint32_t e = 0;  // after the loop: the last event run
         for (;; ++e) {
-            uint32_t evx = evl[(uint64_t)(e + 1u) * 64u + lane];
+            uint32_t evy = evl[(uint64_t)(e + 2u) * 64u + lane];
             if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
@@ -817,6 +834,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 }
                 e += m - 1u;
                 evx = evl[(uint64_t)(e + 1u) * 64u + lane];
+                evy = evl[(uint64_t)(e + 2u) * 64u + lane];
             } else if (kind <= EV_M_MERGE) {
                 // ---- measurement ----
                 // The uniform is drawn only when the outcome is random.  Philox
@@ -1024,6 +1042,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             }
             tile_sync();
             evc = evx;
+            evx = evy;
         }
         tile_sync();
         {
