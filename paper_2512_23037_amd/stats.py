@@ -113,7 +113,7 @@ def rates(c: dict) -> dict:
 
 def noise_scan(text: str, ps, shots_per_p: int, batch: int, bits: int = 32, seed: int = 0,
                noise_keys=("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp"), progress=None,
-               autotune: int = 0) -> list[dict]:
+               autotune: int = 0, noise_mode: int = 0) -> list[dict]:
     """One circuit at each rate of `ps` (uniform circuit-level noise), run as
     the variants of one mixture over consecutive global shot ranges.  With
     autotune > 0 the launch shape and tile placement are tuned on that many
@@ -125,6 +125,7 @@ def noise_scan(text: str, ps, shots_per_p: int, batch: int, bits: int = 32, seed
     ctx.load_mixture([text] * len(ps), [{k: p for k in noise_keys} for p in ps], ends)
     ctx.set_rng(seed)
     ctx.set_precision(bits)
+    ctx.set_noise_mode(noise_mode)
     if autotune:
         ctx.autotune(autotune)
     shape = ctx.launch_shape()
@@ -162,4 +163,45 @@ def batch_sweep(ctx, sizes, reps: int = 3) -> list[dict]:
             e1.synchronize()
             best = min(best, e0.elapsed_time(e1) / 1e3)
         out.append({"shots": n, "seconds": best, "shots_per_s": n / best})
+    return out
+
+
+def p_sweep(text: str, ps, shots: int, bits: int = 32, seed: int = 0, noise_mode: int = 0, reps: int = 3,
+            noise_keys=("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp")) -> list[dict]:
+    """Throughput against the noise rate (uniform circuit-level noise at each
+    p of `ps`): one context per rate, `shots` per launch, the best of `reps`
+    timed launches after a warm-up, with the discard rate and the work per
+    shot from the device counters of the last launch.  Noise changes where
+    shots stop, so it changes the work per shot."""
+    import torch
+
+    from . import soft
+
+    out = []
+    stream = torch.cuda.current_stream()
+    status = torch.empty(shots, dtype=torch.int32, device="cuda")
+    for p in ps:
+        ctx = soft.Context(0)
+        ctx.load_noise(**{k: p for k in noise_keys})
+        ctx.load_circuit(text)
+        ctx.set_rng(seed)
+        ctx.set_precision(bits)
+        ctx.set_noise_mode(noise_mode)
+        ctx.run(0, shots, status=status, stream=stream)  # warm-up and graph capture
+        best = math.inf
+        for r in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.run((r + 1) * shots, shots, status=status, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+        c = ctx.counters()
+        n = max(1, int(c["shots"]))
+        out.append({"p": p, "shots": shots, "seconds": best, "shots_per_s": shots / best,
+                    "discard_rate": c["discarded"] / n, "ler": c["logical_errors"] / max(1, c["passed"]),
+                    "t_entries_per_shot": c["entries_t"] / n, "events_per_shot": c["events"] / n,
+                    "noise_words_per_shot": c["noise_slots"] / n, "restarts": int(c["restarts"])})
+        ctx.close()
     return out
