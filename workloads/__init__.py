@@ -180,9 +180,12 @@ def _layers(pairs: list[tuple[int, int]]) -> list[list[tuple[int, int]]]:
 # ---------------------------------------------------------------------------
 def cultivation_shaped(seed: int, n_data: int, n_anc: int, r_z: int, brackets: list[int],
                        z_per_round: int | None = None, check_weight: int = 6, p: float = 1e-3,
-                       name: str | None = None) -> Workload:
+                       name: str | None = None, inverse_order: str = "same") -> Workload:
     """Data qubits 0..n_data-1, ancillas after them.  ``brackets`` lists the
-    size of each T layer (the first one of size n_data is transversal)."""
+    size of each T layer (the first one of size n_data is transversal).
+    ``inverse_order``: "same" writes each inverse layer in the order of its
+    layer; "shuffled" in a seeded random order; "shuffled_tick" also puts a
+    TICK (idle noise on the qubits not yet touched) in its middle."""
     rng = _rng(seed)
     r_x = n_data - 1 - r_z
     full = (1 << n_data) - 1
@@ -265,7 +268,13 @@ def cultivation_shaped(seed: int, n_data: int, n_anc: int, r_z: int, brackets: l
             rec += 1
         lines.append("TICK")
         lines += ["R %d" % a for a in za] + ["TICK"]
-        lines += ["%s %d" % (second, q) for q in Q] + ["TICK"]
+        inv = list(Q)
+        if inverse_order != "same":
+            inv = [inv[i] for i in rng.permutation(len(inv))]
+        inv_lines = ["%s %d" % (second, q) for q in inv]
+        if inverse_order == "shuffled_tick":
+            inv_lines.insert(len(inv_lines) // 2, "TICK")
+        lines += inv_lines + ["TICK"]
         # X-check round: ancilla in |+>, CNOT ancilla -> data, H, measure.
         xc = round_checks(hx, x_span, x_per_round)
         xa = anc[z_per_round:z_per_round + x_per_round]
