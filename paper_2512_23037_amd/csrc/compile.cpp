@@ -75,18 +75,25 @@ class FrameCompiler {
 
     // ---- Cliffords: x/z columns move, sign flips accumulate in acc_ ----
     void h(int a) {
+        sync();
         spec_touch(a);
         acc_ ^= cx_[a] & cz_[a];
         std::swap(cx_[a], cz_[a]);
     }
-    void s(int a) { acc_ ^= cx_[a] & cz_[a]; cz_[a] ^= cx_[a]; }
+    void s(int a) {
+        sync();
+        acc_ ^= cx_[a] & cz_[a];
+        cz_[a] ^= cx_[a];
+    }
     void sdg(int a) {
+        sync();
         RowMask notz = {~cz_[a].d, ~cz_[a].s};
         acc_ ^= cx_[a] & notz;
         cz_[a] ^= cx_[a];
     }
     // (X + Y)/sqrt2: X -> Y, Y -> X, Z -> -Z
     void hxy(int a) {
+        sync();
         spec_touch(a);
         RowMask notx = {~cx_[a].d, ~cx_[a].s};
         acc_ ^= cz_[a] & notx;
@@ -94,20 +101,27 @@ class FrameCompiler {
     }
     // (X - Y)/sqrt2: X -> -Y, Y -> -X, Z -> -Z
     void hnxy(int a) {
+        sync();
         spec_touch(a);
         acc_ ^= cx_[a] | cz_[a];
         cz_[a] ^= cx_[a];
     }
     void px(int a) {
+        sync();
         spec_touch(a);
         acc_ ^= cz_[a];
     }
-    void pz(int a) { acc_ ^= cx_[a]; }
+    void pz(int a) {
+        sync();
+        acc_ ^= cx_[a];
+    }
     void py(int a) {
+        sync();
         spec_touch(a);
         acc_ ^= cx_[a] ^ cz_[a];
     }
     void cnot(int a, int b) {
+        sync();
         spec_touch(b);  // Z_a commutes with CNOT(a -> b), Z_b does not
         RowMask t = cx_[b] ^ cz_[a];
         RowMask nt = {~t.d, ~t.s};
@@ -116,6 +130,7 @@ class FrameCompiler {
         cz_[a] ^= cz_[b];
     }
     void cz(int a, int b) {
+        sync();
         acc_ ^= cx_[a] & cx_[b] & (cz_[a] ^ cz_[b]);
         cz_[a] ^= cx_[b];
         cz_[b] ^= cx_[a];
@@ -124,6 +139,11 @@ class FrameCompiler {
     // ---- noise locations ----
     void noise(uint32_t kind, double p, int a, int b, uint32_t rec) {
         if (!(p > 0.0)) return;
+        // noise on qubits whose closing T is held back commutes with the
+        // other held-back T gates and stays after its own: it may wait
+        if (!buf_.empty() && !(kind != NZ_FLIP && a >= 0 && ((buf_mask_ >> a) & 1ull) &&
+                               (b < 0 || ((buf_mask_ >> b) & 1ull))))
+            sync();
         NoiseLoc L;
         std::memset(&L, 0, sizeof(L));
         L.thr = (uint64_t)std::floor(p * 4294967296.0);
@@ -144,6 +164,22 @@ class FrameCompiler {
 
     // ---- events ----
     void t_gate(int q, bool dagger, uint32_t src) {
+        if (spec_) {
+            // A T that undoes an open T on a qubit not yet held back joins the
+            // held-back layer; anything else ends the layer first.
+            const int idx = open_match(q, dagger);
+            if (idx >= 0 && !((buf_mask_ >> q) & 1ull)) {
+                if (buf_.empty()) buf_noise_ = (uint32_t)P_.noise.size();
+                buf_.push_back({q, dagger, src, (size_t)idx});
+                buf_mask_ |= bitq(q);
+                return;
+            }
+            sync();
+        }
+        emit_t(q, dagger, src);
+    }
+
+    void emit_t(int q, bool dagger, uint32_t src) {
         PauliStr Z;
         Z.z = bitq(q);
         const uint32_t k_before = (uint32_t)basis_.size();
@@ -187,12 +223,15 @@ class FrameCompiler {
             }
         }
         finish(E);
-        spec_after_t(q, dagger, k_before, src);
+        // coordinates this T's term needs: its new coordinate, or mu's top bit
+        const uint32_t need = E.kind == EV_T_DOUBLE ? k_before + 1u : E.kind == EV_T_BFLY ? E.tstar + 1u : 0u;
+        spec_after_t(q, dagger, k_before, src, need);
     }
 
     // Measurement of P (Hermitian, sign +); reset adds a conditional X_q.
     // reset_z: the reset flips with Z_q (X-basis reset) instead of X_q.
     void measure(const PauliStr &P, uint32_t mslot, int rec, int reset_q, uint32_t src, bool reset_z = false) {
+        sync();
         if ((P.x & open_mask_) || (reset_q >= 0 && !reset_z && ((open_mask_ >> reset_q) & 1ull))) spec_reset();
         Event E = begin(src);
         uint64_t beta, gamma;
@@ -285,6 +324,7 @@ class FrameCompiler {
     }
 
     void parity_check(bool detector, int expect, const std::vector<int> &recs, uint32_t obs, uint32_t src) {
+        sync();
         // fold the record list into (word, mask) pairs; repeats cancel
         std::vector<uint32_t> words, masks;
         for (int r : recs) {
@@ -329,6 +369,7 @@ class FrameCompiler {
 
     // Pauli (1 X, 2 Y, 3 Z) on qubit q when record bit `rec` is 1.
     void feedback(int pauli, int q, uint32_t rec, uint32_t src) {
+        sync();
         if (pauli != 3) spec_touch(q);
         Event E = begin(src);
         E.kind = EV_FEEDBACK;
@@ -345,6 +386,7 @@ class FrameCompiler {
     }
 
     void end(uint32_t src) {
+        sync();
         Event E = begin(src);
         E.kind = EV_END;
         finish(E);
@@ -367,14 +409,51 @@ class FrameCompiler {
     // coefficients back on coordinates < ckpt_k_: a DROP event returns the span
     // to that dimension (the kernel checks the entries above are zero and
     // restarts the shot on the full event list otherwise).
+    //
+    // A layer of such closing T gates on distinct qubits (with only noise on
+    // those qubits in between) is held back and emitted in the reverse order
+    // of the T gates it undoes: the gates commute, each one's noise stays
+    // after it (all of the layer's noise follows the layer), and undoing the
+    // latest T first lets the span shrink step by step: after each closing T,
+    // the still-open T gates need only the coordinates below the largest of
+    // their `need` values (and the checkpoint's), so a DROP returns the span
+    // there.
     struct OpenT {
         int q;
         bool dagger;
+        uint32_t need;  // coordinates its term reaches: new coordinate + 1, or mu's top bit + 1
+    };
+    struct HeldT {
+        int q;
+        bool dagger;
+        uint32_t src;
+        size_t open_idx;  // the open T it undoes
     };
     bool spec_;
     std::vector<OpenT> open_;
     uint64_t open_mask_ = 0;
     uint32_t ckpt_k_ = 0;
+    std::vector<HeldT> buf_;
+    uint64_t buf_mask_ = 0;
+    uint32_t buf_noise_ = 0;          // noise slots when the layer started
+    int64_t noise_end_override_ = -1;  // noise_end of events emitted from the held layer
+
+    int open_match(int q, bool dagger) const {
+        for (size_t i = open_.size(); i-- > 0;)
+            if (open_[i].q == q && open_[i].dagger != dagger) return (int)i;
+        return -1;
+    }
+    // Emit the held-back layer, latest-opened first.
+    void sync() {
+        if (buf_.empty()) return;
+        std::vector<HeldT> b;
+        b.swap(buf_);
+        buf_mask_ = 0;
+        std::sort(b.begin(), b.end(), [](const HeldT &x, const HeldT &y) { return x.open_idx > y.open_idx; });
+        noise_end_override_ = buf_noise_;
+        for (const HeldT &t : b) emit_t(t.q, t.dagger, t.src);
+        noise_end_override_ = -1;
+    }
 
     void spec_reset() {
         open_.clear();
@@ -383,25 +462,28 @@ class FrameCompiler {
     void spec_touch(int q) {
         if ((open_mask_ >> q) & 1ull) spec_reset();
     }
-    void spec_after_t(int q, bool dagger, uint32_t k_before, uint32_t src) {
+    void spec_after_t(int q, bool dagger, uint32_t k_before, uint32_t src, uint32_t need) {
         if (!spec_) return;
-        for (size_t i = open_.size(); i-- > 0;) {
-            if (open_[i].q == q && open_[i].dagger != dagger) {
-                open_.erase(open_.begin() + (long)i);
-                open_mask_ = 0;
-                for (const OpenT &o : open_) open_mask_ |= bitq(o.q);
-                if (open_.empty() && basis_.size() > ckpt_k_) {
-                    Event D = begin(src);
-                    D.kind = EV_DROP;
-                    D.mu = ckpt_k_;
-                    basis_.resize(ckpt_k_);
-                    finish(D);
-                }
-                return;
+        const int i = open_match(q, dagger);
+        if (i >= 0) {
+            open_.erase(open_.begin() + i);
+            open_mask_ = 0;
+            uint32_t keep = ckpt_k_;
+            for (const OpenT &o : open_) {
+                open_mask_ |= bitq(o.q);
+                keep = std::max(keep, o.need);
             }
+            if (basis_.size() > keep) {
+                Event D = begin(src);
+                D.kind = EV_DROP;
+                D.mu = keep;
+                basis_.resize(keep);
+                finish(D);
+            }
+            return;
         }
         if (open_.empty()) ckpt_k_ = k_before;
-        open_.push_back({q, dagger});
+        open_.push_back({q, dagger, need});
         open_mask_ |= bitq(q);
     }
 
@@ -501,7 +583,7 @@ class FrameCompiler {
         Event E;
         std::memset(&E, 0, sizeof(E));
         E.src = src;
-        E.noise_end = (uint32_t)P_.noise.size();
+        E.noise_end = noise_end_override_ >= 0 ? (uint32_t)noise_end_override_ : (uint32_t)P_.noise.size();
         E.k = (uint32_t)basis_.size();
         E.cliffD = acc_.d;
         E.cliffS = acc_.s;

@@ -631,8 +631,8 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             return fr;
         };
         // The speculative event list runs first (a traced shot takes the full
-        // list, so that every trace step exists); a failed DROP check restarts
-        // the shot on the full list.  A shot's draws depend only on its slots,
+        // list, so that every trace step exists); a failed DROP check, or a
+        // support above the cap, restarts the shot on the full list.  A shot's draws depend only on its slots,
         // so the restarted shot is the one the full list gives.
         bool full = tracing || !P.speculate || vdp->ev_off_full == vdp->ev_off;
         for (;;) {
@@ -745,6 +745,12 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 cnt = uni(cnt);
                 maxsup = max(maxsup, cnt);
                 if (cnt > P.support_cap) {
+                    // the speculative list visits other intermediate states:
+                    // the full list decides where (and whether) the cap is hit
+                    if (!full) {
+                        restart = true;
+                        break;
+                    }
                     status = ST_OVERFLOW;
                     abort_src = EV32(src);
                     term = e;

@@ -1,0 +1,68 @@
+"""GPU parity of the speculative event lists on bracket circuits: a T/T-dagger
+layer, a commuting check round, and the inverse layer in another order (held
+back and emitted latest-opened first, with the span dropped step by step),
+optionally with idle noise inside the inverse layer.  Results with speculation
+must equal the oracle's and the full list's bit for bit (FP64), caps that
+force OVERFLOW included."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_helpers import compare_batch, compare_kept, make_ctx, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+SHAPES = [(7, 8, 3, [7, 4], 4), (9, 6, 3, [9, 5], 6), (8, 6, 2, [8], 6), (10, 6, 3, [10, 6, 3], 6)]
+
+
+def bracket_circuit(seed: int):
+    """A small cultivation-shaped circuit whose inverse layers run in another
+    order than their layers (and, for every third seed, with a TICK inside)."""
+    nd, na, rz, br, w = SHAPES[seed % len(SHAPES)]
+    order = "shuffled_tick" if seed % 3 == 0 else "shuffled"
+    return workloads.cultivation_shaped(100 + seed, nd, na, rz, br, check_weight=w, inverse_order=order)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bracket_circuits_match_oracle_and_full_list(seed):
+    text = bracket_circuit(seed).text
+    p = [0.0, 0.002, 0.02][seed % 3]
+    noise = {"p1": p, "p2": p, "p_idle": p, "p_meas": p, "p_reset": p, "p_mpp": p}
+    circ = oracle.Circuit(text, noise)
+    N = 20000
+    ref = circ.batch(40 + seed, 0, N)
+    outs = {}
+    for spec in (True, False):
+        ctx = make_ctx(text, noise, seed=40 + seed, keep=(0, 64))
+        ctx.set_speculation(spec)
+        outs[spec] = run_gpu(ctx, 0, N)
+        compare_batch(outs[spec], ref)
+        compare_kept(ctx, circ, 40 + seed, range(64))
+        c = ctx.counters()
+        if not spec or p == 0.0:
+            assert c["restarts"] == 0
+        if spec and p == 0.02:
+            assert c["restarts"] > 0
+        ctx.close()
+    for key in ("status", "abort_op", "obs", "outcomes"):
+        assert (outs[True][key] == outs[False][key]).all()
+
+
+@pytest.mark.parametrize("seed", [1, 4, 7])
+def test_bracket_circuits_capped(seed):
+    # Caps below the layer's peak support: shots overflow in the T layer, and
+    # the speculative list (which visits other supports in the inverse layer)
+    # must report the full list's statuses and abort ops.
+    text = bracket_circuit(seed).text
+    noise = {"p1": 0.01, "p2": 0.01, "p_idle": 0.0, "p_meas": 0.01, "p_reset": 0.01, "p_mpp": 0.0}
+    circ = oracle.Circuit(text, noise)
+    N = 8000
+    for cap in (4, 16):
+        ref = circ.batch(9, 0, N, cap=cap)
+        ctx = make_ctx(text, noise, seed=9, cap=cap)
+        compare_batch(run_gpu(ctx, 0, N), ref)
+        ctx.close()
