@@ -169,6 +169,15 @@ __device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, c
     });
 }
 
+// Nonzero iff the complex value is not +-0 (sign bits shifted out).
+__device__ __forceinline__ uint32_t nonzero_bits(float2 x) {
+    return (__float_as_uint(x.x) | __float_as_uint(x.y)) << 1;
+}
+__device__ __forceinline__ uint32_t nonzero_bits(double2 x) {
+    const uint64_t b = ((uint64_t)__double_as_longlong(x.x) | (uint64_t)__double_as_longlong(x.y)) << 1;
+    return (uint32_t)(b >> 32) | (uint32_t)b;
+}
+
 constexpr uint32_t kNoHit = 0xFFFFFFFFu;
 
 // Lowest slot with a pending noise hit in the chunk based at cb (lane l holds
@@ -1005,13 +1014,27 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 }
             } else if (kind == EV_DROP) {
                 // ---- speculative span truncation: coordinates >= k0 must be empty ----
-                const uint32_t k0 = EV32(mu), cnt = 1u << k;
-                bool live = false;
-                for (uint32_t j = (1u << k0) + lane; j < cnt; j += 64u) {
-                    const C x = v[j];
-                    live = live || x.x != (R)0 || x.y != (R)0;
+                // every lane ORs the value bits of its entries at or above 2^k0
+                // (the shift drops the sign: -0 is empty too), one ballot
+                const uint32_t k0 = EV32(mu), cnt = 1u << k, lo = 1u << k0;
+                uint32_t live = 0;
+                uint32_t b = lo & ~63u;  // 64-entry blocks; the first may start below lo
+                if (b < lo) {
+                    const uint32_t j = b + lane;
+                    live = (j >= lo && j < cnt) ? nonzero_bits(v[j < cnt ? j : 0u]) : 0u;
+                    b += 64u;
                 }
-                if (__ballot(live) != 0ull) {
+                if (b < cnt) {  // whole blocks, four reads before they are combined
+                    const C *pb = v + b + lane;
+                    const uint32_t nb = (cnt - b) >> 6;
+                    uint32_t i = 0;
+                    for (; i + 4u <= nb; i += 4u) {
+                        const C x0 = pb[64u * i], x1 = pb[64u * i + 64u], x2 = pb[64u * i + 128u], x3 = pb[64u * i + 192u];
+                        live |= nonzero_bits(x0) | nonzero_bits(x1) | nonzero_bits(x2) | nonzero_bits(x3);
+                    }
+                    for (; i < nb; ++i) live |= nonzero_bits(pb[64u * i]);
+                }
+                if (__ballot(live != 0u) != 0ull) {
                     restart = true;
                     break;
                 }
