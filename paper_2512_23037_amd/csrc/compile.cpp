@@ -591,7 +591,9 @@ class FrameCompiler {
         P_.before.push_back(snapshot());
         return E;
     }
-    void finish(const Event &E) {
+    void finish(const Event &E0) {
+        Event E = E0;
+        if (E.cliffD || E.cliffS) E.flags |= EVF_CLIFF;
         P_.events.push_back(E);
         P_.after.push_back(snapshot());
         noise_at_finish_ = P_.noise.size();

@@ -54,6 +54,7 @@ enum EvFlags : uint32_t {
     EVF_RESET = 4u,    // reset: apply X_q (masks xD/xS) when the outcome is 1
     EVF_CHECK = 8u,    // a detector that directly follows this measurement
     EVF_BATCH = 16u,   // first of `bcnt` outcome-fixed measurements run side by side
+    EVF_CLIFF = 32u,   // cliffD or cliffS is nonzero
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane

@@ -531,7 +531,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // measurement words: slots [m_base, m_base + 256), one Philox block per lane
         uint32_t m_base = 0xFFFFFF00u, mw0 = 0, mw1 = 0, mw2 = 0, mw3 = 0;
 
-        const bool tracing = P.trace_n != 0u && shot == P.trace_shot;
+        // steps of this shot to trace (0 unless it is the traced shot)
+        const uint32_t trace_lim = uni(P.trace_n != 0u && shot == P.trace_shot ? P.trace_n : 0u);
+        const bool tracing = trace_lim != 0u;
         // noise tables of this variant (read where used: the draws are rare)
         const VariantDesc *vdp = P.vars + var;
 
@@ -675,7 +677,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         uint32_t e = 0;  // after the loop: the last event run
         for (;; ++e) {
             uint32_t evy = evl[(uint64_t)(e + 2u) * 64u + lane];
-            if (tracing && e > 0u && e - 1u < P.trace_n)  // state after event e-1
+            if (e - 1u < trace_lim)  // state after event e-1 (e = 0 wraps past any limit)
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
                            abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
@@ -698,8 +700,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 if (GAPS) draw_gap(); else draw_chunk();
             }
             // ---- Cliffords since the previous event: one XOR ----
-            rD ^= EV64(cliffD);
-            rS ^= EV64(cliffS);
+            const uint32_t flags = EV32(flags);
+            if (flags & EVF_CLIFF) {
+                rD ^= EV64(cliffD);
+                rS ^= EV64(cliffS);
+            }
             const uint32_t kind = EV32(kind);
             if (kind == EV_END) {
                 term = e;
@@ -750,7 +755,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
                     }
                 }
-                phase8 = (phase8 + ((EV32(flags) & EVF_TDG) ? 15u : 1u)) & 15u;
+                phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u)) & 15u;
                 cnt = uni(cnt);
                 maxsup = max(maxsup, cnt);
                 if (cnt > P.support_cap) {
@@ -766,7 +771,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     after = 1;
                     break;
                 }
-            } else if (kind == EV_M_DET && (EV32(flags) & EVF_BATCH) && !tracing) {
+            } else if (kind == EV_M_DET && (flags & EVF_BATCH) && !tracing) {
                 // ---- a run of outcome-fixed measurements, one member per lane ----
                 // Member i sees the signs rD, rS of the first member, the
                 // Clifford flips since then (cumD, cumS) and the noise hits
@@ -998,12 +1003,12 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     rS = (rS & ~(1ull << p)) | ((uint64_t)(bit ^ EV32(psign)) << p);
                     if ((a >> p) & 1ull) a ^= EV64(beta);
                 }
-                if ((EV32(flags) & EVF_RECORD) && bit) rec_toggle(EV32(rec) >> 5, 1u << (EV32(rec) & 31u));
-                if ((EV32(flags) & EVF_RESET) && bit) {
+                if ((flags & EVF_RECORD) && bit) rec_toggle(EV32(rec) >> 5, 1u << (EV32(rec) & 31u));
+                if ((flags & EVF_RESET) && bit) {
                     rD ^= EV64(xD);
                     rS ^= EV64(xS);
                 }
-                if (EV32(flags) & EVF_CHECK) {  // a detector folded into this event
+                if (flags & EVF_CHECK) {  // a detector folded into this event
                     if (parity_check()) {
                         status = ST_DISCARDED;
                         abort_src = EV32(chk_src);
@@ -1110,7 +1115,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
                        P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
         }
-        if (tracing && term < P.trace_n)
+        if (term < trace_lim)
             dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
                        lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
