@@ -65,7 +65,11 @@ typedef struct {
     uint64_t entries_m;          /* coefficient entries read by measurements */
     uint64_t noise_slots;        /* noise words drawn (256 per Philox refill of a wave) */
     uint64_t events;             /* T/T-dagger and measurements executed      */
-    uint64_t support_hist[16];   /* shots by floor(log2(max |v|)), last bin 15+ */
+    uint64_t support_hist[16];   /* shots by floor(log2(max |v|)), last bin 15+: the
+                                    largest support the kernel held (the speculative
+                                    lists may hold smaller ones than the circuit's
+                                    gate order; with speculation off they are the
+                                    circuit order's) */
     double max_norm_dev;         /* max over shots of |sum |v|^2 - 1| at the end */
     uint64_t restarts;           /* shots re-run on the full event list: the speculative
                                     list's span truncation found amplitude left (noise
@@ -151,10 +155,17 @@ int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
  * check rounds), the product of the pairs is the identity, so a shot whose
  * noise left the pairs intact has its coefficients back on the checkpoint's
  * span.  The compiler then emits a second event list that truncates the span
- * there; the kernel verifies that the dropped coordinates hold exact zeros
- * and otherwise restarts the shot on the full list (counted in
- * soft_counters.restarts).  Results are the full list's either way (up to
- * rounding order in the FP64 sums).  on = 0 runs the full list only. */
+ * there, and step by step as the inverse layer proceeds: it runs the
+ * commuting T gates of a layer in another order (cheapest first in a layer
+ * that opens, latest-opened first in one that closes; each gate's noise stays
+ * after it).  The kernel verifies that the dropped coordinates hold exact
+ * zeros and otherwise restarts the shot on the full list (counted in
+ * soft_counters.restarts).  Records, statuses, abort ops and observables are
+ * the full list's either way (coefficients up to rounding order); the support
+ * histogram is that of the supports the kernel held, which the other gate
+ * order can make smaller.  A run with a support cap (soft_set_caps) uses the
+ * full list only, so that the cap sees the circuit order's supports.  on = 0
+ * runs the full list only. */
 int soft_set_speculation(soft_ctx *ctx, int on);
 
 /* How noise hits are drawn (the same distribution either way: every noise

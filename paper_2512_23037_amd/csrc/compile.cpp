@@ -63,6 +63,26 @@ struct RowMask {
     RowMask &operator^=(const RowMask &o) { d ^= o.d; s ^= o.s; return *this; }
 };
 
+// A GF(2) span kept in reduced echelon form (each row has its own top bit,
+// which no other row has).
+struct Echelon {
+    std::vector<uint64_t> rows;
+    static uint64_t top(uint64_t v) { return 1ULL << (63 - __builtin_clzll(v)); }
+    uint64_t reduce(uint64_t v) const {
+        for (uint64_t r : rows)
+            if (v & top(r)) v ^= r;
+        return v;
+    }
+    bool contains(uint64_t v) const { return reduce(v) == 0; }
+    void add(uint64_t v) {
+        v = reduce(v);
+        if (!v) return;
+        for (uint64_t &r : rows)
+            if (r & top(v)) r ^= v;
+        rows.push_back(v);
+    }
+};
+
 // The shot-independent tableau, by column, plus the span and the event list.
 class FrameCompiler {
   public:
@@ -165,16 +185,19 @@ class FrameCompiler {
     // ---- events ----
     void t_gate(int q, bool dagger, uint32_t src) {
         if (spec_) {
-            // A T that undoes an open T on a qubit not yet held back joins the
-            // held-back layer; anything else ends the layer first.
+            // A T joins the held-back layer when its qubit is not in it yet
+            // and it is of the layer's kind (it undoes an open T, or it opens
+            // one); otherwise the layer is emitted first and a new one starts.
+            const bool closing = open_match(q, dagger) >= 0;
+            if (((buf_mask_ >> q) & 1ull) || (!buf_.empty() && closing != buf_closing_)) sync();
             const int idx = open_match(q, dagger);
-            if (idx >= 0 && !((buf_mask_ >> q) & 1ull)) {
-                if (buf_.empty()) buf_noise_ = (uint32_t)P_.noise.size();
-                buf_.push_back({q, dagger, src, (size_t)idx});
-                buf_mask_ |= bitq(q);
-                return;
+            if (buf_.empty()) {
+                buf_noise_ = (uint32_t)P_.noise.size();
+                buf_closing_ = idx >= 0;
             }
-            sync();
+            buf_.push_back({q, dagger, src, idx >= 0 ? (size_t)idx : 0u});
+            buf_mask_ |= bitq(q);
+            return;
         }
         emit_t(q, dagger, src);
     }
@@ -410,14 +433,17 @@ class FrameCompiler {
     // to that dimension (the kernel checks the entries above are zero and
     // restarts the shot on the full event list otherwise).
     //
-    // A layer of such closing T gates on distinct qubits (with only noise on
-    // those qubits in between) is held back and emitted in the reverse order
-    // of the T gates it undoes: the gates commute, each one's noise stays
-    // after it (all of the layer's noise follows the layer), and undoing the
-    // latest T first lets the span shrink step by step: after each closing T,
-    // the still-open T gates need only the coordinates below the largest of
-    // their `need` values (and the checkpoint's), so a DROP returns the span
-    // there.
+    // A layer of T gates on distinct qubits (with only noise on those qubits
+    // in between) is held back and emitted in another order: the gates
+    // commute, and each one's noise stays after it (all of the layer's noise
+    // follows the layer).  A layer that undoes open T gates goes latest-opened
+    // first, so the span can shrink step by step: after each closing T, the
+    // still-open T gates need only the coordinates below the largest of their
+    // `need` values (and the checkpoint's), so a DROP returns the span there.
+    // A layer that opens T gates goes cheapest first: a gate whose index
+    // shift already lies in the span (a butterfly over the current tile)
+    // before any that adds a coordinate (doubling the tile), and among the
+    // latter the one that brings the most remaining shifts into the span.
     struct OpenT {
         int q;
         bool dagger;
@@ -436,6 +462,7 @@ class FrameCompiler {
     std::vector<HeldT> buf_;
     uint64_t buf_mask_ = 0;
     uint32_t buf_noise_ = 0;          // noise slots when the layer started
+    bool buf_closing_ = false;        // the held layer undoes open T gates
     int64_t noise_end_override_ = -1;  // noise_end of events emitted from the held layer
 
     int open_match(int q, bool dagger) const {
@@ -449,9 +476,45 @@ class FrameCompiler {
         std::vector<HeldT> b;
         b.swap(buf_);
         buf_mask_ = 0;
-        std::sort(b.begin(), b.end(), [](const HeldT &x, const HeldT &y) { return x.open_idx > y.open_idx; });
         noise_end_override_ = buf_noise_;
-        for (const HeldT &t : b) emit_t(t.q, t.dagger, t.src);
+        if (buf_closing_) {
+            std::sort(b.begin(), b.end(), [](const HeldT &x, const HeldT &y) { return x.open_idx > y.open_idx; });
+            for (const HeldT &t : b) emit_t(t.q, t.dagger, t.src);
+        } else {
+            std::vector<uint64_t> shift(b.size());
+            for (size_t i = 0; i < b.size(); ++i) {
+                PauliStr Z;
+                Z.z = bitq(b[i].q);
+                uint64_t gamma;
+                int cexp;
+                decompose(Z, shift[i], gamma, cexp);
+            }
+            std::vector<bool> done(b.size(), false);
+            for (size_t n = 0; n < b.size(); ++n) {
+                Echelon span;
+                for (uint64_t v : basis_) span.add(v);
+                size_t pick = b.size();
+                for (size_t i = 0; i < b.size() && pick == b.size(); ++i)
+                    if (!done[i] && span.contains(shift[i])) pick = i;
+                if (pick == b.size()) {
+                    int best = -1;
+                    for (size_t i = 0; i < b.size(); ++i) {
+                        if (done[i]) continue;
+                        Echelon grown = span;
+                        grown.add(shift[i]);
+                        int inside = 0;
+                        for (size_t j = 0; j < b.size(); ++j)
+                            if (!done[j] && j != i && grown.contains(shift[j])) ++inside;
+                        if (inside > best) {
+                            best = inside;
+                            pick = i;
+                        }
+                    }
+                }
+                done[pick] = true;
+                emit_t(b[pick].q, b[pick].dagger, b[pick].src);
+            }
+        }
         noise_end_override_ = -1;
     }
 

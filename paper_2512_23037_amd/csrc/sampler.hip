@@ -645,7 +645,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // list, so that every trace step exists); a failed DROP check, or a
         // support above the cap, restarts the shot on the full list.  A shot's draws depend only on its slots,
         // so the restarted shot is the one the full list gives.
-        bool full = tracing || !P.speculate || vdp->ev_off_full == vdp->ev_off;
+        // (with a support cap the full list runs: the cap is defined by the
+        // supports of the circuit's own gate order)
+        bool full = tracing || !P.speculate || P.support_cap != 0xFFFFFFFFu || vdp->ev_off_full == vdp->ev_off;
         for (;;) {
         const uint32_t *evl = reinterpret_cast<const uint32_t *>(ev + (full ? vdp->ev_off_full : vdp->ev_off));
         for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64) rec[w] = 0u;
