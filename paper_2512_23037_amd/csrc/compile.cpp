@@ -10,6 +10,7 @@
 #include "compile.h"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 
@@ -82,6 +83,101 @@ struct Echelon {
         rows.push_back(v);
     }
 };
+
+// Tile entries a T writes at span dimension k: 2^k if its index shift lies
+// in the span (butterfly or phase), 2^(k+1) if it adds a coordinate.
+// cheap_order: an order of gates with index shifts `shift`, applied from the
+// span `basis`, with a small sum of those costs: the better of a greedy order
+// (a gate inside the span first, else the one that brings the most remaining
+// shifts into the span) and a beam search over partial orders (states with
+// the same span and the same gates left are merged).
+static uint64_t order_cost(const std::vector<uint64_t> &shift, const std::vector<uint64_t> &basis,
+                           const std::vector<size_t> &order) {
+    Echelon span;
+    for (uint64_t v : basis) span.add(v);
+    uint64_t c = 0;
+    for (size_t i : order) {
+        const size_t k = span.rows.size();
+        if (span.contains(shift[i])) {
+            c += 1ull << k;
+        } else {
+            c += 2ull << k;
+            span.add(shift[i]);
+        }
+    }
+    return c;
+}
+
+static std::vector<size_t> cheap_order(const std::vector<uint64_t> &shift, const std::vector<uint64_t> &basis) {
+    const size_t n = shift.size();
+    Echelon start;
+    for (uint64_t v : basis) start.add(v);
+    // greedy
+    std::vector<size_t> greedy;
+    {
+        Echelon span = start;
+        std::vector<bool> done(n, false);
+        for (size_t step = 0; step < n; ++step) {
+            size_t pick = n;
+            for (size_t i = 0; i < n && pick == n; ++i)
+                if (!done[i] && span.contains(shift[i])) pick = i;
+            if (pick == n) {
+                int best = -1;
+                for (size_t i = 0; i < n; ++i) {
+                    if (done[i]) continue;
+                    Echelon grown = span;
+                    grown.add(shift[i]);
+                    int inside = 0;
+                    for (size_t j = 0; j < n; ++j)
+                        if (!done[j] && j != i && grown.contains(shift[j])) ++inside;
+                    if (inside > best) {
+                        best = inside;
+                        pick = i;
+                    }
+                }
+            }
+            done[pick] = true;
+            span.add(shift[pick]);
+            greedy.push_back(pick);
+        }
+    }
+    if (n > 64) return greedy;
+    // beam search
+    struct State {
+        uint64_t cost;
+        Echelon span;
+        uint64_t left;  // bit i: gate i not placed yet
+        std::vector<size_t> order;
+    };
+    constexpr size_t kWidth = 256;
+    std::vector<State> beam{{0, start, n == 64 ? ~0ull : ((1ull << n) - 1ull), {}}};
+    for (size_t step = 0; step < n; ++step) {
+        std::map<std::pair<std::vector<uint64_t>, uint64_t>, State> next;
+        for (const State &st : beam) {
+            const size_t k = st.span.rows.size();
+            for (size_t i = 0; i < n; ++i) {
+                if (!((st.left >> i) & 1ull)) continue;
+                State nx{st.cost, st.span, st.left & ~(1ull << i), st.order};
+                if (nx.span.contains(shift[i])) {
+                    nx.cost += 1ull << k;
+                } else {
+                    nx.cost += 2ull << k;
+                    nx.span.add(shift[i]);
+                }
+                nx.order.push_back(i);
+                std::vector<uint64_t> key = nx.span.rows;
+                std::sort(key.begin(), key.end());
+                auto it = next.find({key, nx.left});
+                if (it == next.end() || nx.cost < it->second.cost) next[{key, nx.left}] = std::move(nx);
+            }
+        }
+        beam.clear();
+        for (auto &kv : next) beam.push_back(std::move(kv.second));
+        std::stable_sort(beam.begin(), beam.end(), [](const State &a, const State &b) { return a.cost < b.cost; });
+        if (beam.size() > kWidth) beam.resize(kWidth);
+    }
+    return beam[0].cost < order_cost(shift, basis, greedy) ? beam[0].order : greedy;
+}
 
 // The shot-independent tableau, by column, plus the span and the event list.
 class FrameCompiler {
@@ -440,10 +536,8 @@ class FrameCompiler {
     // first, so the span can shrink step by step: after each closing T, the
     // still-open T gates need only the coordinates below the largest of their
     // `need` values (and the checkpoint's), so a DROP returns the span there.
-    // A layer that opens T gates goes cheapest first: a gate whose index
-    // shift already lies in the span (a butterfly over the current tile)
-    // before any that adds a coordinate (doubling the tile), and among the
-    // latter the one that brings the most remaining shifts into the span.
+    // A layer that opens T gates goes in an order with few tile entries
+    // written (cheap_order).
     struct OpenT {
         int q;
         bool dagger;
@@ -489,31 +583,7 @@ class FrameCompiler {
                 int cexp;
                 decompose(Z, shift[i], gamma, cexp);
             }
-            std::vector<bool> done(b.size(), false);
-            for (size_t n = 0; n < b.size(); ++n) {
-                Echelon span;
-                for (uint64_t v : basis_) span.add(v);
-                size_t pick = b.size();
-                for (size_t i = 0; i < b.size() && pick == b.size(); ++i)
-                    if (!done[i] && span.contains(shift[i])) pick = i;
-                if (pick == b.size()) {
-                    int best = -1;
-                    for (size_t i = 0; i < b.size(); ++i) {
-                        if (done[i]) continue;
-                        Echelon grown = span;
-                        grown.add(shift[i]);
-                        int inside = 0;
-                        for (size_t j = 0; j < b.size(); ++j)
-                            if (!done[j] && j != i && grown.contains(shift[j])) ++inside;
-                        if (inside > best) {
-                            best = inside;
-                            pick = i;
-                        }
-                    }
-                }
-                done[pick] = true;
-                emit_t(b[pick].q, b[pick].dagger, b[pick].src);
-            }
+            for (size_t i : cheap_order(shift, basis_)) emit_t(b[i].q, b[i].dagger, b[i].src);
         }
         noise_end_override_ = -1;
     }
