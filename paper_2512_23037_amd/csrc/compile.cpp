@@ -607,11 +607,20 @@ class FrameCompiler {
                 keep = std::max(keep, o.need);
             }
             if (basis_.size() > keep) {
-                Event D = begin(src);
-                D.kind = EV_DROP;
-                D.mu = keep;
-                basis_.resize(keep);
-                finish(D);
+                Event &last = P_.events.back();  // the closing T just emitted
+                if (keep + 1u == basis_.size() && last.kind == EV_T_BFLY && last.tstar + 1u == basis_.size()) {
+                    // the butterfly's partner outputs are exactly the top
+                    // coordinate's half: its pass checks them, no DROP event
+                    last.flags |= EVF_DROP1;
+                    basis_.resize(keep);
+                    P_.after.back() = snapshot();
+                } else {
+                    Event D = begin(src);
+                    D.kind = EV_DROP;
+                    D.mu = keep;
+                    basis_.resize(keep);
+                    finish(D);
+                }
             }
             return;
         }

@@ -55,6 +55,8 @@ enum EvFlags : uint32_t {
     EVF_CHECK = 8u,    // a detector that directly follows this measurement
     EVF_BATCH = 16u,   // first of `bcnt` outcome-fixed measurements run side by side
     EVF_CLIFF = 32u,   // cliffD or cliffS is nonzero
+    EVF_DROP1 = 64u,   // speculative: after this butterfly (mu's top bit k-1) coordinate k-1 must be
+                       // empty, i.e. no partner output kept; then k -> k-1
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane

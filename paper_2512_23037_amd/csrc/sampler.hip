@@ -262,9 +262,11 @@ __device__ __forceinline__ uint32_t next_j(uint32_t J, uint32_t M) { return ((J 
 // the iteration bits of a coordinate are disjoint, so each lane keeps two base
 // pointers for the event (j0's and j1's lane parts, h set in j1's) and an
 // iteration adds one uniform byte offset to each.
+// Returns the kept outputs; `cnt1` receives those at the partner coordinates
+// j0 ^ mu (bit h set).
 template <uint32_t Q, typename R, typename C>
 __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
-                                           uint32_t sig, R tn, R thr) {
+                                           uint32_t sig, R tn, R thr, uint32_t &cnt1) {
     const uint32_t npairs = 1u << (k - 1u);
     // With fewer than 64 pairs the spare lanes repeat a live lane's pair (same
     // values to the same addresses) and are left out of the counts, so the
@@ -279,6 +281,7 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     const R c1 = ((sig ^ par32(g & lc)) != 0u) ? -tn : tn;   // weight of v_j0 in v'_j1
     const R c0 = par32(g & mu) ? -c1 : c1;                   // weight of v_j1 in v'_j0
     uint32_t cnt = 0;
+    cnt1 = 0;
     const uint32_t iters = (npairs + 63u) >> 6;
     // one iteration with the Q or (S = 2) the Q + 2 form, in two halves so
     // that a pair of iterations issues all its LDS reads before any write
@@ -290,7 +293,9 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
         bool k0, k1;
         const C o0 = t_out<QS, R, C>(v0, v1, c0, thr, k0);
         const C o1 = t_out<QS, R, C>(v1, v0, c1, thr, k1);
-        cnt += (uint32_t)__popcll(__ballot(k0) & live) + (uint32_t)__popcll(__ballot(k1) & live);
+        const uint32_t n1 = (uint32_t)__popcll(__ballot(k1) & live);
+        cnt += (uint32_t)__popcll(__ballot(k0) & live) + n1;
+        cnt1 += n1;
         *addr0(J) = o0;
         *addr1(J) = o1;
     };
@@ -516,9 +521,19 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         };
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
-        uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
         double nrm2 = 1.0;
         double tscale2 = 1.0;  // |state|^2 = tscale2 |tile|^2 (branching T leave cos(pi/8) out)
+        // After a span truncation down to one entry, whose exact state has unit
+        // norm: rescale it in FP64 (the cuts the full list runs next do the same).
+        auto renorm_single = [&]() {
+            const C x = v[0];
+            const double q = nrm<R>(x);
+            const R sc = (R)(1.0 / sqrt(q));
+            if (lane == 0) v[0] = scale(x, sc);
+            nrm2 = q * (double)sc * (double)sc;
+            tscale2 = 1.0;
+        };
+        uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
         uint32_t status = ST_PASSED, abort_src = 0xFFFFFFFFu, obs = 0, maxsup = 1;
         uint32_t term = 0, after = 0;
         // noise per slot: 256 slots per chunk, 4 consecutive slots (one Philox
@@ -739,7 +754,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 tscale2 *= EVD(Cs2);
                 const R thr = (R)(tau2 * nrm2 / tscale2);
                 const uint32_t qb = EV32(qb);
-                uint32_t cnt;
+                uint32_t cnt, upper = 0;
                 if (kind == EV_T_DOUBLE) {
                     switch (qb) {
                         case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, tn, thr); break;
@@ -751,10 +766,10 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 } else {
                     const uint32_t mu = EV32(mu), h = EV32(tstar);
                     switch (qb) {
-                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
-                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
-                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
-                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr); break;
+                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
+                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
+                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
+                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
                     }
                 }
                 phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u)) & 15u;
@@ -772,6 +787,15 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     term = e;
                     after = 1;
                     break;
+                }
+                if (flags & EVF_DROP1) {
+                    // speculative: the top coordinate (the partner half) must be empty
+                    if (uni(upper) != 0u) {
+                        restart = true;
+                        break;
+                    }
+                    --k;
+                    if (k == 0u) renorm_single();
                 }
             } else if (kind == EV_M_DET && (flags & EVF_BATCH) && !tracing) {
                 // ---- a run of outcome-fixed measurements, one member per lane ----
@@ -1046,16 +1070,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     break;
                 }
                 k = k0;
-                if (k0 == 0u) {
-                    // One entry is left and the exact state has unit norm: rescale
-                    // it in FP64 (the cuts the full list runs next do the same).
-                    const C x = v[0];
-                    const double q = nrm<R>(x);
-                    const R sc = (R)(1.0 / sqrt(q));
-                    if (lane == 0) v[0] = scale(x, sc);
-                    nrm2 = q * (double)sc * (double)sc;
-                    tscale2 = 1.0;
-                }
+                if (k0 == 0u) renorm_single();
             } else if (kind == EV_FEEDBACK) {
                 // ---- classically controlled Pauli: the record bit is a one-pair check ----
                 if (parity_check()) {

@@ -177,7 +177,7 @@ int compile_variant(soft_ctx *c, Variant &V) {
     V.fast = Program();
     if ((rc = compile_into(c, V.text, V.noise, V.fast, true))) return rc;
     for (const Event &E : V.fast.events)
-        if (E.kind == EV_DROP) V.has_fast = true;
+        if (E.kind == EV_DROP || (E.flags & EVF_DROP1)) V.has_fast = true;
     if (!V.has_fast) V.fast = Program();
     return SOFT_OK;
 }
