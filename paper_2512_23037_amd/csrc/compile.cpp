@@ -326,6 +326,7 @@ class FrameCompiler {
             // cos theta v + sin theta i^qb c' v_partner with i^qb = (-i s) i^cexp.
             E.Tn = sn / cs;
             E.Cs2 = cs * cs;
+            E.iCs2 = 1.0 / E.Cs2;
             E.Tnf = (float)E.Tn;
             E.qb = (uint32_t)((cexp + (dagger ? 1 : 3)) & 3);
             uint32_t mu;

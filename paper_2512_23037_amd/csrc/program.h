@@ -105,7 +105,8 @@ struct alignas(16) Event {
     uint64_t cum_t, cum_m;
     float Tnf;                // Tn in single precision
     uint32_t cum_e;
-    uint32_t pad1[4];
+    double iCs2;              // 1 / Cs2
+    uint32_t pad1[2];
 };
 static_assert(sizeof(Event) == 256, "event layout");
 

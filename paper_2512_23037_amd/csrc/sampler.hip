@@ -522,7 +522,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
         double nrm2 = 1.0;
-        double tscale2 = 1.0;  // |state|^2 = tscale2 |tile|^2 (branching T leave cos(pi/8) out)
+        // |tile|^2 = itscale2 |state|^2: branching T leave cos(pi/8) out of the
+        // tile (kept as the inverse factor, so a T multiplies instead of divides)
+        double itscale2 = 1.0;
         // After a span truncation down to one entry, whose exact state has unit
         // norm: rescale it in FP64 (the cuts the full list runs next do the same).
         auto renorm_single = [&]() {
@@ -531,7 +533,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             const R sc = (R)(1.0 / sqrt(q));
             if (lane == 0) v[0] = scale(x, sc);
             nrm2 = q * (double)sc * (double)sc;
-            tscale2 = 1.0;
+            itscale2 = 1.0;
         };
         uint32_t phase8 = 0;  // global phase e^{i pi phase8 / 8} from branching T gates
         uint32_t status = ST_PASSED, abort_src = 0xFFFFFFFFu, obs = 0, maxsup = 1;
@@ -551,6 +553,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         const bool tracing = trace_lim != 0u;
         // noise tables of this variant (read where used: the draws are rare)
         const VariantDesc *vdp = P.vars + var;
+        const uint32_t n_slots = uni(vdp->n_noise);
 
         // Draw the next 256 noise slots: one Philox block of 4 words per lane.
         auto draw_chunk = [&]() {
@@ -673,7 +676,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         k = 0;
         phase8 = 0;
         nrm2 = 1.0;
-        tscale2 = 1.0;
+        itscale2 = 1.0;
         status = ST_PASSED;
         abort_src = 0xFFFFFFFFu;
         obs = 0;
@@ -697,7 +700,8 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             if (e - 1u < trace_lim)  // state after event e-1 (e = 0 wraps past any limit)
                 dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
                            P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
-                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
+                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u,
+                           1.0 / itscale2);
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
@@ -713,7 +717,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     rS ^= dS;
                     if (fr != kNoHit) rec_toggle(fr >> 5, 1u << (fr & 31u));
                 }
-                if (nend <= nz_drawn || nz_drawn >= vdp->n_noise) break;
+                if (nend <= nz_drawn || nz_drawn >= n_slots) break;
                 if (GAPS) draw_gap(); else draw_chunk();
             }
             // ---- Cliffords since the previous event: one XOR ----
@@ -751,8 +755,8 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 const uint32_t sig = sc ^ ga;
                 // T is unitary: the carried norm stays, and it sets the pruning
                 // level, on the tile's scale once cos^2(pi/8) joins the factor
-                tscale2 *= EVD(Cs2);
-                const R thr = (R)(tau2 * nrm2 / tscale2);
+                itscale2 *= EVD(iCs2);
+                const R thr = (R)(tau2 * nrm2 * itscale2);
                 const uint32_t qb = EV32(qb);
                 uint32_t cnt, upper = 0;
                 if (kind == EV_T_DOUBLE) {
@@ -821,7 +825,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                             myS ^= dS;
                         }
                     }
-                    if (nlast <= nz_drawn || nz_drawn >= vdp->n_noise) break;
+                    if (nlast <= nz_drawn || nz_drawn >= n_slots) break;
                     if (GAPS) draw_gap(); else draw_chunk();
                 }
                 const uint64_t beta = ((uint64_t)q0.y << 32) | q0.x, gamma = ((uint64_t)q0.w << 32) | q0.z;
@@ -944,7 +948,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         v[jp] = x;
                     });
                     nrm2 = wave_sum(nn);
-                    tscale2 = 1.0;
+                    itscale2 = 1.0;
                     --k;
                     if (bsel) a ^= EV64(avec);
                 } else if (kind == EV_M_SPLIT) {
@@ -953,7 +957,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     const uint32_t fs = bit ^ sc ^ ga ^ EV32(gbeta);
                     const uint32_t q0 = (4u - EV32(cexp)) & 3u;
                     const uint32_t cnt = 1u << k, pm = EV32(pm);
-                    const R s = (R)sqrt(tscale2 / nrm2);
+                    const R s = (R)(1.0 / sqrt(itscale2 * nrm2));
                     const C z = mk<C>(0.0, 0.0);
                     double nn = 0.0;
                     lane_pass(cnt, lane, [&](uint32_t j) {
@@ -967,7 +971,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         v[j] = x;
                     });
                     nrm2 = wave_sum(nn);
-                    tscale2 = 1.0;
+                    itscale2 = 1.0;
                 } else {  // EV_M_MERGE
                     const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
                     const uint32_t q0 = (4u - EV32(cexp)) & 3u;
@@ -1016,7 +1020,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         v[p] = o;
                     });
                     nrm2 = wave_sum(nn);
-                    tscale2 = 1.0;
+                    itscale2 = 1.0;
                     --k;
                 }
                 if (kind == EV_M_SPLIT || kind == EV_M_MERGE) {
@@ -1116,7 +1120,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         double nn = 0.0;
         lane_pass(cnt, lane, [&](uint32_t j) { nn += nrm<R>(v[j]); });
         nn = wave_sum(nn);
-        maxdev = fmax(maxdev, fabs(nn * tscale2 - 1.0));
+        maxdev = fmax(maxdev, fabs(nn / itscale2 - 1.0));
         {
             // one store for the record words held in scalar registers and the
             // three per-shot words; record words in LDS follow
@@ -1130,11 +1134,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
             const uint64_t kk = shot - P.keep_lo;
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
-                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
+                       P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, 1.0 / itscale2);
         }
         if (term < trace_lim)
             dump_state(P.trace_meta + (uint64_t)term * KM_COUNT, P.trace_v + (uint64_t)term * P.tile_entries * 2u, v,
-                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, tscale2);
+                       lane, P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, 1.0 / itscale2);
         const uint32_t bucket = min(15u, 31u - (uint32_t)__clz(maxsup));
         myc += (lane == C_SHOTS) + (lane == C_PASSED + status) +
                (lane == C_LOGICAL && status == ST_PASSED && obs != 0u) + (lane == C_HIST0 + bucket);
