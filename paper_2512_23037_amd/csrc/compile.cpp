@@ -341,11 +341,32 @@ class FrameCompiler {
                     throw CompileError{0, "coefficient span dimension exceeds " + std::to_string(kMaxSpanDim)};
                 if (basis_.size() > P_.kmax) P_.kmax = (uint32_t)basis_.size();
             }
+            pass_shape(E);
         }
         finish(E);
         // coordinates this T's term needs: its new coordinate, or mu's top bit
         const uint32_t need = E.kind == EV_T_DOUBLE ? k_before + 1u : E.kind == EV_T_BFLY ? E.tstar + 1u : 0u;
         spec_after_t(q, dagger, k_before, src, need);
+    }
+
+    // The branching T pass runs its entries 64 lanes at a time; iteration
+    // bit u sets coordinate bit pos(u) (a new coordinate: u + 6; a butterfly:
+    // the bits outside the lane bits and tstar).  The iterations' signs
+    // (-1)^(g . J) pair up on the lowest such bit in g.
+    static void pass_shape(Event &E) {
+        const bool bfly = E.kind == EV_T_BFLY;
+        const uint32_t h = bfly ? E.tstar : 32u;
+        const uint32_t entries = bfly ? (1u << (E.k - 1u)) : (1u << E.k);
+        const uint32_t iters = (entries + 63u) >> 6;
+        E.tpair = 0;
+        for (uint32_t u = 0; (1u << u) < iters; ++u) {
+            const uint32_t b = u + 6u < h ? u + 6u : u + 7u;
+            if ((E.g >> b) & 1u) {
+                E.tpair = 1u << b;
+                break;
+            }
+        }
+        E.lmask = bfly ? (((63u >> h) << (h + 1u)) | (63u & ((1u << h) - 1u))) : 63u;
     }
 
     // Measurement of P (Hermitian, sign +); reset adds a conditional X_q.

@@ -106,7 +106,10 @@ struct alignas(16) Event {
     float Tnf;                // Tn in single precision
     uint32_t cum_e;
     double iCs2;              // 1 / Cs2
-    uint32_t pad1[2];
+    // Branching T pass shape, fixed by k and the event: the coordinate bit
+    // that pairs the pass's 64-lane iterations by sign (0: all signs +1), and
+    // (BFLY) the coordinate bits a lane index occupies, ins0(63, tstar).
+    uint32_t tpair, lmask;
 };
 static_assert(sizeof(Event) == 256, "event layout");
 

@@ -242,14 +242,9 @@ template <uint32_t Q, typename R, typename C> __device__ __forceinline__ C t_new
 // Otherwise, with t the lowest iteration bit whose coordinate bit is in g,
 // iterations it and it ^ 2^t have opposite signs: each such pair runs one Q
 // and one Q + 2 update, and which is which is a scalar choice.
-// The coordinate bit that pairs the iterations: the lowest coordinate bit in
-// g that some iteration sets, or 0 when every iteration has sign +1.  `pos`
-// maps iteration bit u to its coordinate bit.
-template <typename Pos> __device__ __forceinline__ uint32_t pair_bit(uint32_t g, uint32_t iters, Pos &&pos) {
-    for (uint32_t u = 0; (1u << u) < iters; ++u)
-        if ((g >> pos(u)) & 1u) return 1u << pos(u);
-    return 0u;
-}
+// The coordinate bit that pairs the iterations (`pb`: the lowest coordinate
+// bit in g that some iteration sets, or 0 when every iteration has sign +1)
+// depends only on the event and k, and comes with the event.
 
 // The iterations' coordinate bits J run over the values with the bits of M
 // clear (M holds the lane bits and any skipped bit): J -> ((J | M) + 1) & ~M
@@ -266,7 +261,8 @@ __device__ __forceinline__ uint32_t next_j(uint32_t J, uint32_t M) { return ((J 
 // j0 ^ mu (bit h set).
 template <uint32_t Q, typename R, typename C>
 __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
-                                           uint32_t sig, R tn, R thr, uint32_t &cnt1) {
+                                           uint32_t sig, R tn, R thr, uint32_t pb, uint32_t lmask,
+                                           uint32_t &cnt1) {
     const uint32_t npairs = 1u << (k - 1u);
     // With fewer than 64 pairs the spare lanes repeat a live lane's pair (same
     // values to the same addresses) and are left out of the counts, so the
@@ -274,7 +270,7 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     const uint32_t lp = npairs >= 64u ? lane : (lane & (npairs - 1u));
     const uint64_t live = npairs >= 64u ? ~0ull : ((1ull << npairs) - 1ull);
     const uint32_t lc = ins0(lp, h);
-    const uint32_t lmask = ins0(63u, h), hb = 1u << h;  // mu's top bit is h
+    const uint32_t hb = 1u << h;  // mu's top bit is h; lmask = ins0(63, h)
     const uint32_t mu_l = mu & lmask, mu_i = mu & ~(lmask | hb);
     char *const p0 = reinterpret_cast<char *>(v + lc);
     char *const p1 = reinterpret_cast<char *>(v + ((lc ^ mu_l) | hb));
@@ -302,7 +298,6 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     auto step = [&](uint32_t J, auto S) { finish(J, *addr0(J), *addr1(J), S); };
     // the iterations' coordinate bits J = ins0(64 it, h): everything outside
     // the lane bits and bit h
-    const uint32_t pb = pair_bit(g, iters, [&](uint32_t u) { return u + 6u < h ? u + 6u : u + 7u; });
     uint32_t J = 0;
     if (pb == 0u) {
         if (iters == 1u) {
@@ -349,7 +344,7 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
 // v'_{j+2^k} = tn i^Q (-1)^(sig ^ g.j) v_j.
 template <uint32_t Q, typename R, typename C>
 __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R tn,
-                                             R thr) {
+                                             R thr, uint32_t pb) {
     const uint32_t half = 1u << k;
     // spare lanes repeat a live lane (see t_bfly)
     const uint32_t lp = half >= 64u ? lane : (lane & (half - 1u));
@@ -371,7 +366,6 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
         *addr0(J) = o0;
         *addr1(J) = o1;
     };
-    const uint32_t pb = pair_bit(g, iters, [](uint32_t u) { return u + 6u; });
     if (iters == 1u) {
         finish(0u, *addr0(0u), std::integral_constant<uint32_t, 0>());
     } else if (pb == 0u) {
@@ -731,12 +725,12 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 term = e;
                 break;
             }
-            const uint32_t sc = par64(rD & EV64(beta)) ^ par64(rS & EV64(gamma));  // sign part of c
-            const uint32_t ga = par64(EV64(gamma) & a);                          // gamma . a
+            // sign part of c, plus gamma . a (always used together): one parity
+            const uint32_t sga = par64((rD & EV64(beta)) ^ ((rS ^ a) & EV64(gamma)));
             const uint32_t g = EV32(g);
             if (kind == EV_T_PHASE) {
                 // lambda_j = (-1)^(sig ^ parity(g & j)); lambda = -1 picks up e^{i s pi/4}
-                const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
+                const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sga;
                 const R fr = (R)EVD(Are), fi = (R)EVD(Aim);
                 const uint32_t cnt = 1u << k;
                 if (g != 0u || sig) {
@@ -752,28 +746,28 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 }
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
                 const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
-                const uint32_t sig = sc ^ ga;
+                const uint32_t sig = sga;
                 // T is unitary: the carried norm stays, and it sets the pruning
                 // level, on the tile's scale once cos^2(pi/8) joins the factor
                 itscale2 *= EVD(iCs2);
                 const R thr = (R)(tau2 * nrm2 * itscale2);
-                const uint32_t qb = EV32(qb);
+                const uint32_t qb = EV32(qb), pb = EV32(tpair);
                 uint32_t cnt, upper = 0;
                 if (kind == EV_T_DOUBLE) {
                     switch (qb) {
-                        case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, tn, thr); break;
-                        case 1: cnt = t_double<1, R, C>(v, lane, k, g, sig, tn, thr); break;
-                        case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, tn, thr); break;
-                        default: cnt = t_double<3, R, C>(v, lane, k, g, sig, tn, thr); break;
+                        case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
+                        case 1: cnt = t_double<1, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
+                        case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
+                        default: cnt = t_double<3, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
                     }
                     ++k;
                 } else {
-                    const uint32_t mu = EV32(mu), h = EV32(tstar);
+                    const uint32_t mu = EV32(mu), h = EV32(tstar), lm = EV32(lmask);
                     switch (qb) {
-                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
-                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
-                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
-                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr, upper); break;
+                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
                     }
                 }
                 phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u)) & 15u;
@@ -910,9 +904,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 }
                 uint32_t bit = 0;
                 if (kind == EV_M_DET) {
-                    bit = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
+                    bit = (EV32(cexp) == 2u ? 1u : 0u) ^ sga;
                 } else if (kind == EV_M_CUT) {
-                    const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sc ^ ga;
+                    const uint32_t sig = (EV32(cexp) == 2u ? 1u : 0u) ^ sga;
                     const uint32_t cnt = 1u << k;
                     double n0 = 0.0, n1 = 0.0;
                     lane_pass(cnt, lane, [&](uint32_t j) {
@@ -954,7 +948,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 } else if (kind == EV_M_SPLIT) {
                     bit = u < 0.5 ? 0u : 1u;
                     const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
-                    const uint32_t fs = bit ^ sc ^ ga ^ EV32(gbeta);
+                    const uint32_t fs = bit ^ sga ^ EV32(gbeta);
                     const uint32_t q0 = (4u - EV32(cexp)) & 3u;
                     const uint32_t cnt = 1u << k, pm = EV32(pm);
                     const R s = (R)(1.0 / sqrt(itscale2 * nrm2));
@@ -976,7 +970,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     const uint32_t ap = (uint32_t)(a >> EV32(pbit)) & 1u;
                     const uint32_t q0 = (4u - EV32(cexp)) & 3u;
                     const uint32_t npairs = 1u << (k - 1u), mu = EV32(mu), h = EV32(tstar), pm = EV32(pm);
-                    const uint32_t fs0 = sc ^ ga;
+                    const uint32_t fs0 = sga;
                     double np = 0.0, nm = 0.0;
                     lane_pass(npairs, lane, [&](uint32_t p) {
                         const uint32_t j0 = ins0(p, h), j1 = j0 ^ mu;
