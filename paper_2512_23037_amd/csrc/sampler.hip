@@ -390,6 +390,16 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
 }
 
 
+// floor(x / d) for x < 16 d (a noise hit's Pauli code from its word): a
+// binary search on exact integer compares instead of a 64-bit division.
+__device__ __forceinline__ uint32_t quot16(uint64_t x, uint64_t d) {
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t b = 8; b != 0u; b >>= 1)
+        if (x >= (uint64_t)(m + b) * d) m += b;
+    return m;
+}
+
 // Fields of the current event (held one dword per lane in `evc`).
 #define EV32(f) ((uint32_t)__builtin_amdgcn_readlane((int)evc, (int)(offsetof(Event, f) / 4u)))
 #define EV64(f)                                                                                  \
@@ -629,9 +639,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             if (nkind == NZ_DEP1 || nkind == NZ_DEP2 || nkind == NZ_XERR || nkind == NZ_ZERR) {
                 uint32_t ca, cb = 0;
                 if (nkind == NZ_DEP1) {
-                    ca = (uint32_t)((3ull * wv) / thr) + 1u;
+                    ca = quot16(3ull * wv, thr) + 1u;  // wv < thr
                 } else if (nkind == NZ_DEP2) {
-                    const uint32_t code = (uint32_t)((15ull * wv) / thr) + 1u;
+                    const uint32_t code = quot16(15ull * wv, thr) + 1u;
                     ca = code >> 2;
                     cb = code & 3u;
                 } else {
