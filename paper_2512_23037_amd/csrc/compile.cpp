@@ -907,6 +907,58 @@ uint64_t fnv1a(const void *data, size_t len, uint64_t h) {
 
 }  // namespace
 
+// Speculative lists: a run of T doublings with no noise slot and no Clifford
+// sign flip between them, whose final tile has at most 64 entries, runs as one
+// pass (EVF_TRUN on the first; the members stay in the list, so the work
+// counts do not change, and the kernel skips them).  Final entry J comes from
+// entry J mod 2^k turned by i^{r_J + 2 (dynamic signs of the members whose
+// coordinate J sets)} and multiplied by tan(pi/8) once per such member, in
+// member order (the products of the separate passes, rounding included).
+static void fuse_doublings(Program &P) {
+    std::vector<Event> &ev = P.events;
+    for (size_t s = 0; s < ev.size();) {
+        Event &A = ev[s];
+        if (A.kind != EV_T_DOUBLE || (A.flags & ~(EVF_TDG | EVF_CLIFF)) != 0u) {
+            ++s;
+            continue;
+        }
+        size_t m = 1;
+        while (s + m < ev.size() && A.k + m + 1u <= 6u) {
+            const Event &B = ev[s + m];
+            if (B.kind != EV_T_DOUBLE || (B.flags & ~EVF_TDG) != 0u || B.noise_end != A.noise_end ||
+                B.k != A.k + m || std::memcmp(&B.Tn, &A.Tn, sizeof(double)) != 0 ||
+                std::memcmp(&B.iCs2, &A.iCs2, sizeof(double)) != 0)
+                break;
+            ++m;
+        }
+        if (m < 2) {
+            ++s;
+            continue;
+        }
+        const uint32_t k0 = A.k, K = A.k + (uint32_t)m;
+        uint64_t r0 = 0, r1 = 0;
+        uint32_t ph = 0;
+        for (uint32_t J = 0; J < (1u << K); ++J) {
+            uint32_t r = 0;
+            for (uint32_t i = 0; i < m; ++i) {
+                if (!((J >> (k0 + i)) & 1u)) continue;
+                const Event &B = ev[s + i];
+                const uint32_t j = J & ((1u << (k0 + i)) - 1u);
+                r += B.qb + 2u * (uint32_t)(__builtin_popcount(B.g & j) & 1);
+            }
+            r0 |= (uint64_t)(r & 1u) << J;
+            r1 |= (uint64_t)((r >> 1) & 1u) << J;
+        }
+        for (size_t i = 0; i < m; ++i) ph += (ev[s + i].flags & EVF_TDG) ? 15u : 1u;
+        A.flags |= EVF_TRUN;
+        A.bcnt = (uint32_t)m;
+        A.boff = ph & 15u;
+        A.trot0 = r0;
+        A.trot1 = r1;
+        s += m;
+    }
+}
+
 // Running work counts of the event list (see Event::cum_t): the span
 // dimension before each event is the same in every shot, so the work of a
 // shot that stops after event e is the sum over the events up to e.
@@ -1121,6 +1173,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     }
     fc.end(src);
     form_batches(out);
+    if (speculate) fuse_doublings(out);
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
     work_sums(out);

@@ -57,6 +57,8 @@ enum EvFlags : uint32_t {
     EVF_CLIFF = 32u,   // cliffD or cliffS is nonzero
     EVF_DROP1 = 64u,   // speculative: after this butterfly (mu's top bit k-1) coordinate k-1 must be
                        // empty, i.e. no partner output kept; then k -> k-1
+    EVF_TRUN = 128u,   // speculative: first of `bcnt` doublings with nothing between them, run as one
+                       // pass (k + bcnt <= 6: one final entry per lane); the others are skipped
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane
@@ -86,13 +88,23 @@ struct alignas(16) Event {
     uint32_t det_cnt;    //   number of pairs
     uint32_t chk_src;    //   op index of a folded detector
     uint32_t dw0, dm0;   //   the first pair, inline
-    uint32_t bcnt;       // EVF_BATCH: number of members (events e .. e + bcnt - 1)
-    uint32_t boff;       //   their first record in the member table
+    uint32_t bcnt;       // EVF_BATCH, EVF_TRUN: number of members (events e .. e + bcnt - 1)
+    uint32_t boff;       //   BATCH: their first record in the member table; TRUN: the run's phase8 step
     uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products
     uint64_t xD, xS;          // reset / feedback: rows anticommuting with the flip Pauli
-    double Are, Aim;          // T_PHASE: e^{i s pi/4}
+    union {
+        struct {
+            double Are, Aim;  // T_PHASE: e^{i s pi/4}
+        };
+        struct {
+            // EVF_TRUN: bit J of trot0 / trot1 = bit 0 / 1 of the fixed quarter
+            // turns of final entry J (sum over the members i whose new
+            // coordinate J sets of qb_i + 2 parity(g_i & (J mod 2^(k + i))))
+            uint64_t trot0, trot1;
+        };
+    };
     // Branching T on a tile that carries the state up to a per-shot real
     // factor: v'_j = v_j + tan(pi/8) i^qb c' v_partner, and cos^2(pi/8) joins
     // the factor's square.

@@ -754,6 +754,63 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         }
                     });
                 }
+            } else if (flags & EVF_TRUN) {
+                // ---- m doublings with nothing between them, as one pass ----
+                // Final entry J (K = k + m <= 6 coordinates: one per lane) is
+                // entry J mod 2^k turned by i^(fixed + 2 x dynamic signs of the
+                // members whose coordinate J sets) and multiplied by tn once per
+                // such member, in member order: the separate passes' products.
+                // Pruning once at the last member's level keeps what they keep
+                // (the level only rises, and an entry is below its source).
+                const uint32_t m = EV32(bcnt), K = k + m;
+                uint32_t sg = 0;  // member `lane`'s sign part (no flips between members)
+                if (lane < m) {
+                    const uint4 bg =
+                        *reinterpret_cast<const uint4 *>(evl + (uint64_t)(e + lane) * 64u + offsetof(Event, beta) / 4u);
+                    const uint64_t B = ((uint64_t)bg.y << 32) | bg.x, G = ((uint64_t)bg.w << 32) | bg.z;
+                    sg = par64((rD & B) ^ ((rS ^ a) & G));
+                }
+                const uint32_t sm = (uint32_t)__ballot(sg != 0u);
+                const uint32_t J = lane & ((1u << K) - 1u);  // lanes past 2^K repeat a live lane
+                const uint32_t nb = J >> k;                    // members whose coordinate J sets
+                const uint32_t q = ((uint32_t)(EV64(trot0) >> J) & 1u) + 2u * ((uint32_t)(EV64(trot1) >> J) & 1u) +
+                                   2u * par32(sm & nb);
+                const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
+                C x = rot(v[J & ((1u << k) - 1u)], q);
+                for (uint32_t i = 0; i < m; ++i) {
+                    if ((nb >> i) & 1u) {
+                        x.x = tn * x.x;
+                        x.y = tn * x.y;
+                    }
+                }
+                const R nq = fma(x.x, x.x, x.y * x.y);
+                const double ics = EVD(iCs2);
+                uint32_t cmax = 0;
+                bool keep = false;
+                for (uint32_t i = 0; i < m; ++i) {  // support after each member
+                    itscale2 *= ics;
+                    const R thr = (R)(tau2 * nrm2 * itscale2);
+                    keep = nq >= thr;
+                    const uint32_t lim = 1u << (k + i + 1u);
+                    const uint64_t lv = lim >= 64u ? ~0ull : ((1ull << lim) - 1ull);
+                    cmax = max(cmax, (uint32_t)__popcll(__ballot(keep) & lv));
+                }
+                if (!keep) {
+                    x.x = 0;
+                    x.y = 0;
+                }
+                v[J] = x;
+                phase8 = (phase8 + EV32(boff)) & 15u;
+                cmax = uni(cmax);
+                maxsup = max(maxsup, cmax);
+                if (cmax > P.support_cap) {  // only the full list enforces a cap
+                    restart = true;
+                    break;
+                }
+                k = K;
+                e += m - 1u;
+                evx = evl[(uint64_t)(e + 1u) * 64u + lane];
+                evy = evl[(uint64_t)(e + 2u) * 64u + lane];
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
                 const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
                 const uint32_t sig = sga;
