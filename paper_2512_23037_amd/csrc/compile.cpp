@@ -959,6 +959,44 @@ static void fuse_doublings(Program &P) {
     }
 }
 
+// Speculative lists: a run of butterflies that each drop the top coordinate
+// (EVF_DROP1), with no noise slot and no Clifford sign flip between them, on
+// a tile of at most 64 entries, runs in registers (EVF_BRUN on the first; the
+// members stay in the list and the kernel skips them).  Each member is the
+// same butterfly, pruning and drop check as its own pass.
+static void fuse_drop_runs(Program &P) {
+    std::vector<Event> &ev = P.events;
+    auto is_member = [](const Event &B) {
+        return B.kind == EV_T_BFLY && (B.flags & EVF_DROP1) && B.tstar + 1u == B.k;
+    };
+    for (size_t s = 0; s < ev.size();) {
+        Event &A = ev[s];
+        if (!is_member(A) || A.k > 6u || (A.flags & ~(EVF_TDG | EVF_CLIFF | EVF_DROP1)) != 0u) {
+            ++s;
+            continue;
+        }
+        size_t m = 1;
+        while (s + m < ev.size() && m < A.k) {
+            const Event &B = ev[s + m];
+            if (!is_member(B) || (B.flags & ~(EVF_TDG | EVF_DROP1)) != 0u || B.noise_end != A.noise_end ||
+                B.k != A.k - m || std::memcmp(&B.Tn, &A.Tn, sizeof(double)) != 0 ||
+                std::memcmp(&B.iCs2, &A.iCs2, sizeof(double)) != 0)
+                break;
+            ++m;
+        }
+        if (m < 2) {
+            ++s;
+            continue;
+        }
+        uint32_t ph = 0;
+        for (size_t i = 0; i < m; ++i) ph += (ev[s + i].flags & EVF_TDG) ? 15u : 1u;
+        A.flags |= EVF_BRUN;
+        A.bcnt = (uint32_t)m;
+        A.boff = ph & 15u;
+        s += m;
+    }
+}
+
 // Running work counts of the event list (see Event::cum_t): the span
 // dimension before each event is the same in every shot, so the work of a
 // shot that stops after event e is the sum over the events up to e.
@@ -1173,7 +1211,10 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     }
     fc.end(src);
     form_batches(out);
-    if (speculate) fuse_doublings(out);
+    if (speculate) {
+        fuse_doublings(out);
+        fuse_drop_runs(out);
+    }
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
     work_sums(out);

@@ -59,6 +59,8 @@ enum EvFlags : uint32_t {
                        // empty, i.e. no partner output kept; then k -> k-1
     EVF_TRUN = 128u,   // speculative: first of `bcnt` doublings with nothing between them, run as one
                        // pass (k + bcnt <= 6: one final entry per lane); the others are skipped
+    EVF_BRUN = 256u,   // speculative: first of `bcnt` EVF_DROP1 butterflies with nothing between them
+                       // (k <= 6), run in registers, one entry per lane; the others are skipped
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane
@@ -88,8 +90,9 @@ struct alignas(16) Event {
     uint32_t det_cnt;    //   number of pairs
     uint32_t chk_src;    //   op index of a folded detector
     uint32_t dw0, dm0;   //   the first pair, inline
-    uint32_t bcnt;       // EVF_BATCH, EVF_TRUN: number of members (events e .. e + bcnt - 1)
-    uint32_t boff;       //   BATCH: their first record in the member table; TRUN: the run's phase8 step
+    uint32_t bcnt;       // EVF_BATCH, EVF_TRUN, EVF_BRUN: number of members (events e .. e + bcnt - 1)
+    uint32_t boff;       //   BATCH: their first record in the member table; TRUN, BRUN: the run's
+                         //   phase8 step
     uint64_t avec;            // offset update: b_{t*} (CUT) or beta (SPLIT, MERGE)
     uint64_t AD, AS;          // rows (besides d_p, s_p) that absorb s_p
     uint64_t PhD, PhS;        // extra sign bits of those products

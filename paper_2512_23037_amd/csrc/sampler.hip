@@ -811,6 +811,79 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 e += m - 1u;
                 evx = evl[(uint64_t)(e + 1u) * 64u + lane];
                 evy = evl[(uint64_t)(e + 2u) * 64u + lane];
+            } else if (flags & EVF_BRUN) {
+                // ---- m butterflies that each drop the top coordinate ----
+                // Entry j sits in lane j (k <= 6).  Member i mixes lanes j and
+                // j ^ mu_i with the partner weight tn i^qb_i (-1)^(sig_i ^
+                // parity(g_i & (j ^ mu_i))), prunes at its level and drops
+                // coordinate k - 1 when no entry with that bit set is kept
+                // (else the shot restarts): the separate passes, step by step.
+                const uint32_t m = EV32(bcnt), k0 = k;
+                uint32_t sg = 0, gv = 0, qv = 0, mv = 0;  // member `lane`'s fields
+                if (lane < m) {
+                    const uint32_t *rp = evl + (uint64_t)(e + lane) * 64u;
+                    const uint4 bg = *reinterpret_cast<const uint4 *>(rp + offsetof(Event, beta) / 4u);
+                    const uint4 kg = *reinterpret_cast<const uint4 *>(rp + offsetof(Event, k) / 4u);
+                    const uint64_t B = ((uint64_t)bg.y << 32) | bg.x, G = ((uint64_t)bg.w << 32) | bg.z;
+                    sg = par64((rD & B) ^ ((rS ^ a) & G));
+                    gv = kg.y;
+                    qv = kg.w;
+                    mv = rp[offsetof(Event, mu) / 4u];
+                }
+                const uint32_t sm = (uint32_t)__ballot(sg != 0u);
+                const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
+                const double ics = EVD(iCs2);
+                C x = v[lane & ((1u << k0) - 1u)];
+                bool fail = false;
+                for (uint32_t i = 0; i < m; ++i) {
+                    const uint32_t mu = uni((uint32_t)__builtin_amdgcn_readlane((int)mv, (int)i));
+                    const uint32_t gi = uni((uint32_t)__builtin_amdgcn_readlane((int)gv, (int)i));
+                    const uint32_t qi = uni((uint32_t)__builtin_amdgcn_readlane((int)qv, (int)i));
+                    const uint32_t pl = lane ^ mu;  // mu < 2^k <= 64
+                    C y;
+                    y.x = __shfl(x.x, (int)pl, 64);
+                    y.y = __shfl(x.y, (int)pl, 64);
+                    const C w = rot(y, qi);
+                    const R c = (((sm >> i) & 1u) ^ par32(gi & pl)) != 0u ? -tn : tn;
+                    itscale2 *= ics;
+                    const R thr = (R)(tau2 * nrm2 * itscale2);
+                    C o;
+                    o.x = fma(c, w.x, x.x);
+                    o.y = fma(c, w.y, x.y);
+                    const bool keep = fma(o.x, o.x, o.y * o.y) >= thr;
+                    if (!keep) {
+                        o.x = 0;
+                        o.y = 0;
+                    }
+                    const uint32_t n = 1u << k;
+                    const uint64_t kb = __ballot(keep) & (n >= 64u ? ~0ull : ((1ull << n) - 1ull));
+                    const uint32_t cnt = uni((uint32_t)__popcll(kb));
+                    maxsup = max(maxsup, cnt);
+                    // lanes n/2 .. n-1 hold the entries with the dropped bit set
+                    if (cnt > P.support_cap || (kb >> (n >> 1)) != 0ull) {
+                        fail = true;
+                        break;
+                    }
+                    x = o;
+                    --k;
+                }
+                if (fail) {
+                    restart = true;
+                    break;
+                }
+                // the dropped halves hold pruned zeros, as the separate passes leave them
+                if (lane < (1u << k0)) {
+                    if (lane >= (1u << k)) {
+                        x.x = 0;
+                        x.y = 0;
+                    }
+                    v[lane] = x;
+                }
+                phase8 = (phase8 + EV32(boff)) & 15u;
+                if (k == 0u) renorm_single();
+                e += m - 1u;
+                evx = evl[(uint64_t)(e + 1u) * 64u + lane];
+                evy = evl[(uint64_t)(e + 2u) * 64u + lane];
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
                 const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
                 const uint32_t sig = sga;
