@@ -158,8 +158,11 @@ int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
  * there, and step by step as the inverse layer proceeds: it runs the
  * commuting T gates of a layer in another order (cheapest first in a layer
  * that opens, latest-opened first in one that closes; each gate's noise stays
- * after it).  The kernel verifies that the dropped coordinates hold exact
- * zeros and otherwise restarts the shot on the full list (counted in
+ * after it).  On that list, runs of such T gates on spans of at most 6
+ * coordinates with nothing between them run as one pass, with the same
+ * arithmetic and the same support after every gate.  The kernel verifies
+ * that the dropped coordinates hold exact zeros and otherwise restarts the
+ * shot on the full list (counted in
  * soft_counters.restarts).  Records, statuses, abort ops and observables are
  * the full list's either way (coefficients up to rounding order); the support
  * histogram is that of the supports the kernel held, which the other gate
