@@ -66,3 +66,24 @@ def test_bracket_circuits_capped(seed):
         ctx = make_ctx(text, noise, seed=9, cap=cap)
         compare_batch(run_gpu(ctx, 0, N), ref)
         ctx.close()
+
+
+@pytest.mark.parametrize("noise_mode", [0, 1])
+def test_42q_speculative_list_equals_full_list(noise_mode):
+    # The benchmark workload at scale: the speculative list (reordered layers,
+    # folded drops, fused runs of doublings and of dropping butterflies) must
+    # give the full list's records, statuses, abort ops and observables for
+    # every shot (FP64), with restarts where noise broke a cancellation.
+    w = workloads.config("cultivation_42q", seed=1)
+    N = 2_000_000
+    outs, restarts = {}, {}
+    for spec in (True, False):
+        ctx = make_ctx(w.text, w.noise, seed=20251223, bits=64)
+        ctx.set_noise_mode(noise_mode)
+        ctx.set_speculation(spec)
+        outs[spec] = run_gpu(ctx, 0, N)
+        restarts[spec] = ctx.counters()["restarts"]
+        ctx.close()
+    assert restarts[False] == 0 and restarts[True] > 0
+    for key in ("status", "abort_op", "obs", "outcomes"):
+        assert (outs[True][key] == outs[False][key]).all(), key
