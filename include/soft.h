@@ -47,7 +47,8 @@ enum { SOFT_PASSED = 0, SOFT_DISCARDED = 1, SOFT_OVERFLOW = 2, SOFT_NUMERIC = 3 
 
 typedef struct soft_ctx soft_ctx;
 
-/* Uniform depolarizing noise model (Sec. III): every probability in [0, 1].
+/* Uniform depolarizing noise model (Sec. III; the per-shot Pauli draws of the
+ * pure-state simulation model of Sec. II-C): every probability in [0, 1].
  * p1: DEP1 after each single-qubit gate (H S SDG X Y Z T TDG); p2: DEP2 after
  * each CX/CZ; p_idle: DEP1 on every qubit untouched since the previous TICK,
  * inserted at the TICK; p_meas: X flip before each M; p_reset: X flip after
@@ -57,7 +58,10 @@ typedef struct {
     double p1, p2, p_idle, p_meas, p_reset, p_mpp;
 } soft_noise;
 
-/* Aggregates of the last soft_run. */
+/* Aggregates of the last soft_run: the small statistics the host reads back
+ * (Sec. IV-B) -- pass / discard counts and the logical-error count behind the
+ * discard rate and logical error rate of Sec. V, plus the work and support
+ * sizes |v| (Definition 1) of the shots. */
 typedef struct {
     uint64_t shots, passed, discarded, overflow, numeric;
     uint64_t logical_errors;     /* passed shots with a nonzero observable   */
@@ -76,20 +80,28 @@ typedef struct {
                                     broke a T / T-dagger cancellation) */
 } soft_counters;
 
-/* Create a context on HIP device `hip_device` (made current for the call).
- * *out receives the handle (NULL on failure). */
+/* Create a context on HIP device `hip_device` (made current for the call):
+ * the device memory that holds the compiled circuit, the counters and the
+ * per-shot states of Sec. IV-B is owned by it.  *out receives the handle
+ * (NULL on failure).  EINVAL: no such device or out == NULL; EDEVICE: a HIP
+ * call failed (message via soft_last_error(NULL)). */
 int soft_create(soft_ctx **out, int hip_device);
 
-/* Free everything the context owns.  NULL is allowed. */
+/* Free everything the context owns (the device memory of Sec. IV-B it
+ * allocated); waits for its last run first.  NULL is allowed. */
 void soft_destroy(soft_ctx *ctx);
 
 /* Message of the last failed call on ctx ("" if none); valid until the next
  * call on ctx.  With ctx == NULL, the message of the last failed
- * soft_create on this thread. */
+ * soft_create on this thread.  Error reporting of this boundary only: no
+ * operation of the paper corresponds to it. */
 const char *soft_last_error(const soft_ctx *ctx);
 
-/* Load circuit text (len bytes, need not be NUL-terminated; copied).  One op
- * per line, '#' starts a comment, first line "QUBITS n":
+/* Load circuit text (len bytes, need not be NUL-terminated; copied): a
+ * Clifford+T circuit with mid-circuit measurements and postselection, the
+ * problem of Sec. II-C, with the operations of the MSC circuits of Sec. III
+ * (Table II counts them).  One op per line, '#' starts a comment, first line
+ * "QUBITS n":
  *   H q | S q | SDG q | X q | Y q | Z q | T q | TDG q | CX c t | CZ a b |
  *   M q | R q | MPP P0*P1*...  (factors X3, Y0, Z7; distinct qubits) |
  *   DEP1 p q... | DEP2 p a b [a b...] | XERR p q... | TICK |
@@ -102,12 +114,16 @@ const char *soft_last_error(const soft_ctx *ctx);
  * exceeds the largest tile the library supports. */
 int soft_load_circuit(soft_ctx *ctx, const char *text, size_t len);
 
-/* Set the noise model inserted around the circuit's ops (default: none).
- * ESTATE while a mixture is loaded (each variant has its own model). */
+/* Set the noise model inserted around the circuit's ops (default: none):
+ * the uniform depolarizing model of Sec. III, sampled per shot as in the
+ * pure-state simulation model of Sec. II-C.  EINVAL: a probability outside
+ * [0, 1]; ESTATE while a mixture is loaded (each variant has its own model). */
 int soft_load_noise(soft_ctx *ctx, const soft_noise *model);
 
 /* Load a mixture: n_variants (1..64) circuits, each with its own noise model,
- * sampled together in one launch by soft_run.  Variant v owns the global
+ * sampled together in one launch by soft_run (the batching of many shots per
+ * launch of Sec. IV-B, across circuits and noise rates as in the noise scans
+ * of Sec. V).  Variant v owns the global
  * shot indices [shot_ends[v-1], shot_ends[v]) (shot_ends[-1] = 0; the ends
  * strictly increase), and a shot of variant v has the same result as the
  * same shot index of a context holding only that circuit and model.
@@ -119,37 +135,52 @@ int soft_load_noise(soft_ctx *ctx, const soft_noise *model);
 int soft_load_mixture(soft_ctx *ctx, uint32_t n_variants, const char *const *texts, const size_t *lens,
                       const soft_noise *models, const uint64_t *shot_ends);
 
-/* Key of the per-shot Philox4x32-10 streams (Salmon et al., SC'11).  Noise
+/* Key of the per-shot random streams that choose each shot's noise Paulis
+ * and measurement branches (the pure-state simulation model of Sec. II-C;
+ * the paper seeds shots by hashing, here Philox4x32-10 of Salmon et al.,
+ * SC'11, keyed by seed and counted by shot index).  Noise
  * slot s of shot t uses word s%4 of the block at counter
  * (s/4, t low 32 bits, t high 32 bits, 0); measurement slot s uses stream 1.
  * A noise slot hits iff word < floor(p * 2^32); a measurement's outcome is
  * +1 (record bit 0) iff (word + 1/2) 2^-32 < P(+1). */
 int soft_set_rng(soft_ctx *ctx, uint64_t seed);
 
-/* Replace Philox by explicit per-shot words (test mode): words_dev holds
+/* Replace Philox by explicit per-shot words (test mode, for the step-by-step
+ * validation of Sec. V-B: both sides see identical draws): words_dev holds
  * n_shots rows of noise_slots + meas_slots words, row i used by the shot at
  * position i of the next soft_run.  The counts must match the loaded circuit
  * and noise model.  words_dev == NULL returns to Philox. */
 int soft_set_uniforms(soft_ctx *ctx, const uint32_t *words_dev, uint64_t n_shots,
                       uint32_t noise_slots, uint32_t meas_slots);
 
-/* Coefficient precision: 64 (FP64, default) or 32 (FP32 complex storage and
- * products; outcome probabilities, renormalisation and norms stay FP64). */
+/* Coefficient precision of the coefficients v of Definition 1 / Eq. 3:
+ * 64 (FP64, the paper's precision; default) or 32 (FP32 complex storage and
+ * products; outcome probabilities, renormalisation and norms stay FP64).
+ * EINVAL for any other value. */
 int soft_set_precision(soft_ctx *ctx, int coeff_bits);
 
 /* Pruning threshold tau: after every T and measurement, coefficients with
- * |v|^2 < tau^2 sum|v|^2 are dropped.  Default 1e-12 (FP64), 1e-6 (FP32);
- * tau < 0 restores the default. */
+ * |v|^2 < tau^2 sum|v|^2 are dropped, so that the support of Definition 1
+ * (the nonzero entries) keeps the bounds of Theorem 1 when T and T-dagger
+ * cancel up to rounding (the paper is silent on pruning).  Default 1e-12
+ * (FP64), 1e-6 (FP32); tau < 0 restores the default; EINVAL for tau >= 1. */
 int soft_set_prune(soft_ctx *ctx, double tau);
 
-/* support_cap: a shot whose support exceeds it after a T ends as OVERFLOW
- * (0 = no cap).  waves_per_block (1..4), blocks_per_cu (1..32), grab (1..64,
- * consecutive shots a wave takes per steal; their outputs are written
- * together): launch shape, 0 = the autotuned or default value. */
+/* Fixed capacities and launch shape (Sec. IV-B: per-shot capacity with an
+ * overflow flag).  support_cap: a shot whose support |v| exceeds it after a T
+ * ends as OVERFLOW (0 = no cap).  waves_per_block (1..4), blocks_per_cu
+ * (1..32), grab (1..64, consecutive shots a wave takes per steal; their
+ * outputs are written together): launch shape, 0 = the autotuned or default
+ * value.  One wave runs one shot at a time, so shots in flight per block =
+ * waves_per_block; the coefficient tile is not a free size (it holds the
+ * circuit's whole span, 2^k_max entries) -- where it lives is
+ * soft_set_tile_memory.  EINVAL for values out of range. */
 int soft_set_caps(soft_ctx *ctx, uint32_t support_cap, uint32_t waves_per_block,
                   uint32_t blocks_per_cu, uint32_t grab);
 
-/* Speculative span truncation (on by default): where every T of a run since
+/* Speculative span truncation (on by default; it rests on the T-layer
+ * structure of Sec. IV-A, Observations 1-3 and Proposition 1): where every T
+ * of a run since
  * a checkpoint meets its inverse on the same qubit with nothing in between
  * that fails to commute with its Z (T and T-dagger layers around commuting
  * check rounds), the product of the pairs is the identity, so a shot whose
@@ -173,7 +204,7 @@ int soft_set_speculation(soft_ctx *ctx, int on);
 
 /* How noise hits are drawn (the same distribution either way: every noise
  * location hit independently with its probability, its Pauli uniform over the
- * channel's list).  mode 0 (default): one Philox word of stream 0 per noise
+ * channel's list, as the uniform depolarizing noise of Sec. III asks).  mode 0 (default): one Philox word of stream 0 per noise
  * location, hit iff word < floor(p 2^32).  mode 1 (gap sampling): candidate
  * locations form a Bernoulli(p_max) process, p_max the largest location
  * probability of the circuit; the gap to the next candidate comes from one
@@ -184,27 +215,39 @@ int soft_set_speculation(soft_ctx *ctx, int on);
  * Returns SOFT_EINVAL for another mode. */
 int soft_set_noise_mode(soft_ctx *ctx, int mode);
 
-/* Where the per-wave coefficient tile lives: 0 = automatic (LDS when one
+/* Where the per-wave coefficient tile lives (the GPU memory layout of
+ * Sec. IV-B, re-planned for LDS and HBM): 0 = automatic (LDS when one
  * wave's tile fits in a block's LDS, else device memory), 1 = LDS, 2 = device
  * memory (HBM; one slab of 2^k_max entries per resident wave, allocated by the
  * library on first use).  LDS is the fast place; device memory lifts the LDS
  * size limit on the span dimension (up to k_max = 20). */
 int soft_set_tile_memory(soft_ctx *ctx, int mode);
 
-/* Time the default launch shape and a grid of others (and, in automatic tile
+/* Batch-schedule autotuning (Sec. V measures throughput against the batch
+ * size; Sec. IV-B launches fixed batches): time the default launch shape and
+ * a grid of others (and, in automatic tile
  * mode, both tile placements) on `sample_shots` shots spread over the
  * variants, in one launch each (outputs discarded; the better of two timings
  * counts), and keep the fastest for this circuit, noise model and precision.
+ * The result is cached for the process, keyed by the device (architecture
+ * name and compute-unit count), the circuit (with a mixture's shot ranges),
+ * precision, pruning threshold, support cap, tile placement and noise draws:
+ * every context on such a device that loads the same circuit uses it.
  * Samples of 10^6 shots or more rank shapes reliably; small samples measure
  * launch overhead.  Runs on hip_stream and synchronizes it. */
 int soft_autotune(soft_ctx *ctx, uint64_t sample_shots, void *hip_stream);
 
-/* Keep the final state of shots [shot_lo, shot_lo + count) of later runs for
- * soft_read_coeffs / soft_read_tableau (count <= 4096; 0 disables). */
+/* Keep the final state (v, B(S, D)) of Definition 1 / Eq. 3 of shots
+ * [shot_lo, shot_lo + count) of later runs for soft_read_coeffs /
+ * soft_read_tableau (count <= 16384; 0 disables; ECAPACITY above). */
 int soft_set_keep(soft_ctx *ctx, uint64_t shot_lo, uint32_t count);
 
-/* Sample shots shot0 .. shot0 + n_shots - 1 (global indices: a shot's result
- * depends only on seed, shot index, circuit and noise, not on batching).
+/* Sample shots shot0 .. shot0 + n_shots - 1: each shot is one independent
+ * pure-state trajectory of the Monte-Carlo model of Sec. II-C (Cliffords by
+ * Theorem 1 part 1, T by Eqs. 1-2 with Eq. 4, measurements by Theorem 1
+ * part 2), stopped at the first failed postselection check (Sec. V-A), all in
+ * one persistent launch (Sec. IV-B).  Indices are global: a shot's result
+ * depends only on seed, shot index, circuit and noise, not on batching.
  * Asynchronous on hip_stream (a hipStream_t; NULL = default stream).
  *   outcomes_dev: uint32 [ceil(records/32)][n_shots], bit r%32 of word r/32
  *                 of shot i = record r (0 after an abort), or NULL;
@@ -217,7 +260,9 @@ int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes
              uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev,
              void *hip_stream);
 
-/* Sample an explicit list of global shot indices: shots_dev (device, uint64,
+/* Re-run of chosen shots (Sec. IV-B: shots over the fixed capacity are run
+ * again under a larger configuration).  Sample an explicit list of global
+ * shot indices: shots_dev (device, uint64,
  * 8-byte aligned) holds n_shots indices in any order; output row i (of
  * outcomes_dev, status_dev, ...) belongs to shots_dev[i], with the layout of
  * soft_run.  A shot's result depends only on its index, so this re-runs
@@ -230,31 +275,38 @@ int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes
 int soft_run_list(soft_ctx *ctx, const uint64_t *shots_dev, uint64_t n_shots, uint32_t *outcomes_dev,
                   uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev, void *hip_stream);
 
-/* Aggregates of the last run; synchronizes that run's stream. */
+/* Aggregates of the last run (the statistics the host reads back, Sec. IV-B;
+ * discard rate and logical errors as in Sec. V); synchronizes that run's
+ * stream.  ESTATE before any run. */
 int soft_read_counters(soft_ctx *ctx, soft_counters *out);
 
 /* Aggregates of the last run over the shots of one variant of a mixture
- * (variant 0 of a single circuit is the whole run).  Synchronizes. */
+ * (variant 0 of a single circuit is the whole run), as soft_read_counters
+ * (Sec. IV-B, Sec. V).  Synchronizes.  EINVAL: no such variant. */
 int soft_read_variant_counters(soft_ctx *ctx, uint32_t variant, soft_counters *out);
 
-/* Final coefficients of a kept shot of the last run, sorted by alpha (bit k =
+/* Final coefficients v_alpha of Definition 1 / Eq. 3 of a kept shot of the
+ * last run: the state is sum_alpha v_alpha d_alpha |psi_S>, with the exact
+ * global phase of Eqs. 1-2.  Sorted by alpha (bit k =
  * destabilizer d_k), entries below the pruning threshold left out.  Up to
  * cap entries are written; *count receives the full number.  Synchronizes. */
 int soft_read_coeffs(soft_ctx *ctx, uint64_t shot, uint64_t *alpha, double *re, double *im,
                      uint32_t cap, uint32_t *count);
 
-/* Final tableau of a kept shot: 2n rows (destabilizers d_0..d_{n-1}, then
+/* Final tableau B(S, D) of a kept shot (the Aaronson-Gottesman tableau of
+ * Sec. II-B, signs included): 2n rows (destabilizers d_0..d_{n-1}, then
  * stabilizers s_0..s_{n-1}); row i is (-1)^r[i] prod_q sigma(x_q, z_q) with
  * x = bit q of x[i], z = bit q of z[i], sigma(1,1) = Y.  Synchronizes. */
 int soft_read_tableau(soft_ctx *ctx, uint64_t shot, uint64_t *x, uint64_t *z, uint8_t *r);
 
-/* Trace mode (the step-by-step cross-check): record the state of shot
+/* Trace mode (the step-by-step validation of Sec. V-B): record the state of shot
  * `shot` after each of its first `steps` events (T/T-dagger, measurements,
  * detectors, observables, end) in the next runs; steps = 0 disables it
  * (steps <= 65536). */
 int soft_set_trace(soft_ctx *ctx, uint64_t shot, uint32_t steps);
 
-/* State of the traced shot after event `step` of the last run.  info[0..5] =
+/* State (v, B(S, D)) of Definition 1 of the traced shot after event `step`
+ * of the last run (Sec. V-B step-by-step validation).  info[0..5] =
  * written (0/1), op index of the event, status at that point, span dimension
  * k, carried FP64 norm (bits of a double), 1 if the shot ended there.
  * x, z, r: 2n tableau rows as in soft_read_tableau; alpha/re/im/count as in
@@ -262,16 +314,18 @@ int soft_set_trace(soft_ctx *ctx, uint64_t shot, uint32_t steps);
 int soft_read_trace(soft_ctx *ctx, uint32_t step, uint64_t info[6], uint64_t *x, uint64_t *z, uint8_t *r,
                     uint64_t *alpha, double *re, double *im, uint32_t cap, uint32_t *count);
 
-/* Facts about the loaded circuit: info[0..7] = qubits, records, noise slots,
+/* Facts about the loaded circuit, in the terms of Table II (qubits,
+ * measurements) and Theorem 2 (the largest span dimension, log2 of the
+ * support bound): info[0..7] = qubits, records, noise slots,
  * measurement slots, observables, events, largest span dimension k_max,
  * record words.  For a mixture, each entry is the largest over the variants
  * (the record words size soft_run's outcome planes). */
 int soft_circuit_info(soft_ctx *ctx, uint64_t info[8]);
 
-/* The same facts for variant `variant` of a mixture. */
+/* The same facts (Table II, Theorem 2) for variant `variant` of a mixture. */
 int soft_variant_info(soft_ctx *ctx, uint32_t variant, uint64_t info[8]);
 
-/* Launch shape used by the next run: out[0..4] = waves_per_block,
+/* Launch shape (Sec. IV-B) used by the next run: out[0..4] = waves_per_block,
  * blocks_per_cu, grab, LDS bytes per wave, 1 if the tiles are in device
  * memory. */
 int soft_launch_shape(soft_ctx *ctx, uint32_t out[5]);

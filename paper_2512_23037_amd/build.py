@@ -22,7 +22,6 @@ def build(jobs: int = 3) -> str:
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
-        lang = [] if src.endswith(".hip") else ["-x", "hip"] if False else []
         cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                                        os.path.join(CSRC, src), "-o", obj]
         procs.append(subprocess.Popen(cmd))

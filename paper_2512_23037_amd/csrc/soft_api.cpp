@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -42,6 +43,19 @@ struct Variant {
 };
 
 constexpr size_t kCounterWords = (size_t)kMaxVariants * C_COUNT + 1;
+
+// Kept final states: at most this many shots, and at most kMaxKeepBytes of
+// dense tiles (FP64 pairs) for them.
+constexpr uint32_t kMaxKeep = 16384;
+constexpr uint64_t kMaxKeepBytes = 4ull << 30;
+
+// Autotuned launch shapes, shared by every context of the process: keyed by
+// the device (architecture name and compute-unit count) and by what changes
+// the timing of a circuit (its hash with the shot ranges, precision, pruning
+// threshold, support cap, tile placement and noise draws).
+typedef std::tuple<std::string, int, uint64_t, int, double, uint32_t, int, int> TuneKey;
+std::mutex g_tune_mu;
+std::map<TuneKey, Shape> g_tuned;
 
 template <typename T> struct DevBuf {
     T *p = nullptr;
@@ -75,7 +89,7 @@ struct soft_ctx {
     bool speculate = true;                    // run speculative event lists where compiled
     int noise_mode = 0;                       // 0 a word per noise slot, 1 gap sampling
     Shape user;                               // explicit launch shape parts
-    std::map<std::tuple<uint64_t, int, double, uint32_t, int, int>, Shape> tuned;
+    std::string arch;                         // gcnArchName of the device (autotune cache key)
 
     DevBuf<Event> d_ev;
     DevBuf<NoiseLoc> d_nz;
@@ -290,10 +304,17 @@ Shape default_shape(const soft_ctx *c) {
     return s;
 }
 
+TuneKey tune_key(const soft_ctx *c) {
+    return TuneKey(c->arch, c->num_cus, c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode, c->noise_mode);
+}
+
 Shape current_shape(const soft_ctx *c) {
     Shape s = default_shape(c);
-    auto it = c->tuned.find(std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode, c->noise_mode));
-    if (it != c->tuned.end()) s = it->second;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(tune_key(c));
+        if (it != g_tuned.end()) s = it->second;
+    }
     if (c->tile_mode) s.gt = c->tile_mode == 2 ? 1u : 0u;
     if (c->user.wpb) s.wpb = c->user.wpb;
     if (c->user.bpc) s.bpc = c->user.bpc;
@@ -390,6 +411,9 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.grab = 1;
     if (c->keep_n) {
         const uint32_t te = tile_entries(c);
+        if ((uint64_t)c->keep_n * te * 16u > kMaxKeepBytes)
+            return fail(c, SOFT_ECAPACITY, "kept states would take more than 4 GiB (" + std::to_string(c->keep_n) +
+                                               " shots of 2^" + std::to_string(c->kmax) + " entries); keep fewer shots");
         int rc;
         if ((rc = ensure(c, c->d_keep_meta, (size_t)c->keep_n * KM_COUNT)) ||
             (rc = ensure(c, c->d_keep_v, (size_t)c->keep_n * te * 2)))
@@ -555,6 +579,11 @@ int soft_create(soft_ctx **out, int hip_device) {
     if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device)) != hipSuccess)
         return bad(e, "hipDeviceGetAttribute");
     c->max_lds_block = lds;
+    {
+        hipDeviceProp_t prop;
+        if ((e = hipGetDeviceProperties(&prop, hip_device)) != hipSuccess) return bad(e, "hipGetDeviceProperties");
+        c->arch = prop.gcnArchName;
+    }
     if (sampler_set_lds_limit(lds) != hipSuccess) {
         (void)hipGetLastError();
         c->max_lds_block = std::min(lds, 65536);
@@ -746,7 +775,7 @@ int soft_set_tile_memory(soft_ctx *c, int mode) {
 
 int soft_set_keep(soft_ctx *c, uint64_t shot_lo, uint32_t count) {
     if (!c) return SOFT_EINVAL;
-    if (count > 4096) return fail(c, SOFT_ECAPACITY, "at most 4096 kept shots");
+    if (count > kMaxKeep) return fail(c, SOFT_ECAPACITY, "at most " + std::to_string(kMaxKeep) + " kept shots");
     c->keep_lo = shot_lo;
     c->keep_n = count;
     return SOFT_OK;
@@ -1050,7 +1079,10 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     (void)hipFree(d_status);
     (void)hipFree(d_list);
     if (rc) return rc;
-    c->tuned[std::make_tuple(c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode, c->noise_mode)] = best;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[tune_key(c)] = best;
+    }
     c->ran = false;  // counters of the last sample run are not a user run
     return SOFT_OK;
 }
