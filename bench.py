@@ -6,7 +6,11 @@ One step = one soft_run over 10^7 shots (the whole hot path: noise draws,
 sign-frame Cliffords, T/T-dagger, measurements, postselection, outputs) with
 every input resident on the GPU.  The headline runs FP32 coefficients (FP64
 probabilities and renormalisation); the FP64-coefficient run of the same
-workload is reported beside it, with the FP32-vs-FP64 differences.
+workload is reported beside it.
+
+Outside the timed region each precision also samples shots 0..9999 with their
+final states kept; the CPU-baseline leg times the oracle on the host and
+compares those shots with it (records, statuses, tableaux, coefficient error).
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -28,17 +32,24 @@ METRIC = "shots/sec on 1 MI355X (42q/72T noisy circuit), FP32 vs FP64 coeffs at 
 WORKLOAD = "cultivation_42q"
 SEED_CIRCUIT = 1
 SEED_RNG = 20251223
+SUBSET = 10000          # shots 0..SUBSET-1 compared with the oracle
 
-# Peak 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Peaks (MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz):
+INT_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit vector lane-ops/s, 39.3 T
+FP32_PEAK_TFLOPS = 157.3                       # published vector FP32 (packed FMA)
+FP32_NONPACKED_TFLOPS = 78.6                   # one FMA per lane per cycle (packed FP32 is off in this build)
 
-# Algorithmic operations per unit of work ("Roofline"):
-OPS_T_BRANCH = 8 + 6    # per coefficient written by a branching T: complex 2-term combination + index/sign
-OPS_T_PHASE = 2 + 3     # per coefficient under a non-branching T: half pick up a phase
-OPS_M = 5 + 4           # per coefficient read by a measurement: |v|^2 in FP64, scale, index/sign
-OPS_NOISE = 25 + 2      # per noise word: a quarter Philox4x32-10 block, threshold compare
+# Algorithmic work per unit (the measurement plan's units):
+INT_PER_ENTRY = 8        # per coefficient entry an event touches: alpha^beta, parity(gamma & alpha), partner compare
+INT_PER_UNIFORM = 25     # per random word: a quarter of a Philox4x32-10 block (~100 32-bit ops)
+FP_T_BRANCH = 8          # per output entry of a branching T: two-term complex combination
+FP_T_PHASE = 4           # per entry that picks up the phase under a non-branching T
+FP_M_IN = 3              # per entry read by a measurement: |v|^2 accumulated
+FP_M_OUT = 2             # per entry a measurement writes: the renormalisation
+FP_M_PAIR = 4            # per representative pair of a beta != 0 measurement: w+ and w-
 
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "sampler_cultivation_42q_traffic.json")
+PROFILE_ISSUE = os.path.join(ROOT, "profiles", "sampler_cultivation_42q_issue.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_23037_amd", "csrc", f)
                   for f in ("sampler.hip", "program.h", "sampler.h")]
 
@@ -48,6 +59,16 @@ def kernel_hash() -> str:
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
+
+
+def profile_of(path, shots):
+    """A profile summary written for this kernel source and launch size, else None."""
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_hash") != kernel_hash() or t.get("shots") != shots:
+        return None
+    return t
 
 
 def make_ctx(soft, w, bits, noise_mode):
@@ -61,6 +82,7 @@ def make_ctx(soft, w, bits, noise_mode):
 
 
 def time_steps(torch, ctx, shots, steps, warmup, bufs):
+    """HIP events on the stream the library launches on (torch's current one)."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         ctx.run(0, shots, *bufs, stream=stream)
@@ -77,7 +99,73 @@ def time_steps(torch, ctx, shots, steps, warmup, bufs):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(w, shots_sample: int, noise_mode: int):
+def sample_subset(torch, soft, ctx, n):
+    """Shots 0..n-1 with their final states kept (outside the timed region)."""
+    ctx.set_keep(0, n)
+    outcomes, status, abort_op, obs = soft.sample(ctx, 0, n)
+    torch.cuda.synchronize()
+    sub = {"status": status.cpu().numpy().view(np.uint32), "abort_op": abort_op.cpu().numpy().view(np.uint32),
+           "obs": obs.cpu().numpy().view(np.uint32), "outcomes": outcomes.cpu().numpy().view(np.uint32)}
+    sub["coeffs"] = [ctx.read_coeffs(s) for s in range(n)]
+    sub["tableau"] = [ctx.read_tableau(s) for s in range(n)]
+    ctx.set_keep(0, 0)
+    return sub
+
+
+def coeff_error(got: dict, ref: dict) -> float:
+    """max_alpha |v_gpu - v_ref| / ||v_ref||_2 over the union of supports."""
+    keys = set(got) | set(ref)
+    norm = np.sqrt(sum(abs(v) ** 2 for v in ref.values())) or 1.0
+    return max([abs(got.get(k, 0) - ref.get(k, 0)) for k in keys] + [0.0]) / norm
+
+
+def compare_with_oracle(oracle, circ, ref, sub, bits, threads):
+    """The GPU's shots 0..n-1 against the oracle's: records, statuses, abort
+    ops and observables bit for bit (FP32: a shot may take the other branch
+    only where a draw lies within 1e-5 of the oracle's probability), tableaux
+    bit for bit and the coefficient error on every shot that agrees."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = len(sub["status"])
+    nw = ref["outcomes"].shape[0]
+    diff = ((sub["status"] != ref["status"][:n]) | (sub["abort_op"] != ref["abort_op"][:n]) |
+            (sub["obs"] != ref["obs"][:n]) | (sub["outcomes"][:nw] != ref["outcomes"][:, :n]).any(axis=0))
+    tau = 1e-12 if bits == 64 else 1e-6
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        shots = list(pool.map(lambda s: circ.shot(SEED_RNG, s, tau=tau), range(n)))
+    in_band = 0
+    for s in np.nonzero(diff)[0]:
+        r = shots[s]
+        near = False
+        for slot in range(circ.n_meas_slots):
+            if np.isnan(r.p0[slot]):
+                continue
+            blk = oracle.philox([slot >> 2, int(s), 0, 1], [SEED_RNG & 0xFFFFFFFF, SEED_RNG >> 32])
+            near |= abs((float(blk[slot & 3]) + 0.5) / 2 ** 32 - r.p0[slot]) < 1e-5
+        in_band += int(near)
+    errs, tab_bad = [], 0
+    for s in range(n):
+        if diff[s]:
+            continue
+        r = shots[s]
+        x, z, rr = sub["tableau"][s]
+        tab_bad += int(not ((x == r.tab_x).all() and (z == r.tab_z).all() and (rr == r.tab_r).all()))
+        errs.append(coeff_error(sub["coeffs"][s], r.coeffs))
+    ok = ~diff
+    passed_g = (sub["status"] == 0) & ok
+    passed_o = (ref["status"][:n] == 0) & ok
+    return {"shots": n, "shots_identical": int(ok.sum()), "outcome_flips": int(diff.sum()),
+            "outcome_flips_in_guard_band": in_band, "outcome_flips_outside_guard_band": int(diff.sum()) - in_band,
+            "tableau_mismatches": tab_bad, "kept_shots_compared": len(errs),
+            "max_coeff_err": float(max(errs)) if errs else None,
+            "ler": float((passed_g & (sub["obs"] != 0)).sum() / max(1, passed_g.sum())),
+            "ler_oracle": float((passed_o & (ref["obs"][:n] != 0)).sum() / max(1, passed_o.sum())),
+            "passed": int(passed_g.sum())}
+
+
+def cpu_baseline(w, shots_sample: int, noise_mode: int, subsets: dict):
+    """The oracle on the host: its throughput on shots 0..shots_sample-1 (the
+    baseline), its work counts (the roofline's units), and the comparison of
+    the GPU's kept subsets with it."""
     import oracle
     oracle.build(force=False)
     circ = oracle.Circuit(w.text, w.noise, noise_mode=noise_mode)
@@ -85,9 +173,53 @@ def cpu_baseline(w, shots_sample: int, noise_mode: int):
     t0 = time.perf_counter()
     r = circ.batch(SEED_RNG, 0, shots_sample, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": shots_sample / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
+    base = {"value": shots_sample / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
             "sample": "shots 0..%d of the same workload (seed %d), %d host threads, %.1f s wall"
-                      % (shots_sample - 1, SEED_RNG, threads, dt)}, r["work"], shots_sample
+                      % (shots_sample - 1, SEED_RNG, threads, dt)}
+    checks = {bits: compare_with_oracle(oracle, circ, r, sub, bits, threads) for bits, sub in subsets.items()}
+    return base, r["work"], shots_sample, checks
+
+
+def roofline(work, nsample, shots, ms, c):
+    """Algorithmic int and FP work of one launch over its measured time."""
+    ps = {k: v / nsample for k, v in work.items()}
+    int_per_shot = (INT_PER_ENTRY * (ps["t_entries"] + ps["t_phase_entries"] + ps["m_entries"]) +
+                    INT_PER_UNIFORM * (ps["noise_words"] + ps["meas_words"]))
+    fp_per_shot = (FP_T_BRANCH * ps["t_entries"] + FP_T_PHASE * ps["t_phase_flips"] + FP_M_IN * ps["m_entries"] +
+                   FP_M_OUT * ps["m_out_entries"] + FP_M_PAIR * ps["m_pairs"])
+    sec = ms / 1e3
+    int_rate = int_per_shot * shots / sec / 1e12
+    fp_rate = fp_per_shot * shots / sec / 1e12
+    out = {"bound": "alu", "achieved": int_rate, "peak": INT_PEAK_TOPS, "unit": "Tops/s", "frac": int_rate / INT_PEAK_TOPS,
+           "traffic": None, "kernel_ms": ms, "kernel_hash": kernel_hash(),
+           "ops_per_shot": int_per_shot, "ops_per_launch": int_per_shot * shots,
+           "units": {"int_per_entry": INT_PER_ENTRY, "int_per_uniform": INT_PER_UNIFORM, "fp_t_branch": FP_T_BRANCH,
+                     "fp_t_phase": FP_T_PHASE, "fp_m_in": FP_M_IN, "fp_m_out": FP_M_OUT, "fp_m_pair": FP_M_PAIR},
+           "work_per_shot": ps,
+           "fp": {"flops_per_shot": fp_per_shot, "achieved": fp_rate, "unit": "TFLOP/s",
+                  "peak": FP32_PEAK_TFLOPS, "frac": fp_rate / FP32_PEAK_TFLOPS,
+                  "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": fp_rate / FP32_NONPACKED_TFLOPS}}
+    t = profile_of(PROFILE_TRAFFIC, shots)
+    out["traffic_source"] = None
+    if t is not None:
+        out["traffic"] = t["bytes_per_launch"]
+        out["traffic_source"] = ("rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE of this kernel source (scaled by a 1 GiB copy): "
+                                 "profiles/sampler_cultivation_42q_traffic.md")
+        out["hbm_frac"] = t["bytes_per_launch"] / sec / 8e12
+    q = profile_of(PROFILE_ISSUE, shots)
+    if q is not None:
+        out["measured"] = {k: q[k] for k in ("valu_insts_per_shot", "salu_insts_per_shot", "valu_issue_frac",
+                                             "salu_issue_frac") if k in q}
+        out["measured"]["source"] = "rocprofv3 --pmc SQ_INSTS_VALU, SQ_INSTS_SALU: profiles/sampler_cultivation_42q_sq_counters.md"
+    # The same unit costs over the work the kernel executed (its own
+    # counters): dense-tile T entries instead of the oracle's sparse support,
+    # no class sums for measurements whose outcome the compiled span fixes.
+    ex_int = INT_PER_ENTRY * (c["entries_t"] + c["entries_m"]) + INT_PER_UNIFORM * c["noise_slots"]
+    out["executed"] = {"ops_per_launch": ex_int, "achieved": ex_int / sec / 1e12,
+                       "frac": ex_int / sec / 1e12 / INT_PEAK_TOPS,
+                       "per_shot": {"t_entries": c["entries_t"] / shots, "m_entries": c["entries_m"] / shots,
+                                    "noise_words": c["noise_slots"] / shots}}
+    return out
 
 
 def bench_mixture(torch, workloads, soft, args):
@@ -141,7 +273,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--shots", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=40000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (its baseline, the roofline's units and the oracle comparison)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--autotune", type=int, default=0, help="sample shots for the autotuner (0 = library default shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -177,6 +310,7 @@ def main():
     stats_tab = workloads.circuit_stats(w.text)
     shots = args.shots
     dev = torch.device("cuda", 0)
+    subset = 0 if args.no_cpu_baseline else min(SUBSET, args.cpu_sample)
 
     results = {}
     for bits in ([32] if args.no_fp64 else [32, 64]):
@@ -188,16 +322,12 @@ def main():
                 torch.zeros(shots, dtype=torch.int32, device=dev),
                 torch.zeros(shots, dtype=torch.int32, device=dev),
                 torch.zeros(shots, dtype=torch.int32, device=dev))
-        # the last timed step keeps shots [(steps-1)*shots, +256) for the FP32-vs-FP64 comparison
-        ctx.set_keep((args.steps - 1) * shots, 256)
         ms, wall = time_steps(torch, ctx, shots, args.steps, args.warmup, bufs)
         c = ctx.counters()   # counters of the last timed step
-        results[bits] = {"ms": ms, "wall": wall, "counters": c, "shape": ctx.launch_shape(),
-                         "status": bufs[1][:200000].cpu().numpy(), "outcomes": bufs[0][:, :200000].cpu().numpy()}
-        base = (args.steps - 1) * shots
-        results[bits]["coeffs"] = [ctx.read_coeffs(base + s) for s in range(256)]
-        results[bits]["kept_status"] = bufs[1][:256].cpu().numpy()
+        results[bits] = {"ms": ms, "wall": wall, "counters": c, "shape": ctx.launch_shape()}
         del bufs
+        if subset:
+            results[bits]["subset"] = sample_subset(torch, soft, ctx, subset)
         ctx.close()
         torch.cuda.empty_cache()
 
@@ -216,55 +346,25 @@ def main():
                    "circuit": stats_tab, "launch": r32["shape"]},
         "stats": {"passed": c["passed"], "discarded": c["discarded"], "overflow": c["overflow"],
                   "numeric": c["numeric"], "logical_errors": c["logical_errors"],
-                  "discard_rate": c["discarded"] / max(1, c["shots"]), "max_norm_dev": c["max_norm_dev"]},
+                  "discard_rate": c["discarded"] / max(1, c["shots"]), "max_norm_dev": c["max_norm_dev"],
+                  "restarts": c["restarts"]},
     }
     if 64 in results:
         r64 = results[64]
         v64 = shots / (r64["ms"] / 1e3)
-        both = (r32["kept_status"] == r64["kept_status"])
-        errs = []
-        for a, b in zip(r32["coeffs"], r64["coeffs"]):
-            keys = set(a) | set(b)
-            nb = np.sqrt(sum(abs(x) ** 2 for x in b.values())) or 1.0
-            errs.append(max([abs(a.get(k, 0) - b.get(k, 0)) for k in keys] + [0.0]) / nb)
-        mism = int(((r32["status"] != r64["status"]) | (r32["outcomes"] != r64["outcomes"]).any(axis=0)).sum())
         c64 = r64["counters"]
-        ler32 = c["logical_errors"] / max(1, c["passed"])
-        ler64 = c64["logical_errors"] / max(1, c64["passed"])
-        out["fp64"] = {"value": v64, "ms_per_step": r64["ms"], "launch": r64["shape"], "fp32_speedup": value / v64}
-        out["fp32_vs_fp64"] = {"max_coeff_err": float(max(errs)) if errs else None,
-                               "kept_shots_compared": int(both.sum()),
-                               "shots_with_different_outcomes": mism, "shots_compared": int(len(r32["status"])),
-                               "ler_fp32": ler32, "ler_fp64": ler64}
+        out["fp64"] = {"value": v64, "ms_per_step": r64["ms"], "launch": r64["shape"], "fp32_speedup": value / v64,
+                       "ler": c64["logical_errors"] / max(1, c64["passed"]), "max_norm_dev": c64["max_norm_dev"]}
+        out["stats"]["ler"] = c["logical_errors"] / max(1, c["passed"])
 
-    # ---- roofline: algorithmic VALU work per launch over the measured time ----
-    work = None
     if not args.no_cpu_baseline:
-        base, work, nsample = cpu_baseline(w, args.cpu_sample, args.noise_mode)
+        subsets = {bits: r["subset"] for bits, r in results.items() if "subset" in r}
+        base, work, nsample, checks = cpu_baseline(w, args.cpu_sample, args.noise_mode, subsets)
         out["cpu_baseline"] = base
-    if work is not None:
-        per_shot = {k: v / nsample for k, v in work.items()}
-        ops = (OPS_T_BRANCH * per_shot["t_entries"] + OPS_T_PHASE * per_shot["t_phase_entries"] +
-               OPS_M * per_shot["m_entries"] + OPS_NOISE * per_shot["noise_words"]) * shots
-        achieved = ops / (r32["ms"] / 1e3) / 1e12
-        traffic = None
-        if os.path.exists(PROFILE_TRAFFIC):
-            t = json.load(open(PROFILE_TRAFFIC))
-            if t.get("kernel_hash") == kernel_hash() and t.get("shots") == shots:
-                traffic = t.get("bytes_per_launch")
-        # The same unit costs over the work the kernel actually executed (its
-        # device counters): dense-tile T entries instead of the oracle's sparse
-        # support, and no coefficient pass for measurements whose outcome the
-        # compiled span fixes (the oracle sums classes for those).
-        ex_ops = (OPS_T_BRANCH * c["entries_t"] + OPS_M * c["entries_m"] + OPS_NOISE * c["noise_slots"])
-        ex_rate = ex_ops / (r32["ms"] / 1e3) / 1e12
-        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                           "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                           "ops_per_launch": ops, "work_per_shot": per_shot,
-                           "executed": {"ops_per_launch": ex_ops, "achieved": ex_rate, "frac": ex_rate / VALU_PEAK_TOPS,
-                                        "per_shot": {"t_entries": c["entries_t"] / shots, "m_entries": c["entries_m"] / shots,
-                                                     "noise_words": c["noise_slots"] / shots}},
-                           "kernel_ms": r32["ms"], "kernel_hash": kernel_hash()}
+        out["fp32_vs_oracle"] = checks.get(32)
+        if 64 in checks:
+            out["fp64_vs_oracle"] = checks[64]
+        out["roofline"] = roofline(work, nsample, shots, r32["ms"], c)
     print(json.dumps(out))
 
 

@@ -330,6 +330,16 @@ int soft_variant_info(soft_ctx *ctx, uint32_t variant, uint64_t info[8]);
  * memory. */
 int soft_launch_shape(soft_ctx *ctx, uint32_t out[5]);
 
+/* Graph reuse of this context (the persistent launch is a hipGraph of two
+ * kernel nodes, Sec. IV-B's batched launches): out[0] = graph
+ * instantiations so far, out[1] = graph launches so far.  A run whose
+ * precision, noise source, tile placement and launch shape match an existing
+ * instantiation only updates the sampler node's arguments (shot range,
+ * outputs, ...), so a scan of equal batches instantiates at most twice (two
+ * instantiations are used in turn, so that one can be updated while the
+ * other runs). */
+int soft_graph_info(soft_ctx *ctx, uint64_t out[2]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,7 +43,12 @@ class _ShotInfo(ctypes.Structure):
                 ("obs", ctypes.c_uint32), ("max_support", ctypes.c_uint32),
                 ("t_entries", ctypes.c_uint64), ("t_phase_entries", ctypes.c_uint64),
                 ("m_entries", ctypes.c_uint64), ("noise_slots", ctypes.c_uint64),
-                ("events", ctypes.c_uint64), ("norm2", ctypes.c_double), ("noise_words", ctypes.c_uint64)]
+                ("events", ctypes.c_uint64), ("norm2", ctypes.c_double), ("noise_words", ctypes.c_uint64),
+                ("m_out_entries", ctypes.c_uint64), ("m_pairs", ctypes.c_uint64),
+                ("t_phase_flips", ctypes.c_uint64), ("meas_words", ctypes.c_uint64)]
+
+WORK_KEYS = ("t_entries", "t_phase_entries", "m_entries", "noise_slots", "events", "noise_words",
+             "m_out_entries", "m_pairs", "t_phase_flips", "meas_words")
 
 
 _lib = None
@@ -170,8 +175,7 @@ class Circuit:
         k = min(nc.value, coeff_cap)
         bits = [int((rec[i >> 5] >> (i & 31)) & 1) for i in range(self.n_records)]
         coeffs = {int(al[i]): complex(re[i], im[i]) for i in range(k)}
-        work = {f: int(getattr(info, f)) for f in ("t_entries", "t_phase_entries", "m_entries",
-                                                   "noise_slots", "events", "noise_words")}
+        work = {f: int(getattr(info, f)) for f in WORK_KEYS}
         return ShotResult(bits, info.status, info.abort_op, info.obs, info.max_support, tx, tz, tr,
                           coeffs, p0[: self.n_meas_slots], work, info.norm2)
 
@@ -186,7 +190,7 @@ class Circuit:
         abort_op = np.zeros(n, dtype=np.uint32)
         obs = np.zeros(n, dtype=np.uint32)
         maxs = np.zeros(n, dtype=np.uint32)
-        work = np.zeros(6, dtype=np.uint64)
+        work = np.zeros(len(WORK_KEYS), dtype=np.uint64)
         w = None
         if words is not None:
             w = np.ascontiguousarray(words, dtype=np.uint32)
@@ -198,6 +202,4 @@ class Circuit:
             raise RuntimeError("oracle_batch failed")
         return {"outcomes": outcomes[:nw], "status": status, "abort_op": abort_op, "obs": obs,
                 "max_support": maxs, "threads": threads,
-                "work": dict(zip(("t_entries", "t_phase_entries", "m_entries", "noise_slots", "events",
-                                  "noise_words"),
-                                 (int(x) for x in work)))}
+                "work": dict(zip(WORK_KEYS, (int(x) for x in work)))}

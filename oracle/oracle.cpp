@@ -510,7 +510,8 @@ void prune(std::map<uint64_t, cplx> &v, double tau) {
 // T^s on qubit q (s = +1 for T, -1 for T-dagger):
 // T^s = e^{i s theta} (cos theta I - i s sin theta Z_q), theta = pi/8 (Eqs. 1-2),
 // with Z_q |b_alpha> = c (-1)^{gamma.alpha} |b_{alpha^beta}> (Eq. 4).
-void apply_t(ShotState &st, int q, int s, double tau) {
+// *flips counts the entries that pick up the phase when beta = 0 (work count).
+void apply_t(ShotState &st, int q, int s, double tau, uint64_t *flips) {
     Pauli Z;
     Z.z = 1ULL << q;
     Decomp d = decompose(st, Z);
@@ -523,6 +524,7 @@ void apply_t(ShotState &st, int q, int s, double tau) {
     if (d.beta == 0) {
         for (const auto &kv : st.v) {
             cplx lam = c * sgn_parity(d.gamma & kv.first);
+            if (lam.real() < 0) ++*flips;
             out[kv.first] = glob * (cs + mi_s * sn * lam) * kv.second;
         }
     } else {
@@ -545,7 +547,8 @@ void apply_t(ShotState &st, int q, int s, double tau) {
 
 // Measurement of the Hermitian Pauli P with uniform u.  Returns the record
 // bit, or -1 for a numerically empty branch.  p0 receives P(outcome +1).
-int measure(ShotState &st, const Pauli &P, double u, double tau, double *p0_out) {
+// *pairs receives the number of representative pairs (beta != 0; work count).
+int measure(ShotState &st, const Pauli &P, double u, double tau, double *p0_out, uint64_t *pairs) {
     Decomp d = decompose(st, P);
     const cplx c = ipow(d.c_exp);
     const int n = st.n;
@@ -578,6 +581,7 @@ int measure(ShotState &st, const Pauli &P, double u, double tau, double *p0_out)
         uint64_t a = kv.first;
         reps.insert(bit(a, p) ? (a ^ d.beta) : a);
     }
+    *pairs += reps.size();
     std::map<uint64_t, cplx> wplus, wminus;
     double Np = 0.0, Nm = 0.0;
     for (uint64_t a : reps) {
@@ -694,7 +698,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 Z.z = 1ULL << o.a;
                 bool branching = decompose(st, Z).beta != 0;
                 if (!branching) res.info.t_phase_entries += st.v.size();
-                apply_t(st, o.a, o.kind == K_T ? +1 : -1, tau);
+                apply_t(st, o.a, o.kind == K_T ? +1 : -1, tau, &res.info.t_phase_flips);
                 if (branching) res.info.t_entries += st.v.size();
                 res.info.events++;
                 note_support();
@@ -715,7 +719,8 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 res.info.m_entries += st.v.size();
                 res.info.events++;
                 double p0 = 0.0;
-                int b = measure(st, P, uniform_of(meas_word(o.slot)), tau, &p0);
+                ++res.info.meas_words;
+                int b = measure(st, P, uniform_of(meas_word(o.slot)), tau, &p0, &res.info.m_pairs);
                 if (p0_trace) p0_trace[o.slot] = p0;
                 if (b < 0) {
                     res.info.status = ORACLE_NUMERIC;
@@ -723,6 +728,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                     res.info.norm2 = norm2(st.v);
                     return;
                 }
+                res.info.m_out_entries += st.v.size();
                 if (b && o.rec >= 0) res.record[o.rec >> 5] |= 1u << (o.rec & 31);
                 // resets bring outcome 1 back to the +1 eigenstate of the measured Pauli
                 if (b && (o.kind == K_R || o.kind == K_MR)) apply_clifford(st, K_X, o.a, -1);
@@ -885,7 +891,7 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
     if (threads < 1) threads = 1;
     const uint64_t stride = (uint64_t)c->n_noise + c->n_meas;
     const int nw = (c->n_rec + 31) / 32;
-    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(6, 0));
+    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(ORACLE_WORK_COUNT, 0));
     auto worker = [&](int t) {
         uint64_t lo = n * t / threads, hi = n * (t + 1) / threads;
         ShotState st;
@@ -904,6 +910,10 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
             part[t][3] += res.info.noise_slots;
             part[t][4] += res.info.events;
             part[t][5] += res.info.noise_words;
+            part[t][6] += res.info.m_out_entries;
+            part[t][7] += res.info.m_pairs;
+            part[t][8] += res.info.t_phase_flips;
+            part[t][9] += res.info.meas_words;
         }
     };
     std::vector<std::thread> pool;
@@ -911,7 +921,7 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
     worker(0);
     for (auto &th : pool) th.join();
     if (work)
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < ORACLE_WORK_COUNT; ++k) {
             work[k] = 0;
             for (int t = 0; t < threads; ++t) work[k] += part[t][k];
         }

@@ -75,7 +75,14 @@ typedef struct {
     uint64_t events;      /* T/TDG + measurements executed                       */
     double   norm2;       /* sum |v|^2 at the end                                */
     uint64_t noise_words; /* random words drawn for noise (one per slot in mode 0) */
+    uint64_t m_out_entries; /* sum over measurements of |v| after the op        */
+    uint64_t m_pairs;     /* sum over beta != 0 measurements of representative pairs */
+    uint64_t t_phase_flips; /* sum over T/TDG with beta == 0 of entries with lambda = -1 */
+    uint64_t meas_words;  /* measurement uniforms used (one per measurement)   */
 } oracle_shot_info;
+
+/* Number of work sums oracle_batch reports. */
+enum { ORACLE_WORK_COUNT = 10 };
 
 /* Run one shot.  words: NULL for Philox4x32-10 draws keyed by (seed, shot),
  * else explicit 32-bit words, [n_noise_slots] then [n_meas_slots].
@@ -96,9 +103,10 @@ int oracle_shot(const oracle_circuit *c, uint64_t seed, uint64_t shot,
 /* Run shots [shot0, shot0+n) on `threads` host threads.
  * words: NULL, or explicit words laid out [n][n_noise_slots + n_meas_slots].
  * outcomes: bit-planes [ceil(n_records/32)][n]; status/abort_op/obs: [n].
- * max_support: [n] or NULL.  work: NULL or 6 sums of the oracle_shot_info
- * counters (t_entries, t_phase_entries, m_entries, noise_slots, events,
- * noise_words). */
+ * max_support: [n] or NULL.  work: NULL or ORACLE_WORK_COUNT sums of the
+ * oracle_shot_info counters (t_entries, t_phase_entries, m_entries,
+ * noise_slots, events, noise_words, m_out_entries, m_pairs, t_phase_flips,
+ * meas_words). */
 int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0,
                  uint64_t n, const uint32_t *words, double tau, uint32_t cap,
                  int threads, uint32_t *outcomes, uint32_t *status,

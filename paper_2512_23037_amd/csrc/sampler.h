@@ -49,6 +49,13 @@ hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long 
 // The persistent sampler: grid x block threads, `lds` bytes of dynamic LDS.
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream);
 
+// Host handles of the kernels, for graphs built from explicit kernel nodes:
+// the sampler instantiation for a precision, noise source and tile placement
+// (arguments: ev, nz, tm1, det, words, bm, then the RunParams by value), and
+// the counter reset (arguments: counters, n, next; one block of 256 threads).
+const void *sampler_kernel(bool fp64, uint32_t noise_source, bool gt);
+const void *reset_kernel();
+
 // Blocks of `block` threads with `lds` bytes of dynamic LDS that one CU keeps
 // resident (registers and LDS).
 hipError_t sampler_occupancy(bool fp64, uint32_t noise_source, bool gt, int block, size_t lds, int *blocks_per_cu);

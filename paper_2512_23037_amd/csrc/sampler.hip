@@ -835,6 +835,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 const double ics = EVD(iCs2);
                 C x = v[lane & ((1u << k0) - 1u)];
                 bool fail = false;
+                uint32_t fi = 0;  // member whose check failed (the last one run)
                 for (uint32_t i = 0; i < m; ++i) {
                     const uint32_t mu = uni((uint32_t)__builtin_amdgcn_readlane((int)mv, (int)i));
                     const uint32_t gi = uni((uint32_t)__builtin_amdgcn_readlane((int)gv, (int)i));
@@ -862,12 +863,15 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     // lanes n/2 .. n-1 hold the entries with the dropped bit set
                     if (cnt > P.support_cap || (kb >> (n >> 1)) != 0ull) {
                         fail = true;
+                        fi = i;
                         break;
                     }
                     x = o;
                     --k;
                 }
                 if (fail) {
+                    // the attempt's work counts up to member fi, as with separate passes
+                    e += fi;
                     restart = true;
                     break;
                 }
@@ -1360,6 +1364,14 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
     }
     return hipGetLastError();
 }
+
+const void *sampler_kernel(bool fp64, uint32_t ns, bool gt) {
+    const void *ks[12];
+    all_kernels(ks);
+    return ks[kernel_index(fp64, ns, gt)];
+}
+
+const void *reset_kernel() { return (const void *)k_reset; }
 
 hipError_t sampler_occupancy(bool fp64, uint32_t ns, bool gt, int block, size_t lds, int *blocks_per_cu) {
     const void *ks[12];

@@ -112,9 +112,26 @@ struct soft_ctx {
     DevBuf<double> d_trace_v;
     uint32_t trace_tile = 0;
 
-    hipStream_t capture_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<unsigned char> gkey;
+    // The reset + sampler pair as a graph of two kernel nodes, instantiated
+    // twice (two slots used in turn).  A run whose kernel and launch shape
+    // match the slot's only updates the sampler node's arguments (shot range,
+    // outputs, ...), so one instantiation serves a whole scan; a slot is
+    // updated only after its previous launch has finished (its event), since
+    // an update may rewrite arguments a running launch still reads.
+    struct GraphSlot {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t sampler = nullptr;
+        hipEvent_t done = nullptr;   // recorded after the slot's last launch
+        bool launched = false;
+        std::vector<unsigned char> key;  // kernel, grid, block, LDS, counters
+        RunParams args;                  // argument storage of the sampler node
+        unsigned long long *r_counters = nullptr, *r_next = nullptr;  // reset node arguments
+        uint32_t r_n = 0;
+    };
+    GraphSlot slots[2];
+    uint32_t next_slot = 0;
+    uint64_t graph_instantiations = 0, graph_launches = 0;
 
     bool ran = false;
     hipStream_t last_stream = nullptr;
@@ -164,10 +181,20 @@ uint32_t wave_bytes(const soft_ctx *c, bool gt) {
     return gt ? std::max<uint32_t>(16u, recb) : ((tile_bytes(c) + 15u) & ~15u) + recb;
 }
 
+void drop_slot(soft_ctx *c, soft_ctx::GraphSlot &g) {
+    if (g.launched && g.done) (void)hipEventSynchronize(g.done);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    g.sampler = nullptr;
+    g.launched = false;
+    g.key.clear();
+    (void)c;
+}
+
 void drop_graph(soft_ctx *c) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-    c->gkey.clear();
+    for (auto &g : c->slots) drop_slot(c, g);
 }
 
 int compile_into(soft_ctx *c, const std::string &text, const NoiseModel &nm, Program &out, bool speculate = false) {
@@ -332,7 +359,9 @@ int check_shape(soft_ctx *c, const Shape &s) {
     return SOFT_OK;
 }
 
-// Launch reset + sampler on `stream` through a cached hipGraph.
+// Launch reset + sampler on `stream` through an instantiated graph: a slot
+// whose kernel and launch shape match gets the new arguments, else a slot is
+// built (reset node -> sampler node) and instantiated.
 int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStream_t stream) {
     const uint32_t wb = wave_bytes(c, s.gt);
     const size_t lds = (size_t)s.wpb * wb;
@@ -347,33 +376,75 @@ int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStrea
         if (rc) return rc;
         rp.gtile = c->d_gtile.p;
     }
-    std::vector<unsigned char> key(sizeof(RunParams) + 3 * sizeof(uint64_t) + sizeof(int));
-    unsigned char *kp = key.data();
-    std::memcpy(kp, &rp, sizeof(RunParams));
-    const uint64_t extra[3] = {grid, (uint64_t)b.x, (uint64_t)lds};
-    std::memcpy(kp + sizeof(RunParams), extra, sizeof(extra));
-    std::memcpy(kp + sizeof(RunParams) + sizeof(extra), &c->bits, sizeof(int));
-    if (!c->gexec || key != c->gkey) {
-        drop_graph(c);
-        hipGraph_t graph = nullptr;
-        HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = launch_reset(rp.counters, rp.n_vars * (uint32_t)C_COUNT, rp.next, c->capture_stream);
-        hipError_t e2 = e1 == hipSuccess ? launch_sampler(rp, c->bits == 64, g, b, lds, c->capture_stream) : e1;
-        hipError_t e3 = hipStreamEndCapture(c->capture_stream, &graph);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
-            return fail(c, SOFT_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        }
-        hipError_t e4 = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e4 != hipSuccess) {
-            c->gexec = nullptr;
-            return fail(c, SOFT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e4));
-        }
-        c->gkey = key;
+    const uint32_t ns = rp.words != nullptr ? NS_EXPLICIT : (rp.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
+    const void *kfn = sampler_kernel(c->bits == 64, ns, s.gt != 0);
+    // what the nodes' launch configuration and the reset node depend on
+    const uint64_t kv[7] = {(uint64_t)(uintptr_t)kfn, grid, (uint64_t)b.x, (uint64_t)lds,
+                            (uint64_t)(uintptr_t)rp.counters, (uint64_t)rp.n_vars, (uint64_t)(uintptr_t)rp.next};
+    std::vector<unsigned char> key((const unsigned char *)kv, (const unsigned char *)kv + sizeof(kv));
+    // The slot to use: one with this key whose last launch is done; else an
+    // empty one (instantiated below); else one with this key (after waiting
+    // for its launch); else the next in turn (rebuilt).
+    auto idle = [&](const soft_ctx::GraphSlot &gs) {
+        if (!gs.launched) return true;
+        const hipError_t q = hipEventQuery(gs.done);
+        if (q != hipSuccess) (void)hipGetLastError();  // "not ready" is no error here
+        return q == hipSuccess;
+    };
+    soft_ctx::GraphSlot *slot = nullptr;
+    for (auto &gs : c->slots)
+        if (!slot && gs.exec && gs.key == key && idle(gs)) slot = &gs;
+    for (auto &gs : c->slots)
+        if (!slot && !gs.exec) slot = &gs;
+    for (auto &gs : c->slots)
+        if (!slot && gs.key == key) slot = &gs;
+    if (!slot) {
+        slot = &c->slots[c->next_slot];
+        c->next_slot ^= 1u;
     }
-    HIPCHK(c, hipGraphLaunch(c->gexec, stream));
+    soft_ctx::GraphSlot &gs = *slot;
+    if (gs.launched) HIPCHK(c, hipEventSynchronize(gs.done));  // its previous launch may still read its arguments
+    gs.args = rp;
+    void *args[7] = {(void *)&gs.args.ev, (void *)&gs.args.nz, (void *)&gs.args.tm1, (void *)&gs.args.det,
+                     (void *)&gs.args.words, (void *)&gs.args.bm, (void *)&gs.args};
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void *>(kfn);
+    kp.gridDim = g;
+    kp.blockDim = b;
+    kp.sharedMemBytes = (unsigned int)lds;
+    kp.kernelParams = args;
+    if (gs.exec && gs.key == key) {
+        HIPCHK(c, hipGraphExecKernelNodeSetParams(gs.exec, gs.sampler, &kp));
+    } else {
+        drop_slot(c, gs);
+        gs.r_counters = rp.counters;
+        gs.r_n = rp.n_vars * (uint32_t)C_COUNT;
+        gs.r_next = rp.next;
+        void *rargs[3] = {(void *)&gs.r_counters, (void *)&gs.r_n, (void *)&gs.r_next};
+        hipKernelNodeParams rk;
+        std::memset(&rk, 0, sizeof(rk));
+        rk.func = const_cast<void *>(reset_kernel());
+        rk.gridDim = dim3(1);
+        rk.blockDim = dim3(256);
+        rk.kernelParams = rargs;
+        hipGraphNode_t rnode = nullptr;
+        hipError_t e = hipGraphCreate(&gs.graph, 0);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&rnode, gs.graph, nullptr, 0, &rk);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&gs.sampler, gs.graph, &rnode, 1, &kp);
+        if (e == hipSuccess) e = hipGraphInstantiate(&gs.exec, gs.graph, nullptr, nullptr, 0);
+        if (e == hipSuccess && !gs.done) e = hipEventCreateWithFlags(&gs.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            drop_slot(c, gs);
+            return fail(c, SOFT_EDEVICE, std::string("graph build: ") + hipGetErrorString(e));
+        }
+        gs.key = key;
+        ++c->graph_instantiations;
+    }
+    HIPCHK(c, hipGraphLaunch(gs.exec, stream));
+    HIPCHK(c, hipEventRecord(gs.done, stream));
+    gs.launched = true;
+    ++c->graph_launches;
     return SOFT_OK;
 }
 
@@ -591,7 +662,6 @@ int soft_create(soft_ctx **out, int hip_device) {
     if ((e = hipMalloc((void **)&c->d_counters, kCounterWords * sizeof(unsigned long long))) != hipSuccess)
         return bad(e, "hipMalloc");
     if ((e = hipMemset(c->d_counters, 0, kCounterWords * sizeof(unsigned long long))) != hipSuccess) return bad(e, "hipMemset");
-    if ((e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess) return bad(e, "hipStreamCreate");
     {
         double tab[32];
         for (int q = 0; q < 16; ++q) {
@@ -624,7 +694,8 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_trace_v);
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->d_phase) (void)hipFree(c->d_phase);
-    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (auto &g : c->slots)
+        if (g.done) (void)hipEventDestroy(g.done);
     delete c;
 }
 
@@ -961,6 +1032,13 @@ int soft_variant_info(soft_ctx *c, uint32_t variant, uint64_t info[8]) {
     if (!c->have_text) return fail(c, SOFT_ESTATE, "no circuit loaded");
     if (variant >= c->vars.size()) return fail(c, SOFT_EINVAL, "no such variant");
     program_info(c->vars[variant].prog, info);
+    return SOFT_OK;
+}
+
+int soft_graph_info(soft_ctx *c, uint64_t out[2]) {
+    if (!c || !out) return fail(c, SOFT_EINVAL, "null argument");
+    out[0] = c->graph_instantiations;
+    out[1] = c->graph_launches;
     return SOFT_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
            "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
-           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode")
+           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode", "soft_graph_info")
 
 
 class SoftError(RuntimeError):
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "soft_run_list": (I, [P, P, U64, P, P, P, P, P]),
         "soft_set_speculation": (I, [P, I]),
         "soft_set_noise_mode": (I, [P, I]),
+        "soft_graph_info": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -295,6 +296,13 @@ class Context:
             self._check(self._lib.soft_variant_info(self._h, variant, _ptr(a)))
         keys = ("qubits", "records", "noise_slots", "meas_slots", "observables", "events", "k_max", "record_words")
         return {k: int(v) for k, v in zip(keys, a)}
+
+    def graph_info(self) -> dict:
+        """Graph instantiations and launches of this context so far."""
+        import numpy as np
+        a = np.zeros(2, dtype=np.uint64)
+        self._check(self._lib.soft_graph_info(self._h, _ptr(a)))
+        return {"instantiations": int(a[0]), "launches": int(a[1])}
 
     def launch_shape(self) -> dict:
         import numpy as np

@@ -77,6 +77,7 @@ def run_batches(ctx, shot0: int, total: int, batch: int, stream=None, progress=N
     sums = [None] * nv
     stream = stream or torch.cuda.current_stream()
     torch.cuda.synchronize()
+    g0 = ctx.graph_info()
     t0 = time.perf_counter()
     done = 0
     while done < total:
@@ -97,7 +98,10 @@ def run_batches(ctx, shot0: int, total: int, batch: int, stream=None, progress=N
         done += n
         if progress:
             progress(done, total, time.perf_counter() - t0)
-    return {"variants": sums, "seconds": time.perf_counter() - t0}
+    g1 = ctx.graph_info()
+    return {"variants": sums, "seconds": time.perf_counter() - t0,
+            "graph_instantiations": g1["instantiations"] - g0["instantiations"],
+            "launches": g1["launches"] - g0["launches"]}
 
 
 def rates(c: dict) -> dict:

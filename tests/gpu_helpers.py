@@ -81,3 +81,44 @@ def compare_kept(ctx, circ, seed, shots, words=None, tol=1e-10, cap=0xFFFFFFFF, 
         assert err <= tol, "shot %d coefficient error %g" % (shot, err)
         worst = max(worst, err)
     return worst
+
+
+def oracle_shots(circ, seed, shots, tau=1e-12, cap=0xFFFFFFFF, threads=16):
+    """Oracle results of single shots, computed on a pool of host threads (the
+    oracle's C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        return list(pool.map(lambda s: circ.shot(seed, int(s), tau=tau, cap=cap), shots))
+
+
+def compare_kept_many(ctx, circ, seed, shots, tol=1e-10, tau=1e-12):
+    """compare_kept for Philox-drawn shots, with the oracle on host threads.
+    Returns the largest coefficient error."""
+    worst = 0.0
+    for shot, r in zip(shots, oracle_shots(circ, seed, shots, tau=tau)):
+        x, z, rr = ctx.read_tableau(int(shot))
+        assert (x == r.tab_x).all() and (z == r.tab_z).all(), "tableau x/z differ at shot %d" % shot
+        assert (rr == r.tab_r).all(), "tableau signs differ at shot %d" % shot
+        err = coeff_error(ctx.read_coeffs(int(shot)), r.coeffs)
+        assert err <= tol, "shot %d coefficient error %g" % (shot, err)
+        worst = max(worst, err)
+    return worst
+
+
+def guard_band_flips(circ, seed, ref_p0_shots, band=1e-5):
+    """For each listed oracle result (shot, ShotResult): True when some
+    measurement's uniform lies within `band` of the oracle's P(+1), i.e. an
+    FP32 run may take the other branch there (the near-tie rule)."""
+    out = []
+    for shot, r in ref_p0_shots:
+        near = False
+        for slot in range(circ.n_meas_slots):
+            p = r.p0[slot]
+            if np.isnan(p):
+                continue
+            blk = oracle.philox([slot >> 2, int(shot) & 0xFFFFFFFF, int(shot) >> 32, 1],
+                                [seed & 0xFFFFFFFF, seed >> 32])
+            u = (float(blk[slot & 3]) + 0.5) / 2 ** 32
+            near |= abs(u - p) < band
+        out.append(near)
+    return out

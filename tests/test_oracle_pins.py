@@ -619,3 +619,105 @@ def test_forced_dep2_code_mapping():
         words = np.array([w, 3, 3], dtype=np.uint32)
         assert zc.shot(0, 0, words=words).record == [int(pa in (1, 2)), int(pb in (1, 2))]
         assert xc.shot(0, 0, words=words).record == [int(pa in (2, 3)), int(pb in (2, 3))]
+
+
+# ---------------------------------------------------------------------------
+# The top bits of the 64-bit words (n = 64)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(4))
+def test_clifford_only_matches_chp_64_qubits(seed):
+    # 64 qubits: every bit of the x/z words and of the two sign words, and
+    # qubit 63 in particular, against the independent CHP tableau.
+    n = 64
+    text, _ = random_circuit(2500 + seed, n, 500, clifford_only=True, allow_mpp=False,
+                             gates=("H", "S", "SDG", "CX", "CZ"))
+    lines = text.strip().split("\n")
+    lines += ["H 63", "CX 63 0", "S 63", "M 63", "CZ 62 63", "M 0"]
+    text = "\n".join(lines) + "\n"
+    c = oracle.Circuit(text)
+    words = random_words(seed, c.words_per_shot)
+    r = c.shot(0, 0, words=words)
+    sim, record = ref_chp.run(text, words[c.n_noise_slots:])
+    assert r.record == record
+    assert [int(v) for v in r.tab_x] == sim.x[: 2 * n]
+    assert [int(v) for v in r.tab_z] == sim.z[: 2 * n]
+    assert [int(v) for v in r.tab_r] == sim.r[: 2 * n]
+    assert any(int(v) >> 63 for v in r.tab_x) and any(int(v) >> 63 for v in r.tab_z)
+
+
+def _relabel(text, f):
+    """The same circuit with qubit q renamed f(q) (QUBITS line left out)."""
+    out = []
+    for line in text.strip().split("\n")[1:]:
+        tok = line.split()
+        g = tok[0]
+        if g == "MPP":
+            facs = ["%s%d" % (x[0], f(int(x[1:]))) for x in tok[1].split("*")]
+            out.append("MPP " + "*".join(facs))
+        elif g in ("DETECTOR", "OBSERVABLE"):
+            out.append(line)
+        elif g in ("XIF", "YIF", "ZIF"):
+            out.append("%s %s %d" % (g, tok[1], f(int(tok[2]))))
+        elif g in ("DEP1", "DEP2", "XERR", "ZERR"):
+            out.append("%s %s %s" % (g, tok[1], " ".join(str(f(int(q))) for q in tok[2:])))
+        else:
+            out.append(" ".join([g] + [str(f(int(q))) for q in tok[1:]]))
+    return "\n".join(out) + "\n"
+
+
+def _spread(x, f, n):
+    y = 0
+    for q in range(n):
+        if (x >> q) & 1:
+            y |= 1 << f(q)
+    return y
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_relabel_onto_64_qubits(seed):
+    # An 8-qubit Clifford+T+measurement circuit (pinned to the dense
+    # statevector by the tests above) renamed onto 8 of 64 qubits by an
+    # increasing map that uses qubit 63: the other 56 qubits stay idle, the
+    # pivots keep their order, so records, tableau rows and coefficients are
+    # the 8-qubit ones with every index renamed.
+    n = 8
+    text, _ = random_circuit(2700 + seed, n, 120, p_msc=0.1 if seed % 2 else 0.0, p_ccz=0.03)
+    f = (lambda q: 9 * q) if seed % 2 == 0 else (lambda q: 56 + q)
+    wide = "QUBITS 64\n" + _relabel(text, f)
+    assert f(7) == 63
+    c8, c64 = oracle.Circuit(text), oracle.Circuit(wide)
+    assert c8.words_per_shot == c64.words_per_shot
+    words = random_words(seed, c8.words_per_shot)
+    a, b = c8.shot(0, 0, words=words), c64.shot(0, 0, words=words)
+    assert a.record == b.record and a.status == b.status
+    inv = {f(q): q for q in range(n)}
+    for i in range(64):
+        src = inv.get(i)
+        for half in (0, 64):
+            if src is None:
+                ex = (1 << i, 0) if half == 0 else (0, 1 << i)
+                assert (int(b.tab_x[half + i]), int(b.tab_z[half + i]), int(b.tab_r[half + i])) == ex + (0,)
+            else:
+                j = (0 if half == 0 else n) + src
+                assert int(b.tab_x[half + i]) == _spread(int(a.tab_x[j]), f, n)
+                assert int(b.tab_z[half + i]) == _spread(int(a.tab_z[j]), f, n)
+                assert int(b.tab_r[half + i]) == int(a.tab_r[j])
+    assert {_spread(k, f, n): v for k, v in a.coeffs.items()} == pytest.approx(b.coeffs, abs=1e-14)
+
+
+def test_work_counts_closed_forms():
+    # The oracle's work counts that price the roofline, on states whose
+    # supports are known in closed form.
+    def work(text):
+        c = oracle.Circuit(text)
+        return c.shot(0, 0, words=np.full(c.words_per_shot, 1 << 31, dtype=np.uint32)).work
+    w = work("QUBITS 1\nX 0\nT 0\n")        # |1>: Z_0 = -s_0, lambda = -1 on the one entry
+    assert (w["t_phase_entries"], w["t_phase_flips"], w["t_entries"]) == (1, 1, 0)
+    w = work("QUBITS 1\nT 0\n")             # |0>: lambda = +1
+    assert (w["t_phase_entries"], w["t_phase_flips"]) == (1, 0)
+    w = work("QUBITS 1\nH 0\nT 0\nMPP X0\n")  # T|+>: two entries; X_0 = s_0 splits them by parity
+    assert (w["t_entries"], w["m_entries"], w["m_out_entries"], w["m_pairs"], w["meas_words"]) == (2, 2, 1, 0, 1)
+    w = work("QUBITS 1\nH 0\nT 0\nM 0\n")     # Z_0 anticommutes with s_0: one representative pair
+    assert (w["m_entries"], w["m_out_entries"], w["m_pairs"], w["meas_words"]) == (2, 1, 1, 1)
+    w = work("QUBITS 2\nH 0\nH 1\nT 0\nT 1\nM 0\nM 1\n")
+    assert (w["t_entries"], w["m_entries"], w["m_pairs"], w["m_out_entries"], w["events"]) == (2 + 4, 4 + 2, 2 + 1, 2 + 1, 4)

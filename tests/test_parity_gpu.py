@@ -11,7 +11,8 @@ import oracle
 import workloads
 from paper_2512_23037_amd import soft
 from tests.gen_small import random_circuit, random_words
-from tests.gpu_helpers import compare_batch, compare_kept, make_ctx, run_gpu, torch
+from tests.gpu_helpers import (compare_batch, compare_kept, compare_kept_many, guard_band_flips, make_ctx,
+                               oracle_shots, run_gpu, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -244,33 +245,41 @@ def test_speculation_noiseless_never_restarts():
     assert ctx.counters()["restarts"] == 0
 
 
+@pytest.mark.parametrize("noise_mode", [0, 1])
 @pytest.mark.parametrize("bits,tol", [(64, 1e-10), (32, 1e-5)])
-def test_cultivation_42q_subset(bits, tol):
+def test_cultivation_42q_oracle_subset(bits, tol, noise_mode):
+    # The precision configuration's oracle subset: shots 0..9999 of the
+    # 42-qubit workload, FP64 and FP32, per-slot draws and gap sampling.
+    # Records, statuses, abort ops and observables of every shot bit-exact
+    # (FP32: a shot may differ only where a draw lies within 1e-5 of the
+    # oracle's probability); kept tableaux and coefficients of every passed
+    # shot and of every fifth other shot.
     w = workloads.config("cultivation_42q", seed=1)
-    circ = oracle.Circuit(w.text, w.noise)
-    N = 3000
-    ctx = make_ctx(w.text, w.noise, seed=11, bits=bits, keep=(0, 200))
+    circ = oracle.Circuit(w.text, w.noise, noise_mode=noise_mode)
+    N = 10000
+    seed = 11 + noise_mode
+    ctx = make_ctx(w.text, w.noise, seed=seed, bits=bits, keep=(0, N))
+    ctx.set_noise_mode(noise_mode)
     gpu = run_gpu(ctx, 0, N)
-    ref = circ.batch(11, 0, N)
+    ref = circ.batch(seed, 0, N)
     diff = (gpu["status"] != ref["status"]) | (gpu["outcomes"] != ref["outcomes"]).any(axis=0)
     if bits == 64:
         assert not diff.any()
     else:
-        # FP32: an outcome may differ only where the draw lies within 1e-5 of
-        # the oracle's probability (guard band); such shots are reported.
-        for shot in np.nonzero(diff)[0][:20]:
-            r = circ.shot(11, int(shot))
-            us = []
-            for slot in range(circ.n_meas_slots):
-                blk = oracle.philox([slot >> 2, int(shot) & 0xFFFFFFFF, int(shot) >> 32, 1], [11, 0])
-                us.append((float(blk[slot & 3]) + 0.5) / 2 ** 32)
-            near = [abs(u - p) < 1e-5 for u, p in zip(us, r.p0) if not np.isnan(p)]
-            assert any(near), "FP32 outcome flip outside the guard band at shot %d" % shot
-        assert diff.sum() <= 3
+        flips = np.nonzero(diff)[0]
+        assert len(flips) <= 5
+        res = oracle_shots(circ, seed, flips)
+        assert all(guard_band_flips(circ, seed, list(zip(flips, res)))), \
+            "FP32 outcome flip outside the guard band"
     compare_batch(gpu, ref, skip=diff)
-    kept = [s for s in range(200) if not diff[s]]
-    worst = compare_kept(ctx, circ, 11, kept, tol=tol, tau=1e-12 if bits == 64 else 1e-6)
-    print("bits=%d worst coefficient error %.3g" % (bits, worst))
+    passed = np.nonzero((ref["status"] == oracle.PASSED) & ~diff)[0]
+    assert len(passed) > 50
+    others = [s for s in range(0, N, 5) if not diff[s] and ref["status"][s] != oracle.PASSED]
+    shots = sorted(set(passed.tolist()) | set(others))
+    assert len(shots) >= 1000
+    worst = compare_kept_many(ctx, circ, seed, shots, tol=tol, tau=1e-12 if bits == 64 else 1e-6)
+    print("bits=%d mode=%d: %d kept shots (%d passed), worst coefficient error %.3g, %d guard-band flips"
+          % (bits, noise_mode, len(shots), len(passed), worst, int(diff.sum())))
 
 
 def test_full_size_sampled_shots():
@@ -405,3 +414,37 @@ def test_work_counters_closed_forms(mode):
     assert c2["entries_t"] == c["entries_t"] and c2["events"] == N * 7
     assert c2["entries_m"] == N * 32
     assert c2["noise_slots"] == N * (3 if mode == 0 else 256)
+
+
+def test_graph_reused_across_batches():
+    # A scan of equal batches launched back to back without synchronizing:
+    # one instantiated graph per slot serves every batch (only the sampler
+    # node's arguments change), and the batches equal one large run.
+    w = workloads.config("cultivation_15q", seed=3)
+    t = torch()
+    big = make_ctx(w.text, w.noise, seed=29)
+    ref = run_gpu(big, 0, 160000)
+    ctx = make_ctx(w.text, w.noise, seed=29)
+    nb, B = 16, 10000
+    outs = [soft.sample(ctx, b * B, B) for b in range(nb)]
+    t.cuda.synchronize()
+    gi = ctx.graph_info()
+    assert gi["launches"] == nb and gi["instantiations"] <= 2
+    nw = ref["outcomes"].shape[0]
+    for b, (oc, st, ab, ob) in enumerate(outs):
+        sl = slice(b * B, (b + 1) * B)
+        assert (st.cpu().numpy().view(np.uint32) == ref["status"][sl]).all(), b
+        assert (ab.cpu().numpy().view(np.uint32) == ref["abort_op"][sl]).all(), b
+        assert (ob.cpu().numpy().view(np.uint32) == ref["obs"][sl]).all(), b
+        assert (oc.cpu().numpy().view(np.uint32)[:nw] == ref["outcomes"][:, sl]).all(), b
+    # the last batch's counters are its own
+    c = ctx.counters()
+    assert c["shots"] == B
+    assert c["passed"] == int((ref["status"][(nb - 1) * B:] == 0).sum())
+    # a different precision instantiates again; going back reuses a slot
+    ctx.set_precision(32)
+    run_gpu(ctx, 0, B)
+    ctx.set_precision(64)
+    again = run_gpu(ctx, 0, B)
+    assert (again["status"] == ref["status"][:B]).all()
+    assert ctx.graph_info()["instantiations"] <= 4

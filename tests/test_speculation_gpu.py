@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_helpers import compare_batch, compare_kept, make_ctx, run_gpu
+from tests.gpu_helpers import coeff_error, compare_batch, compare_kept, make_ctx, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -68,22 +68,41 @@ def test_bracket_circuits_capped(seed):
         ctx.close()
 
 
-@pytest.mark.parametrize("noise_mode", [0, 1])
-def test_42q_speculative_list_equals_full_list(noise_mode):
+@pytest.mark.parametrize("noise_mode,bits", [(0, 64), (1, 64), (1, 32)])
+def test_42q_speculative_list_equals_full_list(noise_mode, bits):
     # The benchmark workload at scale: the speculative list (reordered layers,
     # folded drops, fused runs of doublings and of dropping butterflies) must
     # give the full list's records, statuses, abort ops and observables for
-    # every shot (FP64), with restarts where noise broke a cancellation.
+    # every shot (FP64; FP32 may differ only at near-ties of the two summation
+    # orders), with restarts where noise broke a cancellation, and the same
+    # final coefficients for the 512 kept shots (restarted ones among them):
+    # within 1e-10 in FP64, 1e-5 in FP32.
     w = workloads.config("cultivation_42q", seed=1)
     N = 2_000_000
-    outs, restarts = {}, {}
+    K = 512
+    outs, restarts, kept = {}, {}, {}
     for spec in (True, False):
-        ctx = make_ctx(w.text, w.noise, seed=20251223, bits=64)
+        ctx = make_ctx(w.text, w.noise, seed=20251223, bits=bits, keep=(0, K))
         ctx.set_noise_mode(noise_mode)
         ctx.set_speculation(spec)
         outs[spec] = run_gpu(ctx, 0, N)
         restarts[spec] = ctx.counters()["restarts"]
+        kept[spec] = [ctx.read_coeffs(s_) for s_ in range(K)]
+        if spec:
+            # the kept range itself holds restarted shots
+            run_gpu(ctx, 0, K)
+            assert ctx.counters()["restarts"] > 0
         ctx.close()
     assert restarts[False] == 0 and restarts[True] > 0
-    for key in ("status", "abort_op", "obs", "outcomes"):
-        assert (outs[True][key] == outs[False][key]).all(), key
+    diff = (outs[True]["status"] != outs[False]["status"]) | (outs[True]["outcomes"] != outs[False]["outcomes"]).any(axis=0)
+    assert diff.sum() == 0 if bits == 64 else diff.sum() <= 4
+    for key in ("status", "abort_op", "obs"):
+        assert (outs[True][key][~diff] == outs[False][key][~diff]).all(), key
+    tol = 1e-10 if bits == 64 else 1e-5
+    worst = 0.0
+    for s_ in range(K):
+        if not diff[s_]:
+            err = coeff_error(kept[True][s_], kept[False][s_])
+            assert err < tol, (s_, err)
+            worst = max(worst, err)
+    print("bits=%d mode=%d worst speculative-vs-full coefficient difference %.3g" % (bits, noise_mode, worst))
