@@ -82,7 +82,8 @@ enum Kind {
     K_M, K_MPP, K_R, K_MX, K_RX, K_MR, K_MRX,
     K_DEP1, K_DEP2, K_XERR, K_ZERR, K_FLIP,
     K_DETECTOR, K_OBSERVABLE,
-    K_FEEDBACK  // Pauli `b` (1 X, 2 Y, 3 Z) on qubit a when record bit `rec` is 1
+    K_FEEDBACK,  // Pauli `b` (1 X, 2 Y, 3 Z) on qubit a when record bit `rec` is 1
+    K_DIAG       // diagonal gate: phase e^{i phi[x]} on basis state x of qubits qs (bit j = qubit qs[j])
 };
 
 struct Op {
@@ -97,6 +98,8 @@ struct Op {
     int slot = -1;            // noise slot (noise ops) or measurement slot
     int rec = -1;             // record written (M, MPP) or flipped (FLIP)
     int obs = -1;             // observable index
+    std::vector<int> qs;      // DIAG qubits
+    std::vector<double> phi;  // DIAG phases, 2^|qs| of them
 };
 
 }  // namespace
@@ -226,32 +229,65 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             c.ops.push_back(o);
             active[q] = 1;
             add_noise(K_XERR, nm.p_reset, q, -1, src);
-        } else if (name == "CCZ" || name == "CCX") {
-            // CCZ = exp(i pi x_a x_b x_c) in the computational basis, and
-            // 4 xyz = x + y + z - (x^y) - (x^z) - (y^z) + (x^y^z), so CCZ is T
-            // (diag(1, e^{i pi/4})) on a, b, c and on a^b^c, and T-dagger on
-            // a^b, a^c, b^c; a parity is formed on a target by CNOTs and undone
-            // after.  CCX conjugates the target by H.
-            if (tok.size() != 4) throw ParseError{line, name + " takes three qubits"};
-            int a = qubit(tok[1]), b = qubit(tok[2]), t = qubit(tok[3]);
-            if (a == b || a == t || b == t) throw ParseError{line, name + " on repeated qubits"};
-            auto gate = [&](Kind k, int q0, int q1) {
-                Op o;
-                o.kind = k; o.a = q0; o.b = q1; o.src = src;
-                c.ops.push_back(o);
+        } else if (name == "CCZ" || name == "CCX" || name == "CS" || name == "CSDG" || name == "CPHASE" ||
+                   name == "RZ" || name == "DIAG") {
+            // Diagonal gates, each one multiplying computational basis state x
+            // of its qubits (bit j of x = qubit qs[j]) by e^{i phi[x]}:
+            //   CCZ a b c: phi = pi where a = b = c = 1;  CCX = H_c CCZ H_c;
+            //   CS a b / CSDG a b: phi = +-pi/2 where a = b = 1;
+            //   CPHASE theta a b: phi = theta where a = b = 1;
+            //   RZ theta q: exp(-i theta Z / 2), phi = (-theta/2, +theta/2);
+            //   DIAG k q_0 .. q_{k-1} phi_0 .. phi_{2^k - 1} (k = 1..3, radians).
+            Op o;
+            o.kind = K_DIAG;
+            o.src = src;
+            const double pi = 3.14159265358979323846;
+            size_t nq = 0, first = 1;
+            if (name == "CCZ" || name == "CCX") nq = 3;
+            else if (name == "CS" || name == "CSDG") nq = 2;
+            else if (name == "CPHASE") { nq = 2; first = 2; }
+            else if (name == "RZ") { nq = 1; first = 2; }
+            else {
+                if (tok.size() < 2) throw ParseError{line, "DIAG takes k, k qubits and 2^k phases"};
+                const int k = to_int(tok[1], line);
+                if (k < 1 || k > 3) throw ParseError{line, "DIAG takes 1 to 3 qubits"};
+                nq = (size_t)k;
+                first = 2;
+            }
+            const size_t want = name == "DIAG" ? first + nq + (1u << nq) : first + nq;
+            if (tok.size() != want) throw ParseError{line, name + ": wrong number of arguments"};
+            for (size_t i = 0; i < nq; ++i) o.qs.push_back(qubit(tok[first + i]));
+            for (size_t i = 0; i < nq; ++i)
+                for (size_t j = 0; j < i; ++j)
+                    if (o.qs[i] == o.qs[j]) throw ParseError{line, name + " on repeated qubits"};
+            auto angle = [&](const std::string &t) {
+                char *end = nullptr;
+                double v = std::strtod(t.c_str(), &end);
+                if (end == t.c_str() || *end != '\0' || !std::isfinite(v)) throw ParseError{line, "bad angle '" + t + "'"};
+                return v;
             };
-            if (name == "CCX") gate(K_H, t, -1);
-            gate(K_T, a, -1);
-            gate(K_T, b, -1);
-            gate(K_T, t, -1);
-            gate(K_CX, a, b); gate(K_TDG, b, -1); gate(K_CX, a, b);              // a^b
-            gate(K_CX, a, t); gate(K_TDG, t, -1); gate(K_CX, a, t);              // a^t
-            gate(K_CX, b, t); gate(K_TDG, t, -1); gate(K_CX, b, t);              // b^t
-            gate(K_CX, a, t); gate(K_CX, b, t); gate(K_T, t, -1);                // a^b^t
-            gate(K_CX, b, t); gate(K_CX, a, t);
-            if (name == "CCX") gate(K_H, t, -1);
-            active[a] = active[b] = active[t] = 1;
-            for (int q : {a, b, t}) add_noise(K_DEP1, nm.p1, q, -1, src);
+            o.phi.assign((size_t)1 << nq, 0.0);
+            if (name == "CCZ" || name == "CCX") o.phi[7] = pi;
+            else if (name == "CS") o.phi[3] = pi / 2;
+            else if (name == "CSDG") o.phi[3] = -pi / 2;
+            else if (name == "CPHASE") o.phi[3] = angle(tok[1]);
+            else if (name == "RZ") { o.phi[0] = -angle(tok[1]) / 2; o.phi[1] = angle(tok[1]) / 2; }
+            else
+                for (size_t x = 0; x < o.phi.size(); ++x) o.phi[x] = angle(tok[first + nq + x]);
+            auto hgate = [&](int q) {
+                Op h;
+                h.kind = K_H; h.a = q; h.src = src;
+                c.ops.push_back(h);
+            };
+            if (name == "CCX") hgate(o.qs[2]);
+            c.ops.push_back(o);
+            if (name == "CCX") hgate(o.qs[2]);
+            for (int q : o.qs) active[q] = 1;
+            // model noise: DEP2(p2) after a two-qubit diagonal gate, DEP1(p1)
+            // on each qubit after a one- or three-qubit one
+            if (nq == 2) add_noise(K_DEP2, nm.p2, o.qs[0], o.qs[1], src);
+            else
+                for (int q : o.qs) add_noise(K_DEP1, nm.p1, q, -1, src);
         } else if (name == "MX" || name == "RX" || name == "MR" || name == "MRX") {
             // X-basis measurement / reset to |+>, and measure-then-reset.  The
             // measurement-error flip before a readout and the reset-error flip
@@ -545,6 +581,29 @@ void apply_t(ShotState &st, int q, int s, double tau, uint64_t *flips) {
     prune(st.v, tau);
 }
 
+// Diagonal gate U = sum_x e^{i phi_x} |x><x| on the qubits qs.  Expanded over
+// the Z-strings of those qubits (the expansion behind Proposition 1),
+// U = sum_g c_g Z^g with c_g = 2^-m sum_x e^{i phi_x} (-1)^{g.x}, and each
+// Z^g acts on the basis by Eq. 4: Z^g |b_alpha> = c (-1)^{gamma.alpha}
+// |b_{alpha ^ beta}>.  One pass over the 2^m terms.
+void apply_diag(ShotState &st, const std::vector<int> &qs, const std::vector<double> &phi, double tau) {
+    const size_t m = qs.size(), ng = (size_t)1 << m;
+    std::map<uint64_t, cplx> out;
+    for (size_t g = 0; g < ng; ++g) {
+        cplx cg(0.0, 0.0);
+        for (size_t x = 0; x < ng; ++x) cg += std::exp(cplx(0.0, phi[x])) * sgn_parity((uint64_t)(g & x));
+        cg /= (double)ng;
+        Pauli Z;
+        for (size_t j = 0; j < m; ++j)
+            if ((g >> j) & 1) Z.z |= 1ULL << qs[j];
+        const Decomp d = decompose(st, Z);
+        const cplx w = cg * ipow(d.c_exp);
+        for (const auto &kv : st.v) out[kv.first ^ d.beta] += w * sgn_parity(d.gamma & kv.first) * kv.second;
+    }
+    st.v.swap(out);
+    prune(st.v, tau);
+}
+
 // Measurement of the Hermitian Pauli P with uniform u.  Returns the record
 // bit, or -1 for a numerically empty branch.  p0 receives P(outcome +1).
 // *pairs receives the number of representative pairs (beta != 0; work count).
@@ -700,6 +759,19 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 if (!branching) res.info.t_phase_entries += st.v.size();
                 apply_t(st, o.a, o.kind == K_T ? +1 : -1, tau, &res.info.t_phase_flips);
                 if (branching) res.info.t_entries += st.v.size();
+                res.info.events++;
+                note_support();
+                if (st.v.size() > cap) {
+                    res.info.status = ORACLE_OVERFLOW;
+                    res.info.abort_op = o.src;
+                    res.info.norm2 = norm2(st.v);
+                    return;
+                }
+                break;
+            }
+            case K_DIAG: {
+                apply_diag(st, o.qs, o.phi, tau);
+                res.info.t_entries += st.v.size();
                 res.info.events++;
                 note_support();
                 if (st.v.size() > cap) {

@@ -7,7 +7,7 @@ import numpy as np
 def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: float = 0.08,
                    p_mpp: float = 0.04, p_reset: float = 0.03, p_pauli: float = 0.08,
                    clifford_only: bool = False, allow_mpp: bool = True, gates=("H", "S", "SDG", "CX", "CZ"),
-                   p_msc: float = 0.0, p_ccz: float = 0.0):
+                   p_msc: float = 0.0, p_ccz: float = 0.0, p_diag: float = 0.0):
     """Random circuit text and its measurement-slot count.  With p_msc > 0, a
     fraction p_msc of the ops come from the extended set: H_XY, H_NXY, MX,
     RX, MR, MRX and record-controlled Paulis XIF/YIF/ZIF; with p_ccz > 0 (and
@@ -15,6 +15,7 @@ def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: fl
     rng = np.random.Generator(np.random.PCG64(seed))
     msc = rng if p_msc > 0 else None
     ccz = rng if p_ccz > 0 and n >= 3 else None
+    dg = rng if p_diag > 0 else None
     n_rec = 0
     if clifford_only:
         p_t = 0.0
@@ -23,6 +24,9 @@ def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: fl
     lines = ["QUBITS %d" % n]
     n_meas_slots = 0
     for _ in range(length):
+        if dg is not None and dg.random() < p_diag:
+            lines.append(random_diag(dg, n))
+            continue
         if ccz is not None and ccz.random() < p_ccz:
             a, b, t = (int(x) for x in ccz.choice(n, size=3, replace=False))
             lines.append("%s %d %d %d" % ("CCZ" if ccz.integers(2) == 0 else "CCX", a, b, t))
@@ -68,6 +72,24 @@ def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: fl
             else:
                 lines.append("%s %d" % (g, rng.integers(n)))
     return "\n".join(lines) + "\n", n_meas_slots
+
+
+def random_diag(rng, n: int) -> str:
+    """One diagonal gate: CS, CSDG, CPHASE, RZ, CCZ or a general DIAG on 1-3
+    distinct qubits, angles drawn uniformly (printed exactly)."""
+    kinds = ["RZ", "DIAG1"] + (["CS", "CSDG", "CPHASE", "DIAG2"] if n >= 2 else []) + (["CCZ", "DIAG3"] if n >= 3 else [])
+    kind = kinds[int(rng.integers(len(kinds)))]
+    ang = lambda: repr(float(rng.uniform(-np.pi, np.pi)))  # noqa: E731
+    if kind.startswith("DIAG"):
+        k = int(kind[4])
+        qs = [int(x) for x in rng.choice(n, size=k, replace=False)]
+        return "DIAG %d %s %s" % (k, " ".join(map(str, qs)), " ".join(ang() for _ in range(1 << k)))
+    if kind == "RZ":
+        return "RZ %s %d" % (ang(), int(rng.integers(n)))
+    if kind == "CCZ":
+        return "CCZ %s" % " ".join(str(int(x)) for x in rng.choice(n, size=3, replace=False))
+    a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+    return "CPHASE %s %d %d" % (ang(), a, b) if kind == "CPHASE" else "%s %d %d" % (kind, a, b)
 
 
 def random_words(seed: int, count: int) -> np.ndarray:

@@ -130,6 +130,28 @@ def run(text, meas_words):
                 phi = np.where(on & ((idx >> np.uint64(t)) & np.uint64(1)).astype(bool), -phi, phi)
             else:
                 phi = phi[np.where(on, idx ^ (np.uint64(1) << np.uint64(t)), idx)]
+        elif g in ("CS", "CSDG", "CPHASE", "RZ", "DIAG"):
+            # textbook diagonal matrices: CS = diag(1, 1, 1, i), CSDG its
+            # inverse, CPHASE(t) = diag(1, 1, 1, e^{it}), RZ(t) = exp(-i t Z / 2)
+            # = diag(e^{-it/2}, e^{it/2}); DIAG k q.. phases: entry x of the
+            # qubits (bit j = qubit q_j) gets e^{i phase_x}.  Non-Clifford in
+            # general: the shadow stays.
+            if g == "DIAG":
+                k = int(tok[1])
+                qs = [int(t) for t in tok[2:2 + k]]
+                ph = [float(t) for t in tok[2 + k:]]
+            elif g == "RZ":
+                qs, t = [int(tok[2])], float(tok[1])
+                ph = [-t / 2, t / 2]
+            elif g == "CPHASE":
+                qs, ph = [int(tok[2]), int(tok[3])], [0.0, 0.0, 0.0, float(tok[1])]
+            else:
+                qs, ph = [int(tok[1]), int(tok[2])], [0.0, 0.0, 0.0, np.pi / 2 if g == "CS" else -np.pi / 2]
+            idx = np.arange(1 << n, dtype=np.uint64)
+            x = np.zeros(1 << n, dtype=np.int64)
+            for j, q in enumerate(qs):
+                x |= ((idx >> np.uint64(q)) & np.uint64(1)).astype(np.int64) << j
+            phi = phi * np.exp(1j * np.asarray(ph))[x]
         elif g in ("XIF", "YIF", "ZIF"):
             # classically controlled Pauli
             if record[int(tok[1])]:

@@ -721,3 +721,100 @@ def test_work_counts_closed_forms():
     assert (w["m_entries"], w["m_out_entries"], w["m_pairs"], w["meas_words"]) == (2, 1, 1, 1)
     w = work("QUBITS 2\nH 0\nH 1\nT 0\nT 1\nM 0\nM 1\n")
     assert (w["t_entries"], w["m_entries"], w["m_pairs"], w["m_out_entries"], w["events"]) == (2 + 4, 4 + 2, 2 + 1, 2 + 1, 4)
+
+
+# ---------------------------------------------------------------------------
+# Diagonal gates in one pass: U = sum_g c_g Z^g over the Z-strings of their
+# qubits (CS, CSDG, CPHASE, RZ, CCZ, CCX, DIAG of 1-3 qubits)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(40))
+def test_diagonal_gates_match_dense(seed):
+    n = 2 + seed % 5
+    text, _ = random_circuit(8300 + seed, n, 50, p_diag=0.2, p_t=0.08)
+    assert any(g in text for g in ("CS ", "CSDG", "CPHASE", "RZ", "CCZ", "DIAG"))
+    _check_dense(text, seed)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_diagonal_gates_every_prefix_matches_dense(seed):
+    n = 3 + seed % 3
+    text, _ = random_circuit(8400 + seed, n, 30, p_diag=0.3)
+    lines = text.strip().split("\n")
+    for cut in range(2, len(lines) + 1):
+        _check_dense("\n".join(lines[:cut]) + "\n", seed)
+
+
+def _coeff_diff(a, b):
+    keys = set(a) | set(b)
+    return max([abs(a.get(k, 0) - b.get(k, 0)) for k in keys] + [0.0])
+
+
+def test_ccz_equals_its_seven_t_phase_polynomial():
+    # 4xyz = x + y + z - (x^y) - (x^z) - (y^z) + (x^y^z): T on a, b, c and on
+    # a^b^c, T-dagger on a^b, a^c, b^c (parities formed by CNOTs and undone)
+    # is CCZ with T = diag(1, e^{i pi/4}) exactly.  The one-pass CCZ gives the
+    # same tableau and coefficients on random states.
+    seven = ("T 0\nT 1\nT 2\nCX 0 1\nTDG 1\nCX 0 1\nCX 0 2\nTDG 2\nCX 0 2\nCX 1 2\nTDG 2\nCX 1 2\n"
+             "CX 0 2\nCX 1 2\nT 2\nCX 1 2\nCX 0 2\n")
+    for seed in range(12):
+        prep, _ = random_circuit(8500 + seed, 4, 25, p_meas=0, p_mpp=0, p_reset=0)
+        body = prep.split("\n", 1)[1]
+        a = oracle.Circuit("QUBITS 4\n" + body + "CCZ 0 1 2\n").shot(0, 0)
+        b = oracle.Circuit("QUBITS 4\n" + body + seven).shot(0, 0)
+        assert (a.tab_x == b.tab_x).all() and (a.tab_z == b.tab_z).all() and (a.tab_r == b.tab_r).all()
+        assert _coeff_diff(a.coeffs, b.coeffs) < 1e-12
+
+
+def _gs_state(text):
+    """The oracle's final state of a measurement-free circuit as a
+    statevector: sum_alpha v_alpha d_alpha |psi_S> (Definition 1), with the
+    phase-tracked stabilizer state of the dense checker."""
+    r = oracle.Circuit(text).shot(0, 0)
+    _, shadow, _, _ = ref_dense.run(text, [])
+    return ref_dense.reconstruct(r.tab_x, r.tab_z, r.tab_r, r.coeffs, shadow, r.tab_x.size // 2)
+
+
+def test_diagonal_gate_closed_forms():
+    def coeffs(text):
+        return oracle.Circuit(text).shot(0, 0).coeffs
+    # RZ(pi/4) = e^{-i pi/8} T exactly (T keeps the e^{i pi/8} of Eqs. 1-2;
+    # both take the non-Clifford route, so the coefficients agree), and
+    # RZ(pi/2) = e^{-i pi/4} S as states (S is Clifford: another tableau)
+    for pre in ("H 0\n", "H 0\nT 0\nH 0\n", "X 0\nH 0\nS 0\n"):
+        a, b = coeffs("QUBITS 1\n" + pre + "RZ 0.7853981633974483 0\n"), coeffs("QUBITS 1\n" + pre + "T 0\n")
+        assert _coeff_diff(a, {k: v * np.exp(-1j * np.pi / 8) for k, v in b.items()}) < 1e-12
+        a = _gs_state("QUBITS 1\n" + pre + "RZ 1.5707963267948966 0\n")
+        b = _gs_state("QUBITS 1\n" + pre + "S 0\n")
+        assert np.max(np.abs(a - np.exp(-1j * np.pi / 4) * b)) < 1e-12
+    # CS twice = CZ and CPHASE(pi) = CZ as states; CS then CSDG = I; a DIAG
+    # with equal phases is a global phase; CCZ twice = I (coefficients)
+    prep = "QUBITS 3\nH 0\nH 1\nT 1\nH 2\nCX 0 2\n"
+    base = coeffs(prep)
+    assert np.max(np.abs(_gs_state(prep + "CS 0 1\nCS 0 1\n") - _gs_state(prep + "CZ 0 1\n"))) < 1e-12
+    assert np.max(np.abs(_gs_state(prep + "CPHASE 3.141592653589793 0 1\n") - _gs_state(prep + "CZ 0 1\n"))) < 1e-12
+    assert _coeff_diff(coeffs(prep + "CS 0 1\nCSDG 0 1\n"), base) < 1e-12
+    assert _coeff_diff(coeffs(prep + "DIAG 2 0 2 0.3 0.3 0.3 0.3\n"), {k: v * np.exp(0.3j) for k, v in base.items()}) < 1e-12
+    assert _coeff_diff(coeffs(prep + "CCZ 0 1 2\nCCZ 0 1 2\n"), base) < 1e-12
+    # CS|++> : <X0 X1> = 1/2 and support 4 (two new span directions)
+    r = oracle.Circuit("QUBITS 2\nH 0\nH 1\nCS 0 1\nMPP X0*X1\n").shot(0, 0, words=np.array([0], dtype=np.uint32))
+    assert abs(r.p0[0] - 0.75) < 1e-12
+    assert len(oracle.Circuit("QUBITS 2\nH 0\nH 1\nCS 0 1\n").shot(0, 0).coeffs) == 4
+    # on a computational basis state a diagonal gate only turns the phase: one entry
+    r = oracle.Circuit("QUBITS 3\nX 0\nX 2\nDIAG 3 0 1 2 0.1 0.2 0.3 0.4 0.5 1.25 0.7 0.8\n").shot(0, 0)
+    assert len(r.coeffs) == 1 and abs(list(r.coeffs.values())[0] - np.exp(1.25j)) < 1e-12
+
+
+def test_diagonal_gate_parse_errors_and_noise():
+    for bad, frag in (("QUBITS 2\nCS 0 0\n", "repeated"), ("QUBITS 2\nRZ x 0\n", "angle"),
+                      ("QUBITS 3\nDIAG 4 0 1 2 3\n", "1 to 3"), ("QUBITS 2\nDIAG 2 0 1 0.1 0.2 0.3\n", "arguments"),
+                      ("QUBITS 2\nCPHASE 0.5 0\n", "arguments"), ("QUBITS 2\nRZ inf 0\n", "angle")):
+        with pytest.raises(ValueError, match=frag):
+            oracle.Circuit(bad)
+    # model noise: DEP1 after 1- and 3-qubit diagonal gates, DEP2 after 2-qubit ones
+    model = {"p1": 0.1, "p2": 0.2}
+    for text, slots in (("QUBITS 3\nRZ 0.3 0\n", 1), ("QUBITS 3\nCS 0 1\n", 1), ("QUBITS 3\nCCZ 0 1 2\n", 3),
+                        ("QUBITS 3\nCCX 0 1 2\n", 3), ("QUBITS 3\nDIAG 2 1 2 0 0 0 1\n", 1)):
+        assert oracle.Circuit(text, model).n_noise_slots == slots
+    a = oracle.Circuit("QUBITS 3\nH 0\nH 1\nCS 0 1\nM 0\nM 1\n", model).batch(3, 0, 3000)
+    b = oracle.Circuit("QUBITS 3\nH 0\nDEP1 0.1 0\nH 1\nDEP1 0.1 1\nCS 0 1\nDEP2 0.2 0 1\nM 0\nM 1\n").batch(3, 0, 3000)
+    assert (a["outcomes"] == b["outcomes"]).all()
