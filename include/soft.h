@@ -102,14 +102,26 @@ const char *soft_last_error(const soft_ctx *ctx);
  * problem of Sec. II-C, with the operations of the MSC circuits of Sec. III
  * (Table II counts them).  One op per line, '#' starts a comment, first line
  * "QUBITS n":
- *   H q | S q | SDG q | X q | Y q | Z q | T q | TDG q | CX c t | CZ a b |
- *   M q | R q | MPP P0*P1*...  (factors X3, Y0, Z7; distinct qubits) |
- *   DEP1 p q... | DEP2 p a b [a b...] | XERR p q... | TICK |
+ *   H q | S q | SDG q | X q | Y q | Z q | H_XY q | H_NXY q | T q | TDG q |
+ *   CX c t | CZ a b | M q | R q | MX q | RX q | MR q | MRX q |
+ *   MPP P0*P1*...  (factors X3, Y0, Z7; distinct qubits) |
+ *   CCZ a b c | CCX a b t | CS a b | CSDG a b | CPHASE theta a b | RZ theta q |
+ *   DIAG k q_0..q_{k-1} phi_0..phi_{2^k-1}  (k = 1..3) |
+ *   XIF r q | YIF r q | ZIF r q |
+ *   DEP1 p q... | DEP2 p a b [a b...] | XERR p q... | ZERR p q... | TICK |
  *   DETECTOR e r... | OBSERVABLE e r...
  * M and MPP append to the measurement record; R measures Z and flips back
- * to |0> (not recorded).  DETECTOR ends the shot as DISCARDED when
- * e ^ XOR(record bits r...) != 0; OBSERVABLE stores that parity as an
- * observable bit.  Op indices (used by abort_op) count op lines from 0.
+ * to |0> (not recorded); MX / RX are the X-basis forms, MR / MRX record and
+ * reset.  The diagonal gates multiply basis state x of their qubits (bit j
+ * of x = j-th listed qubit) by e^{i phi_x}: CCZ phi = pi at x = 7, CCX =
+ * H_t CCZ H_t, CS / CSDG phi = +-pi/2 at x = 3, CPHASE phi = theta at
+ * x = 3, RZ theta = exp(-i theta Z / 2), DIAG the listed phases (radians);
+ * each runs in one pass as the sum of its Z-strings (the expansion used in
+ * Proposition 1's proof, each term acting by Eq. 4).  XIF/YIF/ZIF r q apply
+ * the Pauli to q when record bit r is 1.  DETECTOR ends the shot as
+ * DISCARDED when e ^ XOR(record bits r...) != 0; OBSERVABLE stores that
+ * parity as an observable bit.  Op indices (used by abort_op) count op lines
+ * from 0.
  * EPARSE on malformed text; ECAPACITY when the circuit's coefficient span
  * exceeds the largest tile the library supports. */
 int soft_load_circuit(soft_ctx *ctx, const char *text, size_t len);

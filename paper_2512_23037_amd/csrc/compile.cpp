@@ -10,9 +10,10 @@
 #include "compile.h"
 
 #include <algorithm>
-#include <map>
 #include <cmath>
+#include <complex>
 #include <cstring>
+#include <map>
 
 namespace soft {
 namespace {
@@ -347,6 +348,90 @@ class FrameCompiler {
         // coordinates this T's term needs: its new coordinate, or mu's top bit
         const uint32_t need = E.kind == EV_T_DOUBLE ? k_before + 1u : E.kind == EV_T_BFLY ? E.tstar + 1u : 0u;
         spec_after_t(q, dagger, k_before, src, need);
+    }
+
+    // Diagonal gate e^{i phi_x} on basis state x of the qubits qs (bit j of x
+    // = qubit qs[j]), m <= 3, in one pass: U = sum_g c_g Z^g over the Z-strings
+    // of its qubits, each term shifting the coefficients by its beta (Eq. 4).
+    // The span grows by the new betas (terms with c_g = 0 are left out), and
+    // the kernel runs one coset of the shifts' span per lane (DiagInfo).
+    void diag(const std::vector<int> &qs, const std::vector<double> &phi, uint32_t src) {
+        sync();
+        spec_reset();  // the span grows: no T pair of an open run can be dropped past this gate
+        const uint32_t m = (uint32_t)qs.size(), ng = 1u << m;
+        Event E = begin(src);
+        E.kind = EV_DIAG;
+        DiagInfo D;
+        std::memset(&D, 0, sizeof(D));
+        D.ng = ng;
+        uint64_t beta[8], gamma[8];
+        int cexp[8];
+        std::complex<double> dg[8];
+        for (uint32_t g = 0; g < ng; ++g) {
+            std::complex<double> c(0.0, 0.0);
+            for (uint32_t x = 0; x < ng; ++x) {
+                const std::complex<double> e = std::polar(1.0, phi[x]);
+                if (__builtin_parity(g & x)) c -= e;
+                else c += e;
+            }
+            c /= (double)ng;
+            PauliStr Z;
+            for (uint32_t j = 0; j < m; ++j)
+                if ((g >> j) & 1u) Z.z |= bitq(qs[j]);
+            decompose(Z, beta[g], gamma[g], cexp[g]);
+            static const std::complex<double> ipw[4] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+            dg[g] = c * ipw[cexp[g] & 3];
+            // a new index shift adds a coordinate (as a T doubling does)
+            uint32_t mu;
+            if ((c.real() != 0.0 || c.imag() != 0.0) && !coords(beta[g], mu)) {
+                basis_.push_back(beta[g]);
+                if (basis_.size() > kMaxSpanDim)
+                    throw CompileError{0, "coefficient span dimension exceeds " + std::to_string(kMaxSpanDim)};
+                if (basis_.size() > P_.kmax) P_.kmax = (uint32_t)basis_.size();
+            }
+        }
+        D.knew = (uint32_t)basis_.size();
+        // the shifts in the grown span, and a reduced echelon basis of their span
+        uint32_t mus[8];
+        std::vector<uint32_t> ech;  // rows with distinct top bits
+        for (uint32_t g = 0; g < ng; ++g) {
+            mus[g] = 0;
+            if (dg[g].real() == 0.0 && dg[g].imag() == 0.0) continue;
+            if (!coords(beta[g], mus[g])) throw CompileError{0, "internal: diagonal term outside the span"};
+            uint32_t v = mus[g];
+            for (uint32_t e : ech)
+                if (v & (1u << (31 - __builtin_clz(e)))) v ^= e;
+            if (!v) continue;
+            const uint32_t tb = 1u << (31 - __builtin_clz(v));
+            for (uint32_t &e : ech)
+                if (e & tb) e ^= v;
+            ech.push_back(v);
+        }
+        std::sort(ech.begin(), ech.end());  // ascending top bits
+        D.r = (uint32_t)ech.size();
+        for (uint32_t i = 0; i < D.r; ++i) D.lead |= (uint32_t)(31 - __builtin_clz(ech[i])) << (5 * i);
+        for (uint32_t u = 0; u < (1u << D.r); ++u) {
+            D.E[u] = 0;
+            for (uint32_t i = 0; i < D.r; ++i)
+                if ((u >> i) & 1u) D.E[u] ^= ech[i];
+        }
+        for (uint32_t g = 0; g < ng; ++g) {
+            D.beta[g] = beta[g];
+            D.gamma[g] = gamma[g];
+            D.dre[g] = dg[g].real();
+            D.dim[g] = dg[g].imag();
+            D.fre[g] = (float)D.dre[g];
+            D.fim[g] = (float)D.dim[g];
+            D.gm[g] = gmask(gamma[g]);
+            uint32_t ug = 0;
+            for (uint32_t i = 0; i < D.r; ++i)
+                if ((mus[g] >> (31 - __builtin_clz(ech[i]))) & 1u) ug |= 1u << i;
+            D.ug[g] = ug;
+        }
+        E.boff = (uint32_t)P_.diag.size();
+        E.bcnt = D.knew;
+        P_.diag.push_back(D);
+        finish(E);
     }
 
     // The branching T pass runs its entries 64 lanes at a time; iteration
@@ -1013,6 +1098,7 @@ static void work_sums(Program &out) {
             case EV_T_BFLY: t += 1ull << E.k; ++n; break;
             case EV_M_DET: ++n; break;
             case EV_M_CUT: case EV_M_SPLIT: case EV_M_MERGE: m += 1ull << E.k; ++n; break;
+            case EV_DIAG: t += 1ull << E.bcnt; ++n; break;  // bcnt: span dimension after the gate
             default: break;
         }
     }
@@ -1104,27 +1190,53 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
                 fc.measure(Z, out.n_meas++, -1, q, src);
                 fc.noise(NZ_XERR, nm.p_reset, q, -1, 0);
             }
-        } else if (op == "CCZ" || op == "CCX") {
-            // CCZ multiplies |x> by (-1)^{x_a x_b x_c}; with
-            // 4xyz = x + y + z - (x^y) - (x^z) - (y^z) + (x^y^z) it is
-            // T on a, b, c and on a^b^c, T-dagger on a^b, a^c, b^c (T = diag(1,
-            // e^{i pi/4})), each parity formed on one of the qubits by CNOTs and
-            // undone.  At most three new span coordinates, support at most 8x
-            // (Proposition 1).  CCX = H_t CCZ H_t.
-            want(4);
-            int a = qubit(tok[1]), b = qubit(tok[2]), t = qubit(tok[3]);
-            if (a == b || a == t || b == t) throw CompileError{ln, op + " on repeated qubits"};
-            busy[a] = busy[b] = busy[t] = 1;
-            if (op == "CCX") fc.h(t);
-            fc.t_gate(a, false, src);
-            fc.t_gate(b, false, src);
-            fc.t_gate(t, false, src);
-            fc.cnot(a, b); fc.t_gate(b, true, src); fc.cnot(a, b);
-            fc.cnot(a, t); fc.t_gate(t, true, src); fc.cnot(a, t);
-            fc.cnot(b, t); fc.t_gate(t, true, src); fc.cnot(b, t);
-            fc.cnot(a, t); fc.cnot(b, t); fc.t_gate(t, false, src); fc.cnot(b, t); fc.cnot(a, t);
-            if (op == "CCX") fc.h(t);
-            for (int q : {a, b, t}) fc.noise(NZ_DEP1, nm.p1, q, -1, 0);
+        } else if (op == "CCZ" || op == "CCX" || op == "CS" || op == "CSDG" || op == "CPHASE" || op == "RZ" ||
+                   op == "DIAG") {
+            // Diagonal gates: basis state x of the qubits (bit j = j-th qubit)
+            // picks up e^{i phi_x}.  CCZ: phi = pi at x = 7 (CCX = H_c CCZ
+            // H_c); CS / CSDG: +-pi/2 at x = 3; CPHASE t a b: t at x = 3;
+            // RZ t q = exp(-i t Z / 2): (-t/2, t/2); DIAG k q.. phi_0..phi_{2^k-1}.
+            size_t nq = 0, first = 1;
+            if (op == "CCZ" || op == "CCX") nq = 3;
+            else if (op == "CS" || op == "CSDG") nq = 2;
+            else if (op == "CPHASE") { nq = 2; first = 2; }
+            else if (op == "RZ") { nq = 1; first = 2; }
+            else {
+                if (tok.size() < 2) throw CompileError{ln, "DIAG takes k, k qubits and 2^k phases"};
+                const int k = parse_uint(tok[1], ln);
+                if (k < 1 || k > 3) throw CompileError{ln, "DIAG takes 1 to 3 qubits"};
+                nq = (size_t)k;
+                first = 2;
+            }
+            want(op == "DIAG" ? first + nq + (1u << nq) : first + nq);
+            std::vector<int> qs;
+            for (size_t i = 0; i < nq; ++i) qs.push_back(qubit(tok[first + i]));
+            for (size_t i = 0; i < nq; ++i)
+                for (size_t j = 0; j < i; ++j)
+                    if (qs[i] == qs[j]) throw CompileError{ln, op + " on repeated qubits"};
+            auto angle = [&](const std::string &t) {
+                char *endp = nullptr;
+                const double v = std::strtod(t.c_str(), &endp);
+                if (endp == t.c_str() || *endp != '\0' || !std::isfinite(v)) throw CompileError{ln, "bad angle '" + t + "'"};
+                return v;
+            };
+            std::vector<double> phi((size_t)1 << nq, 0.0);
+            if (op == "CCZ" || op == "CCX") phi[7] = M_PI;
+            else if (op == "CS") phi[3] = M_PI / 2;
+            else if (op == "CSDG") phi[3] = -M_PI / 2;
+            else if (op == "CPHASE") phi[3] = angle(tok[1]);
+            else if (op == "RZ") { phi[0] = -angle(tok[1]) / 2; phi[1] = angle(tok[1]) / 2; }
+            else
+                for (size_t x = 0; x < phi.size(); ++x) phi[x] = angle(tok[first + nq + x]);
+            for (int q : qs) busy[q] = 1;
+            if (op == "CCX") fc.h(qs[2]);
+            fc.diag(qs, phi, src);
+            if (op == "CCX") fc.h(qs[2]);
+            // model noise: DEP2(p2) after a two-qubit diagonal gate, DEP1(p1) on
+            // each qubit after a one- or three-qubit one
+            if (nq == 2) fc.noise(NZ_DEP2, nm.p2, qs[0], qs[1], 0);
+            else
+                for (int q : qs) fc.noise(NZ_DEP1, nm.p1, q, -1, 0);
         } else if (op == "MX" || op == "RX" || op == "MR" || op == "MRX") {
             // X-basis readout / reset to |+>, measure-then-reset; the error
             // flips anticommute with the measured Pauli (Z for the X basis)

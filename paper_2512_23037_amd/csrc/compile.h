@@ -32,6 +32,7 @@ struct Program {
     std::vector<uint32_t> gap;        // gap sampling: [g - 1] = floor(q^g 2^32), g = 1..n_noise
     std::vector<uint32_t> det_pairs;  // (record word, mask) pairs
     std::vector<BatchMember> batch;   // members of side-by-side measurement runs
+    std::vector<DiagInfo> diag;       // diagonal gates (EV_DIAG events point here)
     std::vector<Frame> before;        // frame when event e starts
     std::vector<Frame> after;         // frame when event e has finished
     uint64_t hash = 0;                // of the text and the noise model

@@ -45,6 +45,7 @@ enum EvKind : uint32_t {
     EV_OBSERVABLE,   // parity of record bits, stored as an observable bit
     EV_FEEDBACK,     // Pauli flip (masks xD/xS) when record bit `rec` is 1 (as the check dw0/dm0)
     EV_DROP,         // speculative: coordinates >= mu carry no amplitude; k -> mu
+    EV_DIAG,         // diagonal gate on <= 3 qubits, all its Z-strings in one pass (DiagInfo `boff`)
     EV_END
 };
 
@@ -159,6 +160,29 @@ struct alignas(16) BatchMember {
 };
 static_assert(sizeof(BatchMember) == 80, "batch member layout");
 constexpr uint32_t kBatchMax = 64;
+
+// A diagonal gate U = sum_x e^{i phi_x} |x><x| on m <= 3 qubits, applied in
+// one pass.  Over the 2^m Z-strings g of its qubits U = sum_g c_g Z^g
+// (c_g = 2^-m sum_x e^{i phi_x} (-1)^{g.x}, the expansion behind
+// Proposition 1), and Z^g = i^cexp_g (sign part) d_beta_g s_gamma_g acts on
+// the basis by Eq. 4.  In span coordinates term g moves entry j to j ^ mu_g
+// (the span first grows by the new beta_g).  The shifts mu_g span a subspace
+// with a reduced echelon basis e_0..e_{r-1} (top bits lead_i ascending), so
+// the tile splits into 2^(knew - r) cosets j0 ^ span, j0 with zeros at the
+// lead bits, and element u = j0 ^ E_u of a coset becomes
+//   v'[j0 ^ E_u] = sum_g W_g (-1)^(gm_g . j_in) v[j_in],  j_in = j0 ^ E_(u ^ ug_g)
+// (v = 0 past the old span), with W_g = D_g (-1)^(parity(rD & beta_g) ^
+// parity((rS ^ a) & gamma_g)) per shot and D_g = c_g i^cexp_g.
+struct alignas(16) DiagInfo {
+    uint64_t beta[8], gamma[8];  // index shift / anticommuting destabilizers of Z^g
+    double dre[8], dim[8];       // D_g
+    float fre[8], fim[8];        // D_g in single precision
+    uint32_t gm[8];              // bit t = parity(gamma_g & b_t), span after the gate
+    uint32_t ug[8];              // mu_g in the coset basis (bit i = bit lead_i of mu_g)
+    uint32_t E[8];               // coordinates of coset element u (XOR of e_i over the bits of u)
+    uint32_t ng, r, knew, lead;  // Z-strings (2^m), coset dimension, span dimension after, lead_i in bits 5i..5i+4
+};
+static_assert(sizeof(DiagInfo) == 432, "diagonal gate layout");
 
 // A mixture runs several compiled circuits in one launch: global shot indices
 // [previous shot_end, shot_end) belong to the variant, whose events, noise

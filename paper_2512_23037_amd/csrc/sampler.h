@@ -14,6 +14,7 @@ struct RunParams {
     const uint32_t *gaps;     // gap sampling tables of the variants (VariantDesc::gap_off)
     const uint32_t *det;      // DETECTOR/OBSERVABLE (word, mask) pairs
     const BatchMember *bm;    // members of side-by-side measurement runs
+    const DiagInfo *diag;     // diagonal gates (EV_DIAG)
     const VariantDesc *vars;  // shot ranges of the circuits in this run
     const uint32_t *words;    // explicit uniforms [n_shots][word_stride] or null
     const uint64_t *shot_list;  // global shot index of each run position, or null (shot0 + i)

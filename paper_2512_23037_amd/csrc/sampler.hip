@@ -390,6 +390,8 @@ __device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, ui
 }
 
 
+__device__ __forceinline__ float unif(float x) { return __uint_as_float(uni(__float_as_uint(x))); }
+
 // floor(x / d) for x < 16 d (a noise hit's Pauli code from its word): a
 // binary search on exact integer compares instead of a 64-bit division.
 __device__ __forceinline__ uint32_t quot16(uint64_t x, uint64_t d) {
@@ -1213,6 +1215,60 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 }
                 k = k0;
                 if (k0 == 0u) renorm_single();
+            } else if (kind == EV_DIAG) {
+                // ---- diagonal gate: all its Z-strings in one pass ----
+                // Term g moves entry j to j ^ mu_g with weight W_g (-1)^(gm_g . j).
+                // The shifts span 2^r coset elements E_u; lane L of the pass
+                // takes element u = L mod 2^r of coset L >> r and sums its terms
+                // from the coset's entries (0 past the old span).  A coset sits on
+                // the lanes of one iteration, whose reads all come before its
+                // writes, so the update is in place.
+                const DiagInfo *di = P.diag + EV32(boff);
+                const uint32_t ng = uni(di->ng), r = uni(di->r), knew = uni(di->knew), lead = uni(di->lead);
+                uint32_t sgl = 0;  // sign part of term `lane`, with gamma . a
+                if (lane < ng) sgl = par64((rD & di->beta[lane]) ^ ((rS ^ a) & di->gamma[lane]));
+                const uint32_t S = (uint32_t)__ballot(sgl != 0u);
+                const uint32_t e0 = uni(di->E[1]), e1 = uni(di->E[2]), e2 = uni(di->E[4]);
+                auto coset_el = [&](uint32_t w) { return ((w & 1u) ? e0 : 0u) ^ ((w & 2u) ? e1 : 0u) ^ ((w & 4u) ? e2 : 0u); };
+                // the gate is unitary: the carried norm sets the pruning level
+                const R thr = (R)(tau2 * nrm2 * itscale2);
+                const uint32_t kin = 1u << k, um = (1u << r) - 1u;
+                uint32_t cnt = 0;
+                lane_pass(1u << knew, lane, [&](uint32_t L) {
+                    const uint32_t u = L & um;
+                    uint32_t j0 = L >> r;  // zeros at the lead bits, ascending
+                    for (uint32_t i = 0; i < r; ++i) j0 = ins0(j0, (lead >> (5u * i)) & 31u);
+                    C y = mk<C>(0.0, 0.0);
+                    for (uint32_t g = 0; g < ng; ++g) {
+                        const uint32_t jin = j0 ^ coset_el(u ^ uni(di->ug[g]));
+                        C xv = v[jin < kin ? jin : 0u];
+                        if (jin >= kin) xv = mk<C>(0.0, 0.0);
+                        const R wr = sizeof(R) == 4 ? (R)unif(di->fre[g]) : (R)unid(di->dre[g]);
+                        const R wi = sizeof(R) == 4 ? (R)unif(di->fim[g]) : (R)unid(di->dim[g]);
+                        const bool neg = (((S >> g) ^ par32(uni(di->gm[g]) & jin)) & 1u) != 0u;
+                        const R cr = neg ? -wr : wr, ci = neg ? -wi : wi;
+                        y.x = fma(cr, xv.x, fma(-ci, xv.y, y.x));
+                        y.y = fma(cr, xv.y, fma(ci, xv.x, y.y));
+                    }
+                    bool keep;
+                    const C o = t_keep<R, C>(y, thr, keep);
+                    cnt += (uint32_t)__popcll(__ballot(keep));
+                    v[j0 ^ coset_el(u)] = o;
+                });
+                k = knew;
+                cnt = uni(cnt);
+                maxsup = max(maxsup, cnt);
+                if (cnt > P.support_cap) {
+                    if (!full) {  // the full list decides where the cap is hit
+                        restart = true;
+                        break;
+                    }
+                    status = ST_OVERFLOW;
+                    abort_src = EV32(src);
+                    term = e;
+                    after = 1;
+                    break;
+                }
             } else if (kind == EV_FEEDBACK) {
                 // ---- classically controlled Pauli: the record bit is a one-pair check ----
                 if (parity_check()) {

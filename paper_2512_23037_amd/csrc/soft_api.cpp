@@ -95,9 +95,11 @@ struct soft_ctx {
     DevBuf<NoiseLoc> d_nz;
     DevBuf<uint32_t> d_tm1, d_det, d_gap;
     DevBuf<BatchMember> d_bm;
+    DevBuf<DiagInfo> d_diag;
     DevBuf<VariantDesc> d_vars;
     DevBuf<unsigned char> d_gtile;            // device-memory tiles
     unsigned long long *d_counters = nullptr;  // kMaxVariants rows of C_COUNT, then the work cursor
+    const unsigned long long *last_counters = nullptr;  // counters of the last run
     double *d_phase = nullptr;                 // cos/sin of k pi/8, k = 0..15
 
     uint64_t keep_lo = 0;
@@ -233,6 +235,7 @@ int prepare(soft_ctx *c) {
     std::vector<NoiseLoc> nz;
     std::vector<uint32_t> tm1, det, gap;
     std::vector<BatchMember> bm;
+    std::vector<DiagInfo> dg;
     std::vector<VariantDesc> vd;
     c->kmax = 0;
     c->rec_words = 0;
@@ -250,13 +253,16 @@ int prepare(soft_ctx *c) {
         auto append = [&](const Program &Q) {
             const uint32_t off = (uint32_t)ev.size();
             const uint32_t det_base = (uint32_t)(det.size() / 2), bm_base = (uint32_t)bm.size();
+            const uint32_t dg_base = (uint32_t)dg.size();
             for (Event E : Q.events) {
                 E.det_off += det_base;
                 if (E.flags & EVF_BATCH) E.boff += bm_base;
+                if (E.kind == EV_DIAG) E.boff += dg_base;
                 ev.push_back(E);
             }
             det.insert(det.end(), Q.det_pairs.begin(), Q.det_pairs.end());
             bm.insert(bm.end(), Q.batch.begin(), Q.batch.end());
+            dg.insert(dg.end(), Q.diag.begin(), Q.diag.end());
             return off;
         };
         D.ev_off_full = append(P);
@@ -275,6 +281,7 @@ int prepare(soft_ctx *c) {
     if ((rc = ensure(c, c->d_ev, ev.size())) || (rc = ensure(c, c->d_nz, std::max<size_t>(nz.size(), 1))) ||
         (rc = ensure(c, c->d_tm1, tm1.size())) || (rc = ensure(c, c->d_det, std::max<size_t>(det.size(), 2))) ||
         (rc = ensure(c, c->d_bm, std::max<size_t>(bm.size(), 1))) || (rc = ensure(c, c->d_vars, vd.size())) ||
+        (rc = ensure(c, c->d_diag, std::max<size_t>(dg.size(), 1))) ||
         (rc = ensure(c, c->d_gap, std::max<size_t>(gap.size(), 1))))
         return rc;
     if (!gap.empty()) HIPCHK(c, hipMemcpy(c->d_gap.p, gap.data(), gap.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -283,6 +290,7 @@ int prepare(soft_ctx *c) {
     HIPCHK(c, hipMemcpy(c->d_tm1.p, tm1.data(), tm1.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     if (!det.empty()) HIPCHK(c, hipMemcpy(c->d_det.p, det.data(), det.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     if (!bm.empty()) HIPCHK(c, hipMemcpy(c->d_bm.p, bm.data(), bm.size() * sizeof(BatchMember), hipMemcpyHostToDevice));
+    if (!dg.empty()) HIPCHK(c, hipMemcpy(c->d_diag.p, dg.data(), dg.size() * sizeof(DiagInfo), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_vars.p, vd.data(), vd.size() * sizeof(VariantDesc), hipMemcpyHostToDevice));
     c->dirty = false;
     drop_graph(c);
@@ -456,6 +464,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.tm1 = c->d_tm1.p;
     rp.det = c->d_det.p;
     rp.bm = c->d_bm.p;
+    rp.diag = c->d_diag.p;
     rp.speculate = c->speculate ? 1u : 0u;
     rp.gaps = c->d_gap.p;
     rp.noise_mode = (uint32_t)c->noise_mode;
@@ -521,6 +530,7 @@ int run_impl(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, 
         HIPCHK(c, hipMemsetAsync(c->d_trace_meta.p, 0, (size_t)c->trace_n * KM_COUNT * sizeof(unsigned long long), stream));
     if ((rc = launch(c, rp, s, n_shots, stream))) return rc;
     c->ran = true;
+    c->last_counters = c->d_counters;
     c->last_stream = stream;
     c->last_shot0 = shot0;
     c->last_n = n_shots;
@@ -686,6 +696,7 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_gap);
     release(c->d_det);
     release(c->d_bm);
+    release(c->d_diag);
     release(c->d_vars);
     release(c->d_gtile);
     release(c->d_keep_meta);
@@ -882,7 +893,7 @@ int read_rows(soft_ctx *c, uint32_t v0, uint32_t v1, soft_counters *out) {
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->last_stream));
     std::vector<unsigned long long> h((size_t)(v1 - v0) * C_COUNT);
-    HIPCHK(c, hipMemcpy(h.data(), c->d_counters + (size_t)v0 * C_COUNT, h.size() * sizeof(unsigned long long),
+    HIPCHK(c, hipMemcpy(h.data(), c->last_counters + (size_t)v0 * C_COUNT, h.size() * sizeof(unsigned long long),
                         hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
     double dev = 0.0;
