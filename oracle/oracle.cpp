@@ -82,8 +82,9 @@ enum Kind {
     K_M, K_MPP, K_R, K_MX, K_RX, K_MR, K_MRX,
     K_DEP1, K_DEP2, K_XERR, K_ZERR, K_FLIP,
     K_DETECTOR, K_OBSERVABLE,
-    K_FEEDBACK,  // Pauli `b` (1 X, 2 Y, 3 Z) on qubit a when record bit `rec` is 1
-    K_DIAG       // diagonal gate: phase e^{i phi[x]} on basis state x of qubits qs (bit j = qubit qs[j])
+    K_FEEDBACK,  // Pauli `b` (1 X, 2 Y, 3 Z) on qubit a when its condition holds
+    K_DIAG       // diagonal gate: phase e^{i phi[x]} on basis state x of qubits qs (bit j = qubit qs[j]),
+                 // when its condition holds (always, if it has none)
 };
 
 struct Op {
@@ -100,6 +101,10 @@ struct Op {
     int obs = -1;             // observable index
     std::vector<int> qs;      // DIAG qubits
     std::vector<double> phi;  // DIAG phases, 2^|qs| of them
+    // Classical condition of FEEDBACK / DIAG on earlier record bits: their
+    // XOR, or (cond_and) their AND.  Empty: unconditional.
+    std::vector<int> cond;
+    bool cond_and = false;
 };
 
 }  // namespace
@@ -142,6 +147,15 @@ double to_prob(const std::string &s, int line) {
     return p;
 }
 
+// Names of the diagonal gates taken by the Z-string expansion when bare (the
+// Clifford and T names join them under IF).
+bool is_diag_name(const std::string &g) {
+    return g == "CCZ" || g == "CCX" || g == "CS" || g == "CSDG" || g == "CPHASE" || g == "RZ" || g == "DIAG";
+}
+bool is_cond_diag_name(const std::string &g) {
+    return is_diag_name(g) || g == "S" || g == "SDG" || g == "T" || g == "TDG" || g == "CZ";
+}
+
 // Parse the circuit text and lower it: every noise location with p > 0 gets a
 // noise slot, every M / MPP / R a measurement slot, every M / MPP a record.
 void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
@@ -169,6 +183,69 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
         o.kind = K_FLIP; o.rec = rec; o.thr = threshold_of(p); o.p = p; o.src = src;
         o.slot = c.n_noise++;
         c.ops.push_back(o);
+    };
+
+    auto hgate = [&](int q, int src) {
+        Op h;
+        h.kind = K_H; h.a = q; h.src = src;
+        c.ops.push_back(h);
+    };
+    // Diagonal gates, each one multiplying computational basis state x of its
+    // qubits (bit j of x = qubit qs[j]) by e^{i phi[x]}:
+    //   S / SDG q: phi = +-pi/2 where q = 1;  T / TDG q: +-pi/4 (T = diag(1, e^{i pi/4}));
+    //   CZ a b: phi = pi where a = b = 1;
+    //   CCZ a b c: phi = pi where a = b = c = 1;  CCX = H_c CCZ H_c;
+    //   CS a b / CSDG a b: phi = +-pi/2 where a = b = 1;
+    //   CPHASE theta a b: phi = theta where a = b = 1;
+    //   RZ theta q: exp(-i theta Z / 2), phi = (-theta/2, +theta/2);
+    //   DIAG k q_0 .. q_{k-1} phi_0 .. phi_{2^k - 1} (k = 1..3, radians).
+    // S, SDG, T, TDG and CZ take this form only under IF; bare, they are the
+    // Clifford / T ops.  tok[at] names the gate.
+    auto diag_op = [&](const std::vector<std::string> &tok, size_t at, int src) {
+        const std::string &name = tok[at];
+        Op o;
+        o.kind = K_DIAG;
+        o.src = src;
+        const double pi = 3.14159265358979323846;
+        size_t nq = 0, first = at + 1;
+        if (name == "CCZ" || name == "CCX") nq = 3;
+        else if (name == "CS" || name == "CSDG" || name == "CZ") nq = 2;
+        else if (name == "S" || name == "SDG" || name == "T" || name == "TDG") nq = 1;
+        else if (name == "CPHASE") { nq = 2; first = at + 2; }
+        else if (name == "RZ") { nq = 1; first = at + 2; }
+        else {
+            if (tok.size() < at + 2) throw ParseError{line, "DIAG takes k, k qubits and 2^k phases"};
+            const int k = to_int(tok[at + 1], line);
+            if (k < 1 || k > 3) throw ParseError{line, "DIAG takes 1 to 3 qubits"};
+            nq = (size_t)k;
+            first = at + 2;
+        }
+        const size_t want = name == "DIAG" ? first + nq + (1u << nq) : first + nq;
+        if (tok.size() != want) throw ParseError{line, name + ": wrong number of arguments"};
+        for (size_t i = 0; i < nq; ++i) o.qs.push_back(qubit(tok[first + i]));
+        for (size_t i = 0; i < nq; ++i)
+            for (size_t j = 0; j < i; ++j)
+                if (o.qs[i] == o.qs[j]) throw ParseError{line, name + " on repeated qubits"};
+        auto angle = [&](const std::string &t) {
+            char *end = nullptr;
+            double v = std::strtod(t.c_str(), &end);
+            if (end == t.c_str() || *end != '\0' || !std::isfinite(v)) throw ParseError{line, "bad angle '" + t + "'"};
+            return v;
+        };
+        o.phi.assign((size_t)1 << nq, 0.0);
+        if (name == "CCZ" || name == "CCX") o.phi[7] = pi;
+        else if (name == "CZ") o.phi[3] = pi;
+        else if (name == "S") o.phi[1] = pi / 2;
+        else if (name == "SDG") o.phi[1] = -pi / 2;
+        else if (name == "T") o.phi[1] = pi / 4;
+        else if (name == "TDG") o.phi[1] = -pi / 4;
+        else if (name == "CS") o.phi[3] = pi / 2;
+        else if (name == "CSDG") o.phi[3] = -pi / 2;
+        else if (name == "CPHASE") o.phi[3] = angle(tok[at + 1]);
+        else if (name == "RZ") { o.phi[0] = -angle(tok[at + 1]) / 2; o.phi[1] = angle(tok[at + 1]) / 2; }
+        else
+            for (size_t x = 0; x < o.phi.size(); ++x) o.phi[x] = angle(tok[first + nq + x]);
+        return o;
     };
 
     while (std::getline(in, raw)) {
@@ -229,65 +306,60 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             c.ops.push_back(o);
             active[q] = 1;
             add_noise(K_XERR, nm.p_reset, q, -1, src);
-        } else if (name == "CCZ" || name == "CCX" || name == "CS" || name == "CSDG" || name == "CPHASE" ||
-                   name == "RZ" || name == "DIAG") {
-            // Diagonal gates, each one multiplying computational basis state x
-            // of its qubits (bit j of x = qubit qs[j]) by e^{i phi[x]}:
-            //   CCZ a b c: phi = pi where a = b = c = 1;  CCX = H_c CCZ H_c;
-            //   CS a b / CSDG a b: phi = +-pi/2 where a = b = 1;
-            //   CPHASE theta a b: phi = theta where a = b = 1;
-            //   RZ theta q: exp(-i theta Z / 2), phi = (-theta/2, +theta/2);
-            //   DIAG k q_0 .. q_{k-1} phi_0 .. phi_{2^k - 1} (k = 1..3, radians).
-            Op o;
-            o.kind = K_DIAG;
-            o.src = src;
-            const double pi = 3.14159265358979323846;
-            size_t nq = 0, first = 1;
-            if (name == "CCZ" || name == "CCX") nq = 3;
-            else if (name == "CS" || name == "CSDG") nq = 2;
-            else if (name == "CPHASE") { nq = 2; first = 2; }
-            else if (name == "RZ") { nq = 1; first = 2; }
-            else {
-                if (tok.size() < 2) throw ParseError{line, "DIAG takes k, k qubits and 2^k phases"};
-                const int k = to_int(tok[1], line);
-                if (k < 1 || k > 3) throw ParseError{line, "DIAG takes 1 to 3 qubits"};
-                nq = (size_t)k;
-                first = 2;
-            }
-            const size_t want = name == "DIAG" ? first + nq + (1u << nq) : first + nq;
-            if (tok.size() != want) throw ParseError{line, name + ": wrong number of arguments"};
-            for (size_t i = 0; i < nq; ++i) o.qs.push_back(qubit(tok[first + i]));
-            for (size_t i = 0; i < nq; ++i)
-                for (size_t j = 0; j < i; ++j)
-                    if (o.qs[i] == o.qs[j]) throw ParseError{line, name + " on repeated qubits"};
-            auto angle = [&](const std::string &t) {
-                char *end = nullptr;
-                double v = std::strtod(t.c_str(), &end);
-                if (end == t.c_str() || *end != '\0' || !std::isfinite(v)) throw ParseError{line, "bad angle '" + t + "'"};
-                return v;
-            };
-            o.phi.assign((size_t)1 << nq, 0.0);
-            if (name == "CCZ" || name == "CCX") o.phi[7] = pi;
-            else if (name == "CS") o.phi[3] = pi / 2;
-            else if (name == "CSDG") o.phi[3] = -pi / 2;
-            else if (name == "CPHASE") o.phi[3] = angle(tok[1]);
-            else if (name == "RZ") { o.phi[0] = -angle(tok[1]) / 2; o.phi[1] = angle(tok[1]) / 2; }
-            else
-                for (size_t x = 0; x < o.phi.size(); ++x) o.phi[x] = angle(tok[first + nq + x]);
-            auto hgate = [&](int q) {
-                Op h;
-                h.kind = K_H; h.a = q; h.src = src;
-                c.ops.push_back(h);
-            };
-            if (name == "CCX") hgate(o.qs[2]);
+        } else if (is_diag_name(name)) {
+            Op o = diag_op(tok, 0, src);
+            const bool ccx = name == "CCX";
+            if (ccx) hgate(o.qs[2], src);
             c.ops.push_back(o);
-            if (name == "CCX") hgate(o.qs[2]);
+            if (ccx) hgate(o.qs[2], src);
             for (int q : o.qs) active[q] = 1;
             // model noise: DEP2(p2) after a two-qubit diagonal gate, DEP1(p1)
             // on each qubit after a one- or three-qubit one
-            if (nq == 2) add_noise(K_DEP2, nm.p2, o.qs[0], o.qs[1], src);
+            if (o.qs.size() == 2) add_noise(K_DEP2, nm.p2, o.qs[0], o.qs[1], src);
             else
                 for (int q : o.qs) add_noise(K_DEP1, nm.p1, q, -1, src);
+        } else if (name == "IF") {
+            // Classically controlled gate (the corrections of gate
+            // teleportation): IF r0,r1,.. GATE args applies GATE when the XOR
+            // of the listed record bits is 1, IF r0&r1&.. GATE args when all of
+            // them are 1.  GATE is a Pauli (X, Y, Z) or a diagonal gate (S,
+            // SDG, T, TDG, CZ and the diagonal gates above).  No model noise.
+            if (tok.size() < 3) throw ParseError{line, "IF takes record bits and a gate"};
+            std::vector<int> cond;
+            const std::string &cs = tok[1];
+            const bool has_and = cs.find('&') != std::string::npos, has_xor = cs.find(',') != std::string::npos;
+            if (has_and && has_xor) throw ParseError{line, "IF: use ',' (XOR) or '&' (AND), not both"};
+            size_t pos = 0;
+            while (true) {
+                const size_t e = cs.find(has_and ? '&' : ',', pos);
+                const int r = to_int(cs.substr(pos, e == std::string::npos ? std::string::npos : e - pos), line);
+                if (r >= c.n_rec) throw ParseError{line, "record index not yet measured"};
+                cond.push_back(r);
+                if (e == std::string::npos) break;
+                pos = e + 1;
+            }
+            const std::string &g = tok[2];
+            if (g == "X" || g == "Y" || g == "Z") {
+                if (tok.size() != 4) throw ParseError{line, "IF: " + g + " takes one qubit"};
+                Op o;
+                o.kind = K_FEEDBACK; o.src = src;
+                o.a = qubit(tok[3]);
+                o.b = g == "X" ? 1 : g == "Y" ? 2 : 3;
+                o.cond = cond;
+                o.cond_and = has_and;
+                c.ops.push_back(o);
+            } else if (is_cond_diag_name(g)) {
+                Op o = diag_op(tok, 2, src);
+                o.cond = cond;
+                o.cond_and = has_and;
+                const bool ccx = g == "CCX";  // H is unconditional: H IF(CCZ) H
+                if (ccx) hgate(o.qs[2], src);
+                c.ops.push_back(o);
+                if (ccx) hgate(o.qs[2], src);
+                for (int q : o.qs) active[q] = 1;
+            } else {
+                throw ParseError{line, "IF: '" + g + "' is neither a Pauli nor a diagonal gate"};
+            }
         } else if (name == "MX" || name == "RX" || name == "MR" || name == "MRX") {
             // X-basis measurement / reset to |+>, and measure-then-reset.  The
             // measurement-error flip before a readout and the reset-error flip
@@ -311,8 +383,9 @@ void compile(const char *text, const oracle_noise &nm, oracle_circuit &c) {
             if (tok.size() != 3) throw ParseError{line, name + " takes a record index and a qubit"};
             Op o;
             o.kind = K_FEEDBACK; o.src = src;
-            o.rec = to_int(tok[1], line);
-            if (o.rec >= c.n_rec) throw ParseError{line, "record index not yet measured"};
+            const int r = to_int(tok[1], line);
+            if (r >= c.n_rec) throw ParseError{line, "record index not yet measured"};
+            o.cond.push_back(r);
             o.a = qubit(tok[2]);
             o.b = name == "XIF" ? 1 : name == "YIF" ? 2 : 3;
             c.ops.push_back(o);
@@ -739,6 +812,13 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
         return words ? words[c.n_noise + slot] : philox_word(seed, shot, 1, (uint64_t)slot);
     };
     auto rec_bit = [&](int k) { return (int)((res.record[k >> 5] >> (k & 31)) & 1u); };
+    // condition of a classically controlled op: XOR (or AND) of its record bits
+    auto cond_holds = [&](const Op &o) {
+        if (o.cond.empty()) return true;
+        int v = o.cond_and ? 1 : 0;
+        for (int r : o.cond) v = o.cond_and ? (v & rec_bit(r)) : (v ^ rec_bit(r));
+        return v != 0;
+    };
     auto note_support = [&]() {
         res.info.max_support = std::max<uint32_t>(res.info.max_support, (uint32_t)st.v.size());
     };
@@ -750,7 +830,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 apply_clifford(st, o.kind, o.a, o.b);
                 break;
             case K_FEEDBACK:
-                if (rec_bit(o.rec)) apply_pauli_code(st, o.b, o.a);
+                if (cond_holds(o)) apply_pauli_code(st, o.b, o.a);
                 break;
             case K_T: case K_TDG: {
                 Pauli Z;
@@ -770,6 +850,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 break;
             }
             case K_DIAG: {
+                if (!cond_holds(o)) break;  // a classically controlled gate that does not fire
                 apply_diag(st, o.qs, o.phi, tau);
                 res.info.t_entries += st.v.size();
                 res.info.events++;

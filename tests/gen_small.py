@@ -7,15 +7,18 @@ import numpy as np
 def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: float = 0.08,
                    p_mpp: float = 0.04, p_reset: float = 0.03, p_pauli: float = 0.08,
                    clifford_only: bool = False, allow_mpp: bool = True, gates=("H", "S", "SDG", "CX", "CZ"),
-                   p_msc: float = 0.0, p_ccz: float = 0.0, p_diag: float = 0.0):
+                   p_msc: float = 0.0, p_ccz: float = 0.0, p_diag: float = 0.0, p_if: float = 0.0):
     """Random circuit text and its measurement-slot count.  With p_msc > 0, a
     fraction p_msc of the ops come from the extended set: H_XY, H_NXY, MX,
     RX, MR, MRX and record-controlled Paulis XIF/YIF/ZIF; with p_ccz > 0 (and
-    n >= 3) a fraction p_ccz are CCZ / CCX on three distinct qubits."""
+    n >= 3) a fraction p_ccz are CCZ / CCX on three distinct qubits; with
+    p_if > 0, a fraction p_if are classically controlled gates (IF) once a
+    record exists."""
     rng = np.random.Generator(np.random.PCG64(seed))
     msc = rng if p_msc > 0 else None
     ccz = rng if p_ccz > 0 and n >= 3 else None
     dg = rng if p_diag > 0 else None
+    cf = rng if p_if > 0 else None
     n_rec = 0
     if clifford_only:
         p_t = 0.0
@@ -24,6 +27,9 @@ def random_circuit(seed: int, n: int, length: int, p_t: float = 0.15, p_meas: fl
     lines = ["QUBITS %d" % n]
     n_meas_slots = 0
     for _ in range(length):
+        if cf is not None and n_rec and cf.random() < p_if:
+            lines.append(random_if(cf, n, n_rec))
+            continue
         if dg is not None and dg.random() < p_diag:
             lines.append(random_diag(dg, n))
             continue
@@ -90,6 +96,29 @@ def random_diag(rng, n: int) -> str:
         return "CCZ %s" % " ".join(str(int(x)) for x in rng.choice(n, size=3, replace=False))
     a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
     return "CPHASE %s %d %d" % (ang(), a, b) if kind == "CPHASE" else "%s %d %d" % (kind, a, b)
+
+
+def random_if(rng, n: int, n_rec: int) -> str:
+    """One classically controlled gate: IF with the XOR of 1-3 record bits
+    (repeats allowed, so some conditions cancel) or the AND of 2-3, on a
+    Pauli, S, SDG, T, TDG, CZ or one of random_diag's gates."""
+    k = int(rng.integers(1, 4))
+    recs = [str(int(rng.integers(n_rec))) for _ in range(k)]
+    cond = "&".join(recs) if (k > 1 and rng.integers(2) == 0) else ",".join(recs)
+    u = int(rng.integers(6))
+    q = int(rng.integers(n))
+    if u == 0:
+        gate = "%s %d" % ("XYZ"[int(rng.integers(3))], q)
+    elif u == 1:
+        gate = "%s %d" % (("S", "SDG", "T", "TDG")[int(rng.integers(4))], q)
+    elif u == 2 and n >= 2:
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        gate = "CZ %d %d" % (a, b)
+    elif u == 3 and n >= 3:
+        gate = "CCX %s" % " ".join(str(int(x)) for x in rng.choice(n, size=3, replace=False))
+    else:
+        gate = random_diag(rng, n)
+    return "IF %s %s" % (cond, gate)
 
 
 def random_words(seed: int, count: int) -> np.ndarray:

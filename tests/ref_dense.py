@@ -108,6 +108,39 @@ def run(text, meas_words):
     slot = 0
     for tok in ops:
         g = tok[0]
+        if g == "IF":
+            # classically controlled gate: XOR ("a,b") or AND ("a&b") of record
+            # bits.  A Pauli updates the shadow as a bare Pauli does; a diagonal
+            # gate (S, SDG, T, TDG, CZ or a DIAG-family gate) is applied to phi
+            # only, its matrix written out here.
+            cs = tok[1]
+            bits = [record[int(r)] for r in cs.replace("&", ",").split(",")]
+            fire = all(bits) if "&" in cs else (sum(bits) % 2 == 1)
+            sub = tok[2:]
+            if not fire:
+                continue
+            if sub[0] in ("X", "Y", "Z"):
+                q = int(sub[1])
+                phi = apply_1q(phi, MATS[sub[0]], q, n)
+                shadow = apply_1q(shadow, MATS[sub[0]], q, n)
+                continue
+            if sub[0] in ("S", "SDG", "T", "TDG"):
+                ph = {"S": np.pi / 2, "SDG": -np.pi / 2, "T": np.pi / 4, "TDG": -np.pi / 4}[sub[0]]
+                phi = apply_1q(phi, np.diag([1.0, np.exp(1j * ph)]), int(sub[1]), n)
+                continue
+            if sub[0] == "CZ":
+                phi = apply_cz(phi, int(sub[1]), int(sub[2]), n)
+                continue
+            if sub[0] in ("CCZ", "CCX"):
+                a, b, t = int(sub[1]), int(sub[2]), int(sub[3])
+                idx = np.arange(1 << n, dtype=np.uint64)
+                on = ((idx >> np.uint64(a)) & (idx >> np.uint64(b)) & np.uint64(1)).astype(bool)
+                if sub[0] == "CCZ":
+                    phi = np.where(on & ((idx >> np.uint64(t)) & np.uint64(1)).astype(bool), -phi, phi)
+                else:
+                    phi = phi[np.where(on, idx ^ (np.uint64(1) << np.uint64(t)), idx)]
+                continue
+            g, tok = sub[0], sub
         if g in ("H", "S", "SDG", "X", "Y", "Z", "H_XY", "H_NXY"):
             q = int(tok[1])
             phi = apply_1q(phi, MATS[g], q, n)
