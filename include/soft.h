@@ -107,7 +107,7 @@ const char *soft_last_error(const soft_ctx *ctx);
  *   MPP P0*P1*...  (factors X3, Y0, Z7; distinct qubits) |
  *   CCZ a b c | CCX a b t | CS a b | CSDG a b | CPHASE theta a b | RZ theta q |
  *   DIAG k q_0..q_{k-1} phi_0..phi_{2^k-1}  (k = 1..3) |
- *   XIF r q | YIF r q | ZIF r q |
+ *   XIF r q | YIF r q | ZIF r q | IF r0,r1.. GATE args | IF r0&r1&.. GATE args |
  *   DEP1 p q... | DEP2 p a b [a b...] | XERR p q... | ZERR p q... | TICK |
  *   DETECTOR e r... | OBSERVABLE e r...
  * M and MPP append to the measurement record; R measures Z and flips back
@@ -118,7 +118,14 @@ const char *soft_last_error(const soft_ctx *ctx);
  * x = 3, RZ theta = exp(-i theta Z / 2), DIAG the listed phases (radians);
  * each runs in one pass as the sum of its Z-strings (the expansion used in
  * Proposition 1's proof, each term acting by Eq. 4).  XIF/YIF/ZIF r q apply
- * the Pauli to q when record bit r is 1.  DETECTOR ends the shot as
+ * the Pauli to q when record bit r is 1.  IF applies GATE when the XOR of
+ * the listed record bits (',') or their AND ('&') is 1: the corrections of
+ * gate teleportation, which the conclusion names as the next extension.
+ * GATE is X / Y / Z q (sign flips) or a diagonal gate -- S, SDG, T, TDG q,
+ * CZ a b or any of the diagonal gates above -- which acts on the
+ * coefficients by its Z-string expansion in every shot where it fires (the
+ * coefficient span grows in every shot; CCX keeps its H pair unconditional).
+ * IF takes no model noise.  DETECTOR ends the shot as
  * DISCARDED when e ^ XOR(record bits r...) != 0; OBSERVABLE stores that
  * parity as an observable bit.  Op indices (used by abort_op) count op lines
  * from 0.
@@ -229,10 +236,18 @@ int soft_set_noise_mode(soft_ctx *ctx, int mode);
 
 /* Where the per-wave coefficient tile lives (the GPU memory layout of
  * Sec. IV-B, re-planned for LDS and HBM): 0 = automatic (LDS when one
- * wave's tile fits in a block's LDS, else device memory), 1 = LDS, 2 = device
- * memory (HBM; one slab of 2^k_max entries per resident wave, allocated by the
- * library on first use).  LDS is the fast place; device memory lifts the LDS
- * size limit on the span dimension (up to k_max = 20). */
+ * wave's tile fits in a block's LDS, else device memory; soft_autotune also
+ * tries device memory and splits), 1 = LDS, 2 = device memory (HBM; one slab
+ * of 2^k_max entries per resident wave, allocated by the library on first
+ * use), 3 = split: the low 2^L entries of the tile in LDS, the other
+ * 2^k_max - 2^L in a per-wave device-memory slab, with L the autotuned value
+ * or by default the largest L < k_max whose LDS part takes at most 8 KiB;
+ * 256 * L + 3 = split with that L (7 <= L <= 19; L >= k_max acts as
+ * k_max - 1).  A split needs k_max >= 8; below that mode 3 uses LDS.  LDS is
+ * the fast place; device memory lifts the LDS size limit on the span
+ * dimension (up to k_max = 20); a split keeps the small coordinates in LDS
+ * while more waves fit in a CU than with the whole tile there (the support
+ * cap 2^12 with HBM spill of the scale run).  EINVAL for other modes. */
 int soft_set_tile_memory(soft_ctx *ctx, int mode);
 
 /* Batch-schedule autotuning (Sec. V measures throughput against the batch
@@ -338,8 +353,8 @@ int soft_circuit_info(soft_ctx *ctx, uint64_t info[8]);
 int soft_variant_info(soft_ctx *ctx, uint32_t variant, uint64_t info[8]);
 
 /* Launch shape (Sec. IV-B) used by the next run: out[0..4] = waves_per_block,
- * blocks_per_cu, grab, LDS bytes per wave, 1 if the tiles are in device
- * memory. */
+ * blocks_per_cu, grab, LDS bytes per wave (tile or its LDS part, plus record
+ * words), tile placement (0 LDS, 1 device memory, 2 split). */
 int soft_launch_shape(soft_ctx *ctx, uint32_t out[5]);
 
 /* Graph reuse of this context (the persistent launch is a hipGraph of two

@@ -355,12 +355,20 @@ class FrameCompiler {
     // of its qubits, each term shifting the coefficients by its beta (Eq. 4).
     // The span grows by the new betas (terms with c_g = 0 are left out), and
     // the kernel runs one coset of the shifts' span per lane (DiagInfo).
-    void diag(const std::vector<int> &qs, const std::vector<double> &phi, uint32_t src) {
+    // With a condition (`cond` not empty: record bits, XOR or with and_form
+    // AND) the gate is applied only in shots where it holds; the span grows in
+    // every shot and holds zeros at the new coordinates where it does not.
+    void diag(const std::vector<int> &qs, const std::vector<double> &phi, uint32_t src,
+              const std::vector<int> &cond = std::vector<int>(), bool and_form = false) {
         sync();
         spec_reset();  // the span grows: no T pair of an open run can be dropped past this gate
         const uint32_t m = (uint32_t)qs.size(), ng = 1u << m;
         Event E = begin(src);
         E.kind = EV_DIAG;
+        if (!cond.empty()) {
+            E.flags |= EVF_COND;
+            set_condition(E, cond, and_form);
+        }
         DiagInfo D;
         std::memset(&D, 0, sizeof(D));
         D.ng = ng;
@@ -549,21 +557,42 @@ class FrameCompiler {
         finish(E);
     }
 
-    void parity_check(bool detector, int expect, const std::vector<int> &recs, uint32_t obs, uint32_t src) {
-        sync();
-        // fold the record list into (word, mask) pairs; repeats cancel
+    // Record indices as (word, mask) pairs appended to the pair table: under
+    // XOR repeated bits cancel, under AND (merge) they stand once.  Returns the
+    // number of pairs; `off` receives the first.
+    uint32_t record_pairs(const std::vector<int> &recs, bool merge, uint32_t &off) {
         std::vector<uint32_t> words, masks;
         for (int r : recs) {
             uint32_t w = (uint32_t)r >> 5, m = 1u << (r & 31);
             size_t i = 0;
             while (i < words.size() && words[i] != w) ++i;
             if (i == words.size()) { words.push_back(w); masks.push_back(0); }
-            masks[i] ^= m;
+            masks[i] = merge ? (masks[i] | m) : (masks[i] ^ m);
         }
-        const uint32_t off = (uint32_t)(P_.det_pairs.size() / 2);
+        off = (uint32_t)(P_.det_pairs.size() / 2);
         for (size_t i = 0; i < words.size(); ++i)
             if (masks[i]) { P_.det_pairs.push_back(words[i]); P_.det_pairs.push_back(masks[i]); }
-        const uint32_t cnt = (uint32_t)(P_.det_pairs.size() / 2) - off;
+        return (uint32_t)(P_.det_pairs.size() / 2) - off;
+    }
+
+    // The condition of a classically controlled event: its record pairs, the
+    // first one inline, and EVF_AND for the all-bits form.
+    void set_condition(Event &E, const std::vector<int> &recs, bool and_form) {
+        uint32_t off = 0;
+        const uint32_t cnt = record_pairs(recs, and_form, off);
+        E.det_off = off;
+        E.det_cnt = cnt;
+        if (cnt) {
+            E.dw0 = P_.det_pairs[2 * off];
+            E.dm0 = P_.det_pairs[2 * off + 1];
+        }
+        if (and_form) E.flags |= EVF_AND;
+    }
+
+    void parity_check(bool detector, int expect, const std::vector<int> &recs, uint32_t obs, uint32_t src) {
+        sync();
+        uint32_t off = 0;
+        const uint32_t cnt = record_pairs(recs, false, off);
         auto fill = [&](Event &E) {
             E.expect = (uint32_t)expect;
             E.det_off = off;
@@ -593,16 +622,15 @@ class FrameCompiler {
         finish(E);
     }
 
-    // Pauli (1 X, 2 Y, 3 Z) on qubit q when record bit `rec` is 1.
-    void feedback(int pauli, int q, uint32_t rec, uint32_t src) {
+    // Pauli (1 X, 2 Y, 3 Z) on qubit q when the XOR (and_form: the AND) of
+    // the record bits `recs` is 1.
+    void feedback(int pauli, int q, const std::vector<int> &recs, bool and_form, uint32_t src) {
         sync();
         if (pauli != 3) spec_touch(q);
         Event E = begin(src);
         E.kind = EV_FEEDBACK;
-        E.rec = rec;
-        E.det_cnt = 1;  // the record bit, read as a parity check
-        E.dw0 = rec >> 5;
-        E.dm0 = 1u << (rec & 31u);
+        E.rec = recs.empty() ? 0u : (uint32_t)recs[0];
+        set_condition(E, recs, and_form);
         RowMask m;
         if (pauli == 1 || pauli == 2) m ^= cz_[q];
         if (pauli == 3 || pauli == 2) m ^= cx_[q];
@@ -1154,6 +1182,54 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
         auto want = [&](size_t k) {
             if (tok.size() != k) throw CompileError{ln, op + ": wrong number of arguments"};
         };
+        // A diagonal gate named by tok[at]: basis state x of its qubits (bit j
+        // = j-th qubit) picks up e^{i phi_x}.  CCZ: phi = pi at x = 7 (CCX =
+        // H_c CCZ H_c); CS / CSDG: +-pi/2 at x = 3; CPHASE t a b: t at x = 3;
+        // RZ t q = exp(-i t Z / 2): (-t/2, t/2); DIAG k q.. phi_0..phi_{2^k-1}.
+        // Under IF also S / SDG (+-pi/2 at x = 1), T / TDG (+-pi/4, T =
+        // diag(1, e^{i pi/4})) and CZ (pi at x = 3).
+        auto diag_spec = [&](size_t at, std::vector<int> &qs, std::vector<double> &phi) {
+            const std::string &g = tok[at];
+            size_t nq = 0, first = at + 1;
+            if (g == "CCZ" || g == "CCX") nq = 3;
+            else if (g == "CS" || g == "CSDG" || g == "CZ") nq = 2;
+            else if (g == "S" || g == "SDG" || g == "T" || g == "TDG") nq = 1;
+            else if (g == "CPHASE") { nq = 2; first = at + 2; }
+            else if (g == "RZ") { nq = 1; first = at + 2; }
+            else {
+                if (tok.size() < at + 2) throw CompileError{ln, "DIAG takes k, k qubits and 2^k phases"};
+                const int k = parse_uint(tok[at + 1], ln);
+                if (k < 1 || k > 3) throw CompileError{ln, "DIAG takes 1 to 3 qubits"};
+                nq = (size_t)k;
+                first = at + 2;
+            }
+            const size_t need = g == "DIAG" ? first + nq + ((size_t)1 << nq) : first + nq;
+            if (tok.size() != need) throw CompileError{ln, g + ": wrong number of arguments"};
+            qs.clear();
+            for (size_t i = 0; i < nq; ++i) qs.push_back(qubit(tok[first + i]));
+            for (size_t i = 0; i < nq; ++i)
+                for (size_t j = 0; j < i; ++j)
+                    if (qs[i] == qs[j]) throw CompileError{ln, g + " on repeated qubits"};
+            auto angle = [&](const std::string &t) {
+                char *endp = nullptr;
+                const double v = std::strtod(t.c_str(), &endp);
+                if (endp == t.c_str() || *endp != '\0' || !std::isfinite(v)) throw CompileError{ln, "bad angle '" + t + "'"};
+                return v;
+            };
+            phi.assign((size_t)1 << nq, 0.0);
+            if (g == "CCZ" || g == "CCX") phi[7] = M_PI;
+            else if (g == "CZ") phi[3] = M_PI;
+            else if (g == "S") phi[1] = M_PI / 2;
+            else if (g == "SDG") phi[1] = -M_PI / 2;
+            else if (g == "T") phi[1] = M_PI / 4;
+            else if (g == "TDG") phi[1] = -M_PI / 4;
+            else if (g == "CS") phi[3] = M_PI / 2;
+            else if (g == "CSDG") phi[3] = -M_PI / 2;
+            else if (g == "CPHASE") phi[3] = angle(tok[at + 1]);
+            else if (g == "RZ") { phi[0] = -angle(tok[at + 1]) / 2; phi[1] = angle(tok[at + 1]) / 2; }
+            else
+                for (size_t x = 0; x < phi.size(); ++x) phi[x] = angle(tok[first + nq + x]);
+        };
         if (op == "H" || op == "S" || op == "SDG" || op == "X" || op == "Y" || op == "Z" || op == "T" ||
             op == "TDG" || op == "H_XY" || op == "H_NXY") {
             want(2);
@@ -1192,51 +1268,56 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
             }
         } else if (op == "CCZ" || op == "CCX" || op == "CS" || op == "CSDG" || op == "CPHASE" || op == "RZ" ||
                    op == "DIAG") {
-            // Diagonal gates: basis state x of the qubits (bit j = j-th qubit)
-            // picks up e^{i phi_x}.  CCZ: phi = pi at x = 7 (CCX = H_c CCZ
-            // H_c); CS / CSDG: +-pi/2 at x = 3; CPHASE t a b: t at x = 3;
-            // RZ t q = exp(-i t Z / 2): (-t/2, t/2); DIAG k q.. phi_0..phi_{2^k-1}.
-            size_t nq = 0, first = 1;
-            if (op == "CCZ" || op == "CCX") nq = 3;
-            else if (op == "CS" || op == "CSDG") nq = 2;
-            else if (op == "CPHASE") { nq = 2; first = 2; }
-            else if (op == "RZ") { nq = 1; first = 2; }
-            else {
-                if (tok.size() < 2) throw CompileError{ln, "DIAG takes k, k qubits and 2^k phases"};
-                const int k = parse_uint(tok[1], ln);
-                if (k < 1 || k > 3) throw CompileError{ln, "DIAG takes 1 to 3 qubits"};
-                nq = (size_t)k;
-                first = 2;
-            }
-            want(op == "DIAG" ? first + nq + (1u << nq) : first + nq);
             std::vector<int> qs;
-            for (size_t i = 0; i < nq; ++i) qs.push_back(qubit(tok[first + i]));
-            for (size_t i = 0; i < nq; ++i)
-                for (size_t j = 0; j < i; ++j)
-                    if (qs[i] == qs[j]) throw CompileError{ln, op + " on repeated qubits"};
-            auto angle = [&](const std::string &t) {
-                char *endp = nullptr;
-                const double v = std::strtod(t.c_str(), &endp);
-                if (endp == t.c_str() || *endp != '\0' || !std::isfinite(v)) throw CompileError{ln, "bad angle '" + t + "'"};
-                return v;
-            };
-            std::vector<double> phi((size_t)1 << nq, 0.0);
-            if (op == "CCZ" || op == "CCX") phi[7] = M_PI;
-            else if (op == "CS") phi[3] = M_PI / 2;
-            else if (op == "CSDG") phi[3] = -M_PI / 2;
-            else if (op == "CPHASE") phi[3] = angle(tok[1]);
-            else if (op == "RZ") { phi[0] = -angle(tok[1]) / 2; phi[1] = angle(tok[1]) / 2; }
-            else
-                for (size_t x = 0; x < phi.size(); ++x) phi[x] = angle(tok[first + nq + x]);
+            std::vector<double> phi;
+            diag_spec(0, qs, phi);
             for (int q : qs) busy[q] = 1;
             if (op == "CCX") fc.h(qs[2]);
             fc.diag(qs, phi, src);
             if (op == "CCX") fc.h(qs[2]);
             // model noise: DEP2(p2) after a two-qubit diagonal gate, DEP1(p1) on
             // each qubit after a one- or three-qubit one
-            if (nq == 2) fc.noise(NZ_DEP2, nm.p2, qs[0], qs[1], 0);
+            if (qs.size() == 2) fc.noise(NZ_DEP2, nm.p2, qs[0], qs[1], 0);
             else
                 for (int q : qs) fc.noise(NZ_DEP1, nm.p1, q, -1, 0);
+        } else if (op == "IF") {
+            // Classically controlled gate (the corrections of gate
+            // teleportation): IF r0,r1,.. GATE args applies GATE when the XOR of
+            // the record bits is 1, IF r0&r1&.. GATE args when all of them are
+            // 1.  GATE is a Pauli (X, Y, Z: sign flips) or a diagonal gate (S,
+            // SDG, T, TDG, CZ and the diagonal gates above), which acts on the
+            // coefficients by its Z-string expansion so that the x/z frame stays
+            // the same in every shot.  No model noise.
+            if (tok.size() < 3) throw CompileError{ln, "IF takes record bits and a gate"};
+            const std::string &cs = tok[1];
+            const bool has_and = cs.find('&') != std::string::npos, has_xor = cs.find(',') != std::string::npos;
+            if (has_and && has_xor) throw CompileError{ln, "IF: use ',' (XOR) or '&' (AND), not both"};
+            std::vector<int> cond;
+            size_t pos = 0;
+            while (true) {
+                const size_t e = cs.find(has_and ? '&' : ',', pos);
+                const int r = parse_uint(cs.substr(pos, e == std::string::npos ? std::string::npos : e - pos), ln);
+                if ((uint32_t)r >= out.n_rec) throw CompileError{ln, "record index not yet measured"};
+                cond.push_back(r);
+                if (e == std::string::npos) break;
+                pos = e + 1;
+            }
+            const std::string &g = tok[2];
+            if (g == "X" || g == "Y" || g == "Z") {
+                if (tok.size() != 4) throw CompileError{ln, "IF: " + g + " takes one qubit"};
+                fc.feedback(g == "X" ? 1 : g == "Y" ? 2 : 3, qubit(tok[3]), cond, has_and, src);
+            } else if (g == "S" || g == "SDG" || g == "T" || g == "TDG" || g == "CZ" || g == "CCZ" || g == "CCX" ||
+                       g == "CS" || g == "CSDG" || g == "CPHASE" || g == "RZ" || g == "DIAG") {
+                std::vector<int> qs;
+                std::vector<double> phi;
+                diag_spec(2, qs, phi);
+                for (int q : qs) busy[q] = 1;
+                if (g == "CCX") fc.h(qs[2]);  // the H pair is unconditional: H IF(CCZ) H
+                fc.diag(qs, phi, src, cond, has_and);
+                if (g == "CCX") fc.h(qs[2]);
+            } else {
+                throw CompileError{ln, "IF: '" + g + "' is neither a Pauli nor a diagonal gate"};
+            }
         } else if (op == "MX" || op == "RX" || op == "MR" || op == "MRX") {
             // X-basis readout / reset to |+>, measure-then-reset; the error
             // flips anticommute with the measured Pauli (Z for the X basis)
@@ -1257,7 +1338,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
             int r = parse_uint(tok[1], ln);
             if ((uint32_t)r >= out.n_rec) throw CompileError{ln, "record index not yet measured"};
             int q = qubit(tok[2]);
-            fc.feedback(op == "XIF" ? 1 : op == "YIF" ? 2 : 3, q, (uint32_t)r, src);
+            fc.feedback(op == "XIF" ? 1 : op == "YIF" ? 2 : 3, q, std::vector<int>(1, r), false, src);
         } else if (op == "MPP") {
             want(2);
             PauliStr P;

@@ -43,7 +43,9 @@ enum EvKind : uint32_t {
     EV_M_MERGE,      // beta != 0 inside the span: pairs merge, k -> k-1
     EV_DETECTOR,     // parity check of record bits, abort on failure
     EV_OBSERVABLE,   // parity of record bits, stored as an observable bit
-    EV_FEEDBACK,     // Pauli flip (masks xD/xS) when record bit `rec` is 1 (as the check dw0/dm0)
+    EV_FEEDBACK,     // Pauli flip (masks xD/xS) when the XOR of its record bits is 1 (check pairs
+                     // dw0/dm0 and the pair table, as a detector reads them), or with EVF_AND
+                     // when all of them are 1
     EV_DROP,         // speculative: coordinates >= mu carry no amplitude; k -> mu
     EV_DIAG,         // diagonal gate on <= 3 qubits, all its Z-strings in one pass (DiagInfo `boff`)
     EV_END
@@ -62,6 +64,11 @@ enum EvFlags : uint32_t {
                        // pass (k + bcnt <= 6: one final entry per lane); the others are skipped
     EVF_BRUN = 256u,   // speculative: first of `bcnt` EVF_DROP1 butterflies with nothing between them
                        // (k <= 6), run in registers, one entry per lane; the others are skipped
+    EVF_COND = 512u,   // EV_DIAG: classically controlled, applied only when its condition (the check
+                       // pairs, as EV_FEEDBACK reads them) holds; otherwise the span still grows and
+                       // the new coordinates hold zeros
+    EVF_AND = 1024u,   // EV_FEEDBACK / EV_DIAG with EVF_COND: the condition is that every listed
+                       // record bit is 1 (each pair's word covers its whole mask), not their XOR
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane

@@ -7,6 +7,10 @@
 
 namespace soft {
 
+// Where a wave's coefficient tile lives: all in LDS, all in a slab of device
+// memory, or split (the low lds_entries entries in LDS, the rest in a slab).
+enum TileMode : uint32_t { TM_LDS = 0, TM_MEM = 1, TM_SPLIT = 2 };
+
 struct RunParams {
     const Event *ev;
     const NoiseLoc *nz;
@@ -29,7 +33,8 @@ struct RunParams {
     double *keep_v;                // [keep_n][tile_entries][2] or null
     unsigned long long *trace_meta;  // [trace_n][KM_COUNT] or null
     double *trace_v;                 // [trace_n][tile_entries][2] or null
-    void *gtile;              // device-memory tiles, one slab of tile_entries per wave, or null (LDS tiles)
+    void *gtile;              // device-memory slabs, one per wave (TM_MEM: tile_entries entries; TM_SPLIT:
+                              // tile_entries - lds_entries), or null (TM_LDS)
     uint64_t trace_shot;
     uint64_t seed, shot0, n_shots, keep_lo;
     uint64_t word_stride;
@@ -40,6 +45,8 @@ struct RunParams {
                               // record fits in scalar registers and never touches LDS)
     uint32_t speculate;       // 1: run the speculative event list first
     uint32_t noise_mode;      // 0: a word per noise slot, 1: gap sampling (ignored with explicit words)
+    uint32_t tile_mode;       // TileMode
+    uint32_t lds_entries;     // TM_SPLIT: tile entries in LDS (a power of two, 128 .. tile_entries / 2)
     uint32_t pad2_;
     double tau2;              // pruning threshold squared
 };
@@ -51,15 +58,16 @@ hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long 
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream);
 
 // Host handles of the kernels, for graphs built from explicit kernel nodes:
-// the sampler instantiation for a precision, noise source and tile placement
+// the sampler instantiation for a precision, noise source and tile mode
 // (arguments: ev, nz, tm1, det, words, bm, then the RunParams by value), and
 // the counter reset (arguments: counters, n, next; one block of 256 threads).
-const void *sampler_kernel(bool fp64, uint32_t noise_source, bool gt);
+const void *sampler_kernel(bool fp64, uint32_t noise_source, uint32_t tile_mode);
 const void *reset_kernel();
 
 // Blocks of `block` threads with `lds` bytes of dynamic LDS that one CU keeps
 // resident (registers and LDS).
-hipError_t sampler_occupancy(bool fp64, uint32_t noise_source, bool gt, int block, size_t lds, int *blocks_per_cu);
+hipError_t sampler_occupancy(bool fp64, uint32_t noise_source, uint32_t tile_mode, int block, size_t lds,
+                             int *blocks_per_cu);
 
 // Raise the dynamic-LDS limit of every sampler instantiation (called once).
 hipError_t sampler_set_lds_limit(int bytes);

@@ -24,6 +24,7 @@
 #include "sampler.h"
 
 namespace soft {
+
 namespace {
 
 template <typename R> struct Cx;
@@ -130,12 +131,30 @@ template <typename C, typename R> __device__ __forceinline__ C scale(C a, R s) {
     return a;
 }
 
+// The coefficient tile of one wave.  TM = TM_LDS: in LDS; TM_MEM: in a slab
+// of device memory; TM_SPLIT: entries below `lim` in LDS, the others in a
+// slab of device memory (`hi` is that slab's address minus lim entries, so
+// hi + j addresses entry j >= lim).  The split form is read and written
+// through flat addresses, which reach LDS or device memory by the address.
+template <typename C, uint32_t TM> struct Tile {
+    C *lo;
+    C *hi;
+    uint32_t lim;
+    __device__ __forceinline__ C *at(uint32_t j) const { return (TM == TM_SPLIT && j >= lim) ? hi + j : lo + j; }
+    // entry u + l with u wave-uniform and l < 128 <= lim (a power of two):
+    // the place is the same for the whole wave
+    __device__ __forceinline__ C *at_u(uint32_t u, uint32_t l) const {
+        return ((TM == TM_SPLIT && u >= lim) ? hi : lo) + (u + l);
+    }
+    __device__ __forceinline__ C &operator[](uint32_t j) const { return *at(j); }
+};
+
 // Write one shot's state for the readout calls: status, signs, offset, span
 // dimension, carried norm, and the coefficient tile widened to double with the
 // counted global phase e^{i pi phase8 / 8} and the tile's real factor
 // sqrt(tscale2) applied.
-template <typename C>
-__device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const C *v, uint32_t lane,
+template <typename C, uint32_t TM>
+__device__ __forceinline__ void dump_state(unsigned long long *m, double *dst, const Tile<C, TM> &v, uint32_t lane,
                                            uint32_t tile_entries, uint32_t status, uint32_t abort_src, uint32_t term,
                                            uint32_t after, uint64_t rD, uint64_t rS, uint64_t a, uint32_t k,
                                            double nrm2, const double *phase_tab, uint32_t phase8, uint32_t var,
@@ -259,8 +278,8 @@ __device__ __forceinline__ uint32_t next_j(uint32_t J, uint32_t M) { return ((J 
 // iteration adds one uniform byte offset to each.
 // Returns the kept outputs; `cnt1` receives those at the partner coordinates
 // j0 ^ mu (bit h set).
-template <uint32_t Q, typename R, typename C>
-__device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
+template <uint32_t Q, typename R, typename C, uint32_t TM>
+__device__ __forceinline__ uint32_t t_bfly(const Tile<C, TM> &v, uint32_t lane, uint32_t k, uint32_t mu, uint32_t h, uint32_t g,
                                            uint32_t sig, R tn, R thr, uint32_t pb, uint32_t lmask,
                                            uint32_t &cnt1) {
     const uint32_t npairs = 1u << (k - 1u);
@@ -272,8 +291,8 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     const uint32_t lc = ins0(lp, h);
     const uint32_t hb = 1u << h;  // mu's top bit is h; lmask = ins0(63, h)
     const uint32_t mu_l = mu & lmask, mu_i = mu & ~(lmask | hb);
-    char *const p0 = reinterpret_cast<char *>(v + lc);
-    char *const p1 = reinterpret_cast<char *>(v + ((lc ^ mu_l) | hb));
+    char *const p0 = reinterpret_cast<char *>(v.lo + lc);
+    char *const p1 = reinterpret_cast<char *>(v.lo + ((lc ^ mu_l) | hb));
     const R c1 = ((sig ^ par32(g & lc)) != 0u) ? -tn : tn;   // weight of v_j0 in v'_j1
     const R c0 = par32(g & mu) ? -c1 : c1;                   // weight of v_j1 in v'_j0
     uint32_t cnt = 0;
@@ -282,8 +301,16 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
     // one iteration with the Q or (S = 2) the Q + 2 form, in two halves so
     // that a pair of iterations issues all its LDS reads before any write
     // (the iterations of a pass touch disjoint entries)
-    auto addr0 = [&](uint32_t J) { return reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C)); };
-    auto addr1 = [&](uint32_t J) { return reinterpret_cast<C *>(p1 + (J ^ mu_i) * (uint32_t)sizeof(C)); };
+    // (split tile: the lane part is below 128 <= lim, so the uniform part
+    // decides the place of an iteration's entries)
+    auto addr0 = [&](uint32_t J) {
+        if (TM == TM_SPLIT) return v.at_u(J, lc);
+        return reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
+    };
+    auto addr1 = [&](uint32_t J) {
+        if (TM == TM_SPLIT) return v.at_u((J ^ mu_i) | hb, lc ^ mu_l);
+        return reinterpret_cast<C *>(p1 + (J ^ mu_i) * (uint32_t)sizeof(C));
+    };
     auto finish = [&](uint32_t J, C v0, C v1, auto S) {
         constexpr uint32_t QS = (Q + decltype(S)::value) & 3u;
         bool k0, k1;
@@ -342,21 +369,27 @@ __device__ __forceinline__ uint32_t t_bfly(C *v, uint32_t lane, uint32_t k, uint
 
 // Branching T on a new coordinate (k -> k+1): v'_j = v_j and
 // v'_{j+2^k} = tn i^Q (-1)^(sig ^ g.j) v_j.
-template <uint32_t Q, typename R, typename C>
-__device__ __forceinline__ uint32_t t_double(C *v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R tn,
+template <uint32_t Q, typename R, typename C, uint32_t TM>
+__device__ __forceinline__ uint32_t t_double(const Tile<C, TM> &v, uint32_t lane, uint32_t k, uint32_t g, uint32_t sig, R tn,
                                              R thr, uint32_t pb) {
     const uint32_t half = 1u << k;
     // spare lanes repeat a live lane (see t_bfly)
     const uint32_t lp = half >= 64u ? lane : (lane & (half - 1u));
     const uint64_t live = half >= 64u ? ~0ull : ((1ull << half) - 1ull);
     const R c1 = ((sig ^ par32(g & lp)) != 0u) ? -tn : tn;
-    char *const p0 = reinterpret_cast<char *>(v + lp);
-    char *const p1 = reinterpret_cast<char *>(v + half + lp);
+    char *const p0 = reinterpret_cast<char *>(v.lo + lp);
+    char *const p1 = reinterpret_cast<char *>(v.lo + half + lp);
     uint32_t cnt = 0;
     const uint32_t iters = (half + 63u) >> 6;
     // as in t_bfly: a pair of iterations reads before it writes
-    auto addr0 = [&](uint32_t J) { return reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C)); };
-    auto addr1 = [&](uint32_t J) { return reinterpret_cast<C *>(p1 + J * (uint32_t)sizeof(C)); };
+    auto addr0 = [&](uint32_t J) {
+        if (TM == TM_SPLIT) return v.at_u(J, lp);
+        return reinterpret_cast<C *>(p0 + J * (uint32_t)sizeof(C));
+    };
+    auto addr1 = [&](uint32_t J) {
+        if (TM == TM_SPLIT) return v.at_u(J + half, lp);
+        return reinterpret_cast<C *>(p1 + J * (uint32_t)sizeof(C));
+    };
     auto finish = [&](uint32_t J, C v0, auto S) {
         constexpr uint32_t QS = (Q + decltype(S)::value) & 3u;
         bool k0, k1;
@@ -410,7 +443,7 @@ __device__ __forceinline__ uint32_t quot16(uint64_t x, uint64_t d) {
 #define EVF(f) __uint_as_float(EV32(f))
 #define EVD(f) __longlong_as_double((long long)EV64(f))
 
-template <typename R, uint32_t NS, bool GT>
+template <typename R, uint32_t NS, uint32_t TM>
 __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
                                              const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
                                              const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
@@ -420,23 +453,35 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    // The coefficient tile lives in LDS, or (GT) in a per-wave slab of
-    // device memory for spans whose tile does not fit in LDS.  The record
-    // words are always in LDS.
-    C *v;
+    // The coefficient tile lives in LDS; or (TM_MEM) in a per-wave slab of
+    // device memory for spans whose tile does not fit in LDS; or (TM_SPLIT)
+    // its low P.lds_entries entries in LDS and the rest in a per-wave slab.
+    // The record words past kRecSgpr are always in LDS.
+    Tile<C, TM> v;
+    v.hi = nullptr;
+    v.lim = 0;
     uint32_t *rec;
-    if (GT) {
-        v = reinterpret_cast<C *>(P.gtile) + (size_t)(blockIdx.x * (blockDim.x >> 6) + wave) * P.tile_entries;
+    const size_t gwave = (size_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (TM == TM_MEM) {
+        v.lo = reinterpret_cast<C *>(P.gtile) + gwave * P.tile_entries;
         rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes);
     } else {
-        v = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
+        v.lo = reinterpret_cast<C *>(smem + (size_t)wave * P.wave_bytes);
         rec = reinterpret_cast<uint32_t *>(smem + (size_t)wave * P.wave_bytes + P.rec_off);
+        if (TM == TM_SPLIT) {
+            v.lim = P.lds_entries;
+            // hi + j (j >= lim) is entry j's place in the slab: the slab's
+            // address less lim entries, formed as an integer
+            const uintptr_t slab = reinterpret_cast<uintptr_t>(P.gtile) +
+                                   gwave * (size_t)(P.tile_entries - P.lds_entries) * sizeof(C);
+            v.hi = reinterpret_cast<C *>(slab - (uintptr_t)P.lds_entries * sizeof(C));
+        }
     }
     // Lanes read entries that other lanes wrote in the previous pass: with a
-    // device-memory tile, each pass ends with a fence (LDS keeps a wave's
-    // accesses in order by itself).
+    // tile (or its upper part) in device memory, each pass ends with a fence
+    // (LDS keeps a wave's accesses in order by itself).
     auto tile_sync = [&]() {
-        if (GT) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (TM != TM_LDS) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     };
     const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
     const double tau2 = P.tau2;
@@ -524,6 +569,22 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 }
             }
             return uni(pbits);
+        };
+        // Condition of a classically controlled event: the parity of its
+        // record pairs, or (EVF_AND) whether every listed bit is 1.
+        auto cond_check = [&](uint32_t flags) -> uint32_t {
+            if (!(flags & EVF_AND)) return parity_check();
+            const uint32_t cnt_pairs = EV32(det_cnt);
+            uint32_t ok = 1u;
+            if (cnt_pairs) {
+                const uint32_t m0 = EV32(dm0);
+                ok &= (rec_read(EV32(dw0)) & m0) == m0 ? 1u : 0u;
+                for (uint32_t t = 1; t < cnt_pairs; ++t) {
+                    const uint32_t w = det[2u * (EV32(det_off) + t)], m = det[2u * (EV32(det_off) + t) + 1u];
+                    ok &= (rec_read(w) & m) == m ? 1u : 0u;
+                }
+            }
+            return uni(ok);
         };
         uint64_t rD = 0, rS = 0, a = 0;
         uint32_t k = 0;
@@ -901,19 +962,19 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 uint32_t cnt, upper = 0;
                 if (kind == EV_T_DOUBLE) {
                     switch (qb) {
-                        case 0: cnt = t_double<0, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
-                        case 1: cnt = t_double<1, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
-                        case 2: cnt = t_double<2, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
-                        default: cnt = t_double<3, R, C>(v, lane, k, g, sig, tn, thr, pb); break;
+                        case 0: cnt = t_double<0, R, C, TM>(v, lane, k, g, sig, tn, thr, pb); break;
+                        case 1: cnt = t_double<1, R, C, TM>(v, lane, k, g, sig, tn, thr, pb); break;
+                        case 2: cnt = t_double<2, R, C, TM>(v, lane, k, g, sig, tn, thr, pb); break;
+                        default: cnt = t_double<3, R, C, TM>(v, lane, k, g, sig, tn, thr, pb); break;
                     }
                     ++k;
                 } else {
                     const uint32_t mu = EV32(mu), h = EV32(tstar), lm = EV32(lmask);
                     switch (qb) {
-                        case 0: cnt = t_bfly<0, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
-                        case 1: cnt = t_bfly<1, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
-                        case 2: cnt = t_bfly<2, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
-                        default: cnt = t_bfly<3, R, C>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        case 0: cnt = t_bfly<0, R, C, TM>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        case 1: cnt = t_bfly<1, R, C, TM>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        case 2: cnt = t_bfly<2, R, C, TM>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
+                        default: cnt = t_bfly<3, R, C, TM>(v, lane, k, mu, h, g, sig, tn, thr, pb, lm, upper); break;
                     }
                 }
                 phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u)) & 15u;
@@ -1200,14 +1261,24 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     b += 64u;
                 }
                 if (b < cnt) {  // whole blocks, four reads before they are combined
-                    const C *pb = v + b + lane;
                     const uint32_t nb = (cnt - b) >> 6;
                     uint32_t i = 0;
-                    for (; i + 4u <= nb; i += 4u) {
-                        const C x0 = pb[64u * i], x1 = pb[64u * i + 64u], x2 = pb[64u * i + 128u], x3 = pb[64u * i + 192u];
-                        live |= nonzero_bits(x0) | nonzero_bits(x1) | nonzero_bits(x2) | nonzero_bits(x3);
+                    if (TM == TM_SPLIT) {
+                        for (; i + 4u <= nb; i += 4u) {
+                            const uint32_t u = b + 64u * i;
+                            const C x0 = *v.at_u(u, lane), x1 = *v.at_u(u + 64u, lane), x2 = *v.at_u(u + 128u, lane),
+                                    x3 = *v.at_u(u + 192u, lane);
+                            live |= nonzero_bits(x0) | nonzero_bits(x1) | nonzero_bits(x2) | nonzero_bits(x3);
+                        }
+                        for (; i < nb; ++i) live |= nonzero_bits(*v.at_u(b + 64u * i, lane));
+                    } else {
+                        const C *pb = v.lo + b + lane;
+                        for (; i + 4u <= nb; i += 4u) {
+                            const C x0 = pb[64u * i], x1 = pb[64u * i + 64u], x2 = pb[64u * i + 128u], x3 = pb[64u * i + 192u];
+                            live |= nonzero_bits(x0) | nonzero_bits(x1) | nonzero_bits(x2) | nonzero_bits(x3);
+                        }
+                        for (; i < nb; ++i) live |= nonzero_bits(pb[64u * i]);
                     }
-                    for (; i < nb; ++i) live |= nonzero_bits(pb[64u * i]);
                 }
                 if (__ballot(live != 0u) != 0ull) {
                     restart = true;
@@ -1225,53 +1296,63 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 // writes, so the update is in place.
                 const DiagInfo *di = P.diag + EV32(boff);
                 const uint32_t ng = uni(di->ng), r = uni(di->r), knew = uni(di->knew), lead = uni(di->lead);
-                uint32_t sgl = 0;  // sign part of term `lane`, with gamma . a
-                if (lane < ng) sgl = par64((rD & di->beta[lane]) ^ ((rS ^ a) & di->gamma[lane]));
-                const uint32_t S = (uint32_t)__ballot(sgl != 0u);
-                const uint32_t e0 = uni(di->E[1]), e1 = uni(di->E[2]), e2 = uni(di->E[4]);
-                auto coset_el = [&](uint32_t w) { return ((w & 1u) ? e0 : 0u) ^ ((w & 2u) ? e1 : 0u) ^ ((w & 4u) ? e2 : 0u); };
-                // the gate is unitary: the carried norm sets the pruning level
-                const R thr = (R)(tau2 * nrm2 * itscale2);
-                const uint32_t kin = 1u << k, um = (1u << r) - 1u;
-                uint32_t cnt = 0;
-                lane_pass(1u << knew, lane, [&](uint32_t L) {
-                    const uint32_t u = L & um;
-                    uint32_t j0 = L >> r;  // zeros at the lead bits, ascending
-                    for (uint32_t i = 0; i < r; ++i) j0 = ins0(j0, (lead >> (5u * i)) & 31u);
-                    C y = mk<C>(0.0, 0.0);
-                    for (uint32_t g = 0; g < ng; ++g) {
-                        const uint32_t jin = j0 ^ coset_el(u ^ uni(di->ug[g]));
-                        C xv = v[jin < kin ? jin : 0u];
-                        if (jin >= kin) xv = mk<C>(0.0, 0.0);
-                        const R wr = sizeof(R) == 4 ? (R)unif(di->fre[g]) : (R)unid(di->dre[g]);
-                        const R wi = sizeof(R) == 4 ? (R)unif(di->fim[g]) : (R)unid(di->dim[g]);
-                        const bool neg = (((S >> g) ^ par32(uni(di->gm[g]) & jin)) & 1u) != 0u;
-                        const R cr = neg ? -wr : wr, ci = neg ? -wi : wi;
-                        y.x = fma(cr, xv.x, fma(-ci, xv.y, y.x));
-                        y.y = fma(cr, xv.y, fma(ci, xv.x, y.y));
-                    }
-                    bool keep;
-                    const C o = t_keep<R, C>(y, thr, keep);
-                    cnt += (uint32_t)__popcll(__ballot(keep));
-                    v[j0 ^ coset_el(u)] = o;
-                });
-                k = knew;
-                cnt = uni(cnt);
-                maxsup = max(maxsup, cnt);
-                if (cnt > P.support_cap) {
-                    if (!full) {  // the full list decides where the cap is hit
-                        restart = true;
+                if ((flags & EVF_COND) && !cond_check(flags)) {
+                    // a classically controlled gate that does not fire: the
+                    // span still grows, with zeros at the new coordinates
+                    const uint32_t kin = 1u << k, kout = 1u << knew;
+#pragma unroll 1
+                    for (uint32_t b = kin; b < kout; b += 64u)
+                        if (b + lane < kout) v[b + lane] = mk<C>(0.0, 0.0);
+                    k = knew;
+                } else {
+                    uint32_t sgl = 0;  // sign part of term `lane`, with gamma . a
+                    if (lane < ng) sgl = par64((rD & di->beta[lane]) ^ ((rS ^ a) & di->gamma[lane]));
+                    const uint32_t S = (uint32_t)__ballot(sgl != 0u);
+                    const uint32_t e0 = uni(di->E[1]), e1 = uni(di->E[2]), e2 = uni(di->E[4]);
+                    auto coset_el = [&](uint32_t w) { return ((w & 1u) ? e0 : 0u) ^ ((w & 2u) ? e1 : 0u) ^ ((w & 4u) ? e2 : 0u); };
+                    // the gate is unitary: the carried norm sets the pruning level
+                    const R thr = (R)(tau2 * nrm2 * itscale2);
+                    const uint32_t kin = 1u << k, um = (1u << r) - 1u;
+                    uint32_t cnt = 0;
+                    lane_pass(1u << knew, lane, [&](uint32_t L) {
+                        const uint32_t u = L & um;
+                        uint32_t j0 = L >> r;  // zeros at the lead bits, ascending
+                        for (uint32_t i = 0; i < r; ++i) j0 = ins0(j0, (lead >> (5u * i)) & 31u);
+                        C y = mk<C>(0.0, 0.0);
+                        for (uint32_t g = 0; g < ng; ++g) {
+                            const uint32_t jin = j0 ^ coset_el(u ^ uni(di->ug[g]));
+                            C xv = v[jin < kin ? jin : 0u];
+                            if (jin >= kin) xv = mk<C>(0.0, 0.0);
+                            const R wr = sizeof(R) == 4 ? (R)unif(di->fre[g]) : (R)unid(di->dre[g]);
+                            const R wi = sizeof(R) == 4 ? (R)unif(di->fim[g]) : (R)unid(di->dim[g]);
+                            const bool neg = (((S >> g) ^ par32(uni(di->gm[g]) & jin)) & 1u) != 0u;
+                            const R cr = neg ? -wr : wr, ci = neg ? -wi : wi;
+                            y.x = fma(cr, xv.x, fma(-ci, xv.y, y.x));
+                            y.y = fma(cr, xv.y, fma(ci, xv.x, y.y));
+                        }
+                        bool keep;
+                        const C o = t_keep<R, C>(y, thr, keep);
+                        cnt += (uint32_t)__popcll(__ballot(keep));
+                        v[j0 ^ coset_el(u)] = o;
+                    });
+                    k = knew;
+                    cnt = uni(cnt);
+                    maxsup = max(maxsup, cnt);
+                    if (cnt > P.support_cap) {
+                        if (!full) {  // the full list decides where the cap is hit
+                            restart = true;
+                            break;
+                        }
+                        status = ST_OVERFLOW;
+                        abort_src = EV32(src);
+                        term = e;
+                        after = 1;
                         break;
                     }
-                    status = ST_OVERFLOW;
-                    abort_src = EV32(src);
-                    term = e;
-                    after = 1;
-                    break;
                 }
             } else if (kind == EV_FEEDBACK) {
-                // ---- classically controlled Pauli: the record bit is a one-pair check ----
-                if (parity_check()) {
+                // ---- classically controlled Pauli: its record bits read as a check ----
+                if (cond_check(flags)) {
                     rD ^= EV64(xD);
                     rS ^= EV64(xS);
                 }
@@ -1345,20 +1426,20 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
 // registers is what lives across a whole shot (group outputs, shot
 // constants), never the event loop's working set.  FP64 tiles are twice as
 // large: LDS, not registers, sets their occupancy.
-template <uint32_t NS, bool GT>
+template <uint32_t NS, uint32_t TM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sample_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
              const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
              RunParams P) {
-    sample_shots<float, NS, GT>(ev, nz, tm1, det, words, bm, P);
+    sample_shots<float, NS, TM>(ev, nz, tm1, det, words, bm, P);
 }
 
-template <uint32_t NS, bool GT>
+template <uint32_t NS, uint32_t TM>
 __global__ void __launch_bounds__(256)
 k_sample_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
              const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
              RunParams P) {
-    sample_shots<double, NS, GT>(ev, nz, tm1, det, words, bm, P);
+    sample_shots<double, NS, TM>(ev, nz, tm1, det, words, bm, P);
 }
 
 __global__ void k_reset(unsigned long long *counters, uint32_t n, unsigned long long *next) {
@@ -1366,33 +1447,47 @@ __global__ void k_reset(unsigned long long *counters, uint32_t n, unsigned long 
     if (threadIdx.x == 0) *next = 0ull;
 }
 
-template <typename R, uint32_t NS, bool GT> const void *kernel_ptr() {
-    if (sizeof(R) == 4) return (const void *)k_sample_f32<NS, GT>;
-    return (const void *)k_sample_f64<NS, GT>;
+template <typename R, uint32_t NS, uint32_t TM> const void *kernel_ptr() {
+    if (sizeof(R) == 4) return (const void *)k_sample_f32<NS, TM>;
+    return (const void *)k_sample_f64<NS, TM>;
 }
 
-template <typename R, uint32_t NS, bool GT>
+template <typename R, uint32_t NS, uint32_t TM>
 void launch_one(const RunParams &p, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
     if (sizeof(R) == 4)
-        hipLaunchKernelGGL((k_sample_f32<NS, GT>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+        hipLaunchKernelGGL((k_sample_f32<NS, TM>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
     else
-        hipLaunchKernelGGL((k_sample_f64<NS, GT>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
+        hipLaunchKernelGGL((k_sample_f64<NS, TM>), grid, block, lds, stream, p.ev, p.nz, p.tm1, p.det, p.words, p.bm, p);
 }
 
-// The 12 instantiations, indexed by fp64 * 6 + source * 2 + gt.
+// The 18 instantiations, indexed by fp64 * 9 + source * 3 + tile mode.
+constexpr int kKernels = 18;
 template <typename R, uint32_t NS> void kernels_of(const void **out) {
-    out[0] = kernel_ptr<R, NS, false>();
-    out[1] = kernel_ptr<R, NS, true>();
+    out[TM_LDS] = kernel_ptr<R, NS, TM_LDS>();
+    out[TM_MEM] = kernel_ptr<R, NS, TM_MEM>();
+    out[TM_SPLIT] = kernel_ptr<R, NS, TM_SPLIT>();
 }
 void all_kernels(const void **ks) {
     kernels_of<float, NS_SLOTS>(ks + 0);
-    kernels_of<float, NS_EXPLICIT>(ks + 2);
-    kernels_of<float, NS_GAPS>(ks + 4);
-    kernels_of<double, NS_SLOTS>(ks + 6);
-    kernels_of<double, NS_EXPLICIT>(ks + 8);
-    kernels_of<double, NS_GAPS>(ks + 10);
+    kernels_of<float, NS_EXPLICIT>(ks + 3);
+    kernels_of<float, NS_GAPS>(ks + 6);
+    kernels_of<double, NS_SLOTS>(ks + 9);
+    kernels_of<double, NS_EXPLICIT>(ks + 12);
+    kernels_of<double, NS_GAPS>(ks + 15);
 }
-int kernel_index(bool fp64, uint32_t ns, bool gt) { return (fp64 ? 6 : 0) + 2 * (int)ns + (gt ? 1 : 0); }
+int kernel_index(bool fp64, uint32_t ns, uint32_t tm) { return (fp64 ? 9 : 0) + 3 * (int)ns + (int)tm; }
+
+template <uint32_t NS, uint32_t TM> void launch_tm(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds,
+                                                   hipStream_t stream) {
+    if (fp64) launch_one<double, NS, TM>(p, grid, block, lds, stream);
+    else launch_one<float, NS, TM>(p, grid, block, lds, stream);
+}
+template <uint32_t NS> void launch_ns(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds,
+                                      hipStream_t stream) {
+    if (p.tile_mode == TM_SPLIT) launch_tm<NS, TM_SPLIT>(p, fp64, grid, block, lds, stream);
+    else if (p.tile_mode == TM_MEM) launch_tm<NS, TM_MEM>(p, fp64, grid, block, lds, stream);
+    else launch_tm<NS, TM_LDS>(p, fp64, grid, block, lds, stream);
+}
 
 }  // namespace
 
@@ -1403,40 +1498,28 @@ hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long 
 
 hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
     const uint32_t ns = p.words != nullptr ? NS_EXPLICIT : (p.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
-    const bool gt = p.gtile != nullptr;
-    switch (kernel_index(fp64, ns, gt)) {
-        case 0: launch_one<float, NS_SLOTS, false>(p, grid, block, lds, stream); break;
-        case 1: launch_one<float, NS_SLOTS, true>(p, grid, block, lds, stream); break;
-        case 2: launch_one<float, NS_EXPLICIT, false>(p, grid, block, lds, stream); break;
-        case 3: launch_one<float, NS_EXPLICIT, true>(p, grid, block, lds, stream); break;
-        case 4: launch_one<float, NS_GAPS, false>(p, grid, block, lds, stream); break;
-        case 5: launch_one<float, NS_GAPS, true>(p, grid, block, lds, stream); break;
-        case 6: launch_one<double, NS_SLOTS, false>(p, grid, block, lds, stream); break;
-        case 7: launch_one<double, NS_SLOTS, true>(p, grid, block, lds, stream); break;
-        case 8: launch_one<double, NS_EXPLICIT, false>(p, grid, block, lds, stream); break;
-        case 9: launch_one<double, NS_EXPLICIT, true>(p, grid, block, lds, stream); break;
-        case 10: launch_one<double, NS_GAPS, false>(p, grid, block, lds, stream); break;
-        default: launch_one<double, NS_GAPS, true>(p, grid, block, lds, stream); break;
-    }
+    if (ns == NS_EXPLICIT) launch_ns<NS_EXPLICIT>(p, fp64, grid, block, lds, stream);
+    else if (ns == NS_GAPS) launch_ns<NS_GAPS>(p, fp64, grid, block, lds, stream);
+    else launch_ns<NS_SLOTS>(p, fp64, grid, block, lds, stream);
     return hipGetLastError();
 }
 
-const void *sampler_kernel(bool fp64, uint32_t ns, bool gt) {
-    const void *ks[12];
+const void *sampler_kernel(bool fp64, uint32_t ns, uint32_t tm) {
+    const void *ks[kKernels];
     all_kernels(ks);
-    return ks[kernel_index(fp64, ns, gt)];
+    return ks[kernel_index(fp64, ns, tm)];
 }
 
 const void *reset_kernel() { return (const void *)k_reset; }
 
-hipError_t sampler_occupancy(bool fp64, uint32_t ns, bool gt, int block, size_t lds, int *blocks_per_cu) {
-    const void *ks[12];
+hipError_t sampler_occupancy(bool fp64, uint32_t ns, uint32_t tm, int block, size_t lds, int *blocks_per_cu) {
+    const void *ks[kKernels];
     all_kernels(ks);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ks[kernel_index(fp64, ns, gt)], block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ks[kernel_index(fp64, ns, tm)], block, lds);
 }
 
 hipError_t sampler_set_lds_limit(int bytes) {
-    const void *ks[12];
+    const void *ks[kKernels];
     all_kernels(ks);
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

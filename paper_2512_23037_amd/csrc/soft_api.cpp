@@ -30,7 +30,8 @@ thread_local std::string g_create_error;
 
 struct Shape {
     uint32_t wpb = 0, bpc = 0, grab = 0;
-    uint32_t gt = 0;  // 1: coefficient tiles in device memory instead of LDS
+    uint32_t gt = TM_LDS;  // tile placement: TM_LDS, TM_MEM or TM_SPLIT
+    uint32_t lds_log2 = 0; // TM_SPLIT: log2 of the tile entries held in LDS
 };
 
 struct Variant {
@@ -85,7 +86,8 @@ struct soft_ctx {
     int bits = 64;
     double tau = -1.0;
     uint32_t support_cap = 0;
-    int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory
+    int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory, 3 split
+    uint32_t split_log2 = 0;                  // split: log2 of the LDS part asked for (0: default)
     bool speculate = true;                    // run speculative event lists where compiled
     int noise_mode = 0;                       // 0 a word per noise slot, 1 gap sampling
     Shape user;                               // explicit launch shape parts
@@ -175,12 +177,32 @@ double tau_of(const soft_ctx *c) { return c->tau >= 0.0 ? c->tau : (c->bits == 3
 
 uint32_t tile_entries(const soft_ctx *c) { return 1u << c->kmax; }
 uint32_t rec_words(const soft_ctx *c) { return c->rec_words; }
-uint32_t tile_bytes(const soft_ctx *c) { return tile_entries(c) * (c->bits == 64 ? 16u : 8u); }
-// LDS bytes per wave: the tile (unless it lives in device memory) and the record.
-// A record of at most kRecSgpr words stays in scalar registers and takes no LDS.
-uint32_t wave_bytes(const soft_ctx *c, bool gt) {
+uint32_t entry_bytes(const soft_ctx *c) { return c->bits == 64 ? 16u : 8u; }
+uint32_t tile_bytes(const soft_ctx *c) { return tile_entries(c) * entry_bytes(c); }
+// Smallest LDS part of a split tile: the passes put up to 128 consecutive
+// entries of one iteration on a wave's lanes, and the split keeps them in one
+// place.
+constexpr uint32_t kSplitMinLog2 = 7;
+bool split_possible(const soft_ctx *c) { return c->kmax >= kSplitMinLog2 + 1u; }
+// Tile bytes a wave keeps in LDS.
+uint32_t lds_tile_bytes(const soft_ctx *c, const Shape &s) {
+    if (s.gt == TM_MEM) return 0u;
+    if (s.gt == TM_SPLIT) return (1u << s.lds_log2) * entry_bytes(c);
+    return tile_bytes(c);
+}
+// Device-memory slab bytes per wave.
+uint32_t slab_bytes(const soft_ctx *c, const Shape &s) { return tile_bytes(c) - lds_tile_bytes(c, s); }
+// LDS bytes per wave: the tile or its LDS part, and the record.  A record of
+// at most kRecSgpr words stays in scalar registers and takes no LDS.
+uint32_t wave_bytes(const soft_ctx *c, const Shape &s) {
     const uint32_t recb = rec_words(c) > kRecSgpr ? (rec_words(c) * 4u + 15u) & ~15u : 0u;
-    return gt ? std::max<uint32_t>(16u, recb) : ((tile_bytes(c) + 15u) & ~15u) + recb;
+    return std::max<uint32_t>(16u, ((lds_tile_bytes(c, s) + 15u) & ~15u) + recb);
+}
+// Default LDS part of a split tile: at most 8 KiB, below the whole tile.
+uint32_t split_log2_default(const soft_ctx *c) {
+    uint32_t L = c->kmax - 1u;
+    while (L > kSplitMinLog2 && (1u << L) * entry_bytes(c) > 8192u) --L;
+    return L;
 }
 
 void drop_slot(soft_ctx *c, soft_ctx::GraphSlot &g) {
@@ -310,27 +332,37 @@ uint32_t noise_source(const soft_ctx *c) {
     return c->words_dev != nullptr ? NS_EXPLICIT : (c->noise_mode == 1 ? NS_GAPS : NS_SLOTS);
 }
 
-bool tiles_in_memory(const soft_ctx *c) {
-    if (c->tile_mode == 2) return true;
-    if (c->tile_mode == 1) return false;
-    return wave_bytes(c, false) > (uint32_t)c->max_lds_block;
+// The placement asked for (soft_set_tile_memory), or (auto) LDS when one
+// wave's tile fits in a block's LDS, else device memory.  A split needs a
+// span of at least 2^8 entries; below that the tile is small and goes to LDS.
+Shape placement(const soft_ctx *c) {
+    Shape s;
+    if (c->tile_mode == 2) {
+        s.gt = TM_MEM;
+    } else if (c->tile_mode == 3 && split_possible(c)) {
+        s.gt = TM_SPLIT;
+        s.lds_log2 = c->split_log2 ? std::min<uint32_t>(c->split_log2, c->kmax - 1u) : split_log2_default(c);
+    } else if (c->tile_mode == 0) {
+        Shape l;
+        s.gt = wave_bytes(c, l) > (uint32_t)c->max_lds_block ? TM_MEM : TM_LDS;
+    }
+    return s;
 }
 
 // Resident waves per CU when the tile is not the limit (4 waves per SIMD).
 constexpr uint32_t kMemTileWavesPerCu = 16u;
 
 Shape default_shape(const soft_ctx *c) {
-    Shape s;
-    s.gt = tiles_in_memory(c) ? 1u : 0u;
-    const uint32_t wb = wave_bytes(c, s.gt);
-    const uint32_t cap = s.gt ? kMemTileWavesPerCu : kMaxWavesPerCu;
+    Shape s = placement(c);
+    const uint32_t wb = wave_bytes(c, s);
+    const uint32_t cap = s.gt == TM_MEM ? kMemTileWavesPerCu : kMaxWavesPerCu;
     const uint32_t waves_cu = std::max<uint32_t>(1u, std::min<uint32_t>(cap, kLdsPerCu / wb));
     s.wpb = (waves_cu >= 16u && 2u * wb <= (uint32_t)c->max_lds_block) ? 2u : 1u;
     while (s.wpb > 1 && s.wpb * wb > (uint32_t)c->max_lds_block) s.wpb /= 2;
     s.bpc = std::max<uint32_t>(1u, waves_cu / s.wpb);
     // no more blocks than stay resident (registers can be the tighter limit)
     int res = 0;
-    if (sampler_occupancy(c->bits == 64, noise_source(c), s.gt != 0, (int)(64u * s.wpb), (size_t)s.wpb * wb,
+    if (sampler_occupancy(c->bits == 64, noise_source(c), s.gt, (int)(64u * s.wpb), (size_t)s.wpb * wb,
                           &res) == hipSuccess && res > 0)
         s.bpc = std::min<uint32_t>(s.bpc, (uint32_t)res);
     else
@@ -340,7 +372,8 @@ Shape default_shape(const soft_ctx *c) {
 }
 
 TuneKey tune_key(const soft_ctx *c) {
-    return TuneKey(c->arch, c->num_cus, c->hash, c->bits, tau_of(c), c->support_cap, c->tile_mode, c->noise_mode);
+    return TuneKey(c->arch, c->num_cus, c->hash, c->bits, tau_of(c), c->support_cap,
+                   c->tile_mode | (int)(c->split_log2 << 8), c->noise_mode);
 }
 
 Shape current_shape(const soft_ctx *c) {
@@ -350,7 +383,13 @@ Shape current_shape(const soft_ctx *c) {
         auto it = g_tuned.find(tune_key(c));
         if (it != g_tuned.end()) s = it->second;
     }
-    if (c->tile_mode) s.gt = c->tile_mode == 2 ? 1u : 0u;
+    if (c->tile_mode) {  // an explicit placement overrides a tuned one
+        const Shape p = placement(c);
+        if (p.gt != s.gt || (p.gt == TM_SPLIT && c->split_log2)) {
+            s.gt = p.gt;
+            s.lds_log2 = p.lds_log2;
+        }
+    }
     if (c->user.wpb) s.wpb = c->user.wpb;
     if (c->user.bpc) s.bpc = c->user.bpc;
     if (c->user.grab) s.grab = c->user.grab;
@@ -358,7 +397,9 @@ Shape current_shape(const soft_ctx *c) {
 }
 
 int check_shape(soft_ctx *c, const Shape &s) {
-    const uint64_t lds = (uint64_t)s.wpb * wave_bytes(c, s.gt);
+    if (s.gt == TM_SPLIT && (s.lds_log2 < kSplitMinLog2 || s.lds_log2 >= c->kmax))
+        return fail(c, SOFT_EINVAL, "split tile: LDS part out of range");
+    const uint64_t lds = (uint64_t)s.wpb * wave_bytes(c, s);
     if (s.wpb < 1 || s.wpb > 4) return fail(c, SOFT_EINVAL, "waves_per_block must be 1..4");
     if (lds > (uint64_t)c->max_lds_block)
         return fail(c, SOFT_ECAPACITY, "coefficient tile needs " + std::to_string(lds) + " bytes of LDS per block; the device allows " +
@@ -370,22 +411,36 @@ int check_shape(soft_ctx *c, const Shape &s) {
 // Launch reset + sampler on `stream` through an instantiated graph: a slot
 // whose kernel and launch shape match gets the new arguments, else a slot is
 // built (reset node -> sampler node) and instantiated.
-int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStream_t stream) {
-    const uint32_t wb = wave_bytes(c, s.gt);
-    const size_t lds = (size_t)s.wpb * wb;
-    uint64_t blocks_needed = (n_shots + s.wpb - 1) / s.wpb;
-    uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cus * s.bpc, std::max<uint64_t>(blocks_needed, 1));
-    const dim3 g((uint32_t)grid), b(64u * s.wpb);
-    rp.wave_bytes = wb;
-    rp.rec_off = (!s.gt && rec_words(c) > kRecSgpr) ? ((tile_bytes(c) + 15u) & ~15u) : 0u;
+// Blocks of a launch: the resident blocks of the shape, at most one per
+// `wpb` shots.
+uint64_t grid_blocks(const soft_ctx *c, const Shape &s, uint64_t n_shots) {
+    const uint64_t blocks_needed = (n_shots + s.wpb - 1) / s.wpb;
+    return std::min<uint64_t>((uint64_t)c->num_cus * s.bpc, std::max<uint64_t>(blocks_needed, 1));
+}
+
+// LDS layout of a wave's slot (tile unless in device memory, record words
+// past kRecSgpr).
+void set_wave_layout(const soft_ctx *c, const Shape &s, RunParams &rp) {
+    rp.wave_bytes = wave_bytes(c, s);
+    rp.rec_off = (s.gt != TM_MEM && rec_words(c) > kRecSgpr) ? ((lds_tile_bytes(c, s) + 15u) & ~15u) : 0u;
     rp.gtile = nullptr;
-    if (s.gt) {  // one slab per wave of the grid
-        int rc = ensure(c, c->d_gtile, (size_t)grid * s.wpb * tile_bytes(c));
+    rp.tile_mode = s.gt;
+    rp.lds_entries = s.gt == TM_SPLIT ? (1u << s.lds_log2) : 0u;
+}
+
+int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStream_t stream) {
+    const uint32_t wb = wave_bytes(c, s);
+    const size_t lds = (size_t)s.wpb * wb;
+    const uint64_t grid = grid_blocks(c, s, n_shots);
+    const dim3 g((uint32_t)grid), b(64u * s.wpb);
+    set_wave_layout(c, s, rp);
+    if (s.gt != TM_LDS) {  // one slab per wave of the grid
+        int rc = ensure(c, c->d_gtile, (size_t)grid * s.wpb * slab_bytes(c, s));
         if (rc) return rc;
         rp.gtile = c->d_gtile.p;
     }
     const uint32_t ns = rp.words != nullptr ? NS_EXPLICIT : (rp.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
-    const void *kfn = sampler_kernel(c->bits == 64, ns, s.gt != 0);
+    const void *kfn = sampler_kernel(c->bits == 64, ns, s.gt);
     // what the nodes' launch configuration and the reset node depend on
     const uint64_t kv[7] = {(uint64_t)(uintptr_t)kfn, grid, (uint64_t)b.x, (uint64_t)lds,
                             (uint64_t)(uintptr_t)rp.counters, (uint64_t)rp.n_vars, (uint64_t)(uintptr_t)rp.next};
@@ -850,8 +905,12 @@ int soft_set_noise_mode(soft_ctx *c, int mode) {
 
 int soft_set_tile_memory(soft_ctx *c, int mode) {
     if (!c) return SOFT_EINVAL;
-    if (mode < 0 || mode > 2) return fail(c, SOFT_EINVAL, "tile memory mode must be 0 (auto), 1 (LDS) or 2 (device memory)");
-    c->tile_mode = mode;
+    const int base = mode & 0xff, L = mode >> 8;
+    if (mode < 0 || base > 3 || (base != 3 && L != 0) || (L != 0 && (L < (int)kSplitMinLog2 || L > 19)))
+        return fail(c, SOFT_EINVAL, "tile memory mode must be 0 (auto), 1 (LDS), 2 (device memory), 3 (split) or "
+                                    "256 L + 3 (split with 2^L entries in LDS, 7 <= L <= 19)");
+    c->tile_mode = base;
+    c->split_log2 = (uint32_t)L;
     return SOFT_OK;
 }
 
@@ -1062,7 +1121,7 @@ int soft_launch_shape(soft_ctx *c, uint32_t out[5]) {
     out[0] = s.wpb;
     out[1] = s.bpc;
     out[2] = s.grab;
-    out[3] = wave_bytes(c, s.gt);
+    out[3] = wave_bytes(c, s);
     out[4] = s.gt;
     return SOFT_OK;
 }
@@ -1113,15 +1172,35 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
     cands.push_back(default_shape(c));
     const uint32_t wpbs[3] = {1, 2, 4};
     const uint32_t grabs[2] = {16, 64};
-    std::vector<uint32_t> gts;
-    if (c->tile_mode == 1) gts = {0u};
-    else if (c->tile_mode == 2) gts = {1u};
-    else gts = tiles_in_memory(c) ? std::vector<uint32_t>{1u} : std::vector<uint32_t>{0u, 1u};
-    for (uint32_t gt : gts) {
-        const uint32_t wb = wave_bytes(c, gt != 0);
+    // placements: the one asked for; in auto mode LDS (when it fits), device
+    // memory, and splits whose LDS part is 1/2, 1/4 or 1/8 of the tile
+    std::vector<Shape> places;
+    if (c->tile_mode != 0) {
+        places.push_back(placement(c));
+        if (places[0].gt == TM_SPLIT && !c->split_log2)  // other LDS parts of the split
+            for (uint32_t d = 1; d <= 3; ++d) {
+                Shape p = places[0];
+                p.lds_log2 = c->kmax - d;
+                if (p.lds_log2 >= kSplitMinLog2 && p.lds_log2 != places[0].lds_log2) places.push_back(p);
+            }
+    } else {
+        const Shape auto_p = placement(c);
+        if (auto_p.gt == TM_LDS) places.push_back(auto_p);
+        Shape m;
+        m.gt = TM_MEM;
+        places.push_back(m);
+        for (uint32_t d = 1; d <= 3 && split_possible(c); ++d) {
+            Shape p;
+            p.gt = TM_SPLIT;
+            p.lds_log2 = c->kmax - d;
+            if (p.lds_log2 >= kSplitMinLog2) places.push_back(p);
+        }
+    }
+    for (const Shape &place : places) {
+        const uint32_t wb = wave_bytes(c, place);
         for (uint32_t wpb : wpbs) {
             if (wpb * wb > (uint32_t)c->max_lds_block) continue;
-            const uint32_t cap = gt ? kMemTileWavesPerCu : kMaxWavesPerCu;
+            const uint32_t cap = place.gt == TM_MEM ? kMemTileWavesPerCu : kMaxWavesPerCu;
             const uint32_t occ = std::max<uint32_t>(1u, std::min<uint32_t>(kLdsPerCu / (wpb * wb), cap / wpb));
             std::vector<uint32_t> bpcs;
             for (uint32_t d : {4u, 2u, 1u}) {
@@ -1130,11 +1209,10 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
             }
             for (uint32_t bpc : bpcs)
                 for (uint32_t grab : grabs) {
-                    Shape sh;
+                    Shape sh = place;
                     sh.wpb = wpb;
                     sh.bpc = bpc;
                     sh.grab = grab;
-                    sh.gt = gt;
                     cands.push_back(sh);
                 }
         }

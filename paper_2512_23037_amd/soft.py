@@ -205,9 +205,10 @@ class Context:
         """0: one word per noise location (default); 1: gap sampling."""
         self._check(self._lib.soft_set_noise_mode(self._h, mode))
 
-    def set_tile_memory(self, mode: int):
-        """0 automatic, 1 LDS, 2 device memory (HBM)."""
-        self._check(self._lib.soft_set_tile_memory(self._h, mode))
+    def set_tile_memory(self, mode: int, lds_log2: int = 0):
+        """0 automatic, 1 LDS, 2 device memory (HBM), 3 split (the low
+        2^lds_log2 entries in LDS, the rest in HBM; 0 = default / autotuned)."""
+        self._check(self._lib.soft_set_tile_memory(self._h, int(mode) | (int(lds_log2) << 8)))
 
     def set_keep(self, shot_lo: int, count: int):
         self._check(self._lib.soft_set_keep(self._h, shot_lo, count))
