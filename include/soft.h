@@ -287,6 +287,29 @@ int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes
              uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev,
              void *hip_stream);
 
+/* soft_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, outputs and results as soft_run; the caller owns the outputs.
+ * This call allocates nothing: no hipMalloc / hipFree, no graph is built.
+ * It launches the counter reset and the sampler directly on hip_stream (so
+ * a caller may capture them) and takes its counters, work cursor and any
+ * device-memory tiles from a static scratch array of 32 MiB + 64 KiB per GPU,
+ * which the library holds on each GPU it runs on until the process ends.
+ * Device-memory tiles and the device-memory parts of split tiles
+ * (soft_set_tile_memory) get at most 32 MiB of slabs, so such a launch may
+ * run fewer waves; ECAPACITY when one block's slabs exceed 32 MiB.
+ * The circuit's device tables are uploaded (allocated) by the soft_load_*
+ * calls, never here.
+ *   ESTATE: no circuit loaded;
+ *   EUNSUPPORTED: kept states or a trace are on (they use library buffers).
+ * Every call on a GPU, from any context, shares that GPU's scratch and leaves
+ * its counters there: soft_read_counters afterwards reads the last such call
+ * on the GPU.  Calls that overlap on one GPU (other streams, other contexts)
+ * race on the scratch and must be serialized by the caller. */
+int soft_run_noalloc(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes_dev,
+                     uint32_t *status_dev, uint32_t *abort_op_dev, uint32_t *obs_dev,
+                     void *hip_stream);
+
 /* Re-run of chosen shots (Sec. IV-B: shots over the fixed capacity are run
  * again under a larger configuration).  Sample an explicit list of global
  * shot indices: shots_dev (device, uint64,

@@ -72,4 +72,17 @@ hipError_t sampler_occupancy(bool fp64, uint32_t noise_source, uint32_t tile_mod
 // Raise the dynamic-LDS limit of every sampler instantiation (called once).
 hipError_t sampler_set_lds_limit(int bytes);
 
+// Device scratch of the allocation-free run (soft_run_noalloc): a static
+// device array per GPU, held until the process ends.  The counter rows and
+// the work cursor take the first kScratchCounterBytes; device-memory tiles
+// take the rest, one slab per resident wave.
+constexpr size_t kScratchCounterBytes = 64u << 10;
+constexpr size_t kScratchTileBytes = 32u << 20;
+constexpr size_t kScratchBytes = kScratchCounterBytes + kScratchTileBytes;
+
+// Device address of that array on `device` (looked up once per device with
+// the device current, then cached).  Host code must use this address, never
+// the array's own name, which on the host is only a stand-in.
+hipError_t scratch_address(int device, unsigned char **out);
+
 }  // namespace soft

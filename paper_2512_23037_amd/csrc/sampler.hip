@@ -18,12 +18,16 @@
 // renormalisation accumulated in FP64; Pauli noise per shot as sign flips.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "program.h"
 #include "sampler.h"
 
 namespace soft {
+
+// Scratch of the allocation-free run (see scratch_address below).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -1525,6 +1529,28 @@ hipError_t sampler_set_lds_limit(int bytes) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+hipError_t scratch_address(int device, unsigned char **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned char *addr[kMaxDevices] = {};
+    if (!out || device < 0 || device >= kMaxDevices) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<unsigned char *>(p);
+    }
+    *out = addr[device];
     return hipSuccess;
 }
 

@@ -44,6 +44,7 @@ struct Variant {
 };
 
 constexpr size_t kCounterWords = (size_t)kMaxVariants * C_COUNT + 1;
+static_assert(kCounterWords * sizeof(unsigned long long) <= kScratchCounterBytes, "scratch counter area");
 
 // Kept final states: at most this many shots, and at most kMaxKeepBytes of
 // dense tiles (FP64 pairs) for them.
@@ -103,6 +104,7 @@ struct soft_ctx {
     unsigned long long *d_counters = nullptr;  // kMaxVariants rows of C_COUNT, then the work cursor
     const unsigned long long *last_counters = nullptr;  // counters of the last run
     double *d_phase = nullptr;                 // cos/sin of k pi/8, k = 0..15
+    unsigned char *scratch = nullptr;          // this device's static scratch (soft_run_noalloc)
 
     uint64_t keep_lo = 0;
     uint32_t keep_n = 0;
@@ -727,6 +729,8 @@ int soft_create(soft_ctx **out, int hip_device) {
     if ((e = hipMalloc((void **)&c->d_counters, kCounterWords * sizeof(unsigned long long))) != hipSuccess)
         return bad(e, "hipMalloc");
     if ((e = hipMemset(c->d_counters, 0, kCounterWords * sizeof(unsigned long long))) != hipSuccess) return bad(e, "hipMemset");
+    // the static scratch of soft_run_noalloc: its device address on this GPU
+    if ((e = scratch_address(hip_device, &c->scratch)) != hipSuccess) return bad(e, "hipGetSymbolAddress(scratch)");
     {
         double tab[32];
         for (int q = 0; q < 16; ++q) {
@@ -943,6 +947,66 @@ int soft_run(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, 
     Shape s = current_shape(c);
     if ((rc = check_shape(c, s))) return rc;
     return run_impl(c, shot0, n_shots, outcomes, status, abort_op, obs, (hipStream_t)hip_stream, s);
+}
+
+int soft_run_noalloc(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes, uint32_t *status,
+                     uint32_t *abort_op, uint32_t *obs, void *hip_stream) {
+    if (!c) return SOFT_EINVAL;
+    if (!status && n_shots) return fail(c, SOFT_EINVAL, "status_dev is required");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->have_text) return fail(c, SOFT_ESTATE, "no circuit loaded");
+    if (c->dirty)  // the soft_load_* calls upload the tables; this stays only after a failed upload
+        return fail(c, SOFT_ESTATE, "the circuit's device tables are not uploaded (the last soft_load_* failed)");
+    if (c->keep_n || c->trace_n)
+        return fail(c, SOFT_EUNSUPPORTED, "kept states and traces use buffers the library allocates; turn them off "
+                                          "(soft_set_keep(ctx, 0, 0), soft_set_trace(ctx, 0, 0)) for soft_run_noalloc");
+    if (c->words_dev) {
+        if (c->mixture) return fail(c, SOFT_EUNSUPPORTED, "explicit words are for a single circuit, not a mixture");
+        const Program &P = c->vars[0].prog;
+        if (c->words_noise != P.n_noise || c->words_meas != P.n_meas)
+            return fail(c, SOFT_EINVAL, "explicit words: expected " + std::to_string(P.n_noise) + " noise and " +
+                                            std::to_string(P.n_meas) + " measurement slots per shot");
+        if (n_shots > c->words_n) return fail(c, SOFT_EINVAL, "explicit words: fewer rows than shots");
+    }
+    if (shot0 + n_shots < shot0 || shot0 + n_shots > c->vars.back().shot_end)
+        return fail(c, SOFT_EINVAL, "shots beyond the last variant's range");
+    if (n_shots == 0) return SOFT_OK;
+    Shape s = current_shape(c);
+    int rc = check_shape(c, s);
+    if (rc) return rc;
+    RunParams rp;
+    if ((rc = make_params(c, shot0, n_shots, outcomes, status, abort_op, obs, rp))) return rc;
+    rp.grab = s.grab;
+    set_wave_layout(c, s, rp);
+    // counters and cursor, then (device-memory tiles) one slab per wave, all
+    // in this device's static scratch; with slabs the grid shrinks to what
+    // the scratch holds (the kernel is persistent, so fewer waves take more
+    // shots each)
+    rp.counters = reinterpret_cast<unsigned long long *>(c->scratch);
+    rp.next = rp.counters + kCounterWords - 1;
+    uint64_t grid = grid_blocks(c, s, n_shots);
+    if (s.gt != TM_LDS) {
+        const uint64_t slab = (uint64_t)s.wpb * slab_bytes(c, s);
+        const uint64_t fit = kScratchTileBytes / slab;
+        if (fit == 0)
+            return fail(c, SOFT_ECAPACITY, "device-memory tiles of one block need " + std::to_string(slab) +
+                                               " bytes; soft_run_noalloc's scratch holds " +
+                                               std::to_string(kScratchTileBytes) + " (span dimension " +
+                                               std::to_string(c->kmax) + ")");
+        grid = std::min<uint64_t>(grid, fit);
+        rp.gtile = c->scratch + kScratchCounterBytes;
+    }
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    HIPCHK(c, launch_reset(rp.counters, rp.n_vars * (uint32_t)C_COUNT, rp.next, stream));
+    HIPCHK(c, launch_sampler(rp, c->bits == 64, dim3((uint32_t)grid), dim3(64u * s.wpb),
+                             (size_t)s.wpb * wave_bytes(c, s), stream));
+    c->ran = true;
+    c->last_counters = rp.counters;
+    c->last_stream = stream;
+    c->last_shot0 = shot0;
+    c->last_n = n_shots;
+    c->last_list = false;
+    return SOFT_OK;
 }
 
 namespace {

@@ -25,7 +25,7 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
            "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
-           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode", "soft_graph_info")
+           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode", "soft_graph_info", "soft_run_noalloc")
 
 
 class SoftError(RuntimeError):
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
         "soft_autotune": (I, [P, U64, P]),
         "soft_set_keep": (I, [P, U64, U32]),
         "soft_run": (I, [P, U64, U64, P, P, P, P, P]),
+        "soft_run_noalloc": (I, [P, U64, U64, P, P, P, P, P]),
         "soft_read_counters": (I, [P, ctypes.POINTER(soft_counters)]),
         "soft_read_coeffs": (I, [P, U64, P, P, P, U32, ctypes.POINTER(U32)]),
         "soft_read_tableau": (I, [P, U64, P, P, P]),
@@ -222,6 +223,13 @@ class Context:
         of the documented shapes (outcomes [record_words, n_shots])."""
         self._check(self._lib.soft_run(self._h, shot0, n_shots, _ptr(outcomes), _ptr(status), _ptr(abort_op),
                                        _ptr(obs), _stream_handle(stream)))
+
+    def run_noalloc(self, shot0: int, n_shots: int, outcomes=None, status=None, abort_op=None, obs=None,
+                    stream=None):
+        """soft_run_noalloc: as run(), allocating nothing (counters, cursor and
+        device-memory tiles in the library's static per-GPU scratch)."""
+        self._check(self._lib.soft_run_noalloc(self._h, shot0, n_shots, _ptr(outcomes), _ptr(status),
+                                               _ptr(abort_op), _ptr(obs), _stream_handle(stream)))
 
     def run_list(self, shots, outcomes=None, status=None, abort_op=None, obs=None, stream=None):
         """Sample the global shot indices in `shots` (an int64 CUDA tensor);
