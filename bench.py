@@ -33,6 +33,7 @@ WORKLOAD = "cultivation_42q"
 SEED_CIRCUIT = 1
 SEED_RNG = 20251223
 SUBSET = 10000          # shots 0..SUBSET-1 compared with the oracle
+LONG_SHOTS_P = 5e-4     # noise rate of the leg whose discard rate is near the paper's d=5 circuit
 
 # Peaks (MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz):
 INT_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit vector lane-ops/s, 39.3 T
@@ -180,7 +181,7 @@ def cpu_baseline(w, shots_sample: int, noise_mode: int, subsets: dict):
     return base, r["work"], shots_sample, checks
 
 
-def roofline(work, nsample, shots, ms, c):
+def roofline(work, nsample, shots, ms, c, traffic_path=PROFILE_TRAFFIC, issue_path=PROFILE_ISSUE):
     """Algorithmic int and FP work of one launch over its measured time."""
     ps = {k: v / nsample for k, v in work.items()}
     int_per_shot = (INT_PER_ENTRY * (ps["t_entries"] + ps["t_phase_entries"] + ps["m_entries"]) +
@@ -199,18 +200,19 @@ def roofline(work, nsample, shots, ms, c):
            "fp": {"flops_per_shot": fp_per_shot, "achieved": fp_rate, "unit": "TFLOP/s",
                   "peak": FP32_PEAK_TFLOPS, "frac": fp_rate / FP32_PEAK_TFLOPS,
                   "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": fp_rate / FP32_NONPACKED_TFLOPS}}
-    t = profile_of(PROFILE_TRAFFIC, shots)
+    t = profile_of(traffic_path, shots)
     out["traffic_source"] = None
     if t is not None:
         out["traffic"] = t["bytes_per_launch"]
         out["traffic_source"] = ("rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE of this kernel source (scaled by a 1 GiB copy): "
-                                 "profiles/sampler_cultivation_42q_traffic.md")
+                                 "profiles/" + os.path.basename(traffic_path).replace(".json", ".md"))
         out["hbm_frac"] = t["bytes_per_launch"] / sec / 8e12
-    q = profile_of(PROFILE_ISSUE, shots)
+    q = profile_of(issue_path, shots)
     if q is not None:
         out["measured"] = {k: q[k] for k in ("valu_insts_per_shot", "salu_insts_per_shot", "valu_issue_frac",
                                              "salu_issue_frac") if k in q}
-        out["measured"]["source"] = "rocprofv3 --pmc SQ_INSTS_VALU, SQ_INSTS_SALU: profiles/sampler_cultivation_42q_sq_counters.md"
+        out["measured"]["source"] = ("rocprofv3 --pmc SQ_INSTS_VALU, SQ_INSTS_SALU: profiles/" +
+                                     os.path.basename(issue_path).replace("_issue.json", "_sq_counters.md"))
     # The same unit costs over the work the kernel executed (its own
     # counters): dense-tile T entries instead of the oracle's sparse support,
     # no class sums for measurements whose outcome the compiled span fixes.
@@ -220,6 +222,87 @@ def roofline(work, nsample, shots, ms, c):
                        "per_shot": {"t_entries": c["entries_t"] / shots, "m_entries": c["entries_m"] / shots,
                                     "noise_words": c["noise_slots"] / shots}}
     return out
+
+
+SCALE_WORKLOAD = "cultivation_42q_k12"
+SCALE_PS = (2.5e-4, 5e-4, 1e-3)
+PROFILE_SCALE_TRAFFIC = os.path.join(ROOT, "profiles", "sampler_scale_k12_traffic.json")
+PROFILE_SCALE_ISSUE = os.path.join(ROOT, "profiles", "sampler_scale_k12_issue.json")
+
+
+def bench_scale(torch, workloads, soft, args):
+    """The scale configuration: the span-12 member of the 42-qubit family
+    (coefficient support up to 2^12, the scale run's cap) at p = 2.5e-4,
+    5e-4 and 1e-3 as three variants of one mixture, --shots per launch split
+    evenly; FP32 coefficients, gap-sampled noise; tile placement (LDS, device
+    memory or LDS with the upper coordinates spilled to device memory) and
+    launch shape from the autotuner.  The roofline's units come from the
+    oracle's work counts on a sample of each variant, which is also the CPU
+    baseline."""
+    import oracle
+    shots = args.shots
+    w = workloads.config(SCALE_WORKLOAD, seed=SEED_CIRCUIT)
+    models = [{k: p for k in ("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp")} for p in SCALE_PS]
+    ends = [shots * (v + 1) // len(SCALE_PS) for v in range(len(SCALE_PS))]
+    ctx = soft.Context(0)
+    ctx.load_mixture([w.text] * len(SCALE_PS), models, ends)
+    ctx.set_rng(SEED_RNG)
+    ctx.set_precision(32)
+    ctx.set_noise_mode(args.noise_mode)
+    ctx.set_tile_memory(args.tile_memory)
+    if args.autotune:
+        ctx.autotune(args.autotune)
+    dev = torch.device("cuda", 0)
+    nw = ctx.info()["record_words"]
+    bufs = (torch.zeros((nw, shots), dtype=torch.int32, device=dev), torch.zeros(shots, dtype=torch.int32, device=dev),
+            torch.zeros(shots, dtype=torch.int32, device=dev), torch.zeros(shots, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.run(0, shots, *bufs, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.run(0, shots, *bufs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    c = ctx.counters()
+    per = []
+    for v, p in enumerate(SCALE_PS):
+        cv = ctx.counters(v)
+        per.append({"p": p, "shots": cv["shots"], "passed": cv["passed"], "logical_errors": cv["logical_errors"],
+                    "ler": cv["logical_errors"] / max(1, cv["passed"])})
+    out = {"metric": "shots/sec on 1 MI355X, scale run (span-12 42q/72T circuit, support cap 2^12)",
+           "value": shots / (ms / 1e3), "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "cultivation-shaped 42q/72T circuit with 7 Z checks (span 12), p in "
+                                  "{2.5e-4, 5e-4, 1e-3} as one mixture, %d shots per launch" % shots,
+                      "launch": ctx.launch_shape(),
+                      "noise_draws": ["a word per noise location", "gap sampling"][args.noise_mode]},
+           "stats": {"passed": c["passed"], "discarded": c["discarded"], "overflow": c["overflow"],
+                     "restarts": c["restarts"], "support_hist": c["support_hist"]},
+           "variants": per}
+    ctx.close()
+    if not args.no_cpu_baseline:
+        oracle.build(force=False)
+        threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+        per_v = max(1, args.cpu_sample // len(SCALE_PS))
+        work, dt = None, 0.0
+        for v, (p, m) in enumerate(zip(SCALE_PS, models)):
+            circ = oracle.Circuit(w.text, m, noise_mode=args.noise_mode)
+            lo = 0 if v == 0 else ends[v - 1]
+            t0 = time.perf_counter()
+            r = circ.batch(SEED_RNG, lo, per_v, threads=threads)
+            dt += time.perf_counter() - t0
+            work = dict(r["work"]) if work is None else {k: work[k] + r["work"][k] for k in work}
+        n = per_v * len(SCALE_PS)
+        out["cpu_baseline"] = {"value": n / dt, "unit": "shots/s", "cores": threads, "kind": "oracle",
+                               "sample": "%d shots of each variant (seed %d), %d host threads, %.1f s wall"
+                                         % (per_v, SEED_RNG, threads, dt)}
+        out["roofline"] = roofline(work, n, shots, ms, c, PROFILE_SCALE_TRAFFIC, PROFILE_SCALE_ISSUE)
+    print(json.dumps(out))
 
 
 def bench_mixture(torch, workloads, soft, args):
@@ -276,6 +359,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (its baseline, the roofline's units and the oracle comparison)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-long-shots", action="store_true", help="skip the FP32 leg at p = 5e-4")
     ap.add_argument("--autotune", type=int, default=0, help="sample shots for the autotuner (0 = library default shape)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy 3 times (HBM counter calibration for rocprofv3 --pmc)")
@@ -283,6 +367,12 @@ def main():
                     help="0: one noise word per location; 1: gap sampling (same distribution)")
     ap.add_argument("--mixture", action="store_true",
                     help="instead: the batching run (27 circuit/noise variants, --shots in one launch per step)")
+    ap.add_argument("--scale", action="store_true",
+                    help="instead: the scale configuration (span-12 circuit at three noise rates, FP32, "
+                         "autotuned tile placement; --shots in one launch per step)")
+    ap.add_argument("--tile-memory", type=int, default=0,
+                    help="--scale: tile placement (0 auto/autotuned, 1 LDS, 2 device memory, 3 split, "
+                         "256 L + 3 split with 2^L entries in LDS)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the sampler shards shot ranges across GPUs by design, "
@@ -304,6 +394,11 @@ def main():
 
     if args.mixture:
         bench_mixture(torch, workloads, soft, args)
+        return
+    if args.scale:
+        if args.autotune == 0 and args.tile_memory == 0:
+            args.autotune = 1 << 21
+        bench_scale(torch, workloads, soft, args)
         return
 
     w = workloads.config(WORKLOAD, seed=SEED_CIRCUIT)
@@ -331,6 +426,27 @@ def main():
         ctx.close()
         torch.cuda.empty_cache()
 
+    # The same circuit at p = 5e-4, where its discard rate (~87%) is close to
+    # the 85.6% of the paper's d=5 circuit at p = 1e-3: shots run longer
+    # before their first failed check.  FP32, reported beside the headline.
+    long_leg = None
+    if not args.no_long_shots:
+        wl = workloads.config(WORKLOAD, seed=SEED_CIRCUIT, p=LONG_SHOTS_P)
+        ctx = make_ctx(soft, wl, 32, args.noise_mode)
+        nw = ctx.info()["record_words"]
+        bufs = (torch.zeros((nw, shots), dtype=torch.int32, device=dev),
+                torch.zeros(shots, dtype=torch.int32, device=dev),
+                torch.zeros(shots, dtype=torch.int32, device=dev),
+                torch.zeros(shots, dtype=torch.int32, device=dev))
+        ms_l, _ = time_steps(torch, ctx, shots, max(1, min(args.steps, 3)), 1, bufs)
+        cl = ctx.counters()
+        long_leg = {"p": LONG_SHOTS_P, "value": shots / (ms_l / 1e3), "ms_per_step": ms_l,
+                    "discard_rate": cl["discarded"] / max(1, cl["shots"]),
+                    "ler": cl["logical_errors"] / max(1, cl["passed"]), "passed_per_s": cl["passed"] / (ms_l / 1e3)}
+        del bufs
+        ctx.close()
+        torch.cuda.empty_cache()
+
     r32 = results[32]
     value = shots / (r32["ms"] / 1e3)
     c = r32["counters"]
@@ -349,6 +465,8 @@ def main():
                   "discard_rate": c["discarded"] / max(1, c["shots"]), "max_norm_dev": c["max_norm_dev"],
                   "restarts": c["restarts"]},
     }
+    if long_leg is not None:
+        out["fp32_at_paper_discard_rate"] = long_leg
     if 64 in results:
         r64 = results[64]
         v64 = shots / (r64["ms"] / 1e3)
