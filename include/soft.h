@@ -78,6 +78,9 @@ typedef struct {
     uint64_t restarts;           /* shots re-run on the full event list: the speculative
                                     list's span truncation found amplitude left (noise
                                     broke a T / T-dagger cancellation) */
+    uint64_t prefix_shots;       /* attempts that started from a checkpoint of the noiseless
+                                    trajectory (soft_set_shared_prefix); the work fields
+                                    above count only the work run */
 } soft_counters;
 
 /* Create a context on HIP device `hip_device` (made current for the call):
@@ -234,6 +237,22 @@ int soft_set_speculation(soft_ctx *ctx, int on);
  * Returns SOFT_EINVAL for another mode. */
 int soft_set_noise_mode(soft_ctx *ctx, int mode);
 
+/* Checkpoints of the noiseless trajectory (default on).  Up to the first
+ * measurement with a random outcome, every event of a circuit is
+ * deterministic in a shot that no noise has hit (Sec. II-C's model: the
+ * noise Paulis are the only per-shot randomness before it), so every such
+ * shot is in the same state at each point there.  The compiler marks up to 16
+ * checkpoints per event list (around the check rounds, and before the first
+ * random measurement or the end); each run first computes the noiseless
+ * trajectory once per variant and list on the GPU (the same per-shot code,
+ * noise off) and stores the state at every checkpoint; a shot then starts at
+ * the last checkpoint before its first noise hit, and loads that
+ * checkpoint's coefficient tile only if an event reads it.  Results are
+ * identical bit for bit either way (the same arithmetic on the same values);
+ * on = 0 runs every shot from the start.  The counters' work fields count the
+ * work run; prefix_shots counts the shots that started from a checkpoint. */
+int soft_set_shared_prefix(soft_ctx *ctx, int on);
+
 /* Where the per-wave coefficient tile lives (the GPU memory layout of
  * Sec. IV-B, re-planned for LDS and HBM): 0 = automatic (LDS when one
  * wave's tile fits in a block's LDS, else device memory; soft_autotune also
@@ -292,9 +311,11 @@ int soft_run(soft_ctx *ctx, uint64_t shot0, uint64_t n_shots, uint32_t *outcomes
  * arguments, outputs and results as soft_run; the caller owns the outputs.
  * This call allocates nothing: no hipMalloc / hipFree, no graph is built.
  * It launches the counter reset and the sampler directly on hip_stream (so
- * a caller may capture them) and takes its counters, work cursor and any
- * device-memory tiles from a static scratch array of 32 MiB + 64 KiB per GPU,
- * which the library holds on each GPU it runs on until the process ends.
+ * a caller may capture them) and takes its counters, work cursors,
+ * checkpoint slots (soft_set_shared_prefix; at most 4 MiB, else shots run
+ * from the start with the same results) and any device-memory tiles from a static
+ * scratch array of 36 MiB + 64 KiB per GPU, which the library holds on each
+ * GPU it runs on until the process ends.
  * Device-memory tiles and the device-memory parts of split tiles
  * (soft_set_tile_memory) get at most 32 MiB of slabs, so such a launch may
  * run fewer waves; ECAPACITY when one block's slabs exceed 32 MiB.

@@ -1113,6 +1113,54 @@ static void fuse_drop_runs(Program &P) {
 // Running work counts of the event list (see Event::cum_t): the span
 // dimension before each event is the same in every shot, so the work of a
 // shot that stops after event e is the sum over the events up to e.
+// Events that read or write the coefficient tile.
+static bool touches_tile(const Event &E) {
+    return E.kind == EV_T_PHASE || E.kind == EV_T_DOUBLE || E.kind == EV_T_BFLY || E.kind == EV_M_CUT ||
+           E.kind == EV_M_SPLIT || E.kind == EV_M_MERGE || E.kind == EV_DROP || E.kind == EV_DIAG;
+}
+
+// Checkpoints of the noiseless trajectory.  The kernel steps over a list one
+// iteration at a time (a fused run of doublings or of dropping butterflies,
+// or a run of outcome-fixed measurements, is one iteration), and a shot can
+// start at any iteration boundary.  Up to the first measurement with a random
+// outcome every event is deterministic in a shot that no noise has hit.  A
+// checkpoint goes at each boundary where the iterations switch between those
+// that touch the tile and those that do not (outcome-fixed measurements,
+// checks, feedback), and before the first random measurement or the list's
+// end, when noise slots lie between it and the last one; the first
+// tile-touching iteration at or after a checkpoint is flagged EVF_MAT (a shot
+// started there loads the checkpoint's tile then, if ever).
+static void checkpoints(Program &out) {
+    out.ckpts.clear();
+    const uint32_t n = (uint32_t)out.events.size();
+    uint32_t e = 0, nz = 0, last_nz = 0;
+    int prev_tile = -1;
+    bool need_mat = false;
+    while (e < n) {
+        Event &E = out.events[e];
+        const bool tile = touches_tile(E);
+        // the end of the list, or a measurement whose outcome is random: the
+        // trajectory stops being shared here (a last checkpoint before it)
+        const bool stop = E.kind == EV_END || E.kind == EV_M_CUT || E.kind == EV_M_SPLIT || E.kind == EV_M_MERGE;
+        if (e > 0 && prev_tile >= 0 && ((int)tile != prev_tile || stop) && (nz > last_nz || out.ckpts.empty()) &&
+            out.ckpts.size() < kMaxCheckpoints) {
+            out.ckpts.push_back(Checkpoint{e, nz});
+            last_nz = nz;
+            need_mat = true;
+        }
+        if (tile && need_mat) {
+            E.flags |= EVF_MAT;
+            need_mat = false;
+        }
+        if (stop) break;
+        const uint32_t step = (E.flags & (EVF_TRUN | EVF_BRUN)) ? E.bcnt
+                            : (E.kind == EV_M_DET && (E.flags & EVF_BATCH)) ? E.bcnt : 1u;
+        for (uint32_t i = 0; i < step && e + i < n; ++i) nz = std::max(nz, out.events[e + i].noise_end);
+        prev_tile = tile ? 1 : 0;
+        e += step;
+    }
+}
+
 static void work_sums(Program &out) {
     uint64_t t = 0, m = 0;
     uint32_t n = 0;
@@ -1410,6 +1458,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     }
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
+    checkpoints(out);
     work_sums(out);
     gap_tables(out);
     // pad the threshold table to whole 256-slot chunks

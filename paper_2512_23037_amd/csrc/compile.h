@@ -36,6 +36,10 @@ struct Program {
     std::vector<Frame> before;        // frame when event e starts
     std::vector<Frame> after;         // frame when event e has finished
     uint64_t hash = 0;                // of the text and the noise model
+    // Checkpoints of the noiseless trajectory, by increasing event and noise
+    // slot: a shot with no noise hit among slots [0, nz) reaches event ev in
+    // the same state as every other such shot.
+    std::vector<Checkpoint> ckpts;
 };
 
 struct CompileError {

@@ -69,6 +69,8 @@ enum EvFlags : uint32_t {
                        // the new coordinates hold zeros
     EVF_AND = 1024u,   // EV_FEEDBACK / EV_DIAG with EVF_COND: the condition is that every listed
                        // record bit is 1 (each pair's word covers its whole mask), not their XOR
+    EVF_MAT = 2048u,   // the first event at or after a checkpoint that reads or writes the tile: a
+                       // shot started from that checkpoint loads the checkpoint's tile here
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane
@@ -200,9 +202,36 @@ struct alignas(16) VariantDesc {
     uint32_t n_noise;
     uint32_t ev_off_full;  // the full event list (ev_off: the speculative one, or the same)
     uint32_t gap_off;      // gap-sampling threshold table of this variant (n_noise entries)
+    // checkpoints of the noiseless trajectory (Program::ckpts) of the list at
+    // ev_off and of the full list: [ck_off, ck_off + ck_cnt) of the table
+    uint32_t ck_off, ck_cnt, ck_off_full, ck_cnt_full;
 };
-static_assert(sizeof(VariantDesc) == 32, "variant layout");
+static_assert(sizeof(VariantDesc) == 48, "variant layout");
 constexpr uint32_t kMaxVariants = 64;
+
+// A checkpoint of the noiseless trajectory: the point before event `ev` of a
+// list, after noise slots [0, nz).  Up to the first measurement with a random
+// outcome every event is deterministic in a shot that no noise has hit, so
+// every such shot is in the same state there.
+struct Checkpoint {
+    uint32_t ev, nz;
+};
+constexpr uint32_t kMaxCheckpoints = 16;
+
+// A checkpoint's state, built once per launch (one slot per checkpoint of the
+// table): this header at the slot's start, the record words at byte 128, the
+// coefficient tile (2^k entries of the run's precision) after them, 16-byte
+// aligned.
+struct alignas(16) CkptState {
+    uint64_t rD, rS, a;
+    double nrm2, itscale2;
+    double tnorm;     // sum of |v_j|^2 over the tile, summed as a shot's end sums it
+    uint32_t k, phase8, maxsup, obs;
+    uint32_t valid;   // 1 once the build reached the checkpoint
+    uint32_t pad[3];
+};
+static_assert(sizeof(CkptState) == 80, "checkpoint layout");
+constexpr uint32_t kCkptRecOff = 128;
 
 enum NoiseKind : uint32_t { NZ_NONE = 0, NZ_DEP1, NZ_DEP2, NZ_XERR, NZ_FLIP, NZ_ZERR };
 
@@ -243,6 +272,7 @@ enum Counter {
     C_SHOTS = 0, C_PASSED, C_DISCARDED, C_OVERFLOW, C_NUMERIC, C_LOGICAL,
     C_ENTRIES_T, C_ENTRIES_M, C_NOISE, C_EVENTS, C_NORMDEV_BITS,
     C_RESTARTS,              // shots restarted on the full list after a failed DROP check
+    C_PREFIX,                // attempts that started from a checkpoint of the noiseless trajectory
     C_HIST0,                 // 16 buckets of floor(log2(max |v|))
     C_COUNT = C_HIST0 + 16
 };

@@ -35,6 +35,9 @@ struct RunParams {
     double *trace_v;                 // [trace_n][tile_entries][2] or null
     void *gtile;              // device-memory slabs, one per wave (TM_MEM: tile_entries entries; TM_SPLIT:
                               // tile_entries - lds_entries), or null (TM_LDS)
+    const Checkpoint *ckpts;  // checkpoint table (VariantDesc::ck_off / ck_cnt index it)
+    unsigned char *prefix;    // checkpoint state slots, one per table entry (CkptState, record, tile), or
+                              // null (every shot runs from the start)
     uint64_t trace_shot;
     uint64_t seed, shot0, n_shots, keep_lo;
     uint64_t word_stride;
@@ -47,11 +50,16 @@ struct RunParams {
     uint32_t noise_mode;      // 0: a word per noise slot, 1: gap sampling (ignored with explicit words)
     uint32_t tile_mode;       // TileMode
     uint32_t lds_entries;     // TM_SPLIT: tile entries in LDS (a power of two, 128 .. tile_entries / 2)
+    uint32_t prefix_build;    // 1: the build launch -- item i runs variant i / 2's list (i odd: the full
+                              // list) without noise up to its last checkpoint, writing each checkpoint's
+                              // slot
+    uint32_t prefix_stride;   // bytes per prefix slot
     uint32_t pad2_;
     double tau2;              // pruning threshold squared
 };
 
-// Zero `n` counters and the work cursor (a kernel, so it can live in a graph).
+// Zero `n` counters and the two work cursors next[0] (sampler) and next[1]
+// (prefix build): a kernel, so it can live in a graph.
 hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long long *next, hipStream_t stream);
 
 // The persistent sampler: grid x block threads, `lds` bytes of dynamic LDS.
@@ -63,6 +71,10 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
 // the counter reset (arguments: counters, n, next; one block of 256 threads).
 const void *sampler_kernel(bool fp64, uint32_t noise_source, uint32_t tile_mode);
 const void *reset_kernel();
+// The shared-prefix build kernel for a precision and tile mode (arguments as
+// the sampler's, with RunParams::prefix_build set), and a direct launch of it.
+const void *prefix_kernel(bool fp64, uint32_t tile_mode);
+hipError_t launch_prefix_build(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream);
 
 // Blocks of `block` threads with `lds` bytes of dynamic LDS that one CU keeps
 // resident (registers and LDS).
@@ -77,11 +89,13 @@ hipError_t sampler_set_lds_limit(int bytes);
 // the work cursor take the first kScratchCounterBytes; device-memory tiles
 // take the rest, one slab per resident wave.
 constexpr size_t kScratchCounterBytes = 64u << 10;
+constexpr size_t kScratchPrefixBytes = 4u << 20;
 constexpr size_t kScratchTileBytes = 32u << 20;
-constexpr size_t kScratchBytes = kScratchCounterBytes + kScratchTileBytes;
+constexpr size_t kScratchBytes = kScratchCounterBytes + kScratchPrefixBytes + kScratchTileBytes;
 
 // Device address of that array on `device` (looked up once per device with
-// the device current, then cached).  Host code must use this address, never
+// the device current, then cached).  Layout: counters and cursors,
+// checkpoint slots (kScratchPrefixBytes), tile slabs.  Host code must use this address, never
 // the array's own name, which on the host is only a stand-in.
 hipError_t scratch_address(int device, unsigned char **out);
 

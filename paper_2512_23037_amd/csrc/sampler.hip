@@ -153,6 +153,18 @@ template <typename C, uint32_t TM> struct Tile {
     __device__ __forceinline__ C &operator[](uint32_t j) const { return *at(j); }
 };
 
+// Sum of |v_j|^2 in FP64 over a tile of 2^k entries: the end-of-shot norm
+// check, and the same sum stored with a checkpoint's tile.
+template <typename C, uint32_t TM>
+__device__ __forceinline__ double tile_norm(const Tile<C, TM> &v, uint32_t k, uint32_t lane) {
+    double nn = 0.0;
+    lane_pass(1u << k, lane, [&](uint32_t j) {
+        const C x = v[j];
+        nn += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+    });
+    return wave_sum(nn);
+}
+
 // Write one shot's state for the readout calls: status, signs, offset, span
 // dimension, carried norm, and the coefficient tile widened to double with the
 // counted global phase e^{i pi phase8 / 8} and the tile's real factor
@@ -500,6 +512,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
     bool var_ok = false;
     uint64_t var_lo = 0, var_end = 0;
     auto flush_counters = [&]() {
+        if (P.prefix_build) {  // the build samples no shots
+            myc = 0;
+            maxdev = 0.0;
+            return;
+        }
         unsigned long long *row = P.counters + (size_t)var * C_COUNT;
         if (lane < (uint32_t)C_COUNT && lane != (uint32_t)C_NORMDEV_BITS && myc) atomicAdd(row + lane, (unsigned long long)myc);
         if (lane == (uint32_t)C_NORMDEV_BITS) atomicMax(row + lane, (unsigned long long)__double_as_longlong(maxdev));
@@ -535,7 +552,9 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         }
         const uint64_t i = group_base + group_pos;
         // a vector load of a uniform address: say that the result is uniform
-        const uint64_t shot = uni64(P.shot_list ? P.shot_list[i] : P.shot0 + i);
+        // (item i of the prefix build runs the first shot of variant i / 2)
+        const uint64_t shot = uni64(P.prefix_build ? ((i >> 1) ? P.vars[(i >> 1) - 1u].shot_end : 0ull)
+                                    : P.shot_list ? P.shot_list[i] : P.shot0 + i);
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
         if (!var_ok || shot >= var_end || shot < var_lo) {
             if (var_ok) flush_counters();
@@ -737,6 +756,19 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // (with a support cap the full list runs: the cap is defined by the
         // supports of the circuit's own gate order)
         bool full = tracing || !P.speculate || P.support_cap != 0xFFFFFFFFu || vdp->ev_off_full == vdp->ev_off;
+        if (P.prefix_build) full = (i & 1u) != 0u || vdp->ev_off_full == vdp->ev_off;
+        bool pfx_done = false;      // the build wrote every checkpoint of this item's list
+        uint32_t ck_next_done = 0;  // checkpoints written
+        // the checkpoint whose tile the shot still has to load (null: the
+        // tile is in place)
+        const unsigned char *lazy_slot = nullptr;
+        const uint32_t tile_off = kCkptRecOff + ((P.rec_words * 4u + 15u) & ~15u);
+        auto materialize = [&]() {
+            const C *pt = reinterpret_cast<const C *>(lazy_slot + tile_off);
+            lane_pass(1u << k, lane, [&](uint32_t j) { v[j] = pt[j]; });
+            tile_sync();
+            lazy_slot = nullptr;
+        };
         for (;;) {
         const uint32_t *evl = reinterpret_cast<const uint32_t *>(ev + (full ? vdp->ev_off_full : vdp->ev_off));
         for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64) rec[w] = 0u;
@@ -760,19 +792,123 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         gd = 0;
         m_base = 0xFFFFFF00u;
         bool restart = false;
+        // Checkpoints of the noiseless trajectory of this list: entries
+        // [ck_o, ck_o + ck_c) of the checkpoint table, each with a state slot
+        // the build launch wrote for this launch.
+        const uint32_t ck_o = uni(full ? vdp->ck_off_full : vdp->ck_off);
+        const uint32_t ck_c = uni(full ? vdp->ck_cnt_full : vdp->ck_cnt);
+        auto ck_slot = [&](uint32_t t) { return P.prefix + (size_t)t * P.prefix_stride; };
+        // The build: no noise (every slot counts as drawn, none hit); the
+        // list's events run up to its last checkpoint, and the state at each
+        // checkpoint goes to its slot (the full list's item only, when the
+        // variant has one list).
+        uint32_t ck_next = 0;
+        if (P.prefix_build) {
+            nz_drawn = n_slots;
+            if (ck_c == 0u || (!(i & 1u) && vdp->ev_off_full == vdp->ev_off)) {
+                pfx_done = true;  // nothing to write (or the odd item writes these slots)
+                break;
+            }
+        }
+        auto write_ckpt = [&](uint32_t t) {
+            unsigned char *slot = ck_slot(t);
+            C *pt = reinterpret_cast<C *>(slot + tile_off);
+            const double nn = tile_norm(v, k, lane);
+            lane_pass(1u << k, lane, [&](uint32_t j) { pt[j] = v[j]; });
+            uint32_t *pr = reinterpret_cast<uint32_t *>(slot + kCkptRecOff);
+            if (lane < kRecSgpr && lane < P.rec_words) pr[lane] = rrv;
+            for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64u) pr[w] = rec[w];
+            if (lane == 0) {
+                CkptState *cs = reinterpret_cast<CkptState *>(slot);
+                cs->rD = rD;
+                cs->rS = rS;
+                cs->a = a;
+                cs->nrm2 = nrm2;
+                cs->itscale2 = itscale2;
+                cs->tnorm = nn;
+                cs->k = k;
+                cs->phase8 = phase8;
+                cs->maxsup = maxsup;
+                cs->obs = obs;
+                cs->valid = 1u;
+            }
+        };
+        // A shot starts at the last checkpoint before its first noise hit:
+        // the noise slots are decided here as the event loop would decide
+        // them (the same draws; no hit is taken, there is none before the
+        // checkpoint), the scalars and the record come from the slot, and the
+        // tile is loaded only if an event reads it (EVF_MAT): a shot that a
+        // check ends first never needs it.
+        uint32_t e0 = 0;
+        lazy_slot = nullptr;
+        if (P.prefix != nullptr && !P.prefix_build && !tracing && ck_c != 0u) {
+            // checkpoint c's noise count and validity in lane c (one load each)
+            uint32_t cev = 0u, cnz = 0xFFFFFFFFu, cok = 0u;
+            if (lane < ck_c) {
+                const Checkpoint cp = P.ckpts[ck_o + lane];
+                cev = cp.ev;
+                cnz = cp.nz;
+                cok = reinterpret_cast<const CkptState *>(ck_slot(ck_o + lane))->valid;
+            }
+            uint32_t best = 0xFFFFFFFFu;
+            for (uint32_t c = 0; c < ck_c; ++c) {
+                const uint32_t pn = uni((uint32_t)__builtin_amdgcn_readlane((int)cnz, (int)c));
+                while (next_hit >= pn && nz_drawn < pn && nz_drawn < n_slots) {
+                    if (GAPS) draw_gap(); else draw_chunk();
+                }
+                if (next_hit < pn || (uint32_t)__builtin_amdgcn_readlane((int)cok, (int)c) != 1u) break;
+                best = c;
+            }
+            if (best != 0xFFFFFFFFu) {
+                // the slot's header, dword d in lane d
+                const unsigned char *slot = ck_slot(ck_o + best);
+                const uint32_t hd = lane < (uint32_t)(sizeof(CkptState) / 4u) ? reinterpret_cast<const uint32_t *>(slot)[lane] : 0u;
+                auto h32 = [&](uint32_t off) { return (uint32_t)__builtin_amdgcn_readlane((int)hd, (int)(off / 4u)); };
+                auto h64 = [&](uint32_t off) { return ((uint64_t)h32(off + 4u) << 32) | (uint64_t)h32(off); };
+                rD = h64(offsetof(CkptState, rD));
+                rS = h64(offsetof(CkptState, rS));
+                a = h64(offsetof(CkptState, a));
+                nrm2 = __longlong_as_double((long long)h64(offsetof(CkptState, nrm2)));
+                itscale2 = __longlong_as_double((long long)h64(offsetof(CkptState, itscale2)));
+                k = h32(offsetof(CkptState, k));
+                phase8 = h32(offsetof(CkptState, phase8));
+                maxsup = h32(offsetof(CkptState, maxsup));
+                obs = h32(offsetof(CkptState, obs));
+                const uint32_t *pr = reinterpret_cast<const uint32_t *>(slot + kCkptRecOff);
+                if (lane < kRecSgpr && lane < P.rec_words) rrv = pr[lane];
+                for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64u) rec[w] = pr[w];
+                lazy_slot = slot;
+                e0 = uni((uint32_t)__builtin_amdgcn_readlane((int)cev, (int)best));
+                myc += lane == (uint32_t)C_PREFIX ? 1u : 0u;
+            }
+        }
         // Event e sits in evc, one dword per lane; event e + 1 is in evx, and
         // event e + 2 is loaded while event e runs (the list ends with three
         // END events).
-        evc = evl[lane];
-        uint32_t evx = evl[64u + lane];
-        uint32_t e = 0;  // after the loop: the last event run
+        evc = evl[(uint64_t)e0 * 64u + lane];
+        uint32_t evx = evl[(uint64_t)(e0 + 1u) * 64u + lane];
+        uint32_t e = e0;  // after the loop: the last event run
+        // trace steps, or (build) the events up to the last checkpoint
+        const uint32_t dump_lim = (P.prefix_build && ck_c) ? uni(P.ckpts[ck_o + ck_c - 1u].ev) + 1u : trace_lim;
         for (;; ++e) {
             uint32_t evy = evl[(uint64_t)(e + 2u) * 64u + lane];
-            if (e - 1u < trace_lim)  // state after event e-1 (e = 0 wraps past any limit)
-                dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
-                           P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
-                           abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u,
-                           1.0 / itscale2);
+            if (e - 1u < dump_lim) {  // state after event e-1 (e = 0 wraps past any limit)
+                if (P.prefix_build) {
+                    if (e == uni(P.ckpts[ck_o + ck_next].ev)) {
+                        write_ckpt(ck_o + ck_next);
+                        ck_next_done = ++ck_next;
+                        if (ck_next == ck_c) {
+                            pfx_done = true;
+                            break;
+                        }
+                    }
+                } else {
+                    dump_state(P.trace_meta + (uint64_t)(e - 1u) * KM_COUNT,
+                               P.trace_v + (uint64_t)(e - 1u) * P.tile_entries * 2u, v, lane, P.tile_entries, status,
+                               abort_src, e - 1u, 1u, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u,
+                               1.0 / itscale2);
+                }
+            }
             // ---- noise slots before this event ----
             // Hits are rare: `next_hit` is the lowest pending hit of the drawn
             // chunk, so an event with none before it costs two compares.
@@ -793,9 +929,12 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             }
             // ---- Cliffords since the previous event: one XOR ----
             const uint32_t flags = EV32(flags);
-            if (flags & EVF_CLIFF) {
-                rD ^= EV64(cliffD);
-                rS ^= EV64(cliffS);
+            if (flags & (EVF_CLIFF | EVF_MAT)) {
+                if (flags & EVF_CLIFF) {
+                    rD ^= EV64(cliffD);
+                    rS ^= EV64(cliffS);
+                }
+                if ((flags & EVF_MAT) && lazy_slot != nullptr) materialize();
             }
             const uint32_t kind = EV32(kind);
             if (kind == EV_END) {
@@ -1382,23 +1521,38 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         {
             // work of this attempt: the list's running sums at the event after
             // the last one run, and the noise words drawn
+            // (less the running sums at e0 when the shot started from a
+            // shared prefix: the work the kernel ran)
             const Event *nx = reinterpret_cast<const Event *>(evl) + e + 1u;
-            const uint64_t wt = uni64(nx->cum_t), wm = uni64(nx->cum_m);
-            const uint32_t we = uni(nx->cum_e);
+            const Event *n0 = reinterpret_cast<const Event *>(evl) + e0;
+            const uint64_t wt = uni64(nx->cum_t) - uni64(n0->cum_t), wm = uni64(nx->cum_m) - uni64(n0->cum_m);
+            const uint32_t we = uni(nx->cum_e) - uni(n0->cum_e);
             const uint32_t wn = GAPS ? ((gd + 255u) & ~255u) : min(nz_drawn, vdp->n_noise);
             myc += lane == (uint32_t)C_ENTRIES_T ? wt : lane == (uint32_t)C_ENTRIES_M ? wm
                  : lane == (uint32_t)C_EVENTS ? (uint64_t)we : lane == (uint32_t)C_NOISE ? (uint64_t)wn : 0ull;
         }
-        if (!restart) break;
+        if (!restart || P.prefix_build) break;
         full = true;
         myc += lane == (uint32_t)C_RESTARTS ? 1u : 0u;
         }
+        if (P.prefix_build) {
+            // a list that ended (or stopped) before a checkpoint leaves its slot invalid
+            if (!pfx_done && lane == 0) {
+                const uint32_t o = full ? vdp->ck_off_full : vdp->ck_off, cnt = full ? vdp->ck_cnt_full : vdp->ck_cnt;
+                for (uint32_t t = ck_next_done; t < cnt; ++t)
+                    reinterpret_cast<CkptState *>(P.prefix + (size_t)(o + t) * P.prefix_stride)->valid = 0u;
+            }
+            ++group_pos;
+            continue;
+        }
 
         // ---- shot end: norm check, outputs, kept states, counters ----
-        const uint32_t cnt = 1u << k;
-        double nn = 0.0;
-        lane_pass(cnt, lane, [&](uint32_t j) { nn += nrm<R>(v[j]); });
-        nn = wave_sum(nn);
+        // (a shot that ended on a checkpoint's tile without loading it: the
+        // sum stored with it, computed the same way)
+        const bool kept = P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n;
+        if (lazy_slot != nullptr && kept) materialize();
+        const double nn = lazy_slot != nullptr ? unid(reinterpret_cast<const CkptState *>(lazy_slot)->tnorm)
+                                               : tile_norm(v, k, lane);
         maxdev = fmax(maxdev, fabs(nn / itscale2 - 1.0));
         {
             // one store for the record words held in scalar registers and the
@@ -1410,7 +1564,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         if (P.outcomes)
             for (uint32_t w = kRecSgpr + lane; w < P.rec_words; w += 64u) P.outcomes[(uint64_t)w * P.n_shots + i] = rec[w];
         ++group_pos;
-        if (P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
+        if (kept) {
             const uint64_t kk = shot - P.keep_lo;
             dump_state(P.keep_meta + kk * KM_COUNT, P.keep_v + kk * (uint64_t)P.tile_entries * 2u, v, lane,
                        P.tile_entries, status, abort_src, term, after, rD, rS, a, k, nrm2, P.phase_tab, phase8, var, full ? 1u : 0u, 1.0 / itscale2);
@@ -1446,9 +1600,28 @@ k_sample_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, cons
     sample_shots<double, NS, TM>(ev, nz, tm1, det, words, bm, P);
 }
 
+// The shared-prefix build (RunParams::prefix_build): the same per-shot code
+// with the same register budget, under its own name so that profiles show it
+// apart from the sampler.  It draws no noise, so one noise source serves.
+template <uint32_t TM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_prefix_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
+             const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
+             RunParams P) {
+    sample_shots<float, NS_SLOTS, TM>(ev, nz, tm1, det, words, bm, P);
+}
+
+template <uint32_t TM>
+__global__ void __launch_bounds__(256)
+k_prefix_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
+             const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
+             RunParams P) {
+    sample_shots<double, NS_SLOTS, TM>(ev, nz, tm1, det, words, bm, P);
+}
+
 __global__ void k_reset(unsigned long long *counters, uint32_t n, unsigned long long *next) {
     for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) counters[t] = 0ull;
-    if (threadIdx.x == 0) *next = 0ull;
+    if (threadIdx.x < 2u) next[threadIdx.x] = 0ull;  // the sampler's and the prefix build's cursors
 }
 
 template <typename R, uint32_t NS, uint32_t TM> const void *kernel_ptr() {
@@ -1516,6 +1689,19 @@ const void *sampler_kernel(bool fp64, uint32_t ns, uint32_t tm) {
 
 const void *reset_kernel() { return (const void *)k_reset; }
 
+const void *prefix_kernel(bool fp64, uint32_t tm) {
+    const void *ks[6] = {(const void *)k_prefix_f32<TM_LDS>, (const void *)k_prefix_f32<TM_MEM>,
+                         (const void *)k_prefix_f32<TM_SPLIT>, (const void *)k_prefix_f64<TM_LDS>,
+                         (const void *)k_prefix_f64<TM_MEM>, (const void *)k_prefix_f64<TM_SPLIT>};
+    return ks[(fp64 ? 3 : 0) + (tm > TM_SPLIT ? TM_LDS : tm)];
+}
+
+hipError_t launch_prefix_build(const RunParams &p, bool fp64, dim3 grid, dim3 block, size_t lds, hipStream_t stream) {
+    void *args[7] = {(void *)&p.ev, (void *)&p.nz, (void *)&p.tm1, (void *)&p.det, (void *)&p.words, (void *)&p.bm,
+                     (void *)&p};
+    return hipLaunchKernel(prefix_kernel(fp64, p.tile_mode), grid, block, args, lds, stream);
+}
+
 hipError_t sampler_occupancy(bool fp64, uint32_t ns, uint32_t tm, int block, size_t lds, int *blocks_per_cu) {
     const void *ks[kKernels];
     all_kernels(ks);
@@ -1527,6 +1713,11 @@ hipError_t sampler_set_lds_limit(int bytes) {
     all_kernels(ks);
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < 6; ++i) {
+        hipError_t e = hipFuncSetAttribute(prefix_kernel(i >= 3, (uint32_t)(i % 3)),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

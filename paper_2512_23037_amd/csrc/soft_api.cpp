@@ -43,7 +43,8 @@ struct Variant {
     bool has_fast = false;
 };
 
-constexpr size_t kCounterWords = (size_t)kMaxVariants * C_COUNT + 1;
+// counter rows, then the sampler's and the prefix build's work cursors
+constexpr size_t kCounterWords = (size_t)kMaxVariants * C_COUNT + 2;
 static_assert(kCounterWords * sizeof(unsigned long long) <= kScratchCounterBytes, "scratch counter area");
 
 // Kept final states: at most this many shots, and at most kMaxKeepBytes of
@@ -90,6 +91,8 @@ struct soft_ctx {
     int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory, 3 split
     uint32_t split_log2 = 0;                  // split: log2 of the LDS part asked for (0: default)
     bool speculate = true;                    // run speculative event lists where compiled
+    bool shared_prefix = true;                // start hit-free shots from the noiseless prefix state
+    bool any_prefix = false;                  // some variant's lists have checkpoints
     int noise_mode = 0;                       // 0 a word per noise slot, 1 gap sampling
     Shape user;                               // explicit launch shape parts
     std::string arch;                         // gcnArchName of the device (autotune cache key)
@@ -101,6 +104,9 @@ struct soft_ctx {
     DevBuf<DiagInfo> d_diag;
     DevBuf<VariantDesc> d_vars;
     DevBuf<unsigned char> d_gtile;            // device-memory tiles
+    DevBuf<unsigned char> d_prefix;           // checkpoint state slots (one per table entry)
+    DevBuf<Checkpoint> d_ckpt;                // checkpoint table
+    uint32_t n_ckpt = 0;                      // its entries
     unsigned long long *d_counters = nullptr;  // kMaxVariants rows of C_COUNT, then the work cursor
     const unsigned long long *last_counters = nullptr;  // counters of the last run
     double *d_phase = nullptr;                 // cos/sin of k pi/8, k = 0..15
@@ -128,10 +134,12 @@ struct soft_ctx {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         hipGraphNode_t sampler = nullptr;
+        hipGraphNode_t build = nullptr;  // the prefix build (between reset and sampler), if any
         hipEvent_t done = nullptr;   // recorded after the slot's last launch
         bool launched = false;
         std::vector<unsigned char> key;  // kernel, grid, block, LDS, counters
         RunParams args;                  // argument storage of the sampler node
+        RunParams bargs;                 // and of the prefix build node
         unsigned long long *r_counters = nullptr, *r_next = nullptr;  // reset node arguments
         uint32_t r_n = 0;
     };
@@ -200,6 +208,36 @@ uint32_t wave_bytes(const soft_ctx *c, const Shape &s) {
     const uint32_t recb = rec_words(c) > kRecSgpr ? (rec_words(c) * 4u + 15u) & ~15u : 0u;
     return std::max<uint32_t>(16u, ((lds_tile_bytes(c, s) + 15u) & ~15u) + recb);
 }
+// Bytes of one checkpoint slot: the state, the record words and a whole
+// tile, 256-aligned.
+uint32_t prefix_stride(const soft_ctx *c) {
+    return (kCkptRecOff + ((rec_words(c) * 4u + 15u) & ~15u) + tile_bytes(c) + 255u) & ~255u;
+}
+bool use_prefix(const soft_ctx *c) { return c->shared_prefix && c->any_prefix; }
+
+// The prefix build launch's parameters: item i = variant i / 2, list i & 1,
+// no outputs, no kept states or trace, its own work cursor.
+RunParams build_params(const RunParams &rp) {
+    RunParams b = rp;
+    b.prefix_build = 1;
+    b.n_shots = 2ull * rp.n_vars;
+    b.shot0 = 0;
+    b.shot_list = nullptr;
+    b.outcomes = nullptr;
+    b.status = nullptr;
+    b.abort_op = nullptr;
+    b.obs = nullptr;
+    b.keep_meta = nullptr;
+    b.keep_v = nullptr;
+    b.keep_n = 0;
+    b.trace_meta = nullptr;
+    b.trace_v = nullptr;
+    b.trace_n = 0;
+    b.grab = 1;
+    b.next = rp.next + 1;
+    return b;
+}
+
 // Default LDS part of a split tile: at most 8 KiB, below the whole tile.
 uint32_t split_log2_default(const soft_ctx *c) {
     uint32_t L = c->kmax - 1u;
@@ -214,6 +252,7 @@ void drop_slot(soft_ctx *c, soft_ctx::GraphSlot &g) {
     g.exec = nullptr;
     g.graph = nullptr;
     g.sampler = nullptr;
+    g.build = nullptr;
     g.launched = false;
     g.key.clear();
     (void)c;
@@ -261,6 +300,7 @@ int prepare(soft_ctx *c) {
     std::vector<BatchMember> bm;
     std::vector<DiagInfo> dg;
     std::vector<VariantDesc> vd;
+    std::vector<Checkpoint> ck;
     c->kmax = 0;
     c->rec_words = 0;
     uint64_t h = 1469598103934665603ULL;
@@ -291,6 +331,17 @@ int prepare(soft_ctx *c) {
         };
         D.ev_off_full = append(P);
         D.ev_off = V.has_fast ? append(V.fast) : D.ev_off_full;
+        // checkpoints of each list (one set when the variant has one list)
+        D.ck_off_full = (uint32_t)ck.size();
+        D.ck_cnt_full = (uint32_t)P.ckpts.size();
+        ck.insert(ck.end(), P.ckpts.begin(), P.ckpts.end());
+        D.ck_off = D.ck_off_full;
+        D.ck_cnt = D.ck_cnt_full;
+        if (V.has_fast) {
+            D.ck_off = (uint32_t)ck.size();
+            D.ck_cnt = (uint32_t)V.fast.ckpts.size();
+            ck.insert(ck.end(), V.fast.ckpts.begin(), V.fast.ckpts.end());
+        }
         nz.insert(nz.end(), P.noise.begin(), P.noise.end());
         tm1.insert(tm1.end(), P.noise_tm1.begin(), P.noise_tm1.end());
         gap.insert(gap.end(), P.gap.begin(), P.gap.end());
@@ -301,13 +352,17 @@ int prepare(soft_ctx *c) {
         h = (h ^ V.shot_end) * 1099511628211ULL;
     }
     c->hash = h;
+    c->any_prefix = !ck.empty();
+    c->n_ckpt = (uint32_t)ck.size();
     int rc;
     if ((rc = ensure(c, c->d_ev, ev.size())) || (rc = ensure(c, c->d_nz, std::max<size_t>(nz.size(), 1))) ||
         (rc = ensure(c, c->d_tm1, tm1.size())) || (rc = ensure(c, c->d_det, std::max<size_t>(det.size(), 2))) ||
         (rc = ensure(c, c->d_bm, std::max<size_t>(bm.size(), 1))) || (rc = ensure(c, c->d_vars, vd.size())) ||
         (rc = ensure(c, c->d_diag, std::max<size_t>(dg.size(), 1))) ||
-        (rc = ensure(c, c->d_gap, std::max<size_t>(gap.size(), 1))))
+        (rc = ensure(c, c->d_gap, std::max<size_t>(gap.size(), 1))) ||
+        (rc = ensure(c, c->d_ckpt, std::max<size_t>(ck.size(), 1))))
         return rc;
+    if (!ck.empty()) HIPCHK(c, hipMemcpy(c->d_ckpt.p, ck.data(), ck.size() * sizeof(Checkpoint), hipMemcpyHostToDevice));
     if (!gap.empty()) HIPCHK(c, hipMemcpy(c->d_gap.p, gap.data(), gap.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_ev.p, ev.data(), ev.size() * sizeof(Event), hipMemcpyHostToDevice));
     if (!nz.empty()) HIPCHK(c, hipMemcpy(c->d_nz.p, nz.data(), nz.size() * sizeof(NoiseLoc), hipMemcpyHostToDevice));
@@ -441,11 +496,23 @@ int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStrea
         if (rc) return rc;
         rp.gtile = c->d_gtile.p;
     }
+    // shared-prefix slots, filled by the build launch before the sampler
+    const bool pfx = use_prefix(c);
+    rp.prefix = nullptr;
+    rp.prefix_stride = 0;
+    if (pfx) {
+        int rc = ensure(c, c->d_prefix, (size_t)c->n_ckpt * prefix_stride(c));
+        if (rc) return rc;
+        rp.prefix = c->d_prefix.p;
+        rp.prefix_stride = prefix_stride(c);
+    }
+    const uint64_t bgrid = std::min<uint64_t>(grid, (2ull * rp.n_vars + s.wpb - 1) / s.wpb);
     const uint32_t ns = rp.words != nullptr ? NS_EXPLICIT : (rp.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
     const void *kfn = sampler_kernel(c->bits == 64, ns, s.gt);
     // what the nodes' launch configuration and the reset node depend on
-    const uint64_t kv[7] = {(uint64_t)(uintptr_t)kfn, grid, (uint64_t)b.x, (uint64_t)lds,
-                            (uint64_t)(uintptr_t)rp.counters, (uint64_t)rp.n_vars, (uint64_t)(uintptr_t)rp.next};
+    const uint64_t kv[9] = {(uint64_t)(uintptr_t)kfn, grid, (uint64_t)b.x, (uint64_t)lds,
+                            (uint64_t)(uintptr_t)rp.counters, (uint64_t)rp.n_vars, (uint64_t)(uintptr_t)rp.next,
+                            (uint64_t)pfx, pfx ? bgrid : 0ull};
     std::vector<unsigned char> key((const unsigned char *)kv, (const unsigned char *)kv + sizeof(kv));
     // The slot to use: one with this key whose last launch is done; else an
     // empty one (instantiated below); else one with this key (after waiting
@@ -470,16 +537,24 @@ int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStrea
     soft_ctx::GraphSlot &gs = *slot;
     if (gs.launched) HIPCHK(c, hipEventSynchronize(gs.done));  // its previous launch may still read its arguments
     gs.args = rp;
+    gs.bargs = build_params(rp);
     void *args[7] = {(void *)&gs.args.ev, (void *)&gs.args.nz, (void *)&gs.args.tm1, (void *)&gs.args.det,
                      (void *)&gs.args.words, (void *)&gs.args.bm, (void *)&gs.args};
-    hipKernelNodeParams kp;
+    void *bargs[7] = {(void *)&gs.bargs.ev, (void *)&gs.bargs.nz, (void *)&gs.bargs.tm1, (void *)&gs.bargs.det,
+                      (void *)&gs.bargs.words, (void *)&gs.bargs.bm, (void *)&gs.bargs};
+    hipKernelNodeParams kp, kb;
     std::memset(&kp, 0, sizeof(kp));
     kp.func = const_cast<void *>(kfn);
     kp.gridDim = g;
     kp.blockDim = b;
     kp.sharedMemBytes = (unsigned int)lds;
     kp.kernelParams = args;
+    kb = kp;
+    kb.func = const_cast<void *>(prefix_kernel(c->bits == 64, s.gt));
+    kb.gridDim = dim3((uint32_t)bgrid);
+    kb.kernelParams = bargs;
     if (gs.exec && gs.key == key) {
+        if (pfx) HIPCHK(c, hipGraphExecKernelNodeSetParams(gs.exec, gs.build, &kb));
         HIPCHK(c, hipGraphExecKernelNodeSetParams(gs.exec, gs.sampler, &kp));
     } else {
         drop_slot(c, gs);
@@ -496,7 +571,12 @@ int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStrea
         hipGraphNode_t rnode = nullptr;
         hipError_t e = hipGraphCreate(&gs.graph, 0);
         if (e == hipSuccess) e = hipGraphAddKernelNode(&rnode, gs.graph, nullptr, 0, &rk);
-        if (e == hipSuccess) e = hipGraphAddKernelNode(&gs.sampler, gs.graph, &rnode, 1, &kp);
+        hipGraphNode_t before = rnode;
+        if (e == hipSuccess && pfx) {
+            e = hipGraphAddKernelNode(&gs.build, gs.graph, &rnode, 1, &kb);
+            before = gs.build;
+        }
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&gs.sampler, gs.graph, &before, 1, &kp);
         if (e == hipSuccess) e = hipGraphInstantiate(&gs.exec, gs.graph, nullptr, nullptr, 0);
         if (e == hipSuccess && !gs.done) e = hipEventCreateWithFlags(&gs.done, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -522,6 +602,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.det = c->d_det.p;
     rp.bm = c->d_bm.p;
     rp.diag = c->d_diag.p;
+    rp.ckpts = c->d_ckpt.p;
     rp.speculate = c->speculate ? 1u : 0u;
     rp.gaps = c->d_gap.p;
     rp.noise_mode = (uint32_t)c->noise_mode;
@@ -535,7 +616,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.abort_op = abort_op;
     rp.obs = obs;
     rp.counters = c->d_counters;
-    rp.next = c->d_counters + kCounterWords - 1;
+    rp.next = c->d_counters + kCounterWords - 2;
     rp.seed = c->seed;
     rp.shot0 = shot0;
     rp.n_shots = n_shots;
@@ -758,6 +839,8 @@ void soft_destroy(soft_ctx *c) {
     release(c->d_diag);
     release(c->d_vars);
     release(c->d_gtile);
+    release(c->d_prefix);
+    release(c->d_ckpt);
     release(c->d_keep_meta);
     release(c->d_keep_v);
     release(c->d_trace_meta);
@@ -900,6 +983,12 @@ int soft_set_speculation(soft_ctx *c, int on) {
     return SOFT_OK;
 }
 
+int soft_set_shared_prefix(soft_ctx *c, int on) {
+    if (!c) return SOFT_EINVAL;
+    c->shared_prefix = on != 0;
+    return SOFT_OK;
+}
+
 int soft_set_noise_mode(soft_ctx *c, int mode) {
     if (!c) return SOFT_EINVAL;
     if (mode < 0 || mode > 1) return fail(c, SOFT_EINVAL, "noise mode must be 0 (a word per slot) or 1 (gap sampling)");
@@ -983,7 +1072,12 @@ int soft_run_noalloc(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *ou
     // the scratch holds (the kernel is persistent, so fewer waves take more
     // shots each)
     rp.counters = reinterpret_cast<unsigned long long *>(c->scratch);
-    rp.next = rp.counters + kCounterWords - 1;
+    rp.next = rp.counters + kCounterWords - 2;
+    // shared-prefix slots when they fit their part of the scratch (without
+    // them every shot runs from the start: the same results)
+    const bool pfx = use_prefix(c) && (uint64_t)c->n_ckpt * prefix_stride(c) <= kScratchPrefixBytes;
+    rp.prefix = pfx ? c->scratch + kScratchCounterBytes : nullptr;
+    rp.prefix_stride = pfx ? prefix_stride(c) : 0u;
     uint64_t grid = grid_blocks(c, s, n_shots);
     if (s.gt != TM_LDS) {
         const uint64_t slab = (uint64_t)s.wpb * slab_bytes(c, s);
@@ -994,10 +1088,14 @@ int soft_run_noalloc(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *ou
                                                std::to_string(kScratchTileBytes) + " (span dimension " +
                                                std::to_string(c->kmax) + ")");
         grid = std::min<uint64_t>(grid, fit);
-        rp.gtile = c->scratch + kScratchCounterBytes;
+        rp.gtile = c->scratch + kScratchCounterBytes + kScratchPrefixBytes;
     }
     const hipStream_t stream = (hipStream_t)hip_stream;
     HIPCHK(c, launch_reset(rp.counters, rp.n_vars * (uint32_t)C_COUNT, rp.next, stream));
+    if (pfx)
+        HIPCHK(c, launch_prefix_build(build_params(rp), c->bits == 64,
+                                 dim3((uint32_t)std::min<uint64_t>(grid, (2ull * rp.n_vars + s.wpb - 1) / s.wpb)),
+                                 dim3(64u * s.wpb), (size_t)s.wpb * wave_bytes(c, s), stream));
     HIPCHK(c, launch_sampler(rp, c->bits == 64, dim3((uint32_t)grid), dim3(64u * s.wpb),
                              (size_t)s.wpb * wave_bytes(c, s), stream));
     c->ran = true;
@@ -1033,6 +1131,7 @@ int read_rows(soft_ctx *c, uint32_t v0, uint32_t v1, soft_counters *out) {
         out->noise_slots += r[C_NOISE];
         out->events += r[C_EVENTS];
         out->restarts += r[C_RESTARTS];
+        out->prefix_shots += r[C_PREFIX];
         for (int b = 0; b < 16; ++b) out->support_hist[b] += r[C_HIST0 + b];
         double d;
         std::memcpy(&d, &r[C_NORMDEV_BITS], sizeof(double));

@@ -25,7 +25,8 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_autotune", "soft_set_keep", "soft_run", "soft_read_counters", "soft_read_coeffs",
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
            "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
-           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode", "soft_graph_info", "soft_run_noalloc")
+           "soft_run_list", "soft_set_speculation", "soft_set_noise_mode", "soft_graph_info", "soft_run_noalloc",
+           "soft_set_shared_prefix")
 
 
 class SoftError(RuntimeError):
@@ -43,7 +44,7 @@ class soft_counters(ctypes.Structure):
                 ("overflow", ctypes.c_uint64), ("numeric", ctypes.c_uint64), ("logical_errors", ctypes.c_uint64),
                 ("entries_t", ctypes.c_uint64), ("entries_m", ctypes.c_uint64), ("noise_slots", ctypes.c_uint64),
                 ("events", ctypes.c_uint64), ("support_hist", ctypes.c_uint64 * 16), ("max_norm_dev", ctypes.c_double),
-                ("restarts", ctypes.c_uint64)]
+                ("restarts", ctypes.c_uint64), ("prefix_shots", ctypes.c_uint64)]
 
 
 _lib = None
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "soft_run_list": (I, [P, P, U64, P, P, P, P, P]),
         "soft_set_speculation": (I, [P, I]),
         "soft_set_noise_mode": (I, [P, I]),
+        "soft_set_shared_prefix": (I, [P, I]),
         "soft_graph_info": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
@@ -201,6 +203,12 @@ class Context:
     def set_speculation(self, on: bool):
         """Run the speculative (span-truncating) event lists first (default)."""
         self._check(self._lib.soft_set_speculation(self._h, 1 if on else 0))
+
+    def set_shared_prefix(self, on: bool):
+        """Start each shot at the last checkpoint of the noiseless trajectory
+        before its first noise hit (default on; results are the same either
+        way)."""
+        self._check(self._lib.soft_set_shared_prefix(self._h, 1 if on else 0))
 
     def set_noise_mode(self, mode: int):
         """0: one word per noise location (default); 1: gap sampling."""

@@ -395,20 +395,27 @@ def test_work_counters_closed_forms(mode):
     # T on a fresh |+> qubit adds a span coordinate: the k-th such T writes
     # 2^(k+1) tile entries; a second T on the same qubit is a butterfly over
     # the 2^k entries.  No measurement, no noise: every shot runs every event.
+    # The whole list is a shared T prefix: with it on (the default) every
+    # shot starts at its end and runs no T work; off, every shot runs it.
     N = 5000
     text = "QUBITS 5\n" + "".join("H %d\n" % q for q in range(5)) + "".join("T %d\n" % q for q in range(5)) + "T 0\n"
     ctx = make_ctx(text, None, seed=3)
     ctx.set_noise_mode(mode)
     run_gpu(ctx, 0, N)
     c = ctx.counters()
+    assert c["entries_t"] == 0 and c["events"] == 0 and c["prefix_shots"] == N
+    ctx.set_shared_prefix(False)
+    run_gpu(ctx, 0, N)
+    c = ctx.counters()
     assert c["entries_t"] == N * ((2 + 4 + 8 + 16 + 32) + 32)
-    assert c["entries_m"] == 0 and c["events"] == N * 6 and c["noise_slots"] == 0
+    assert c["entries_m"] == 0 and c["events"] == N * 6 and c["noise_slots"] == 0 and c["prefix_shots"] == 0
     # one measurement pass over the 2^5 entries per shot, and a noise table of
     # 3 slots drawn once per shot (per slot: the 3 words; gap sampling: one
     # 256-word block of stream 2)
     text2 = text + "DEP1 0.1 1\nDEP1 0.2 2\nDEP1 0.3 3\nMPP X0\n"
     ctx2 = make_ctx(text2, None, seed=3)
     ctx2.set_noise_mode(mode)
+    ctx2.set_shared_prefix(False)
     run_gpu(ctx2, 0, N)
     c2 = ctx2.counters()
     assert c2["entries_t"] == c["entries_t"] and c2["events"] == N * 7
