@@ -45,7 +45,8 @@ class _ShotInfo(ctypes.Structure):
                 ("m_entries", ctypes.c_uint64), ("noise_slots", ctypes.c_uint64),
                 ("events", ctypes.c_uint64), ("norm2", ctypes.c_double), ("noise_words", ctypes.c_uint64),
                 ("m_out_entries", ctypes.c_uint64), ("m_pairs", ctypes.c_uint64),
-                ("t_phase_flips", ctypes.c_uint64), ("meas_words", ctypes.c_uint64)]
+                ("t_phase_flips", ctypes.c_uint64), ("meas_words", ctypes.c_uint64),
+                ("shared", ctypes.c_uint64 * 10)]
 
 WORK_KEYS = ("t_entries", "t_phase_entries", "m_entries", "noise_slots", "events", "noise_words",
              "m_out_entries", "m_pairs", "t_phase_flips", "meas_words")
@@ -70,7 +71,7 @@ def _load():
                                     P, ctypes.POINTER(_ShotInfo), P, P, P, P, P, P, ctypes.c_uint32, P, P]
         lib.oracle_batch.restype = ctypes.c_int
         lib.oracle_batch.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, P, ctypes.c_double,
-                                     ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, P]
+                                     ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, P, P]
         lib.oracle_set_noise_mode.restype = ctypes.c_int
         lib.oracle_set_noise_mode.argtypes = [P, ctypes.c_int]
         lib.oracle_philox.argtypes = [P, P, P]
@@ -117,6 +118,7 @@ class ShotResult:
     p0: np.ndarray        # P(outcome +1) per measurement slot
     work: dict
     norm2: float
+    shared_work: dict     # the part of `work` done on the noiseless trajectory all shots share
 
 
 class Circuit:
@@ -176,8 +178,9 @@ class Circuit:
         bits = [int((rec[i >> 5] >> (i & 31)) & 1) for i in range(self.n_records)]
         coeffs = {int(al[i]): complex(re[i], im[i]) for i in range(k)}
         work = {f: int(getattr(info, f)) for f in WORK_KEYS}
+        shared = dict(zip(WORK_KEYS, (int(x) for x in info.shared)))
         return ShotResult(bits, info.status, info.abort_op, info.obs, info.max_support, tx, tz, tr,
-                          coeffs, p0[: self.n_meas_slots], work, info.norm2)
+                          coeffs, p0[: self.n_meas_slots], work, info.norm2, shared)
 
     def batch(self, seed: int, shot0: int, n: int, words=None, tau: float = 1e-12,
               cap: int = 0xFFFFFFFF, threads: int | None = None) -> dict:
@@ -191,15 +194,17 @@ class Circuit:
         obs = np.zeros(n, dtype=np.uint32)
         maxs = np.zeros(n, dtype=np.uint32)
         work = np.zeros(len(WORK_KEYS), dtype=np.uint64)
+        shared = np.zeros(len(WORK_KEYS), dtype=np.uint64)
         w = None
         if words is not None:
             w = np.ascontiguousarray(words, dtype=np.uint32)
             if w.shape != (n, self.words_per_shot):
                 raise ValueError("explicit words: expected shape (%d, %d)" % (n, self.words_per_shot))
         rc = lib.oracle_batch(self._h, seed, shot0, n, _ptr(w), tau, cap, threads, _ptr(outcomes),
-                              _ptr(status), _ptr(abort_op), _ptr(obs), _ptr(maxs), _ptr(work))
+                              _ptr(status), _ptr(abort_op), _ptr(obs), _ptr(maxs), _ptr(work), _ptr(shared))
         if rc != 0:
             raise RuntimeError("oracle_batch failed")
         return {"outcomes": outcomes[:nw], "status": status, "abort_op": abort_op, "obs": obs,
                 "max_support": maxs, "threads": threads,
-                "work": dict(zip(WORK_KEYS, (int(x) for x in work)))}
+                "work": dict(zip(WORK_KEYS, (int(x) for x in work))),
+                "shared_work": dict(zip(WORK_KEYS, (int(x) for x in shared)))}

@@ -753,12 +753,29 @@ int measure(ShotState &st, const Pauli &P, double u, double tau, double *p0_out,
 struct ShotResult {
     std::vector<uint32_t> record;
     oracle_shot_info info;
+    bool on_path = true;  // still on the noiseless trajectory every shot shares
 };
+
+// The work counters of `at` in the order of oracle_batch's sums, with the
+// shot's own noise draws left out (they are never shared).
+void shared_of(const oracle_shot_info &at, uint64_t out[ORACLE_WORK_COUNT]) {
+    const uint64_t w[ORACLE_WORK_COUNT] = {at.t_entries, at.t_phase_entries, at.m_entries, 0, at.events, 0,
+                                           at.m_out_entries, at.m_pairs, at.t_phase_flips, at.meas_words};
+    for (int k = 0; k < ORACLE_WORK_COUNT; ++k) out[k] = w[k];
+}
+
+// The shot leaves the shared trajectory; `at` holds its counters just before
+// the event that made it leave.
+void leave_path(ShotResult &res, const oracle_shot_info &at) {
+    if (!res.on_path) return;
+    res.on_path = false;
+    shared_of(at, res.info.shared);
+}
 
 double uniform_of(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
 
-void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint32_t *words, double tau,
-              uint32_t cap, ShotState &st, ShotResult &res, double *p0_trace) {
+void run_ops(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint32_t *words, double tau,
+             uint32_t cap, ShotState &st, ShotResult &res, double *p0_trace) {
     const int n = c.n;
     st.n = n;
     st.x.assign(2 * n, 0);
@@ -772,6 +789,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
     st.v[0] = cplx(1.0, 0.0);
     res.record.assign((c.n_rec + 31) / 32, 0u);
     std::memset(&res.info, 0, sizeof(res.info));
+    res.on_path = true;
     res.info.abort_op = 0xffffffffu;
     res.info.max_support = 1;
 
@@ -869,12 +887,14 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                 if (o.kind == K_MPP) { P.x = o.px; P.z = o.pz; }
                 else if (xb) P.x = 1ULL << o.a;
                 else P.z = 1ULL << o.a;
+                const oracle_shot_info before = res.info;
                 res.info.m_entries += st.v.size();
                 res.info.events++;
                 double p0 = 0.0;
                 ++res.info.meas_words;
                 int b = measure(st, P, uniform_of(meas_word(o.slot)), tau, &p0, &res.info.m_pairs);
                 if (p0_trace) p0_trace[o.slot] = p0;
+                if (p0 > 0.0 && p0 < 1.0) leave_path(res, before);  // the outcome was drawn
                 if (b < 0) {
                     res.info.status = ORACLE_NUMERIC;
                     res.info.abort_op = o.src;
@@ -904,6 +924,7 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
                     thr = o.thr;
                     if ((uint64_t)w >= thr) break;
                 }
+                leave_path(res, res.info);  // a hit
                 if (o.kind == K_DEP1) {
                     int idx = (int)((3ULL * w) / thr);  // 0,1,2 -> X,Y,Z
                     apply_pauli_code(st, idx + 1, o.a);
@@ -939,6 +960,12 @@ void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint3
     }
     res.info.status = ORACLE_PASSED;
     res.info.norm2 = norm2(st.v);
+}
+
+void run_shot(const oracle_circuit &c, uint64_t seed, uint64_t shot, const uint32_t *words, double tau,
+              uint32_t cap, ShotState &st, ShotResult &res, double *p0_trace) {
+    run_ops(c, seed, shot, words, tau, cap, st, res, p0_trace);
+    if (res.on_path) shared_of(res.info, res.info.shared);  // it never left: all of its work was shared
 }
 
 }  // namespace
@@ -1039,12 +1066,12 @@ int oracle_shot(const oracle_circuit *c, uint64_t seed, uint64_t shot, const uin
 
 int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_t n, const uint32_t *words,
                  double tau, uint32_t cap, int threads, uint32_t *outcomes, uint32_t *status, uint32_t *abort_op,
-                 uint32_t *obs, uint32_t *max_support, uint64_t *work) {
+                 uint32_t *obs, uint32_t *max_support, uint64_t *work, uint64_t *shared_work) {
     if (!c || !(tau >= 0.0)) return -1;
     if (threads < 1) threads = 1;
     const uint64_t stride = (uint64_t)c->n_noise + c->n_meas;
     const int nw = (c->n_rec + 31) / 32;
-    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(ORACLE_WORK_COUNT, 0));
+    std::vector<std::vector<uint64_t>> part(threads, std::vector<uint64_t>(2 * ORACLE_WORK_COUNT, 0));
     auto worker = [&](int t) {
         uint64_t lo = n * t / threads, hi = n * (t + 1) / threads;
         ShotState st;
@@ -1067,6 +1094,7 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
             part[t][7] += res.info.m_pairs;
             part[t][8] += res.info.t_phase_flips;
             part[t][9] += res.info.meas_words;
+            for (int k = 0; k < ORACLE_WORK_COUNT; ++k) part[t][ORACLE_WORK_COUNT + k] += res.info.shared[k];
         }
     };
     std::vector<std::thread> pool;
@@ -1077,6 +1105,11 @@ int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0, uint64_
         for (int k = 0; k < ORACLE_WORK_COUNT; ++k) {
             work[k] = 0;
             for (int t = 0; t < threads; ++t) work[k] += part[t][k];
+        }
+    if (shared_work)
+        for (int k = 0; k < ORACLE_WORK_COUNT; ++k) {
+            shared_work[k] = 0;
+            for (int t = 0; t < threads; ++t) shared_work[k] += part[t][ORACLE_WORK_COUNT + k];
         }
     return 0;
 }

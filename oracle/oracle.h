@@ -79,6 +79,14 @@ typedef struct {
     uint64_t m_pairs;     /* sum over beta != 0 measurements of representative pairs */
     uint64_t t_phase_flips; /* sum over T/TDG with beta == 0 of entries with lambda = -1 */
     uint64_t meas_words;  /* measurement uniforms used (one per measurement)   */
+    /* The part of the counters above (t_entries .. meas_words, in the order of
+     * oracle_batch's work sums) spent while the shot was still on the
+     * noiseless trajectory that every shot of the circuit shares: before its
+     * first applied noise hit (a Pauli or a record flip) and before its first
+     * measurement whose outcome was not certain (0 < p0 < 1); all of it if the
+     * shot never left that trajectory.  noise_slots and noise_words are 0
+     * here: each shot draws its own noise whatever its path. */
+    uint64_t shared[10];
 } oracle_shot_info;
 
 /* Number of work sums oracle_batch reports. */
@@ -106,12 +114,13 @@ int oracle_shot(const oracle_circuit *c, uint64_t seed, uint64_t shot,
  * max_support: [n] or NULL.  work: NULL or ORACLE_WORK_COUNT sums of the
  * oracle_shot_info counters (t_entries, t_phase_entries, m_entries,
  * noise_slots, events, noise_words, m_out_entries, m_pairs, t_phase_flips,
- * meas_words). */
+ * meas_words).  shared_work: NULL or the ORACLE_WORK_COUNT sums of
+ * oracle_shot_info.shared, in the same order. */
 int oracle_batch(const oracle_circuit *c, uint64_t seed, uint64_t shot0,
                  uint64_t n, const uint32_t *words, double tau, uint32_t cap,
                  int threads, uint32_t *outcomes, uint32_t *status,
                  uint32_t *abort_op, uint32_t *obs, uint32_t *max_support,
-                 uint64_t *work);
+                 uint64_t *work, uint64_t *shared_work);
 
 /* Philox4x32-10 block (Salmon, Moraes, Dror, Shaw, SC'11). */
 void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

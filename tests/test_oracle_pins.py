@@ -818,3 +818,122 @@ def test_diagonal_gate_parse_errors_and_noise():
     a = oracle.Circuit("QUBITS 3\nH 0\nH 1\nCS 0 1\nM 0\nM 1\n", model).batch(3, 0, 3000)
     b = oracle.Circuit("QUBITS 3\nH 0\nDEP1 0.1 0\nH 1\nDEP1 0.1 1\nCS 0 1\nDEP2 0.2 0 1\nM 0\nM 1\n").batch(3, 0, 3000)
     assert (a["outcomes"] == b["outcomes"]).all()
+
+
+# ---------------------------------------------------------------------------
+# Work on the shared noiseless trajectory: the part of a shot's work done
+# before its first noise hit and before its first measurement whose outcome
+# was drawn.  Prices the roofline of a sampler that computes that part once.
+# ---------------------------------------------------------------------------
+_NOISE_FREE = ("noise_slots", "noise_words")
+
+
+def _no_noise(work):
+    return {k: (0 if k in _NOISE_FREE else v) for k, v in work.items()}
+
+
+def test_shared_work_closed_forms():
+    def shot(text, noise_words=None):
+        c = oracle.Circuit(text)
+        w = np.full(c.words_per_shot, 1 << 31, dtype=np.uint32)
+        w[: c.n_noise_slots] = 0xFFFFFFFF if noise_words is None else noise_words
+        return c.shot(0, 0, words=w)
+    r = shot("QUBITS 1\nH 0\nT 0\nM 0\n")  # M on T|+> has p0 = 1/2: the shot leaves at the M
+    assert r.shared_work["t_entries"] == 2 and r.shared_work["events"] == 1
+    assert r.shared_work["m_entries"] == 0 and r.shared_work["meas_words"] == 0
+    r = shot("QUBITS 1\nT 0\nM 0\n")       # |0> stays |0>: every outcome is certain
+    assert r.shared_work == _no_noise(r.work)
+    text = "QUBITS 2\nH 0\nT 0\nXERR 0.5 1\nM 1\nH 0\nT 0\n"
+    r = shot(text, noise_words=[0xFFFFFFFF])   # no hit: M 1 is certain, so all is shared
+    assert r.shared_work == _no_noise(r.work) and r.work["events"] == 3
+    r = shot(text, noise_words=[0])            # a hit before M 1: only the first T is shared
+    assert r.shared_work["t_entries"] == 2 and r.shared_work["events"] == 1 and r.shared_work["m_entries"] == 0
+    assert r.record == [1]
+
+
+def _noisy_random_circuit(seed, n, length):
+    """Clifford+T with explicit DEP1 noise after some gates and Z readouts;
+    returns the lines and, per line, ('noise', slot, thr), ('meas', slot) or
+    None."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lines, tags = [], []
+    ns = ms = 0
+    for _ in range(length):
+        u = rng.random()
+        q = int(rng.integers(n))
+        if u < 0.25:
+            lines.append("H %d" % q)
+        elif u < 0.35:
+            lines.append("S %d" % q)
+        elif u < 0.55:
+            a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+            lines.append("CX %d %d" % (a, b))
+        elif u < 0.7:
+            lines.append("%s %d" % ("T" if rng.integers(2) == 0 else "TDG", q))
+        elif u < 0.8:
+            lines.append("M %d" % q)
+            tags.append(("meas", ms))
+            ms += 1
+            continue
+        else:
+            p = 0.3
+            lines.append("DEP1 %.1f %d" % (p, q))
+            tags.append(("noise", ns, int(np.floor(p * 2 ** 32))))
+            ns += 1
+            continue
+        tags.append(None)
+    return lines, tags, ns, ms
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_shared_work_is_the_noiseless_run_cut_where_the_shot_leaves_it(seed):
+    # Brute force: find where each shot leaves the noiseless trajectory from
+    # the noiseless run's own p0 trace and the shot's noise words, cut the
+    # circuit there and run the cut circuit without noise; its work is the
+    # shot's shared work.
+    n = 2 + seed % 4
+    lines, tags, ns, ms = _noisy_random_circuit(9100 + seed, n, 60)
+    text = "QUBITS %d\n" % n + "\n".join(lines) + "\n"
+    c = oracle.Circuit(text)
+    assert (c.n_noise_slots, c.n_meas_slots) == (ns, ms)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for s in range(20):
+        w = rng.integers(0, 2 ** 32, size=ns + ms, dtype=np.uint64).astype(np.uint32)
+        w0 = w.copy()
+        w0[:ns] = 0xFFFFFFFF
+        clean = c.shot(0, 0, words=w0)
+        cut = len(lines)
+        for j, t in enumerate(tags):
+            if t is None:
+                continue
+            if t[0] == "noise" and int(w[t[1]]) < t[2]:
+                cut = j
+                break
+            if t[0] == "meas" and 0.0 < clean.p0[t[1]] < 1.0:
+                cut = j
+                break
+        r = c.shot(0, 0, words=w)
+        sub = oracle.Circuit("QUBITS %d\n" % n + "".join(x + "\n" for x in lines[:cut]))
+        wn = [w0[t[1]] for t in tags[:cut] if t and t[0] == "noise"]
+        wm = [w[ns + t[1]] for t in tags[:cut] if t and t[0] == "meas"]
+        ref = sub.shot(0, 0, words=np.array(wn + wm, dtype=np.uint32))
+        assert r.shared_work == _no_noise(ref.work), (seed, s, cut)
+
+
+def test_shared_work_batch_sums_and_noiseless_workload():
+    # Batch sums equal the per-shot values; with no noise the 15-qubit
+    # cultivation circuit never draws an outcome, so all of its work is shared.
+    w = workloads.config("cultivation_15q", seed=2)
+    c = oracle.Circuit(w.text, w.noise, noise_mode=1)
+    b = c.batch(3, 0, 40, threads=2)
+    tot = {k: 0 for k in oracle.WORK_KEYS}
+    for s in range(40):
+        r = c.shot(3, s)
+        for k in tot:
+            tot[k] += r.shared_work[k]
+        assert all(r.shared_work[k] <= r.work[k] for k in tot)
+    assert b["shared_work"] == tot
+    assert tot["noise_words"] == 0 and tot["noise_slots"] == 0
+    c0 = oracle.Circuit(w.text, {})
+    b0 = c0.batch(3, 0, 10, threads=2)
+    assert b0["shared_work"] == _no_noise(b0["work"])
