@@ -73,7 +73,8 @@ typedef struct {
                                     largest support the kernel held (the speculative
                                     lists may hold smaller ones than the circuit's
                                     gate order; with speculation off they are the
-                                    circuit order's) */
+                                    circuit order's; a shot that ended with a deferred
+                                    T run skipped counts the supports it computed) */
     double max_norm_dev;         /* max over shots of |sum |v|^2 - 1| at the end */
     uint64_t restarts;           /* shots re-run on the full event list: the speculative
                                     list's span truncation found amplitude left (noise
@@ -81,6 +82,8 @@ typedef struct {
     uint64_t prefix_shots;       /* attempts that started from a checkpoint of the noiseless
                                     trajectory (soft_set_shared_prefix); the work fields
                                     above count only the work run */
+    uint64_t redo_shots;         /* attempts run again because an event needed the tile of a
+                                    T run they had deferred (soft_set_deferred_t) */
 } soft_counters;
 
 /* Create a context on HIP device `hip_device` (made current for the call):
@@ -252,6 +255,21 @@ int soft_set_noise_mode(soft_ctx *ctx, int mode);
  * on = 0 runs every shot from the start.  The counters' work fields count the
  * work run; prefix_shots counts the shots that started from a checkpoint. */
 int soft_set_shared_prefix(soft_ctx *ctx, int on);
+
+/* Deferred T runs (default on).  T gates change only the coefficients, never
+ * the tableau signs that outcome-fixed measurements, checks and feedback read
+ * (Theorem 1: T leaves the tableau alone), so a run of T gates with no noise
+ * between them, followed by such events, can be skipped: a shot that a check
+ * ends before any event reads the coefficients never needs the run (most
+ * shots with an early fault, Sec. V's early stop of discarded shots).  When
+ * an event does need them, or the shot's final state is kept, the attempt
+ * runs again with every run applied; the same draws give the same results,
+ * so records, statuses, abort ops, observables and kept states are identical
+ * either way.  Off with a support cap (the cap is checked on every T).  What
+ * differs: a shot that ended with a run skipped reports, in support_hist,
+ * the largest support it computed, and the norm check covers the
+ * coefficients it computed.  on = 0 applies every run. */
+int soft_set_deferred_t(soft_ctx *ctx, int on);
 
 /* Where the per-wave coefficient tile lives (the GPU memory layout of
  * Sec. IV-B, re-planned for LDS and HBM): 0 = automatic (LDS when one

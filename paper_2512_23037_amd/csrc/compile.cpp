@@ -1161,6 +1161,54 @@ static void checkpoints(Program &out) {
     }
 }
 
+// Deferrable T runs: consecutive iterations of T gates (non-branching,
+// doublings, butterflies that do not drop, fused runs of doublings) with no
+// noise slot and no Clifford sign flip between their events, after which the
+// list goes on with events that do not touch the tile.  The signs do not
+// depend on T gates, so the events up to the next tile-touching one run the
+// same whether the run was applied or not; a shot that a check ends before
+// then never needs the run's coefficients.  The first event gets EVF_DEFER
+// (mslot = the run's events) and the next tile-touching iteration EVF_MAT.
+static void deferrable_runs(Program &out) {
+    const uint32_t n = (uint32_t)out.events.size();
+    auto step_of = [&](const Event &E) -> uint32_t {
+        return (E.flags & (EVF_TRUN | EVF_BRUN)) ? E.bcnt : (E.kind == EV_M_DET && (E.flags & EVF_BATCH)) ? E.bcnt : 1u;
+    };
+    auto is_t = [&](const Event &E) {
+        return E.kind == EV_T_PHASE || E.kind == EV_T_DOUBLE || (E.kind == EV_T_BFLY && !(E.flags & (EVF_DROP1 | EVF_BRUN)));
+    };
+    uint32_t e = 0;
+    while (e < n && out.events[e].kind != EV_END) {
+        if (!is_t(out.events[e])) {
+            e += step_of(out.events[e]);
+            continue;
+        }
+        // the longest run from e
+        const uint32_t d0 = e, nz = out.events[e].noise_end;
+        uint32_t d1 = e;
+        while (d1 < n && is_t(out.events[d1])) {
+            const Event &E = out.events[d1];
+            const uint32_t st = step_of(E);
+            bool ok = true;
+            for (uint32_t i = 0; i < st; ++i) {
+                const Event &M = out.events[d1 + i];
+                if (M.noise_end != nz || (d1 + i > d0 && (M.flags & EVF_CLIFF))) ok = false;
+            }
+            if (!ok) break;
+            d1 += st;
+        }
+        // followed by events that do not touch the tile, then (maybe) one that does
+        uint32_t f = d1;
+        while (f < n && out.events[f].kind != EV_END && !touches_tile(out.events[f])) f += step_of(out.events[f]);
+        if (f > d1) {
+            out.events[d0].flags |= EVF_DEFER;
+            out.events[d0].mslot = d1 - d0;
+            if (f < n && out.events[f].kind != EV_END) out.events[f].flags |= EVF_MAT;
+        }
+        e = d1;
+    }
+}
+
 static void work_sums(Program &out) {
     uint64_t t = 0, m = 0;
     uint32_t n = 0;
@@ -1459,6 +1507,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     out.n_src = src;
     out.n_noise = (uint32_t)out.noise.size();
     checkpoints(out);
+    deferrable_runs(out);
     work_sums(out);
     gap_tables(out);
     // pad the threshold table to whole 256-slot chunks

@@ -48,7 +48,8 @@ enum EvKind : uint32_t {
                      // when all of them are 1
     EV_DROP,         // speculative: coordinates >= mu carry no amplitude; k -> mu
     EV_DIAG,         // diagonal gate on <= 3 qubits, all its Z-strings in one pass (DiagInfo `boff`)
-    EV_END
+    EV_END,
+    EV_NOP           // never in a list: the kernel's kind for an event it skips
 };
 
 enum EvFlags : uint32_t {
@@ -69,8 +70,13 @@ enum EvFlags : uint32_t {
                        // the new coordinates hold zeros
     EVF_AND = 1024u,   // EV_FEEDBACK / EV_DIAG with EVF_COND: the condition is that every listed
                        // record bit is 1 (each pair's word covers its whole mask), not their XOR
-    EVF_MAT = 2048u,   // the first event at or after a checkpoint that reads or writes the tile: a
-                       // shot started from that checkpoint loads the checkpoint's tile here
+    EVF_MAT = 2048u,   // the first event at or after a checkpoint, or after a deferrable T run, that
+                       // reads or writes the tile: a shot started from that checkpoint loads the
+                       // checkpoint's tile here, and a shot that deferred the run is redone
+    EVF_DEFER = 4096u, // first of `mslot` events that form a deferrable T run (T gates with no noise
+                       // slot and no Clifford flip between them, followed by events that do not
+                       // touch the tile): a shot may skip them and is redone without skipping only
+                       // if an event needs the tile
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane
@@ -91,7 +97,7 @@ struct alignas(16) Event {
     uint32_t tstar;      // coordinate removed (CUT, MERGE) / top bit of mu (BFLY)
     uint32_t pm;         // bit t = bit p of b_t (SPLIT, MERGE)
     uint32_t pbit;       // pivot p (SPLIT, MERGE)
-    uint32_t mslot;      // measurement slot (M, MPP, R)
+    uint32_t mslot;      // measurement slot (M, MPP, R) / EVF_DEFER: events in the run
     uint32_t rec;        // record index (recorded measurements) / observable index
     uint32_t gbeta;      // parity(gamma & beta)
     uint32_t psign;      // sign bit of the measured Pauli (0 for parsed ops)
@@ -273,6 +279,7 @@ enum Counter {
     C_ENTRIES_T, C_ENTRIES_M, C_NOISE, C_EVENTS, C_NORMDEV_BITS,
     C_RESTARTS,              // shots restarted on the full list after a failed DROP check
     C_PREFIX,                // attempts that started from a checkpoint of the noiseless trajectory
+    C_REDO,                  // attempts redone because a deferred T run's tile was needed
     C_HIST0,                 // 16 buckets of floor(log2(max |v|))
     C_COUNT = C_HIST0 + 16
 };

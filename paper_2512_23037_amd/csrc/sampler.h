@@ -54,7 +54,7 @@ struct RunParams {
                               // list) without noise up to its last checkpoint, writing each checkpoint's
                               // slot
     uint32_t prefix_stride;   // bytes per prefix slot
-    uint32_t pad2_;
+    uint32_t defer;           // 1: skip deferrable T runs (EVF_DEFER) until an event needs their tile
     double tau2;              // pruning threshold squared
 };
 

@@ -762,6 +762,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // the checkpoint whose tile the shot still has to load (null: the
         // tile is in place)
         const unsigned char *lazy_slot = nullptr;
+        // Deferred T runs (EVF_DEFER): skipped while defer_ok; `deferred` once
+        // one was skipped, and `redo` when an event needed its tile (the
+        // attempt then runs again with defer_ok off).
+        bool defer_ok = P.defer != 0u && !tracing && !P.prefix_build && P.support_cap == 0xFFFFFFFFu;
+        bool deferred = false, redo = false;
         const uint32_t tile_off = kCkptRecOff + ((P.rec_words * 4u + 15u) & ~15u);
         auto materialize = [&]() {
             const C *pt = reinterpret_cast<const C *>(lazy_slot + tile_off);
@@ -841,6 +846,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // check ends first never needs it.
         uint32_t e0 = 0;
         lazy_slot = nullptr;
+        deferred = false;
         if (P.prefix != nullptr && !P.prefix_build && !tracing && ck_c != 0u) {
             // checkpoint c's noise count and validity in lane c (one load each)
             uint32_t cev = 0u, cnz = 0xFFFFFFFFu, cok = 0u;
@@ -928,15 +934,39 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 if (GAPS) draw_gap(); else draw_chunk();
             }
             // ---- Cliffords since the previous event: one XOR ----
-            const uint32_t flags = EV32(flags);
-            if (flags & (EVF_CLIFF | EVF_MAT)) {
+            uint32_t flags = EV32(flags);
+            uint32_t kind = EV32(kind);
+            if (flags & (EVF_CLIFF | EVF_MAT | EVF_DEFER)) {
+                // an event that needs the tile after a deferred T run: redo
+                // the attempt without deferring
+                if ((flags & EVF_MAT) && deferred) {
+                    redo = true;
+                    restart = true;
+                    --e;  // event e did not run (the attempt's work ends before it)
+                    break;
+                }
                 if (flags & EVF_CLIFF) {
                     rD ^= EV64(cliffD);
                     rS ^= EV64(cliffS);
                 }
-                if ((flags & EVF_MAT) && lazy_slot != nullptr) materialize();
+                if ((flags & EVF_DEFER) && defer_ok) {
+                    // skip the run: its gates change only the tile, which no
+                    // event needs before the one flagged EVF_MAT
+                    const uint32_t m = EV32(mslot);
+                    // (the work counters count the work run: the run's is taken off)
+                    const Event *d0 = reinterpret_cast<const Event *>(evl) + e, *d1 = d0 + m;
+                    if (lane == (uint32_t)C_ENTRIES_T) myc -= d1->cum_t - d0->cum_t;
+                    if (lane == (uint32_t)C_EVENTS) myc -= (uint64_t)(d1->cum_e - d0->cum_e);
+                    deferred = true;
+                    e += m - 1u;
+                    evx = evl[(uint64_t)(e + 1u) * 64u + lane];
+                    evy = evl[(uint64_t)(e + 2u) * 64u + lane];
+                    kind = EV_NOP;
+                    flags = 0u;
+                } else if ((flags & EVF_MAT) && lazy_slot != nullptr) {
+                    materialize();
+                }
             }
-            const uint32_t kind = EV32(kind);
             if (kind == EV_END) {
                 term = e;
                 break;
@@ -1493,6 +1523,8 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                         break;
                     }
                 }
+            } else if (kind == EV_NOP) {
+                // a deferred T run, skipped
             } else if (kind == EV_FEEDBACK) {
                 // ---- classically controlled Pauli: its record bits read as a check ----
                 if (cond_check(flags)) {
@@ -1531,9 +1563,21 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             myc += lane == (uint32_t)C_ENTRIES_T ? wt : lane == (uint32_t)C_ENTRIES_M ? wm
                  : lane == (uint32_t)C_EVENTS ? (uint64_t)we : lane == (uint32_t)C_NOISE ? (uint64_t)wn : 0ull;
         }
+        // a kept shot whose last deferred run was never applied: its final
+        // state needs it, so the attempt runs again without deferring
+        if (!restart && deferred && P.keep_n && shot >= P.keep_lo && shot - P.keep_lo < P.keep_n) {
+            restart = true;
+            redo = true;
+        }
         if (!restart || P.prefix_build) break;
-        full = true;
-        myc += lane == (uint32_t)C_RESTARTS ? 1u : 0u;
+        if (redo) {  // the same list again, every T run applied
+            redo = false;
+            defer_ok = false;
+            myc += lane == (uint32_t)C_REDO ? 1u : 0u;
+        } else {
+            full = true;
+            myc += lane == (uint32_t)C_RESTARTS ? 1u : 0u;
+        }
         }
         if (P.prefix_build) {
             // a list that ended (or stopped) before a checkpoint leaves its slot invalid

@@ -91,7 +91,8 @@ struct soft_ctx {
     int tile_mode = 0;                        // 0 auto, 1 LDS, 2 device memory, 3 split
     uint32_t split_log2 = 0;                  // split: log2 of the LDS part asked for (0: default)
     bool speculate = true;                    // run speculative event lists where compiled
-    bool shared_prefix = true;                // start hit-free shots from the noiseless prefix state
+    bool shared_prefix = true;                // start shots at checkpoints of the noiseless trajectory
+    bool defer_t = true;                      // skip deferrable T runs until an event needs their tile
     bool any_prefix = false;                  // some variant's lists have checkpoints
     int noise_mode = 0;                       // 0 a word per noise slot, 1 gap sampling
     Shape user;                               // explicit launch shape parts
@@ -603,6 +604,7 @@ int make_params(soft_ctx *c, uint64_t shot0, uint64_t n_shots, uint32_t *outcome
     rp.bm = c->d_bm.p;
     rp.diag = c->d_diag.p;
     rp.ckpts = c->d_ckpt.p;
+    rp.defer = c->defer_t ? 1u : 0u;
     rp.speculate = c->speculate ? 1u : 0u;
     rp.gaps = c->d_gap.p;
     rp.noise_mode = (uint32_t)c->noise_mode;
@@ -989,6 +991,12 @@ int soft_set_shared_prefix(soft_ctx *c, int on) {
     return SOFT_OK;
 }
 
+int soft_set_deferred_t(soft_ctx *c, int on) {
+    if (!c) return SOFT_EINVAL;
+    c->defer_t = on != 0;
+    return SOFT_OK;
+}
+
 int soft_set_noise_mode(soft_ctx *c, int mode) {
     if (!c) return SOFT_EINVAL;
     if (mode < 0 || mode > 1) return fail(c, SOFT_EINVAL, "noise mode must be 0 (a word per slot) or 1 (gap sampling)");
@@ -1132,6 +1140,7 @@ int read_rows(soft_ctx *c, uint32_t v0, uint32_t v1, soft_counters *out) {
         out->events += r[C_EVENTS];
         out->restarts += r[C_RESTARTS];
         out->prefix_shots += r[C_PREFIX];
+        out->redo_shots += r[C_REDO];
         for (int b = 0; b < 16; ++b) out->support_hist[b] += r[C_HIST0 + b];
         double d;
         std::memcpy(&d, &r[C_NORMDEV_BITS], sizeof(double));

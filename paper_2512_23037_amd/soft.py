@@ -26,7 +26,7 @@ EXPORTS = ("soft_create", "soft_destroy", "soft_last_error", "soft_load_circuit"
            "soft_read_tableau", "soft_circuit_info", "soft_launch_shape", "soft_set_trace", "soft_read_trace",
            "soft_load_mixture", "soft_read_variant_counters", "soft_variant_info", "soft_set_tile_memory",
            "soft_run_list", "soft_set_speculation", "soft_set_noise_mode", "soft_graph_info", "soft_run_noalloc",
-           "soft_set_shared_prefix")
+           "soft_set_shared_prefix", "soft_set_deferred_t")
 
 
 class SoftError(RuntimeError):
@@ -44,7 +44,8 @@ class soft_counters(ctypes.Structure):
                 ("overflow", ctypes.c_uint64), ("numeric", ctypes.c_uint64), ("logical_errors", ctypes.c_uint64),
                 ("entries_t", ctypes.c_uint64), ("entries_m", ctypes.c_uint64), ("noise_slots", ctypes.c_uint64),
                 ("events", ctypes.c_uint64), ("support_hist", ctypes.c_uint64 * 16), ("max_norm_dev", ctypes.c_double),
-                ("restarts", ctypes.c_uint64), ("prefix_shots", ctypes.c_uint64)]
+                ("restarts", ctypes.c_uint64), ("prefix_shots", ctypes.c_uint64),
+                ("redo_shots", ctypes.c_uint64)]
 
 
 _lib = None
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "soft_set_speculation": (I, [P, I]),
         "soft_set_noise_mode": (I, [P, I]),
         "soft_set_shared_prefix": (I, [P, I]),
+        "soft_set_deferred_t": (I, [P, I]),
         "soft_graph_info": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
@@ -209,6 +211,11 @@ class Context:
         before its first noise hit (default on; results are the same either
         way)."""
         self._check(self._lib.soft_set_shared_prefix(self._h, 1 if on else 0))
+
+    def set_deferred_t(self, on: bool):
+        """Skip T runs whose coefficients no event needs before the shot ends
+        (default on; a shot that needs them runs again with them applied)."""
+        self._check(self._lib.soft_set_deferred_t(self._h, 1 if on else 0))
 
     def set_noise_mode(self, mode: int):
         """0: one word per noise location (default); 1: gap sampling."""

@@ -30,6 +30,7 @@ def _on_off(build, N, kept=64, shot0=0):
     for on in (True, False):
         ctx = build()
         ctx.set_shared_prefix(on)
+        ctx.set_deferred_t(False)  # (deferred T runs change the support histogram: tested apart)
         ctx.set_keep(shot0, kept)
         out = run_gpu(ctx, shot0, N)
         res.append((out, ctx.counters(), [ctx.read_coeffs(s) for s in range(shot0, shot0 + kept)]))
@@ -80,6 +81,7 @@ def test_prefix_on_off_15q_full_list_and_oracle():
     assert on["prefix_shots"] > 0
     ref = circ.batch(7, 0, N)
     ctx = build()
+    ctx.set_deferred_t(False)
     ctx.set_keep(0, 128)
     compare_batch(run_gpu(ctx, 0, N), ref)
     compare_kept(ctx, circ, 7, range(128))

@@ -19,9 +19,11 @@ from tests.gpu_helpers import make_ctx
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("shots", "passed", "discarded", "overflow", "numeric", "logical_errors", "restarts", "prefix_shots")
-# work run: the same when both calls start the same shots from checkpoints
-# (the no-alloc call keeps checkpoint slots only while they fit its scratch)
-WORK = ("entries_t", "entries_m", "noise_slots", "events")
+# work run, and the supports and norms of what was computed: the same when
+# both calls start the same shots from checkpoints (the no-alloc call keeps
+# checkpoint slots only while they fit its scratch; a shot started elsewhere
+# may skip a different set of deferred T runs)
+WORK = ("entries_t", "entries_m", "noise_slots", "events", "redo_shots")
 
 
 def _outputs(ctx, n):
@@ -49,8 +51,9 @@ def _same(a, b):
         if f == "prefix_shots" and not same_start:
             continue
         assert ca[f] == cb[f], f
-    assert list(ca["support_hist"]) == list(cb["support_hist"])
-    assert ca["max_norm_dev"] == cb["max_norm_dev"]
+    if same_start:
+        assert list(ca["support_hist"]) == list(cb["support_hist"])
+        assert ca["max_norm_dev"] == cb["max_norm_dev"]
     return same_start
 
 
