@@ -273,8 +273,9 @@ int soft_set_deferred_t(soft_ctx *ctx, int on);
 
 /* Where the per-wave coefficient tile lives (the GPU memory layout of
  * Sec. IV-B, re-planned for LDS and HBM): 0 = automatic (LDS when one
- * wave's tile fits in a block's LDS, else device memory; soft_autotune also
- * tries device memory and splits), 1 = LDS, 2 = device memory (HBM; one slab
+ * wave's tile takes at most 8 KiB; a split as mode 3 picks it when the tile
+ * is larger but fits in a block's LDS; else device memory; soft_autotune also
+ * tries device memory and other splits), 1 = LDS, 2 = device memory (HBM; one slab
  * of 2^k_max entries per resident wave, allocated by the library on first
  * use), 3 = split: the low 2^L entries of the tile in LDS, the other
  * 2^k_max - 2^L in a per-wave device-memory slab, with L the autotuned value

@@ -401,8 +401,17 @@ Shape placement(const soft_ctx *c) {
         s.gt = TM_SPLIT;
         s.lds_log2 = c->split_log2 ? std::min<uint32_t>(c->split_log2, c->kmax - 1u) : split_log2_default(c);
     } else if (c->tile_mode == 0) {
+        // LDS up to 8 KiB a wave (20 waves a CU, the register-bound
+        // occupancy), a split above that while the tile would fit a block's
+        // LDS (its LDS part holds twice the waves or more), device memory for
+        // tiles no block holds
         Shape l;
-        s.gt = wave_bytes(c, l) > (uint32_t)c->max_lds_block ? TM_MEM : TM_LDS;
+        if (wave_bytes(c, l) > (uint32_t)c->max_lds_block) {
+            s.gt = TM_MEM;
+        } else if (tile_bytes(c) > 8192u && split_possible(c)) {
+            s.gt = TM_SPLIT;
+            s.lds_log2 = split_log2_default(c);
+        }
     }
     return s;
 }
@@ -1356,8 +1365,8 @@ int soft_autotune(soft_ctx *c, uint64_t sample_shots, void *hip_stream) {
                 if (p.lds_log2 >= kSplitMinLog2 && p.lds_log2 != places[0].lds_log2) places.push_back(p);
             }
     } else {
-        const Shape auto_p = placement(c);
-        if (auto_p.gt == TM_LDS) places.push_back(auto_p);
+        const Shape lds_p;  // the whole tile in LDS, when a block holds it
+        if (wave_bytes(c, lds_p) <= (uint32_t)c->max_lds_block) places.push_back(lds_p);
         Shape m;
         m.gt = TM_MEM;
         places.push_back(m);
