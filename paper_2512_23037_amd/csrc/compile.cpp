@@ -1240,6 +1240,7 @@ static void gap_tables(Program &out) {
     for (size_t s = 0; s < n; ++s)
         out.noise[s].acc = out.noise[s].thr ? (uint64_t)std::floor(out.noise_p[s] / pmax * 4294967296.0) : 0u;
     out.gap.assign(n, 0xFFFFFFFFu);
+    out.gap_pmax = pmax;
     if (pmax > 0.0) {
         const double q = 1.0 - pmax;
         double t = 1.0;

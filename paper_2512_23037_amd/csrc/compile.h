@@ -30,6 +30,7 @@ struct Program {
     std::vector<uint32_t> noise_tm1;  // per slot: thr-1 (hit iff word <= it), padded
     std::vector<double> noise_p;      // per slot: probability
     std::vector<uint32_t> gap;        // gap sampling: [g - 1] = floor(q^g 2^32), g = 1..n_noise
+    double gap_pmax = 0.0;            //   p_max (q = 1 - p_max); 0 without noise
     std::vector<uint32_t> det_pairs;  // (record word, mask) pairs
     std::vector<BatchMember> batch;   // members of side-by-side measurement runs
     std::vector<DiagInfo> diag;       // diagonal gates (EV_DIAG events point here)

@@ -211,8 +211,14 @@ struct alignas(16) VariantDesc {
     // checkpoints of the noiseless trajectory (Program::ckpts) of the list at
     // ev_off and of the full list: [ck_off, ck_off + ck_cnt) of the table
     uint32_t ck_off, ck_cnt, ck_off_full, ck_cnt_full;
+    // gap sampling: 1 / log2(q) (0 without noise), which puts the gap of a
+    // word w within a few slots of log2(w / 2^32) / log2(q); and 1 when
+    // every slot accepts every candidate (acc = 2^32: one probability)
+    float gap_l2q;
+    uint32_t acc_one;
+    uint32_t pad_[2];
 };
-static_assert(sizeof(VariantDesc) == 48, "variant layout");
+static_assert(sizeof(VariantDesc) == 64, "variant layout");
 constexpr uint32_t kMaxVariants = 64;
 
 // A checkpoint of the noiseless trajectory: the point before event `ev` of a

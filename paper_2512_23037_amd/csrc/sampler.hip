@@ -670,6 +670,13 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // held one block per lane).  The gap G = #{j : w < gap[j]} (a prefix,
         // the table falls with j) is found 64 entries apart, then entry by
         // entry, one entry per lane; entries past the last slot count as false.
+        // The one-round-trip estimate, and skipping the acceptance load when
+        // every slot accepts, pay where few waves share a SIMD to hide the
+        // table's latency (FP64 tiles: 3; split or device-memory tiles);
+        // with FP32 LDS tiles (5 waves) their registers cost more than they
+        // save (measured: +2.5% FP64 and +2% on span-12 split tiles, -2% on
+        // FP32 LDS tiles).
+        constexpr bool kGapEstimate = sizeof(R) == 8 || TM != TM_LDS;
         auto draw_gap = [&]() {
             if ((gd & ~255u) != nz_cb) {
                 nz_cb = gd & ~255u;
@@ -682,16 +689,37 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             gd += 2u;
             const uint32_t lim = vdp->n_noise - nz_drawn;
             const uint32_t *tb = P.gaps + vdp->gap_off;
-            uint32_t G = 0;
-            for (;;) {
-                const uint32_t j1 = G + 64u * lane;
-                const uint32_t n1 = (uint32_t)__builtin_popcountll(__ballot(j1 < lim && w < tb[j1]));
-                if (n1 == 0u) break;
-                const uint32_t b2 = G + 64u * (n1 - 1u) + 1u;
-                const uint32_t j2 = b2 + lane;
-                const uint32_t n2 = (uint32_t)__builtin_popcountll(__ballot(lane < 63u && j2 < lim && w < tb[j2]));
-                G = b2 + n2;
-                if (n1 < 64u || n2 < 63u) break;
+            // G = #{j < lim : w < tb[j]} (tb is non-increasing).  q^G is
+            // about w / 2^32, so G is within a slot or two of
+            // x = log2(w / 2^32) / log2(q): with kGapEstimate, lanes 0..3
+            // test the entries floor(x) - 2 .. floor(x) + 1 (an index below 0
+            // counts as passing), and when lane 0 passes and lane 3 fails
+            // they bracket G exactly, in one round trip to the table.
+            // Otherwise the search below, 64 entries a step (two or more
+            // round trips).
+            uint32_t G = 0xFFFFFFFFu;
+            if (kGapEstimate) {
+                const float x = fminf(fmaxf((__log2f((float)w + 0.5f) - 32.0f) * vdp->gap_l2q, 0.0f),
+                                      (float)lim + 4.0f);
+                const int32_t base = (int32_t)x - 2;
+                const int32_t j = base + (int32_t)lane;
+                bool t = j < 0;
+                if (lane < 4u && j >= 0 && (uint32_t)j < lim) t = w < tb[j];
+                const uint64_t b = __ballot(lane < 4u && t);
+                if ((b & 1ull) && !(b & 8ull)) G = (uint32_t)(base + (int32_t)__builtin_popcountll(b));
+            }
+            if (G == 0xFFFFFFFFu) {
+                G = 0;
+                for (;;) {
+                    const uint32_t j1 = G + 64u * lane;
+                    const uint32_t n1 = (uint32_t)__builtin_popcountll(__ballot(j1 < lim && w < tb[j1]));
+                    if (n1 == 0u) break;
+                    const uint32_t b2 = G + 64u * (n1 - 1u) + 1u;
+                    const uint32_t j2 = b2 + lane;
+                    const uint32_t n2 = (uint32_t)__builtin_popcountll(__ballot(lane < 63u && j2 < lim && w < tb[j2]));
+                    G = b2 + n2;
+                    if (n1 < 64u || n2 < 63u) break;
+                }
             }
             G = uni(G);
             if (G >= lim) {
@@ -700,7 +728,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             }
             const uint32_t cslot = nz_drawn + G;
             nz_drawn = cslot + 1u;
-            if ((uint64_t)aw < nz[vdp->nz_off + cslot].acc) {
+            if ((kGapEstimate && vdp->acc_one) || (uint64_t)aw < nz[vdp->nz_off + cslot].acc) {
                 next_hit = cslot;
                 hw = aw;
             }

@@ -314,6 +314,10 @@ int prepare(soft_ctx *c) {
         D.tm1_off = (uint32_t)tm1.size();
         D.n_noise = P.n_noise;
         D.gap_off = (uint32_t)gap.size();
+        D.gap_l2q = (P.gap_pmax > 0.0 && P.gap_pmax < 1.0) ? (float)(1.0 / std::log2(1.0 - P.gap_pmax)) : 0.0f;
+        D.acc_one = P.noise.empty() ? 0u : 1u;
+        for (const NoiseLoc &L : P.noise)
+            if (L.acc != (1ull << 32)) D.acc_one = 0u;
         // each event list with its own check pairs and run members
         auto append = [&](const Program &Q) {
             const uint32_t off = (uint32_t)ev.size();
