@@ -1209,6 +1209,36 @@ static void deferrable_runs(Program &out) {
     }
 }
 
+// Butterfly pairs: a plain butterfly (mu) followed by a butterfly (mu'),
+// plain or the last before a drop, on the same span with no noise slot and no
+// Clifford flip between them.  The pair runs as one pass over the quads
+// {j, j^mu, j^mu', j^mu^mu'}: the first butterfly on the quad's two mu-pairs,
+// then the second on its two mu'-pairs, so each entry is read and written once
+// instead of twice.  The quads are indexed by the coordinates less two bits
+// that mu and mu' pivot on: mu's top bit, and the top bit of mu' once mu is
+// taken out of it (so the two are independent and the quads tile the span).
+// Spans below 2^8 (fewer than 64 quads) are left alone.
+static void butterfly_pairs(Program &out) {
+    const uint32_t n = (uint32_t)out.events.size();
+    auto plain = [](const Event &E) {
+        return E.kind == EV_T_BFLY && !(E.flags & (EVF_DROP1 | EVF_TRUN | EVF_BRUN | EVF_PAIR));
+    };
+    for (uint32_t e = 0; e + 1 < n; ++e) {
+        Event &A = out.events[e];
+        const Event &B = out.events[e + 1];
+        if (!plain(A) || B.kind != EV_T_BFLY || (B.flags & (EVF_TRUN | EVF_BRUN | EVF_CLIFF | EVF_MAT | EVF_DEFER)))
+            continue;
+        if (B.noise_end != A.noise_end || B.k != A.k || A.k < 8u) continue;
+        const uint32_t p1 = A.tstar;
+        const uint32_t m2 = ((B.mu >> p1) & 1u) ? (B.mu ^ A.mu) : B.mu;
+        if (m2 == 0u) continue;  // the same coordinate shift twice
+        const uint32_t p2 = 31u - (uint32_t)__builtin_clz(m2);
+        A.flags |= EVF_PAIR;
+        A.pbit = std::min(p1, p2) | (std::max(p1, p2) << 8);
+        ++e;  // B is taken
+    }
+}
+
 static void work_sums(Program &out) {
     uint64_t t = 0, m = 0;
     uint32_t n = 0;
@@ -1509,6 +1539,7 @@ void compile_circuit(const std::string &text, const NoiseModel &nm, Program &out
     out.n_noise = (uint32_t)out.noise.size();
     checkpoints(out);
     deferrable_runs(out);
+    butterfly_pairs(out);
     work_sums(out);
     gap_tables(out);
     // pad the threshold table to whole 256-slot chunks

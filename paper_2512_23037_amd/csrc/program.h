@@ -77,6 +77,10 @@ enum EvFlags : uint32_t {
                        // slot and no Clifford flip between them, followed by events that do not
                        // touch the tile): a shot may skip them and is redone without skipping only
                        // if an event needs the tile
+    EVF_PAIR = 8192u,  // a plain butterfly whose next event is a butterfly (plain or EVF_DROP1) on the
+                       // same span with nothing between them: both run in one pass over quads
+                       // {j, j^mu, j^mu', j^mu^mu'}, whose two coordinate bits left out of the
+                       // pass index are pbit (low byte) and pbit >> 8
 };
 
 // One event: 64 dwords, which one wavefront loads with one dword per lane
@@ -96,7 +100,7 @@ struct alignas(16) Event {
     uint32_t mu;         // coordinates of beta in the span (BFLY, MERGE)
     uint32_t tstar;      // coordinate removed (CUT, MERGE) / top bit of mu (BFLY)
     uint32_t pm;         // bit t = bit p of b_t (SPLIT, MERGE)
-    uint32_t pbit;       // pivot p (SPLIT, MERGE)
+    uint32_t pbit;       // pivot p (SPLIT, MERGE) / EVF_PAIR: the quad's two coordinate bits
     uint32_t mslot;      // measurement slot (M, MPP, R) / EVF_DEFER: events in the run
     uint32_t rec;        // record index (recorded measurements) / observable index
     uint32_t gbeta;      // parity(gamma & beta)

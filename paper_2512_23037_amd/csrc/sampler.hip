@@ -383,6 +383,76 @@ __device__ __forceinline__ uint32_t t_bfly(const Tile<C, TM> &v, uint32_t lane, 
     return cnt;
 }
 
+// a + c i^q b for a wave-uniform q (the swap and signs of rotc chosen at run
+// time; c (+-1) w = (+-c) w exactly, so this equals t_out<q>), then dropped
+// below the pruning level.
+template <typename R, typename C>
+__device__ __forceinline__ C t_out_q(C a, C b, R c, uint32_t q, R thr, bool &keep) {
+    const R wx = (q & 1u) ? b.y : b.x, wy = (q & 1u) ? b.x : b.y;
+    const R cx = (q == 1u || q == 2u) ? -c : c, cy = (q >= 2u) ? -c : c;
+    C o;
+    o.x = fma(cx, wx, a.x);
+    o.y = fma(cy, wy, a.y);
+    keep = fma(o.x, o.x, o.y * o.y) >= thr;
+    if (!keep) { o.x = 0; o.y = 0; }
+    return o;
+}
+
+// Two branching T on existing coordinates, mu1 then mu2, in one pass (the
+// pair of an EVF_PAIR event and the next): each lane takes the quad
+// {j, j ^ mu1, j ^ mu2, j ^ mu1 ^ mu2} with j's bits plo and phi clear (the
+// quads tile the span), applies the first butterfly to its two mu1-pairs and
+// the second to its two mu2-pairs, pruning after each at its own level: the
+// separate passes' arithmetic on every entry.  Butterfly t updates
+// v'_x = v_x + tn_t i^q_t (-1)^(s_t ^ g_t.(x ^ mu_t)) v_(x ^ mu_t); the parity
+// of g_t over a quad's four members is that over j plus a uniform constant.
+// k >= 8: 2^(k-2) quads, a multiple of 64.  cnt1, cnt2: outputs kept by each;
+// upper: nonzero when the second keeps an output with coordinate bit k - 1
+// set (its drop check).
+template <typename R, typename C, uint32_t TM>
+__device__ __forceinline__ void t_bfly_pair(const Tile<C, TM> &v, uint32_t lane, uint32_t k, uint32_t plo, uint32_t phi,
+                                            uint32_t mu1, uint32_t g1, uint32_t s1, uint32_t q1, R tn1, R thr1,
+                                            uint32_t mu2, uint32_t g2, uint32_t s2, uint32_t q2, R tn2, R thr2,
+                                            uint32_t &cnt1, uint32_t &cnt2, uint64_t &upper) {
+    const uint32_t a1 = par32(g1 & mu1), b1 = par32(g1 & mu2);  // parity of g1 over mu1, mu2
+    const uint32_t a2 = par32(g2 & mu1), b2 = par32(g2 & mu2);
+    const uint32_t top = 1u << (k - 1u);
+    const uint32_t iters = 1u << (k - 8u);
+    cnt1 = 0;
+    cnt2 = 0;
+    upper = 0;
+    auto sgn = [](uint32_t s, R t) { return s ? -t : t; };
+    for (uint32_t it = 0; it < iters; ++it) {
+        const uint32_t j = ins0(ins0(lane + 64u * it, plo), phi);
+        const uint32_t jb = j ^ mu1, jc = j ^ mu2, jd = jb ^ mu2;
+        C *pa = v.at(j), *pb = v.at(jb), *pc = v.at(jc), *pd = v.at(jd);
+        const C A = *pa, B = *pb, Cc = *pc, D = *pd;
+        // first butterfly: (j, jb) and (jc, jd); the weight of v_y in v'_x
+        // has the parity of g1 over y
+        const uint32_t t1 = s1 ^ par32(g1 & j);
+        bool kA, kB, kC, kD;
+        const C A1 = t_out_q<R, C>(A, B, sgn(t1 ^ a1, tn1), q1, thr1, kA);
+        const C B1 = t_out_q<R, C>(B, A, sgn(t1, tn1), q1, thr1, kB);
+        const C C1 = t_out_q<R, C>(Cc, D, sgn(t1 ^ a1 ^ b1, tn1), q1, thr1, kC);
+        const C D1 = t_out_q<R, C>(D, Cc, sgn(t1 ^ b1, tn1), q1, thr1, kD);
+        cnt1 += (uint32_t)(__popcll(__ballot(kA)) + __popcll(__ballot(kB)) + __popcll(__ballot(kC)) +
+                           __popcll(__ballot(kD)));
+        // second butterfly: (j, jc) and (jb, jd)
+        const uint32_t t2 = s2 ^ par32(g2 & j);
+        const C A2 = t_out_q<R, C>(A1, C1, sgn(t2 ^ b2, tn2), q2, thr2, kA);
+        const C C2 = t_out_q<R, C>(C1, A1, sgn(t2, tn2), q2, thr2, kC);
+        const C B2 = t_out_q<R, C>(B1, D1, sgn(t2 ^ a2 ^ b2, tn2), q2, thr2, kB);
+        const C D2 = t_out_q<R, C>(D1, B1, sgn(t2 ^ a2, tn2), q2, thr2, kD);
+        cnt2 += (uint32_t)(__popcll(__ballot(kA)) + __popcll(__ballot(kB)) + __popcll(__ballot(kC)) +
+                           __popcll(__ballot(kD)));
+        upper |= __ballot((kA && (j & top)) || (kB && (jb & top)) || (kC && (jc & top)) || (kD && (jd & top)));
+        *pa = A2;
+        *pb = B2;
+        *pc = C2;
+        *pd = D2;
+    }
+}
+
 // Branching T on a new coordinate (k -> k+1): v'_j = v_j and
 // v'_{j+2^k} = tn i^Q (-1)^(sig ^ g.j) v_j.
 template <uint32_t Q, typename R, typename C, uint32_t TM>
@@ -458,6 +528,11 @@ __device__ __forceinline__ uint32_t quot16(uint64_t x, uint64_t d) {
      (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evc, (int)(offsetof(Event, f) / 4u)))
 #define EVF(f) __uint_as_float(EV32(f))
 #define EVD(f) __longlong_as_double((long long)EV64(f))
+// Fields of the next event (prefetched in `evx`).
+#define EVX32(f) ((uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u)))
+#define EVX64(f)                                                                                 \
+    (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u + 1u)) << 32) | \
+     (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u)))
 
 template <typename R, uint32_t NS, uint32_t TM>
 __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
@@ -794,6 +869,17 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // one was skipped, and `redo` when an event needed its tile (the
         // attempt then runs again with defer_ok off).
         bool defer_ok = P.defer != 0u && !tracing && !P.prefix_build && P.support_cap == 0xFFFFFFFFu;
+        // Butterfly pairs run as one pass where an FP32 pass reads and
+        // writes device memory (tiles there, or split tiles larger than
+        // their LDS part): each entry crosses to the slab once instead of
+        // twice (+9% on span-12 split tiles).  Elsewhere the two separate
+        // passes, tuned per quarter turn, are faster: the pair pass measured
+        // -10% on FP32 LDS tiles and -6% on FP64 split tiles of span 10
+        // (half the tile in the slab, and twice the arithmetic per byte).
+        // Not when a trace wants the state after each event or a support cap
+        // is checked after each T.
+        constexpr bool kPairs = TM != TM_LDS && sizeof(R) == 4;
+        const bool pair_ok = kPairs && !tracing && P.support_cap == 0xFFFFFFFFu;
         bool deferred = false, redo = false;
         const uint32_t tile_off = kCkptRecOff + ((P.rec_words * 4u + 15u) & ~15u);
         auto materialize = [&]() {
@@ -1152,6 +1238,37 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 e += m - 1u;
                 evx = evl[(uint64_t)(e + 1u) * 64u + lane];
                 evy = evl[(uint64_t)(e + 2u) * 64u + lane];
+            } else if (kPairs && (flags & EVF_PAIR) && pair_ok && (TM == TM_MEM || (1u << k) > v.lim)) {
+                // ---- a butterfly and the next one, in one pass ----
+                // Nothing acts between them (no noise slot, no Clifford
+                // flip): the second's sign comes from the same signs, and
+                // its scalar updates follow the first's, as in two passes.
+                const uint32_t f2 = EVX32(flags);
+                const uint32_t sg2 = par64((rD & EVX64(beta)) ^ ((rS ^ a) & EVX64(gamma)));
+                itscale2 *= EVD(iCs2);
+                const R tn1 = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
+                const R thr1 = (R)(tau2 * nrm2 * itscale2);
+                itscale2 *= __longlong_as_double((long long)EVX64(iCs2));
+                const R tn2 = sizeof(R) == 4 ? (R)__uint_as_float(EVX32(Tnf)) : (R)__longlong_as_double((long long)EVX64(Tn));
+                const R thr2 = (R)(tau2 * nrm2 * itscale2);
+                const uint32_t pv = EV32(pbit);
+                uint32_t cnt1, cnt2;
+                uint64_t upper;
+                t_bfly_pair<R, C, TM>(v, lane, k, pv & 255u, pv >> 8, EV32(mu), g, sga, EV32(qb), tn1, thr1, EVX32(mu),
+                                      EVX32(g), sg2, EVX32(qb), tn2, thr2, cnt1, cnt2, upper);
+                phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u) + ((f2 & EVF_TDG) ? 15u : 1u)) & 15u;
+                maxsup = max(maxsup, max(uni(cnt1), uni(cnt2)));
+                // the second event has run: the list goes on after it
+                ++e;
+                evx = evy;
+                evy = evl[(uint64_t)(e + 2u) * 64u + lane];
+                if (f2 & EVF_DROP1) {
+                    if (upper != 0ull) {
+                        restart = true;
+                        break;
+                    }
+                    --k;
+                }
             } else if (kind == EV_T_DOUBLE || kind == EV_T_BFLY) {
                 const R tn = sizeof(R) == 4 ? (R)EVF(Tnf) : (R)EVD(Tn);
                 const uint32_t sig = sga;
