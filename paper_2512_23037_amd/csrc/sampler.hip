@@ -1771,8 +1771,10 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
 // An FP32 tile of a 2^10 span takes 8 KiB of LDS, so LDS holds 5 waves per
 // SIMD; the register budget is set to match.  What no longer fits in
 // registers is what lives across a whole shot (group outputs, shot
-// constants), never the event loop's working set.  FP64 tiles are twice as
-// large: LDS, not registers, sets their occupancy.
+// constants), never the event loop's working set.  FP64 asks for 4 waves per
+// SIMD (128 VGPRs, a few values spilled): left to itself the compiler takes
+// 154 VGPRs and 3 waves, and the 42-qubit FP64 rate is 15% lower (105.7
+// against 121.4 M shots/s; asking for 5 waves spills more and gains nothing).
 template <uint32_t NS, uint32_t TM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sample_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
@@ -1782,7 +1784,7 @@ k_sample_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, cons
 }
 
 template <uint32_t NS, uint32_t TM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_sample_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
              const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
              RunParams P) {
@@ -1801,7 +1803,7 @@ k_prefix_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, cons
 }
 
 template <uint32_t TM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_prefix_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
              const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
              RunParams P) {
