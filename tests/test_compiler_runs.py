@@ -11,6 +11,12 @@ compiler is built with g++ into a small driver that prints the events.
   that nothing separates (same noise slots, no Clifford sign flips), span
   dimensions that step by one, tiles of at most 64 entries, and the summed
   global-phase step.
+- A butterfly pair (EVF_PAIR) joins a plain butterfly and the next butterfly
+  that nothing separates, on a span of 2^8 or more; its two left-out bits
+  make the quads {j, j^mu, j^mu', j^mu^mu'} tile the span, and the quad pass
+  (both butterflies on each quad, the second's partner weights from parities
+  over j plus constants) equals the two butterflies applied one after the
+  other to the whole vector.
 """
 from __future__ import annotations
 
@@ -43,13 +49,14 @@ int main(int argc, char **argv) {
     Program P;
     compile_circuit(ss.str(), nm, P, true);
     for (const Event &E : P.events)
-        std::printf("%u %u %u %u %u %u %u %u %u %u %llu %llu\n", E.kind, E.k, E.flags, E.bcnt, E.boff, E.qb, E.g,
-                    E.mu, E.tstar, E.noise_end, (unsigned long long)E.trot0, (unsigned long long)E.trot1);
+        std::printf("%u %u %u %u %u %u %u %u %u %u %llu %llu %u\n", E.kind, E.k, E.flags, E.bcnt, E.boff, E.qb, E.g,
+                    E.mu, E.tstar, E.noise_end, (unsigned long long)E.trot0, (unsigned long long)E.trot1, E.pbit);
     return 0;
 }
 """
 
-FIELDS = ("kind", "k", "flags", "bcnt", "boff", "qb", "g", "mu", "tstar", "noise_end", "trot0", "trot1")
+FIELDS = ("kind", "k", "flags", "bcnt", "boff", "qb", "g", "mu", "tstar", "noise_end", "trot0", "trot1", "pbit")
+EVF_MAT, EVF_DEFER, EVF_PAIR = 2048, 4096, 8192
 
 
 @pytest.fixture(scope="module")
@@ -73,6 +80,7 @@ def events(driver, text):
 
 def circuits():
     yield "cultivation_42q", workloads.config("cultivation_42q", seed=1).text
+    yield "cultivation_42q_k12", workloads.config("cultivation_42q_k12", seed=1).text
     shapes = [(7, 8, 3, [7, 4], 4), (9, 6, 3, [9, 5], 6), (8, 6, 2, [8], 6), (10, 6, 3, [10, 6, 3], 6)]
     for seed, (nd, na, rz, br, w) in enumerate(shapes):
         yield "bracket%d" % seed, workloads.cultivation_shaped(100 + seed, nd, na, rz, br, check_weight=w,
@@ -150,3 +158,77 @@ def test_dropping_butterfly_runs_are_well_formed(driver, name, text):
             assert (x["mu"] >> x["tstar"]) == 1  # mu's top bit is the dropped coordinate
     if name == "cultivation_42q":
         assert runs >= 4
+
+
+def ins0(p, h):
+    lo = p & ((1 << h) - 1)
+    return ((p ^ lo) << 1) | lo
+
+
+def bfly(v, mu, g, s, q, tn):
+    """One branching T on an existing coordinate, over the whole vector:
+    v'_x = v_x + tn i^q (-1)^(s ^ g.(x ^ mu)) v_(x ^ mu)."""
+    out = v.copy()
+    for x in range(len(v)):
+        y = x ^ mu
+        out[x] = v[x] + tn * (1j ** q) * (-1) ** (s ^ parity(g & y)) * v[y]
+    return out
+
+
+@pytest.mark.parametrize("name,text", list(circuits()), ids=[n for n, _ in circuits()])
+def test_butterfly_pairs_tile_the_span_and_match_two_passes(driver, name, text):
+    ev = events(driver, text)
+    rng = np.random.default_rng(11)
+    tn = np.tan(np.pi / 8)
+    pairs = 0
+    for i, A in enumerate(ev):
+        if not A["flags"] & EVF_PAIR:
+            continue
+        pairs += 1
+        B = ev[i + 1]
+        assert A["kind"] == EV_T_BFLY and not A["flags"] & (EVF_DROP1 | EVF_TRUN | EVF_BRUN)
+        assert B["kind"] == EV_T_BFLY and not B["flags"] & (EVF_TRUN | EVF_BRUN | EVF_CLIFF | EVF_MAT | EVF_DEFER | EVF_PAIR)
+        assert A["noise_end"] == B["noise_end"] and A["k"] == B["k"] >= 8
+        k = A["k"]
+        plo, phi = A["pbit"] & 255, A["pbit"] >> 8
+        assert plo < phi < k
+        mu1, mu2 = A["mu"], B["mu"]
+        # the quads tile the span
+        seen = set()
+        for qi in range(1 << (k - 2)):
+            j = ins0(ins0(qi, plo), phi)
+            seen.update((j, j ^ mu1, j ^ mu2, j ^ mu1 ^ mu2))
+        assert seen == set(range(1 << k))
+        # the quad pass equals the two butterflies in turn (for both signs)
+        v = rng.normal(size=1 << k) + 1j * rng.normal(size=1 << k)
+        for s1, s2 in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            ref = bfly(bfly(v, mu1, A["g"], s1, A["qb"], tn), mu2, B["g"], s2, B["qb"], tn)
+            out = v.copy()
+            g1, g2 = A["g"], B["g"]
+            a1, b1, a2, b2 = parity(g1 & mu1), parity(g1 & mu2), parity(g2 & mu1), parity(g2 & mu2)
+            w1, w2 = tn * 1j ** A["qb"], tn * 1j ** B["qb"]
+            sg = lambda t: -1.0 if t else 1.0
+            for qi in range(1 << (k - 2)):
+                j = ins0(ins0(qi, plo), phi)
+                jb, jc = j ^ mu1, j ^ mu2
+                jd = jb ^ mu2
+                a, b, c, d = out[j], out[jb], out[jc], out[jd]
+                t1 = s1 ^ parity(g1 & j)
+                a, b, c, d = (a + sg(t1 ^ a1) * w1 * b, b + sg(t1) * w1 * a,
+                              c + sg(t1 ^ a1 ^ b1) * w1 * d, d + sg(t1 ^ b1) * w1 * c)
+                t2 = s2 ^ parity(g2 & j)
+                a, c, b, d = (a + sg(t2 ^ b2) * w2 * c, c + sg(t2) * w2 * a,
+                              b + sg(t2 ^ a2 ^ b2) * w2 * d, d + sg(t2 ^ a2) * w2 * b)
+                out[j], out[jb], out[jc], out[jd] = a, b, c, d
+            np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12)
+    # every plain butterfly that could pair with the next one does
+    for i in range(len(ev) - 1):
+        A, B = ev[i], ev[i + 1]
+        if (A["kind"] == EV_T_BFLY == B["kind"] and A["k"] >= 8 and A["noise_end"] == B["noise_end"]
+                and not A["flags"] & (EVF_DROP1 | EVF_TRUN | EVF_BRUN)
+                and not B["flags"] & (EVF_TRUN | EVF_BRUN | EVF_CLIFF | EVF_MAT | EVF_DEFER)
+                and not (i > 0 and ev[i - 1]["flags"] & EVF_PAIR)):
+            assert A["flags"] & EVF_PAIR, i
+    expect = {"cultivation_42q": 5, "cultivation_42q_k12": 4}
+    if name in expect:
+        assert pairs == expect[name]
