@@ -408,9 +408,12 @@ __device__ __forceinline__ C t_out_q(C a, C b, R c, uint32_t q, R thr, bool &kee
 // of g_t over a quad's four members is that over j plus a uniform constant.
 // k >= 8: 2^(k-2) quads, a multiple of 64.  cnt1, cnt2: outputs kept by each;
 // upper: nonzero when the second keeps an output with coordinate bit k - 1
-// set (its drop check).
-template <typename R, typename C, uint32_t TM>
-__device__ __forceinline__ void t_bfly_pair(const Tile<C, TM> &v, uint32_t lane, uint32_t k, uint32_t plo, uint32_t phi,
+// set (its drop check).  The inputs come from `src`: the tile itself, or the
+// tile of the checkpoint a shot started from, not yet loaded (every entry is
+// written, so the pass also loads it).
+template <typename R, typename C, uint32_t TM, uint32_t TMS>
+__device__ __forceinline__ void t_bfly_pair(const Tile<C, TM> &v, const Tile<C, TMS> &src, uint32_t lane, uint32_t k,
+                                            uint32_t plo, uint32_t phi,
                                             uint32_t mu1, uint32_t g1, uint32_t s1, uint32_t q1, R tn1, R thr1,
                                             uint32_t mu2, uint32_t g2, uint32_t s2, uint32_t q2, R tn2, R thr2,
                                             uint32_t &cnt1, uint32_t &cnt2, uint64_t &upper) {
@@ -426,7 +429,7 @@ __device__ __forceinline__ void t_bfly_pair(const Tile<C, TM> &v, uint32_t lane,
         const uint32_t j = ins0(ins0(lane + 64u * it, plo), phi);
         const uint32_t jb = j ^ mu1, jc = j ^ mu2, jd = jb ^ mu2;
         C *pa = v.at(j), *pb = v.at(jb), *pc = v.at(jc), *pd = v.at(jd);
-        const C A = *pa, B = *pb, Cc = *pc, D = *pd;
+        const C A = *src.at(j), B = *src.at(jb), Cc = *src.at(jc), D = *src.at(jd);
         // first butterfly: (j, jb) and (jc, jd); the weight of v_y in v'_x
         // has the parity of g1 over y
         const uint32_t t1 = s1 ^ par32(g1 & j);
@@ -880,6 +883,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // is checked after each T.
         constexpr bool kPairs = TM != TM_LDS && sizeof(R) == 4;
         const bool pair_ok = kPairs && !tracing && P.support_cap == 0xFFFFFFFFu;
+        auto pair_now = [&](uint32_t fl) { return (fl & EVF_PAIR) && pair_ok && (1u << k) > v.lim; };
         bool deferred = false, redo = false;
         const uint32_t tile_off = kCkptRecOff + ((P.rec_words * 4u + 15u) & ~15u);
         auto materialize = [&]() {
@@ -1077,7 +1081,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     evy = evl[(uint64_t)(e + 2u) * 64u + lane];
                     kind = EV_NOP;
                     flags = 0u;
-                } else if ((flags & EVF_MAT) && lazy_slot != nullptr) {
+                } else if ((flags & EVF_MAT) && lazy_slot != nullptr && !(kPairs && pair_now(flags))) {
                     materialize();
                 }
             }
@@ -1238,7 +1242,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 e += m - 1u;
                 evx = evl[(uint64_t)(e + 1u) * 64u + lane];
                 evy = evl[(uint64_t)(e + 2u) * 64u + lane];
-            } else if (kPairs && (flags & EVF_PAIR) && pair_ok && (TM == TM_MEM || (1u << k) > v.lim)) {
+            } else if (kPairs && pair_now(flags)) {
                 // ---- a butterfly and the next one, in one pass ----
                 // Nothing acts between them (no noise slot, no Clifford
                 // flip): the second's sign comes from the same signs, and
@@ -1254,8 +1258,19 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 const uint32_t pv = EV32(pbit);
                 uint32_t cnt1, cnt2;
                 uint64_t upper;
-                t_bfly_pair<R, C, TM>(v, lane, k, pv & 255u, pv >> 8, EV32(mu), g, sga, EV32(qb), tn1, thr1, EVX32(mu),
-                                      EVX32(g), sg2, EVX32(qb), tn2, thr2, cnt1, cnt2, upper);
+                if (lazy_slot != nullptr) {
+                    // the shot's tile is still the checkpoint's: read it there
+                    Tile<C, TM_MEM> ck;
+                    ck.lo = reinterpret_cast<C *>(const_cast<unsigned char *>(lazy_slot) + tile_off);
+                    ck.hi = nullptr;
+                    ck.lim = 0;
+                    t_bfly_pair<R, C, TM, TM_MEM>(v, ck, lane, k, pv & 255u, pv >> 8, EV32(mu), g, sga, EV32(qb), tn1,
+                                                  thr1, EVX32(mu), EVX32(g), sg2, EVX32(qb), tn2, thr2, cnt1, cnt2, upper);
+                    lazy_slot = nullptr;
+                } else {
+                    t_bfly_pair<R, C, TM, TM>(v, v, lane, k, pv & 255u, pv >> 8, EV32(mu), g, sga, EV32(qb), tn1, thr1,
+                                              EVX32(mu), EVX32(g), sg2, EVX32(qb), tn2, thr2, cnt1, cnt2, upper);
+                }
                 phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u) + ((f2 & EVF_TDG) ? 15u : 1u)) & 15u;
                 maxsup = max(maxsup, max(uni(cnt1), uni(cnt2)));
                 // the second event has run: the list goes on after it
