@@ -410,13 +410,16 @@ __device__ __forceinline__ C t_out_q(C a, C b, R c, uint32_t q, R thr, bool &kee
 // upper: nonzero when the second keeps an output with coordinate bit k - 1
 // set (its drop check).  The inputs come from `src`: the tile itself, or the
 // tile of the checkpoint a shot started from, not yet loaded (every entry is
-// written, so the pass also loads it).
+// written, so the pass also loads it).  With drop2 (the second drops
+// coordinate k - 1) the outputs at coordinates with that bit set are not
+// stored: the span leaves them when the check passes, and nothing reads the
+// tile past 2^k; when it fails the shot restarts.
 template <typename R, typename C, uint32_t TM, uint32_t TMS>
 __device__ __forceinline__ void t_bfly_pair(const Tile<C, TM> &v, const Tile<C, TMS> &src, uint32_t lane, uint32_t k,
                                             uint32_t plo, uint32_t phi,
                                             uint32_t mu1, uint32_t g1, uint32_t s1, uint32_t q1, R tn1, R thr1,
                                             uint32_t mu2, uint32_t g2, uint32_t s2, uint32_t q2, R tn2, R thr2,
-                                            uint32_t &cnt1, uint32_t &cnt2, uint64_t &upper) {
+                                            bool drop2, uint32_t &cnt1, uint32_t &cnt2, uint64_t &upper) {
     const uint32_t a1 = par32(g1 & mu1), b1 = par32(g1 & mu2);  // parity of g1 over mu1, mu2
     const uint32_t a2 = par32(g2 & mu1), b2 = par32(g2 & mu2);
     const uint32_t top = 1u << (k - 1u);
@@ -449,10 +452,10 @@ __device__ __forceinline__ void t_bfly_pair(const Tile<C, TM> &v, const Tile<C, 
         cnt2 += (uint32_t)(__popcll(__ballot(kA)) + __popcll(__ballot(kB)) + __popcll(__ballot(kC)) +
                            __popcll(__ballot(kD)));
         upper |= __ballot((kA && (j & top)) || (kB && (jb & top)) || (kC && (jc & top)) || (kD && (jd & top)));
-        *pa = A2;
-        *pb = B2;
-        *pc = C2;
-        *pd = D2;
+        if (!drop2 || !(j & top)) *pa = A2;
+        if (!drop2 || !(jb & top)) *pb = B2;
+        if (!drop2 || !(jc & top)) *pc = C2;
+        if (!drop2 || !(jd & top)) *pd = D2;
     }
 }
 
@@ -1265,11 +1268,13 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     ck.hi = nullptr;
                     ck.lim = 0;
                     t_bfly_pair<R, C, TM, TM_MEM>(v, ck, lane, k, pv & 255u, pv >> 8, EV32(mu), g, sga, EV32(qb), tn1,
-                                                  thr1, EVX32(mu), EVX32(g), sg2, EVX32(qb), tn2, thr2, cnt1, cnt2, upper);
+                                                  thr1, EVX32(mu), EVX32(g), sg2, EVX32(qb), tn2, thr2,
+                                                  (f2 & EVF_DROP1) != 0u, cnt1, cnt2, upper);
                     lazy_slot = nullptr;
                 } else {
                     t_bfly_pair<R, C, TM, TM>(v, v, lane, k, pv & 255u, pv >> 8, EV32(mu), g, sga, EV32(qb), tn1, thr1,
-                                              EVX32(mu), EVX32(g), sg2, EVX32(qb), tn2, thr2, cnt1, cnt2, upper);
+                                              EVX32(mu), EVX32(g), sg2, EVX32(qb), tn2, thr2, (f2 & EVF_DROP1) != 0u,
+                                              cnt1, cnt2, upper);
                 }
                 phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u) + ((f2 & EVF_TDG) ? 15u : 1u)) & 15u;
                 maxsup = max(maxsup, max(uni(cnt1), uni(cnt2)));
