@@ -69,7 +69,10 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
 // the sampler instantiation for a precision, noise source and tile mode
 // (arguments: ev, nz, tm1, det, words, bm, then the RunParams by value), and
 // the counter reset (arguments: counters, n, next; one block of 256 threads).
-const void *sampler_kernel(bool fp64, uint32_t noise_source, uint32_t tile_mode);
+const void *sampler_kernel(bool fp64, uint32_t noise_source, uint32_t tile_mode, bool lean);
+// Whether a launch with these parameters runs the lean kernel (no kept
+// states, no trace, no explicit words; see sampler.hip).
+bool sampler_lean(const RunParams &p, bool fp64);
 const void *reset_kernel();
 // The shared-prefix build kernel for a precision and tile mode (arguments as
 // the sampler's, with RunParams::prefix_build set), and a direct launch of it.

@@ -458,3 +458,23 @@ def test_graph_reused_across_batches():
     again = run_gpu(ctx, 0, B)
     assert (again["status"] == ref["status"][:B]).all()
     assert ctx.graph_info()["instantiations"] <= 4
+
+
+@pytest.mark.parametrize("bits,mode", [(32, 1), (64, 1), (32, 0), (64, 0)])
+def test_lean_kernel_equals_full_kernel(bits, mode):
+    # A launch with no kept states and no trace runs the lean kernel (those
+    # paths compiled out); keeping a few states switches to the full one.
+    # Records, statuses, abort ops, observables and the pass / discard /
+    # logical counts are the same either way.
+    w = workloads.config("cultivation_42q", seed=1)
+    res = []
+    for keep in (None, (7, 16)):
+        ctx = make_ctx(w.text, w.noise, seed=20251223, bits=bits, keep=keep)
+        ctx.set_noise_mode(mode)
+        res.append((run_gpu(ctx, 0, 400_000), ctx.counters()))
+        ctx.close()
+    (a, ca), (b, cb) = res
+    for k in ("status", "abort_op", "obs", "outcomes"):
+        assert (a[k] == b[k]).all(), k
+    for f in ("shots", "passed", "discarded", "overflow", "numeric", "logical_errors", "restarts"):
+        assert ca[f] == cb[f], f
