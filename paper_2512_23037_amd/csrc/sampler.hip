@@ -540,8 +540,9 @@ __device__ __forceinline__ uint32_t quot16(uint64_t x, uint64_t d) {
     (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u + 1u)) << 32) | \
      (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u)))
 
-// LEAN: a launch with no kept states and no trace; those paths compile out,
-// which frees scalar registers in the event loop.
+// LEAN: a launch with no kept states and no trace (and never the prefix
+// build); those paths compile out, which frees scalar registers in the event
+// loop.
 template <typename R, uint32_t NS, uint32_t TM, bool LEAN = false>
 __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
                                              const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
@@ -595,7 +596,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
     bool var_ok = false;
     uint64_t var_lo = 0, var_end = 0;
     auto flush_counters = [&]() {
-        if (P.prefix_build) {  // the build samples no shots
+        if ((!LEAN && P.prefix_build)) {  // the build samples no shots
             myc = 0;
             maxdev = 0.0;
             return;
@@ -636,7 +637,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         const uint64_t i = group_base + group_pos;
         // a vector load of a uniform address: say that the result is uniform
         // (item i of the prefix build runs the first shot of variant i / 2)
-        const uint64_t shot = uni64(P.prefix_build ? ((i >> 1) ? P.vars[(i >> 1) - 1u].shot_end : 0ull)
+        const uint64_t shot = uni64((!LEAN && P.prefix_build) ? ((i >> 1) ? P.vars[(i >> 1) - 1u].shot_end : 0ull)
                                     : P.shot_list ? P.shot_list[i] : P.shot0 + i);
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
         if (!var_ok || shot >= var_end || shot < var_lo) {
@@ -867,7 +868,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // (with a support cap the full list runs: the cap is defined by the
         // supports of the circuit's own gate order)
         bool full = tracing || !P.speculate || P.support_cap != 0xFFFFFFFFu || vdp->ev_off_full == vdp->ev_off;
-        if (P.prefix_build) full = (i & 1u) != 0u || vdp->ev_off_full == vdp->ev_off;
+        if ((!LEAN && P.prefix_build)) full = (i & 1u) != 0u || vdp->ev_off_full == vdp->ev_off;
         bool pfx_done = false;      // the build wrote every checkpoint of this item's list
         uint32_t ck_next_done = 0;  // checkpoints written
         // the checkpoint whose tile the shot still has to load (null: the
@@ -876,7 +877,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // Deferred T runs (EVF_DEFER): skipped while defer_ok; `deferred` once
         // one was skipped, and `redo` when an event needed its tile (the
         // attempt then runs again with defer_ok off).
-        bool defer_ok = P.defer != 0u && !tracing && !P.prefix_build && P.support_cap == 0xFFFFFFFFu;
+        bool defer_ok = P.defer != 0u && !tracing && !(!LEAN && P.prefix_build) && P.support_cap == 0xFFFFFFFFu;
         // Butterfly pairs run as one pass where an FP32 pass reads and
         // writes device memory (tiles there, or split tiles larger than
         // their LDS part): each entry crosses to the slab once instead of
@@ -931,7 +932,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // checkpoint goes to its slot (the full list's item only, when the
         // variant has one list).
         uint32_t ck_next = 0;
-        if (P.prefix_build) {
+        if ((!LEAN && P.prefix_build)) {
             nz_drawn = n_slots;
             if (ck_c == 0u || (!(i & 1u) && vdp->ev_off_full == vdp->ev_off)) {
                 pfx_done = true;  // nothing to write (or the odd item writes these slots)
@@ -970,7 +971,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         uint32_t e0 = 0;
         lazy_slot = nullptr;
         deferred = false;
-        if (P.prefix != nullptr && !P.prefix_build && !tracing && ck_c != 0u) {
+        if (P.prefix != nullptr && !(!LEAN && P.prefix_build) && !tracing && ck_c != 0u) {
             // checkpoint c's noise count and validity in lane c (one load each)
             uint32_t cev = 0u, cnz = 0xFFFFFFFFu, cok = 0u;
             if (lane < ck_c) {
@@ -1018,11 +1019,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         uint32_t evx = evl[(uint64_t)(e0 + 1u) * 64u + lane];
         uint32_t e = e0;  // after the loop: the last event run
         // trace steps, or (build) the events up to the last checkpoint
-        const uint32_t dump_lim = (P.prefix_build && ck_c) ? uni(P.ckpts[ck_o + ck_c - 1u].ev) + 1u : trace_lim;
+        const uint32_t dump_lim = ((!LEAN && P.prefix_build) && ck_c) ? uni(P.ckpts[ck_o + ck_c - 1u].ev) + 1u : trace_lim;
         for (;; ++e) {
             uint32_t evy = evl[(uint64_t)(e + 2u) * 64u + lane];
             if (e - 1u < dump_lim) {  // state after event e-1 (e = 0 wraps past any limit)
-                if (P.prefix_build) {
+                if ((!LEAN && P.prefix_build)) {
                     if (e == uni(P.ckpts[ck_o + ck_next].ev)) {
                         write_ckpt(ck_o + ck_next);
                         ck_next_done = ++ck_next;
@@ -1736,7 +1737,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             restart = true;
             redo = true;
         }
-        if (!restart || P.prefix_build) break;
+        if (!restart || (!LEAN && P.prefix_build)) break;
         if (redo) {  // the same list again, every T run applied
             redo = false;
             defer_ok = false;
@@ -1746,7 +1747,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             myc += lane == (uint32_t)C_RESTARTS ? 1u : 0u;
         }
         }
-        if (P.prefix_build) {
+        if ((!LEAN && P.prefix_build)) {
             // a list that ended (or stopped) before a checkpoint leaves its slot invalid
             if (!pfx_done && lane == 0) {
                 const uint32_t o = full ? vdp->ck_off_full : vdp->ck_off, cnt = full ? vdp->ck_cnt_full : vdp->ck_cnt;
@@ -1869,12 +1870,13 @@ int kernel_index(bool fp64, uint32_t ns, uint32_t tm, bool lean) {
 }
 }  // namespace
 
-// The lean kernels run launches with no kept states and no trace (not the
-// prefix build, which has its own kernels).  FP32 split and device-memory
-// tiles keep the full kernel: there the lean one measured 0.8% slower (on
-// LDS tiles it is 3.8% faster in FP32, 3.4% in FP64).
+// The lean kernels run launches with no kept states and no trace (never the
+// prefix build, which has its own kernels).  With the build's code out as
+// well, the FP32 LDS kernel spills 90 SGPRs instead of 245: measured +11%
+// FP32 and +14% FP64 on the 42-qubit workload, +11% on span-12 split tiles.
 bool sampler_lean(const RunParams &p, bool fp64) {
-    return p.keep_n == 0u && p.trace_n == 0u && p.words == nullptr && (fp64 || p.tile_mode == TM_LDS);
+    (void)fp64;
+    return p.keep_n == 0u && p.trace_n == 0u && p.words == nullptr;
 }
 
 hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long long *next, hipStream_t stream) {
