@@ -755,12 +755,10 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // the table falls with j) is found 64 entries apart, then entry by
         // entry, one entry per lane; entries past the last slot count as false.
         // The one-round-trip estimate, and skipping the acceptance load when
-        // every slot accepts, pay where few waves share a SIMD to hide the
-        // table's latency (FP64 tiles: 3; split or device-memory tiles);
-        // with FP32 LDS tiles (5 waves) their registers cost more than they
-        // save (measured: +2.5% FP64 and +2% on span-12 split tiles, -2% on
-        // FP32 LDS tiles).
-        constexpr bool kGapEstimate = sizeof(R) == 8 || TM != TM_LDS;
+        // every slot accepts: measured +2.5% FP64, +2% on span-12 split
+        // tiles and, in the lean kernels, +2.4% on FP32 LDS tiles (where,
+        // before the lean kernels freed registers, it cost 2%).
+        constexpr bool kGapEstimate = true;
         auto draw_gap = [&]() {
             if ((gd & ~255u) != nz_cb) {
                 nz_cb = gd & ~255u;
