@@ -1792,10 +1792,11 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
 // An FP32 tile of a 2^10 span takes 8 KiB of LDS, so LDS holds 5 waves per
 // SIMD; the register budget is set to match.  What no longer fits in
 // registers is what lives across a whole shot (group outputs, shot
-// constants), never the event loop's working set.  FP64 asks for 4 waves per
-// SIMD (128 VGPRs, a few values spilled): left to itself the compiler takes
-// 154 VGPRs and 3 waves, and the 42-qubit FP64 rate is 15% lower (105.7
-// against 121.4 M shots/s; asking for 5 waves spills more and gains nothing).
+// constants), never the event loop's working set.  FP64 asks for 5 waves per
+// SIMD as well (96 VGPRs, more spilled): left to itself the compiler takes
+// 154 VGPRs and 3 waves.  On the 42-qubit workload 4 waves (128 VGPRs) were
+// 15% faster than 3, and once the lean kernels had freed registers 5 waves
+// were 2.4% faster than 4 (141.3 against 137.9 M shots/s).
 template <uint32_t NS, uint32_t TM, bool LEAN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sample_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
@@ -1805,7 +1806,7 @@ k_sample_f32(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, cons
 }
 
 template <uint32_t NS, uint32_t TM, bool LEAN>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_sample_f64(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz, const uint32_t *__restrict__ tm1,
              const uint32_t *__restrict__ det, const uint32_t *__restrict__ words, const BatchMember *__restrict__ bm,
              RunParams P) {
