@@ -82,8 +82,9 @@ typedef struct {
     uint64_t prefix_shots;       /* attempts that started from a checkpoint of the noiseless
                                     trajectory (soft_set_shared_prefix); the work fields
                                     above count only the work run */
-    uint64_t redo_shots;         /* attempts run again because an event needed the tile of a
-                                    T run they had deferred (soft_set_deferred_t) */
+    uint64_t redo_shots;         /* deferred T runs applied late because an event needed the
+                                    tile, and attempts run again to keep a state
+                                    (soft_set_deferred_t) */
 } soft_counters;
 
 /* Create a context on HIP device `hip_device` (made current for the call):
@@ -262,10 +263,12 @@ int soft_set_shared_prefix(soft_ctx *ctx, int on);
  * between them, followed by such events, can be skipped: a shot that a check
  * ends before any event reads the coefficients never needs the run (most
  * shots with an early fault, Sec. V's early stop of discarded shots).  When
- * an event does need them, or the shot's final state is kept, the attempt
- * runs again with every run applied; the same draws give the same results,
- * so records, statuses, abort ops, observables and kept states are identical
- * either way.  Off with a support cap (the cap is checked on every T).  What
+ * an event does need them, the run is applied then, with the tableau signs
+ * it saw (the events in between changed only signs and records), before that
+ * event; when the shot's final state is kept and a run is still skipped at
+ * the end, the attempt runs again with every run applied.  The arithmetic
+ * is the same either way, so records, statuses, abort ops, observables and
+ * kept states are identical.  Off with a support cap (the cap is checked on every T).  What
  * differs: a shot that ended with a run skipped reports, in support_hist,
  * the largest support it computed, and the norm check covers the
  * coefficients it computed.  on = 0 applies every run. */

@@ -889,6 +889,16 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         const bool pair_ok = kPairs && !tracing && P.support_cap == 0xFFFFFFFFu;
         auto pair_now = [&](uint32_t fl) { return (fl & EVF_PAIR) && pair_ok && (1u << k) > v.lim; };
         bool deferred = false, redo = false;
+        // A deferred run applied late: the signs the run saw and the state
+        // to come back to live in lanes of one register (rarely touched):
+        // lanes 0-3 the signs at the run, 4-7 the signs at the event that
+        // needs the tile, 8 that event, 9 and 10 the run's first event and
+        // the one after it.
+        bool replaying = false;
+        uint32_t stash = 0u;
+        auto put = [&](uint32_t l, uint32_t x) { stash = lane == l ? x : stash; };
+        auto get = [&](uint32_t l) { return uni((uint32_t)__builtin_amdgcn_readlane((int)stash, (int)l)); };
+        auto get64 = [&](uint32_t l) { return ((uint64_t)get(l + 1u) << 32) | (uint64_t)get(l); };
         const uint32_t tile_off = kCkptRecOff + ((P.rec_words * 4u + 15u) & ~15u);
         auto materialize = [&]() {
             const C *pt = reinterpret_cast<const C *>(lazy_slot + tile_off);
@@ -969,6 +979,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         uint32_t e0 = 0;
         lazy_slot = nullptr;
         deferred = false;
+        replaying = false;
         if (P.prefix != nullptr && !(!LEAN && P.prefix_build) && !tracing && ck_c != 0u) {
             // checkpoint c's noise count and validity in lane c (one load each)
             uint32_t cev = 0u, cnz = 0xFFFFFFFFu, cok = 0u;
@@ -1019,6 +1030,17 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // trace steps, or (build) the events up to the last checkpoint
         const uint32_t dump_lim = ((!LEAN && P.prefix_build) && ck_c) ? uni(P.ckpts[ck_o + ck_c - 1u].ev) + 1u : trace_lim;
         for (;; ++e) {
+            if (replaying && e == get(10)) {
+                // the deferred run is applied: back to the event that needed
+                // it, with the signs it had (its own Clifford flips not yet
+                // applied), to run it from its start
+                rD = get64(4);
+                rS = get64(6);
+                e = get(8);
+                evc = evl[(uint64_t)e * 64u + lane];
+                evx = evl[(uint64_t)(e + 1u) * 64u + lane];
+                replaying = false;
+            }
             uint32_t evy = evl[(uint64_t)(e + 2u) * 64u + lane];
             if (e - 1u < dump_lim) {  // state after event e-1 (e = 0 wraps past any limit)
                 if ((!LEAN && P.prefix_build)) {
@@ -1058,14 +1080,34 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
             // ---- Cliffords since the previous event: one XOR ----
             uint32_t flags = EV32(flags);
             uint32_t kind = EV32(kind);
+            // a run applied late: its first event's Clifford flips are in
+            // the saved signs, and it is neither deferred nor loaded again
+            if (replaying) flags &= ~(EVF_CLIFF | EVF_MAT | EVF_DEFER);
             if (flags & (EVF_CLIFF | EVF_MAT | EVF_DEFER)) {
-                // an event that needs the tile after a deferred T run: redo
-                // the attempt without deferring
+                // an event that needs the tile after a deferred T run: apply
+                // the run now, with the signs it saw (T reads only those; the
+                // events since then left the tile alone), then come back here
                 if ((flags & EVF_MAT) && deferred) {
-                    redo = true;
-                    restart = true;
-                    --e;  // event e did not run (the attempt's work ends before it)
-                    break;
+                    if (lazy_slot != nullptr) materialize();
+                    put(4u, (uint32_t)rD);
+                    put(5u, (uint32_t)(rD >> 32));
+                    put(6u, (uint32_t)rS);
+                    put(7u, (uint32_t)(rS >> 32));
+                    put(8u, e);
+                    rD = get64(0u);
+                    rS = get64(2u);
+                    const uint32_t r0 = get(9u);
+                    const Event *d0 = reinterpret_cast<const Event *>(evl) + r0, *d1 = d0 + (get(10u) - r0);
+                    if (lane == (uint32_t)C_ENTRIES_T) myc += d1->cum_t - d0->cum_t;
+                    if (lane == (uint32_t)C_EVENTS) myc += (uint64_t)(d1->cum_e - d0->cum_e);
+                    myc += lane == (uint32_t)C_REDO ? 1u : 0u;
+                    deferred = false;
+                    replaying = true;
+                    e = r0 - 1u;  // the loop's step takes it to the run's first event
+                    evx = evl[(uint64_t)r0 * 64u + lane];
+                    evy = evl[(uint64_t)(r0 + 1u) * 64u + lane];
+                    kind = EV_NOP;
+                    flags = 0u;
                 }
                 if (flags & EVF_CLIFF) {
                     rD ^= EV64(cliffD);
@@ -1080,6 +1122,12 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     if (lane == (uint32_t)C_ENTRIES_T) myc -= d1->cum_t - d0->cum_t;
                     if (lane == (uint32_t)C_EVENTS) myc -= (uint64_t)(d1->cum_e - d0->cum_e);
                     deferred = true;
+                    put(0u, (uint32_t)rD);
+                    put(1u, (uint32_t)(rD >> 32));
+                    put(2u, (uint32_t)rS);
+                    put(3u, (uint32_t)(rS >> 32));
+                    put(9u, e);
+                    put(10u, e + m);
                     e += m - 1u;
                     evx = evl[(uint64_t)(e + 1u) * 64u + lane];
                     evy = evl[(uint64_t)(e + 2u) * 64u + lane];
