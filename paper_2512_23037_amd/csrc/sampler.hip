@@ -1921,10 +1921,7 @@ int kernel_index(bool fp64, uint32_t ns, uint32_t tm, bool lean) {
 // prefix build, which has its own kernels).  With the build's code out as
 // well, the FP32 LDS kernel spills 90 SGPRs instead of 245: measured +11%
 // FP32 and +14% FP64 on the 42-qubit workload, +11% on span-12 split tiles.
-bool sampler_lean(const RunParams &p, bool fp64) {
-    (void)fp64;
-    return p.keep_n == 0u && p.trace_n == 0u && p.words == nullptr;
-}
+bool sampler_lean(const RunParams &p) { return p.keep_n == 0u && p.trace_n == 0u && p.words == nullptr; }
 
 hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long long *next, hipStream_t stream) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, stream, counters, n, next);
@@ -1935,8 +1932,7 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
     const uint32_t ns = p.words != nullptr ? NS_EXPLICIT : (p.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
     void *args[7] = {(void *)&p.ev, (void *)&p.nz, (void *)&p.tm1, (void *)&p.det, (void *)&p.words, (void *)&p.bm,
                      (void *)&p};
-    return hipLaunchKernel(sampler_kernel(fp64, ns, p.tile_mode, sampler_lean(p, fp64)), grid, block, args, lds,
-                           stream);
+    return hipLaunchKernel(sampler_kernel(fp64, ns, p.tile_mode, sampler_lean(p)), grid, block, args, lds, stream);
 }
 
 const void *sampler_kernel(bool fp64, uint32_t ns, uint32_t tm, bool lean) {

@@ -522,7 +522,7 @@ int launch(soft_ctx *c, RunParams rp, const Shape &s, uint64_t n_shots, hipStrea
     }
     const uint64_t bgrid = std::min<uint64_t>(grid, (2ull * rp.n_vars + s.wpb - 1) / s.wpb);
     const uint32_t ns = rp.words != nullptr ? NS_EXPLICIT : (rp.noise_mode == 1u ? NS_GAPS : NS_SLOTS);
-    const void *kfn = sampler_kernel(c->bits == 64, ns, s.gt, sampler_lean(rp, c->bits == 64));
+    const void *kfn = sampler_kernel(c->bits == 64, ns, s.gt, sampler_lean(rp));
     // what the nodes' launch configuration and the reset node depend on
     const uint64_t kv[9] = {(uint64_t)(uintptr_t)kfn, grid, (uint64_t)b.x, (uint64_t)lds,
                             (uint64_t)(uintptr_t)rp.counters, (uint64_t)rp.n_vars, (uint64_t)(uintptr_t)rp.next,
