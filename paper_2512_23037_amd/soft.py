@@ -214,7 +214,9 @@ class Context:
 
     def set_deferred_t(self, on: bool):
         """Skip T runs whose coefficients no event needs before the shot ends
-        (default on; a shot that needs them runs again with them applied)."""
+        (default on; a shot that needs them applies the run when it does, with
+        the signs the run saw; a kept shot that ends with a run skipped runs
+        again with every run applied)."""
         self._check(self._lib.soft_set_deferred_t(self._h, 1 if on else 0))
 
     def set_noise_mode(self, mode: int):

@@ -1,8 +1,10 @@
 """Deferred T runs (soft_set_deferred_t): a run of T gates with no noise
 between them, followed by events that read only the tableau signs, is
 skipped; a shot whose check fails before any event reads the coefficients
-never needs it, and a shot that does need it (or whose final state is kept)
-runs again with every run applied.  Records, statuses, abort ops,
+never needs it; a shot that does need it applies the run late, at the event
+that needs it, with the tableau signs the run saw, and a shot whose final
+state is kept and still has a run skipped runs again with every run
+applied.  Records, statuses, abort ops,
 observables, kept final states and pass / discard / logical counts are
 identical with deferral on and off, with and without checkpoints, in both
 precisions and noise draws; the oracle agrees with it on."""
@@ -57,7 +59,7 @@ def test_defer_on_off_42q(bits, mode, prefix):
 
     on, off = _on_off(build, 400_000, kept=128)
     # shots with a fault before the first T layer skip it and most end at the
-    # first check round; the others that need it run again
+    # first check round; the others apply it late
     assert on["redo_shots"] > 0
     assert on["entries_t"] < off["entries_t"]
 
@@ -81,7 +83,8 @@ def test_defer_on_off_15q_both_lists_and_oracle():
 @pytest.mark.parametrize("seed", range(6))
 def test_defer_random_circuits_explicit_words(seed):
     # T gates followed by outcome-fixed measurements and checks, under dense
-    # noise: deferred runs, redone attempts and kept states against the oracle
+    # noise: deferred runs, runs applied late, redone kept attempts and kept
+    # states against the oracle
     n = 4 + seed % 3
     text, _ = random_circuit(91000 + seed, n, 120, p_t=0.2, p_meas=0.15)
     lines = text.strip().split("\n")
