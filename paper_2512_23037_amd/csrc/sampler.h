@@ -71,7 +71,8 @@ hipError_t launch_sampler(const RunParams &p, bool fp64, dim3 grid, dim3 block, 
 // the counter reset (arguments: counters, n, next; one block of 256 threads).
 const void *sampler_kernel(bool fp64, uint32_t noise_source, uint32_t tile_mode, bool lean);
 // Whether a launch with these parameters runs the lean kernel (no kept
-// states, no trace, no explicit words; see sampler.hip).
+// states, no trace, no support cap, no shot list, no explicit words; see
+// sampler.hip).
 bool sampler_lean(const RunParams &p);
 const void *reset_kernel();
 // The shared-prefix build kernel for a precision and tile mode (arguments as

@@ -540,9 +540,9 @@ __device__ __forceinline__ uint32_t quot16(uint64_t x, uint64_t d) {
     (((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u + 1u)) << 32) | \
      (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)evx, (int)(offsetof(Event, f) / 4u)))
 
-// LEAN: a launch with no kept states and no trace (and never the prefix
-// build); those paths compile out, which frees scalar registers in the event
-// loop.
+// LEAN: a launch with no kept states, no trace, no support cap and no shot
+// list (and never the prefix build); those paths compile out, which frees
+// scalar registers in the event loop.
 template <typename R, uint32_t NS, uint32_t TM, bool LEAN = false>
 __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const NoiseLoc *__restrict__ nz,
                                              const uint32_t *__restrict__ tm1, const uint32_t *__restrict__ det,
@@ -638,7 +638,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // a vector load of a uniform address: say that the result is uniform
         // (item i of the prefix build runs the first shot of variant i / 2)
         const uint64_t shot = uni64((!LEAN && P.prefix_build) ? ((i >> 1) ? P.vars[(i >> 1) - 1u].shot_end : 0ull)
-                                    : P.shot_list ? P.shot_list[i] : P.shot0 + i);
+                                    : (!LEAN && P.shot_list) ? P.shot_list[i] : P.shot0 + i);
         const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
         if (!var_ok || shot >= var_end || shot < var_lo) {
             if (var_ok) flush_counters();
@@ -865,7 +865,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // so the restarted shot is the one the full list gives.
         // (with a support cap the full list runs: the cap is defined by the
         // supports of the circuit's own gate order)
-        bool full = tracing || !P.speculate || P.support_cap != 0xFFFFFFFFu || vdp->ev_off_full == vdp->ev_off;
+        bool full = tracing || !P.speculate || (LEAN ? 0xFFFFFFFFu : P.support_cap) != 0xFFFFFFFFu || vdp->ev_off_full == vdp->ev_off;
         if ((!LEAN && P.prefix_build)) full = (i & 1u) != 0u || vdp->ev_off_full == vdp->ev_off;
         bool pfx_done = false;      // the build wrote every checkpoint of this item's list
         uint32_t ck_next_done = 0;  // checkpoints written
@@ -875,7 +875,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // Deferred T runs (EVF_DEFER): skipped while defer_ok; `deferred` once
         // one was skipped, and `redo` when an event needed its tile (the
         // attempt then runs again with defer_ok off).
-        bool defer_ok = P.defer != 0u && !tracing && !(!LEAN && P.prefix_build) && P.support_cap == 0xFFFFFFFFu;
+        bool defer_ok = P.defer != 0u && !tracing && !(!LEAN && P.prefix_build) && (LEAN ? 0xFFFFFFFFu : P.support_cap) == 0xFFFFFFFFu;
         // Butterfly pairs run as one pass where an FP32 pass reads and
         // writes device memory (tiles there, or split tiles larger than
         // their LDS part): each entry crosses to the slab once instead of
@@ -886,7 +886,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
         // Not when a trace wants the state after each event or a support cap
         // is checked after each T.
         constexpr bool kPairs = TM != TM_LDS && sizeof(R) == 4;
-        const bool pair_ok = kPairs && !tracing && P.support_cap == 0xFFFFFFFFu;
+        const bool pair_ok = kPairs && !tracing && (LEAN ? 0xFFFFFFFFu : P.support_cap) == 0xFFFFFFFFu;
         auto pair_now = [&](uint32_t fl) { return (fl & EVF_PAIR) && pair_ok && (1u << k) > v.lim; };
         bool deferred = false, redo = false;
         // A deferred run applied late: the signs the run saw and the state
@@ -1209,7 +1209,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 phase8 = (phase8 + EV32(boff)) & 15u;
                 cmax = uni(cmax);
                 maxsup = max(maxsup, cmax);
-                if (cmax > P.support_cap) {  // only the full list enforces a cap
+                if (cmax > (LEAN ? 0xFFFFFFFFu : P.support_cap)) {  // only the full list enforces a cap
                     restart = true;
                     break;
                 }
@@ -1267,7 +1267,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     const uint32_t cnt = uni((uint32_t)__popcll(kb));
                     maxsup = max(maxsup, cnt);
                     // lanes n/2 .. n-1 hold the entries with the dropped bit set
-                    if (cnt > P.support_cap || (kb >> (n >> 1)) != 0ull) {
+                    if (cnt > (LEAN ? 0xFFFFFFFFu : P.support_cap) || (kb >> (n >> 1)) != 0ull) {
                         fail = true;
                         fi = i;
                         break;
@@ -1367,7 +1367,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                 phase8 = (phase8 + ((flags & EVF_TDG) ? 15u : 1u)) & 15u;
                 cnt = uni(cnt);
                 maxsup = max(maxsup, cnt);
-                if (cnt > P.support_cap) {
+                if (cnt > (LEAN ? 0xFFFFFFFFu : P.support_cap)) {
                     // the speculative list visits other intermediate states:
                     // the full list decides where (and whether) the cap is hit
                     if (!full) {
@@ -1725,7 +1725,7 @@ __device__ __forceinline__ void sample_shots(const Event *__restrict__ ev, const
                     k = knew;
                     cnt = uni(cnt);
                     maxsup = max(maxsup, cnt);
-                    if (cnt > P.support_cap) {
+                    if (cnt > (LEAN ? 0xFFFFFFFFu : P.support_cap)) {
                         if (!full) {  // the full list decides where the cap is hit
                             restart = true;
                             break;
@@ -1917,11 +1917,16 @@ int kernel_index(bool fp64, uint32_t ns, uint32_t tm, bool lean) {
 }
 }  // namespace
 
-// The lean kernels run launches with no kept states and no trace (never the
-// prefix build, which has its own kernels).  With the build's code out as
-// well, the FP32 LDS kernel spills 90 SGPRs instead of 245: measured +11%
-// FP32 and +14% FP64 on the 42-qubit workload, +11% on span-12 split tiles.
-bool sampler_lean(const RunParams &p) { return p.keep_n == 0u && p.trace_n == 0u && p.words == nullptr; }
+// The lean kernels run launches with no kept states, no trace, no support
+// cap and no shot list (never the prefix build, which has its own kernels).
+// With the build's code out as well, the FP32 LDS kernel spilled 90 SGPRs
+// instead of 245: measured +11% FP32 and +14% FP64 on the 42-qubit workload,
+// +11% on span-12 split tiles; leaving out the cap and the shot list then
+// added 1-2%.
+bool sampler_lean(const RunParams &p) {
+    return p.keep_n == 0u && p.trace_n == 0u && p.words == nullptr && p.support_cap == 0xFFFFFFFFu &&
+           p.shot_list == nullptr;
+}
 
 hipError_t launch_reset(unsigned long long *counters, uint32_t n, unsigned long long *next, hipStream_t stream) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, stream, counters, n, next);
