@@ -1,0 +1,99 @@
+"""GPU parity on random feature-rich circuits under random library options.
+
+Each seed draws a circuit (Cliffords, T/T-dagger, Z and Pauli-product
+measurements, resets, the extended measurement-and-reset set, record-controlled
+Paulis, CCZ/CCX, diagonal gates, classically controlled gates, detectors and
+an observable), a uniform noise rate, and one setting of every option that
+must not change results: per-slot or gap-sampled noise, FP64 or FP32
+coefficients, speculative lists, checkpoints of the noiseless trajectory,
+deferred T runs, and the tile placement (automatic, LDS, device memory,
+split).  Records, statuses, abort ops and observables are compared with the
+oracle on 1500 shots (FP64 bit-exact; FP32 may differ only where a
+measurement's uniform lies within 1e-5 of the oracle's probability), and the
+final tableau and coefficients of shots 0..63 (1e-10 FP64, 1e-5 FP32)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gen_small import random_circuit
+from tests.gpu_helpers import compare_batch, compare_kept_many, guard_band_flips, make_ctx, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+N = 1500
+KEPT = 64
+REC_OPS = ("M ", "MPP", "MX ", "MR ", "MRX")
+
+
+def draw_case(seed):
+    """The circuit text, noise model and options of one seed."""
+    rng = np.random.default_rng(seed)
+    big = seed % 3 == 0
+    n = int(rng.integers(2, 15 if big else 11))
+    length = int(rng.integers(60, 500 if big else 240))
+    text, _ = random_circuit(880000 + seed, n, length, p_t=float(rng.uniform(0.05, 0.3)),
+                             p_meas=float(rng.uniform(0.03, 0.12)), p_msc=0.05, p_ccz=0.02 if n >= 3 else 0.0,
+                             p_diag=0.03, p_if=0.03)
+    lines = text.strip().split("\n")
+    head = []
+    if n <= 10 and rng.random() < 0.5:  # grow the span early
+        head = ["H %d\nT %d" % (q, q) for q in range(n)]
+    out = [lines[0]] + head
+    nrec = 0
+    pdet = float(rng.choice([0.0, 0.03, 0.1]))
+    for line in lines[1:]:
+        out.append(line)
+        if line.startswith(REC_OPS):
+            nrec += 1
+            if rng.random() < pdet:
+                k = int(rng.integers(1, min(3, nrec) + 1))
+                recs = rng.choice(nrec, size=k, replace=False)
+                out.append("DETECTOR %d %s" % (int(rng.integers(2)), " ".join(str(int(r)) for r in recs)))
+    if nrec:
+        out.append("OBSERVABLE 0 %d" % int(rng.integers(nrec)))
+    text = "\n".join(out) + "\n"
+    p = float(rng.choice([0.0, 0.002, 0.01, 0.03]))
+    noise = {"p1": p, "p2": p, "p_meas": p, "p_reset": p, "p_mpp": p}
+    opts = {"mode": int(rng.integers(2)), "bits": 64 if rng.random() < 0.7 else 32}
+    opts["spec"], opts["prefix"], opts["defer"] = (bool(rng.integers(2)) for _ in range(3))
+    opts["tile"] = int(rng.integers(4))
+    opts["lds_log2"] = 7 if rng.random() < 0.5 else 0
+    return text, noise, opts
+
+
+def run_case(seed):
+    text, noise, o = draw_case(seed)
+    circ = oracle.Circuit(text, noise, noise_mode=o["mode"])
+    ctx = make_ctx(text, noise, seed=seed, bits=o["bits"], keep=(0, KEPT))
+    ctx.set_noise_mode(o["mode"])
+    ctx.set_speculation(o["spec"])
+    ctx.set_shared_prefix(o["prefix"])
+    ctx.set_deferred_t(o["defer"])
+    kmax = ctx.info()["k_max"]
+    tile = 2 if (o["tile"] == 3 and kmax < 8) else o["tile"]  # a split tile needs a span of 2^8
+    ctx.set_tile_memory(tile, o["lds_log2"] if tile == 3 else 0)
+    print("seed %d n=%d k_max=%d %s noise %g tile %d" % (seed, circ.n_qubits, kmax, o, noise["p1"], tile), flush=True)
+    gpu = run_gpu(ctx, 0, N)
+    ref = circ.batch(seed, 0, N)
+    if o["bits"] == 64:
+        compare_batch(gpu, ref)
+        compare_kept_many(ctx, circ, seed, list(range(KEPT)))
+    else:
+        diff = (gpu["status"] != ref["status"]) | (gpu["abort_op"] != ref["abort_op"]) | (gpu["obs"] != ref["obs"])
+        if ref["outcomes"].size:
+            diff |= (gpu["outcomes"] != ref["outcomes"]).any(axis=0)
+        bad = np.nonzero(diff)[0]
+        assert len(bad) <= 10
+        res = [circ.shot(seed, int(s)) for s in bad]
+        assert all(guard_band_flips(circ, seed, list(zip(bad, res)))), "FP32 difference outside the guard band"
+        compare_batch(gpu, ref, skip=diff)
+        compare_kept_many(ctx, circ, seed, [s for s in range(KEPT) if not diff[s]], tol=1e-5, tau=1e-6)
+    ctx.close()
+
+
+@pytest.mark.parametrize("chunk", range(12))
+def test_random_circuits_random_options(chunk):
+    for seed in range(150 + 16 * chunk, 150 + 16 * (chunk + 1)):
+        run_case(seed)
