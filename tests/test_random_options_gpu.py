@@ -10,15 +10,19 @@ deferred T runs, and the tile placement (automatic, LDS, device memory,
 split).  Records, statuses, abort ops and observables are compared with the
 oracle on 1500 shots (FP64 bit-exact; FP32 may differ only where a
 measurement's uniform lies within 1e-5 of the oracle's probability), and the
-final tableau and coefficients of shots 0..63 (1e-10 FP64, 1e-5 FP32)."""
+final tableau and coefficients of shots 0..63 (1e-10 FP64, 1e-5 FP32).
+A second group runs the same circuits in FP64 through the other ways in:
+shot offsets up to 2^40, support caps (overflow statuses, counters and the
+tableau at the abort), shot lists in any order, explicit per-shot words, and
+the no-alloc entry point against the regular one."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
 import oracle
-from tests.gen_small import random_circuit
-from tests.gpu_helpers import compare_batch, compare_kept_many, guard_band_flips, make_ctx, run_gpu
+from tests.gen_small import random_circuit, random_words
+from tests.gpu_helpers import compare_batch, compare_kept, compare_kept_many, guard_band_flips, make_ctx, run_gpu, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -97,3 +101,86 @@ def run_case(seed):
 def test_random_circuits_random_options(chunk):
     for seed in range(150 + 16 * chunk, 150 + 16 * (chunk + 1)):
         run_case(seed)
+
+
+def _outs(ctx, n):
+    t = torch()
+    nw = ctx.info()["record_words"]
+    return [t.zeros((max(nw, 1), n), dtype=t.int32, device="cuda")] + \
+        [t.zeros(n, dtype=t.int32, device="cuda") for _ in range(3)]
+
+
+def _host(outs, nw):
+    d = {k: x.cpu().numpy().view(np.uint32) for k, x in zip(("outcomes", "status", "abort_op", "obs"), outs)}
+    d["outcomes"] = d["outcomes"][:nw]
+    return d
+
+
+def run_entry_case(seed):
+    text, noise, o = draw_case(seed)
+    rng = np.random.default_rng(10 ** 6 + seed)
+    kind = int(rng.integers(4))  # offset, cap, list, explicit words + no-alloc
+    circ = oracle.Circuit(text, noise, noise_mode=o["mode"])
+    n = 1000
+    print("seed %d kind %d n=%d %s" % (seed, kind, circ.n_qubits, o), flush=True)
+    if kind == 0:
+        shot0 = int(rng.integers(1, 1 << 40))
+        ctx = make_ctx(text, noise, seed=seed, keep=(shot0 + 7, 32))
+        ctx.set_noise_mode(o["mode"])
+        ctx.set_deferred_t(o["defer"])
+        compare_batch(run_gpu(ctx, shot0, n), circ.batch(seed, shot0, n))
+        compare_kept_many(ctx, circ, seed, list(range(shot0 + 7, shot0 + 39)))
+    elif kind == 1:
+        cap = int(2 ** rng.integers(0, 7))
+        ctx = make_ctx(text, noise, seed=seed, cap=cap, keep=(0, 32))
+        ctx.set_noise_mode(o["mode"])
+        gpu = run_gpu(ctx, 0, n)
+        ref = circ.batch(seed, 0, n, cap=cap)
+        compare_batch(gpu, ref)
+        assert ctx.counters()["overflow"] == int((ref["status"] == oracle.OVERFLOW).sum())
+        for s in range(32):
+            r = circ.shot(seed, s, cap=cap)
+            x, z, rr = ctx.read_tableau(s)
+            assert (x == r.tab_x).all() and (z == r.tab_z).all() and (rr == r.tab_r).all(), "tableau of shot %d" % s
+    elif kind == 2:
+        shots = rng.choice(1 << 36, size=n, replace=False).astype(np.int64)
+        ctx = make_ctx(text, noise, seed=seed)
+        ctx.set_noise_mode(o["mode"])
+        ctx.set_deferred_t(o["defer"])
+        ctx.set_shared_prefix(o["prefix"])
+        nw = ctx.info()["record_words"]
+        outs = _outs(ctx, n)
+        ctx.run_list(torch().from_numpy(shots).cuda(), *outs)
+        torch().cuda.synchronize()
+        gpu = _host(outs, nw)
+        for i in rng.choice(n, size=100, replace=False):
+            r = circ.batch(seed, int(shots[i]), 1)
+            for k in ("status", "abort_op", "obs"):
+                assert gpu[k][i] == r[k][0], (k, int(shots[i]))
+            if nw:
+                assert (gpu["outcomes"][:, i] == r["outcomes"][:, 0]).all(), ("outcomes", int(shots[i]))
+    else:
+        circ0 = oracle.Circuit(text, noise)
+        words = random_words(seed, n * circ0.words_per_shot).reshape(n, circ0.words_per_shot)
+        ctx = make_ctx(text, noise, seed=seed, keep=(0, 64))
+        ctx.set_deferred_t(o["defer"])
+        compare_batch(run_gpu(ctx, 0, n, words), circ0.batch(0, 0, n, words=words))
+        compare_kept(ctx, circ0, 0, range(64), words=words)
+        ctx.close()
+        ctx = make_ctx(text, noise, seed=seed)
+        ctx.set_noise_mode(o["mode"])
+        ref = run_gpu(ctx, 0, n)
+        nw = ctx.info()["record_words"]
+        outs = _outs(ctx, n)
+        ctx.run_noalloc(0, n, *outs)
+        torch().cuda.synchronize()
+        got = _host(outs, nw)
+        for k in ("status", "abort_op", "obs", "outcomes"):
+            assert (got[k] == ref[k]).all(), ("no-alloc", k)
+    ctx.close()
+
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_random_circuits_every_entry(chunk):
+    for seed in range(600 + 16 * chunk, 600 + 16 * (chunk + 1)):
+        run_entry_case(seed)
