@@ -14,7 +14,8 @@ final tableau and coefficients of shots 0..63 (1e-10 FP64, 1e-5 FP32).
 A second group runs the same circuits in FP64 through the other ways in:
 shot offsets up to 2^40, support caps (overflow statuses, counters and the
 tableau at the abort), shot lists in any order, explicit per-shot words, and
-the no-alloc entry point against the regular one."""
+the no-alloc entry point against the regular one.  A third group puts 2-6 of
+these circuits and noise models in one mixed launch."""
 from __future__ import annotations
 
 import numpy as np
@@ -22,7 +23,8 @@ import pytest
 
 import oracle
 from tests.gen_small import random_circuit, random_words
-from tests.gpu_helpers import compare_batch, compare_kept, compare_kept_many, guard_band_flips, make_ctx, run_gpu, torch
+from tests.gpu_helpers import (coeff_error, compare_batch, compare_kept, compare_kept_many, guard_band_flips, make_ctx,
+                               run_gpu, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -184,3 +186,56 @@ def run_entry_case(seed):
 def test_random_circuits_every_entry(chunk):
     for seed in range(600 + 16 * chunk, 600 + 16 * (chunk + 1)):
         run_entry_case(seed)
+
+
+def run_mixture_case(seed):
+    """2-6 of the random circuits and noise models in one launch (random range
+    sizes, the first variant's options): each range against its own variant's
+    oracle, per-variant counters, and the states around the first boundary."""
+    from paper_2512_23037_amd import soft
+    rng = np.random.default_rng(2 * 10 ** 6 + seed)
+    nv = int(rng.integers(2, 7))
+    cases = [draw_case(5000 + seed * 8 + j) for j in range(nv)]
+    ends = [int(x) for x in np.cumsum(rng.integers(50, 500, size=nv))]
+    o = cases[0][2]
+    keys = ("p1", "p2", "p_idle", "p_meas", "p_reset", "p_mpp")
+    models = [{k: c[1].get(k, 0.0) for k in keys} for c in cases]
+    print("seed %d: %d variants, %d shots, %s" % (seed, nv, ends[-1], o), flush=True)
+    ctx = soft.Context(0)
+    ctx.load_mixture([c[0] for c in cases], models, ends)
+    ctx.set_rng(seed)
+    ctx.set_precision(64)
+    ctx.set_noise_mode(o["mode"])
+    ctx.set_speculation(o["spec"])
+    ctx.set_shared_prefix(o["prefix"])
+    ctx.set_deferred_t(o["defer"])
+    tile = 2 if (o["tile"] == 3 and ctx.info()["k_max"] < 8) else o["tile"]
+    ctx.set_tile_memory(tile, o["lds_log2"] if tile == 3 else 0)
+    b = ends[0]
+    ctx.set_keep(b - 16, 32)
+    gpu = run_gpu(ctx, 0, ends[-1])
+    lo, circs = 0, []
+    for v, ((text, _, _), hi) in enumerate(zip(cases, ends)):
+        circ = oracle.Circuit(text, models[v], noise_mode=o["mode"])
+        circs.append(circ)
+        ref = circ.batch(seed, lo, hi - lo)
+        sub = {k: (x[:, lo:hi] if x.ndim == 2 else x[lo:hi]) for k, x in gpu.items()}
+        nw = (circ.n_records + 31) // 32
+        assert not sub["outcomes"][nw:].any(), "record words past the variant's records must stay 0"
+        sub["outcomes"] = sub["outcomes"][:nw]
+        compare_batch(sub, ref)
+        cv = ctx.counters(v)
+        assert cv["shots"] == hi - lo and cv["passed"] == int((ref["status"] == 0).sum()), v
+        lo = hi
+    for shot in range(b - 16, b + 16):
+        r = circs[ctx.variant_of(shot)].shot(seed, shot)
+        x, z, rr = ctx.read_tableau(shot)
+        assert (x == r.tab_x).all() and (z == r.tab_z).all() and (rr == r.tab_r).all(), shot
+        assert coeff_error(ctx.read_coeffs(shot), r.coeffs) < 1e-10, shot
+    ctx.close()
+
+
+@pytest.mark.parametrize("chunk", range(2))
+def test_random_mixtures(chunk):
+    for seed in range(16 * chunk, 16 * (chunk + 1)):
+        run_mixture_case(seed)
