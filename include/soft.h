@@ -395,7 +395,9 @@ int soft_read_tableau(soft_ctx *ctx, uint64_t shot, uint64_t *x, uint64_t *z, ui
 /* Trace mode (the step-by-step validation of Sec. V-B): record the state of shot
  * `shot` after each of its first `steps` events (T/T-dagger, measurements,
  * detectors, observables, end) in the next runs; steps = 0 disables it
- * (steps <= 65536). */
+ * (steps <= 65536).  Cliffords make no event: they reach the state at the next
+ * event, so the state recorded for CCX a b t (H_t CCZ H_t) is the one after
+ * its CCZ, with the second H_t still to come. */
 int soft_set_trace(soft_ctx *ctx, uint64_t shot, uint32_t steps);
 
 /* State (v, B(S, D)) of Definition 1 of the traced shot after event `step`

@@ -15,7 +15,8 @@ A second group runs the same circuits in FP64 through the other ways in:
 shot offsets up to 2^40, support caps (overflow statuses, counters and the
 tableau at the abort), shot lists in any order, explicit per-shot words, and
 the no-alloc entry point against the regular one.  A third group puts 2-6 of
-these circuits and noise models in one mixed launch."""
+these circuits and noise models in one mixed launch, and a fourth checks the
+state after every event of one shot against the oracle on the prefix."""
 from __future__ import annotations
 
 import numpy as np
@@ -239,3 +240,51 @@ def run_mixture_case(seed):
 def test_random_mixtures(chunk):
     for seed in range(16 * chunk, 16 * (chunk + 1)):
         run_mixture_case(seed)
+
+
+def run_trace_case(seed):
+    """The state after every event of one shot (Sec. V-B's step-by-step
+    check) against the oracle run on the circuit's prefix.  Even seeds drop
+    the detectors so that the shot runs every event."""
+    text, _, o = draw_case(seed)
+    if seed % 2 == 0:
+        text = "\n".join(x for x in text.strip().split("\n") if not x.startswith("DETECTOR")) + "\n"
+    lines = text.strip().split("\n")
+    circ = oracle.Circuit(text)
+    words = random_words(seed, circ.words_per_shot)
+    bits = o["bits"]
+    tau = 1e-12 if bits == 64 else 1e-6
+    ctx = make_ctx(text, bits=bits, tau=tau)
+    kmax = ctx.info()["k_max"]
+    tile = 2 if (o["tile"] == 3 and kmax < 8) else o["tile"]
+    if tile == 1 and kmax > 12:
+        tile = 0
+    ctx.set_tile_memory(tile, o["lds_log2"] if tile == 3 else 0)
+    events = ctx.info()["events"]
+    ctx.set_trace(0, events)
+    run_gpu(ctx, 0, 1, words.reshape(1, -1))
+    steps = 0
+    for step in range(events):
+        t = ctx.read_trace(step)
+        if t is None:
+            break
+        upto = lines[: t["op"] + 2]
+        tok = upto[-1].split() if t["op"] + 1 < len(lines) else []
+        if "CCX" in tok:  # the event is the CCZ of H_t CCZ H_t
+            i = tok.index("CCX")
+            upto[-1] = "H %s\n%s" % (tok[i + 3], " ".join(tok[:i] + ["CCZ"] + tok[i + 1:]))
+        pc = oracle.Circuit("\n".join(upto) + "\n")
+        r = pc.shot(0, 0, words=words[: pc.words_per_shot], tau=tau)
+        if t["final"] and r.status != oracle.PASSED:
+            assert t["status"] == r.status, step
+        assert (t["x"] == r.tab_x).all() and (t["z"] == r.tab_z).all() and (t["r"] == r.tab_r).all(), step
+        assert coeff_error(t["coeffs"], r.coeffs) < (1e-10 if bits == 64 else 1e-5), (step, upto[-1])
+        steps += 1
+    ctx.close()
+    return steps
+
+
+@pytest.mark.parametrize("chunk", range(2))
+def test_random_traces_step_by_step(chunk):
+    steps = sum(run_trace_case(seed) for seed in range(16 * chunk, 16 * (chunk + 1)))
+    assert steps > 500
