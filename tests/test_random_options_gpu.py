@@ -23,6 +23,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2512_23037_amd import soft
 from tests.gen_small import random_circuit, random_words
 from tests.gpu_helpers import (coeff_error, compare_batch, compare_kept, compare_kept_many, guard_band_flips, make_ctx,
                                run_gpu, torch)
@@ -193,7 +194,6 @@ def run_mixture_case(seed):
     """2-6 of the random circuits and noise models in one launch (random range
     sizes, the first variant's options): each range against its own variant's
     oracle, per-variant counters, and the states around the first boundary."""
-    from paper_2512_23037_amd import soft
     rng = np.random.default_rng(2 * 10 ** 6 + seed)
     nv = int(rng.integers(2, 7))
     cases = [draw_case(5000 + seed * 8 + j) for j in range(nv)]
