@@ -12,7 +12,7 @@ Outside the timed region each precision also samples shots 0..9999 with their
 final states kept; the CPU-baseline leg times the oracle on the host and
 compares those shots with it (records, statuses, tableaux, coefficient error).
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -38,7 +38,7 @@ LONG_SHOTS_P = 5e-4     # noise rate of the leg whose discard rate is near the p
 # Peaks (MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz):
 INT_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit vector lane-ops/s, 39.3 T
 FP32_PEAK_TFLOPS = 157.3                       # published vector FP32 (packed FMA)
-FP32_NONPACKED_TFLOPS = 78.6                   # one FMA per lane per cycle (packed FP32 is off in this build)
+FP32_NONPACKED_TFLOPS = 78.6                   # one FMA per lane per cycle (the kernels are compiled without packed FP32)
 
 # Algorithmic work per unit (the measurement plan's units):
 INT_PER_ENTRY = 8        # per coefficient entry an event touches: alpha^beta, parity(gamma & alpha), partner compare
@@ -385,7 +385,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the sampler shards shot ranges across GPUs by design, "
-              "but this build launches no multi-GPU runs); use --gpus 1", file=sys.stderr)
+              "but the benchmark launches no multi-GPU runs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
